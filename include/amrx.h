@@ -1,0 +1,190 @@
+/*
+ * amrx.h -- C ABI of libamrx, the gfx950 (MI355X) hot path of patch-based AMR MHD.
+ *
+ * The library advances a static, properly nested hierarchy of ghost-padded
+ * patches with refinement ratio R = 2 and ghost width G = 4 = R * n_g, n_g = 2
+ * being the stencil depth of one substep.  It follows the paper's statement
+ * of the problem (Carroll-Nellenback, Shroyer, Frank & Ding, "Efficient
+ * Parallelization for AMR MHD Multiphysics Calculations; Implementation in
+ * AstroBEAR"):
+ *   - patches on levels l with cell width dx_{l-1} = R dx_l, each refined patch
+ *     nested in a single parent (Sec. 2);
+ *   - one step of level l = Advance, Prolongate pre-advance data to the
+ *     children, the children's R substeps, Restrict data and fluxes onto the
+ *     parent, Synchronise fluxes with same-level neighbours (Sec. 2.2, the
+ *     recursive AMR(l) routine);
+ *   - extended ghost cells: a refined patch first updates a region R*n_g
+ *     wider than its interior and then successively smaller ones, so it needs
+ *     ghost data from its parent only before its first substep (Sec. 2.3);
+ *   - level advances may proceed independently, finer levels first (Sec. 4).
+ * The per-patch advance is an unsplit MUSCL-Hancock step with HLLD fluxes
+ * (Miyoshi & Kusano 2005) and constrained-transport EMFs (Gardiner & Stone
+ * 2005); the paper does not describe its solver.
+ *
+ * Conventions shared by every entry point
+ *   - Return value: AMRX_OK (0) or a negative AMRX_E* code.  No entry point
+ *     aborts or throws; the text of the last error is hier_last_error().
+ *   - Indices are (x, y, z) triples in the index space of the patch's level
+ *     (level l has root_n[d] * 2^l cells along axis d on [lo, hi) of the
+ *     domain, periodic on all axes).
+ *   - Device memory is owned by the caller (e.g. PyTorch tensors) and bound
+ *     once with hier_bind(); the library never allocates or frees device
+ *     memory.  The library owns only host metadata.
+ *   - Asynchrony: every call after hier_bind() is enqueued on desc.stream and
+ *     returns without waiting, except cfl_dt(), hier_step(), hier_conservation()
+ *     and hier_diag(), which synchronise that stream.  Calls on one hierarchy
+ *     must not run concurrently from several host threads.
+ *
+ * Memory layout of the state arena (hier_state_bytes() bytes)
+ *   Every patch owns two state buffers (current and next; an advance writes
+ *   the next buffer and then swaps).  A buffer holds 8 arrays of the patch's
+ *   node-padded volume V = (nx+2G+1)(ny+2G+1)(nz+2G+1) real numbers, each
+ *   indexed [z][y][x] with x fastest: rho, m_x, m_y, m_z, E (cell centred,
+ *   valid on [0, n+2G) per axis) and b_x, b_y, b_z (face-normal field; entry
+ *   [k][j][i] of b_x is the face at x = i - 1/2 of padded cell i, likewise for
+ *   y and z).  Padded index i corresponds to level index lo_x - G + i.  The
+ *   real type is double for AMRX_FP64 and float for both FP32 modes.
+ *   patch_layout() gives the byte offset of each array of each buffer.
+ */
+#ifndef AMRX_H
+#define AMRX_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  AMRX_OK = 0,
+  AMRX_EINVAL = -1,   /* bad argument (null pointer, bad size, bad level, ...) */
+  AMRX_ENEST = -2,    /* box violates nesting: odd corner, or not inside exactly one parent's
+                         interior shrunk by one parent cell on every side */
+  AMRX_EOVERLAP = -3, /* box overlaps a patch of the same level */
+  AMRX_ENOMEM = -4,   /* a bound buffer is too small */
+  AMRX_EHIP = -5,     /* a HIP runtime call failed (message in hier_last_error) */
+  AMRX_ESTATE = -6,   /* call out of order (e.g. patch_add after hier_finalize) */
+  AMRX_EPHYS = -7     /* device flagged rho <= 0, p <= 0 or a non-finite value */
+};
+
+enum { AMRX_FP64 = 0, AMRX_FP32 = 1, AMRX_FP32_MIXED = 2 };
+
+/* Schedules of hier_step(). */
+enum {
+  AMRX_PLAIN = 0,     /* every stage launched separately for every patch */
+  AMRX_BATCHED = 1,   /* every stage launched once for all patches of a level substep */
+  AMRX_GRAPH = 2      /* AMRX_BATCHED captured once into a HIP graph and replayed */
+};
+
+typedef struct amrx_hier amrx_hier;
+
+typedef struct {
+  int root_n[3];      /* level-0 cells per axis; refinement requires root_n[0]==root_n[1]==root_n[2] */
+  int max_level;      /* deepest level that may hold patches (0 .. 15) */
+  int ratio;          /* refinement ratio; must be 2 */
+  int nghost;         /* ghost width; must be 4 */
+  double gamma;       /* adiabatic index of the ideal gas */
+  double cfl;         /* Courant number used by cfl_dt() */
+  int precision;      /* AMRX_FP64, AMRX_FP32 or AMRX_FP32_MIXED */
+  void* stream;       /* hipStream_t all work is enqueued on (NULL = default stream) */
+} amrx_desc;
+
+/* Create an empty hierarchy.  Pure host call.  EINVAL on a bad descriptor. */
+int hier_create(const amrx_desc* desc, amrx_hier** out);
+
+/* Destroy host metadata.  Bound device memory stays with its owner. */
+int hier_destroy(amrx_hier* h);
+
+/* Text of the last error on h (never NULL). */
+const char* hier_last_error(const amrx_hier* h);
+
+/* Add the patch [lo, hi) on `level` (Sec. 2: a grid's node with its position and its parent).
+ * Level-0 patches must tile the root grid (checked by hier_finalize).  On
+ * levels >= 1, lo and hi must be even and the box must lie inside exactly one
+ * level-(l-1) patch's interior shrunk by one parent cell; same-level boxes
+ * must not overlap.  Pure host call.  Errors: EINVAL, ENEST, EOVERLAP, ESTATE. */
+int patch_add(amrx_hier* h, int level, const int lo[3], const int hi[3], int* patch_id);
+
+/* Freeze the topology and build every index list (ghost sources, prolongation
+ * cells, coverage maps, register layouts, stage task tables).  Pure host call.
+ * Reports the byte sizes of the state arena and of the scratch arena the
+ * caller must allocate.  Errors: ESTATE (twice), ENEST (root not tiled). */
+int hier_finalize(amrx_hier* h, size_t* state_bytes, size_t* scratch_bytes);
+
+/* Byte offsets, within the state arena, of the 8 arrays (rho, mx, my, mz, E,
+ * bx, by, bz) of buffer `which` (0 or 1) of a patch, and the padded array
+ * shape dims = (NX+1, NY+1, NZ+1).  Pure host call after hier_finalize. */
+int patch_layout(const amrx_hier* h, int patch_id, int which, size_t offsets[8], int dims[3]);
+
+/* Index of the buffer (0 or 1) that currently holds the state of a patch. */
+int patch_current(const amrx_hier* h, int patch_id, int* which);
+
+/* Bind the caller-owned device arenas (256-byte aligned) and upload the index
+ * lists.  Must follow hier_finalize.  ENOMEM if a size is too small. */
+int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size_t scratch_bytes);
+
+/* Ghost update of every patch of `level` before substep `substep`: copy the
+ * interior (closure, for faces) of the same-level patch holding each ghost
+ * value's periodic image (Sec. 2.1: data shared between neighbours of one
+ * iteration); on levels >= 1 at substep 0, prolongate the parent's
+ * pre-advance data into the ghost values no same-level patch holds (Sec. 2.2
+ * "Prolongate initial (pre-advanced) data", Sec. 2.3). */
+int level_ghost_fill(amrx_hier* h, int level, int substep);
+
+/* Advance every patch of `level` by dt_level (Sec. 2.2 "Advance"): substep s
+ * of a refined patch updates its interior grown by (R-1-s)*n_g cells, level 0
+ * its interior (Sec. 2.3).  Records boundary fluxes and EMFs for refluxing
+ * and synchronisation, then makes the written buffer current. */
+int advance_level(amrx_hier* h, int level, double dt_level, int substep);
+
+/* Restrict level fine_level onto its parents (Sec. 2.2 "Restrict"; "data and
+ * fluxes are restricted and applied to their parent"): covered coarse cells
+ * and faces take the volume / area mean of the fine data; uncovered coarse
+ * cells and faces next to the fine region are corrected so that the coarse
+ * fluxes and EMFs across the coverage boundary equal the time and space
+ * averages of the fine ones. */
+int restrict_level(amrx_hier* h, int fine_level);
+
+/* Synchronise fluxes through faces shared by patches of `level` (Sec. 2.2
+ * "Synchronize fluxes between neighboring level l grids"): the two sides'
+ * fluxes of the last substep are compared, replaced by their mean and the
+ * adjacent cells corrected; the largest difference seen is kept for hier_diag. */
+int sync_level(amrx_hier* h, int level);
+
+/* Largest stable root time step: dt_l,max = cfl / max over the level's
+ * interior cells of sum_d (|v_d| + c_f,d) / dx_l, dt0 = min_l 2^l dt_l,max
+ * (the level time steps then follow dt_{l+1} = dt_l / R, Sec. 2.2).
+ * Synchronising.  EPHYS if the device flagged an unphysical state. */
+int cfl_dt(amrx_hier* h, double* dt0);
+
+/* One root step (Sec. 2.2 recursion AMR(0); serial visit order 0,1,2,2,1,2,2
+ * for three levels, Sec. 4).  If *dt0 > 0 on entry it is used, otherwise
+ * cfl_dt() chooses it and it is returned.  Synchronising. */
+int hier_step(amrx_hier* h, int mode, double* dt0);
+
+/* Sums over leaf cells (not covered by a finer patch) of (rho, m_x, m_y,
+ * m_z, E, B_x, B_y, B_z) * cell volume, in float64 with compensated
+ * summation: sum[i] + comp[i] is the result.  Synchronising. */
+int hier_conservation(amrx_hier* h, double sum[8], double comp[8]);
+
+/* Diagnostics: out[0] = largest flux mismatch seen by sync_level, out[1] =
+ * largest face-field mismatch on shared faces, out[2] = 1 if the device
+ * flagged an unphysical state.  Synchronising.  n = number of slots (<= 3). */
+int hier_diag(amrx_hier* h, double* out, int n);
+
+/* Debug / test exports (pure host, after hier_finalize).  For every padded
+ * cell (kind 0) or face normal to axis kind-1 (kind 1..3) of a patch, in
+ * node-padded [z][y][x] order: the same-level source as
+ * src_patch * 2^32 + linear padded index, the patch's own interior (closure)
+ * entries included, or -1 where none exists.  `out` holds V entries. */
+int hier_debug_sources(const amrx_hier* h, int patch_id, int kind, long long* out);
+
+/* Number of parent cells prolongated into a patch at substep 0, and (if out
+ * is non-NULL, cap entries) their level-(l-1) (x, y, z) indices. */
+int hier_debug_prolong_cells(const amrx_hier* h, int patch_id, int* count, int* out, int cap);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* AMRX_H */

@@ -75,6 +75,17 @@ class NestingError(ValueError):
     pass
 
 
+class _LazyMaps:
+    """Dictionary-like access to per-patch source maps that are built on first use."""
+
+    def __init__(self, h, kind):
+        self.h, self.kind = h, kind
+
+    def __getitem__(self, pid):
+        m = self.h._maps_of(int(pid))
+        return m[0] if self.kind == 0 else m[1]
+
+
 def update_box(lo, hi, level, substep, ratio=R, n_g=mhd.N_G):
     """Cell box a patch updates at a substep (Sec. 2.3 extended ghost cells).
 
@@ -184,63 +195,82 @@ class Hierarchy:
 
     # ------------------------------------------------------------------ ghost maps (brute force)
     def _images(self, p, q):
-        """Periodic shifts s with q's box + s meeting p's padded box."""
+        """Periodic shifts s with q's box + s meeting p's padded box (faces reach one entry further)."""
         nl = self.nl(p.level)
         out = []
         for sz in (-1, 0, 1):
             for sy in (-1, 0, 1):
                 for sx in (-1, 0, 1):
                     s = np.array([sx, sy, sz]) * nl
-                    if _box_inter(p.lo - G, p.hi + G, q.lo + s, q.hi + s + 1) is not None:
+                    if _box_inter(p.lo - G, p.hi + G + 1, q.lo + s, q.hi + s + 1) is not None:
                         out.append(s)
         return out
 
+    def _candidates(self, p):
+        """p itself, then the same-level patches (id order) whose periodic images can meet p's padded box."""
+        same = self.level_patches(p.level)
+        los = np.array([q.lo for q in same])
+        his = np.array([q.hi for q in same])
+        nl = self.nl(p.level)
+        near = np.zeros(len(same), dtype=bool)
+        for sz in (-1, 0, 1):
+            for sy in (-1, 0, 1):
+                for sx in (-1, 0, 1):
+                    s = np.array([sx, sy, sz]) * nl
+                    lo = np.maximum(p.lo - G, los + s)
+                    hi = np.minimum(p.hi + G + 1, his + s + 1)
+                    near |= np.all(hi > lo, axis=1)
+        return [p] + [q for q, ok in zip(same, near) if ok and q is not p]
+
     def _build_maps(self):
-        """Source of every padded cell and face of every patch (same level only).
+        """Source of every padded cell and face of every patch (same level only), built on first use.
 
         cell_src[p.id]: int64 array (Z, Y, X) over padded cells: q_id * 2**32 + linear
         padded index in q, or -1 when no same-level patch holds the cell.
         face_src[p.id][d]: same for the faces normal to axis d.
         """
-        self.cell_src = {}
-        self.face_src = {}
-        for p in self.patches:
-            Z, Y, X = p.shape
-            csrc = np.full((Z, Y, X), -1, dtype=np.int64)
-            fsrc = [np.full((Z, Y, X), -1, dtype=np.int64) for _ in range(3)]
-            gz, gy, gx = np.meshgrid(*(np.arange(p.shape[2 - a]) + p.origin()[a] for a in (2, 1, 0)), indexing='ij')
-            g = [gx, gy, gz]
-            valid_cell = (gx < p.hi[0] + G) & (gy < p.hi[1] + G) & (gz < p.hi[2] + G)
-            # candidates: p itself first, then same-level patches by id
-            cands = [p] + [q for q in self.level_patches(p.level) if q is not p]
-            for q in cands:
-                for s in self._images(p, q):
-                    qlo = q.lo + s
-                    qhi = q.hi + s
-                    inside = valid_cell.copy()
+        self.cell_src = _LazyMaps(self, 0)
+        self.face_src = _LazyMaps(self, 1)
+        self._maps = {}
+
+    def _maps_of(self, pid):
+        if pid in self._maps:
+            return self._maps[pid]
+        p = self.patches[pid]
+        Z, Y, X = p.shape
+        csrc = np.full((Z, Y, X), -1, dtype=np.int64)
+        fsrc = [np.full((Z, Y, X), -1, dtype=np.int64) for _ in range(3)]
+        gz, gy, gx = np.meshgrid(*(np.arange(p.shape[2 - a]) + p.origin()[a] for a in (2, 1, 0)), indexing='ij')
+        g = [gx, gy, gz]
+        valid_cell = (gx < p.hi[0] + G) & (gy < p.hi[1] + G) & (gz < p.hi[2] + G)
+        for q in self._candidates(p):
+            for s in self._images(p, q):
+                qlo = q.lo + s
+                qhi = q.hi + s
+                inside = valid_cell.copy()
+                for a in range(3):
+                    inside &= (g[a] >= qlo[a]) & (g[a] < qhi[a])
+                take = inside & (csrc < 0)
+                if np.any(take):
+                    qi = [g[a] - s[a] - q.origin()[a] for a in range(3)]
+                    lin = (qi[2] * q.shape[1] + qi[1]) * q.shape[2] + qi[0]
+                    csrc[take] = q.id * 2 ** 32 + lin[take]
+                for d in range(3):
+                    inside = np.ones_like(valid_cell)
                     for a in range(3):
-                        inside &= (g[a] >= qlo[a]) & (g[a] < qhi[a])
-                    take = inside & (csrc < 0)
+                        top = p.hi[a] + G + (1 if a == d else 0)
+                        inside &= g[a] < top
+                        if a == d:
+                            inside &= (g[a] >= qlo[a]) & (g[a] <= qhi[a])
+                        else:
+                            inside &= (g[a] >= qlo[a]) & (g[a] < qhi[a])
+                    take = inside & (fsrc[d] < 0)
                     if np.any(take):
                         qi = [g[a] - s[a] - q.origin()[a] for a in range(3)]
                         lin = (qi[2] * q.shape[1] + qi[1]) * q.shape[2] + qi[0]
-                        csrc[take] = q.id * 2 ** 32 + lin[take]
-                    for d in range(3):
-                        inside = np.ones_like(valid_cell)
-                        for a in range(3):
-                            top = p.hi[a] + G + (1 if a == d else 0)
-                            inside &= g[a] < top
-                            if a == d:
-                                inside &= (g[a] >= qlo[a]) & (g[a] <= qhi[a])
-                            else:
-                                inside &= (g[a] >= qlo[a]) & (g[a] < qhi[a])
-                        take = inside & (fsrc[d] < 0)
-                        if np.any(take):
-                            qi = [g[a] - s[a] - q.origin()[a] for a in range(3)]
-                            lin = (qi[2] * q.shape[1] + qi[1]) * q.shape[2] + qi[0]
-                            fsrc[d][take] = q.id * 2 ** 32 + lin[take]
-            self.cell_src[p.id] = csrc
-            self.face_src[p.id] = fsrc
+                        fsrc[d][take] = q.id * 2 ** 32 + lin[take]
+        self._maps[pid] = (csrc, fsrc)
+        return self._maps[pid]
 
     # ------------------------------------------------------------------ state
     def set_state(self, field):

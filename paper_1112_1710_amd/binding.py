@@ -1,0 +1,236 @@
+"""ctypes binding of libamrx (argument marshalling only; every step runs in the library)."""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libamrx.so")
+
+FP64, FP32, FP32_MIXED = 0, 1, 2
+PLAIN, BATCHED, GRAPH = 0, 1, 2
+G = 4
+
+_ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
+
+
+class AmrxError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+
+
+class Desc(C.Structure):
+    _fields_ = [("root_n", C.c_int * 3), ("max_level", C.c_int), ("ratio", C.c_int), ("nghost", C.c_int),
+                ("gamma", C.c_double), ("cfl", C.c_double), ("precision", C.c_int), ("stream", C.c_void_p)]
+
+
+_lib = None
+
+EXPORTS = {
+    "hier_create": ([C.POINTER(Desc), C.POINTER(C.c_void_p)], C.c_int),
+    "hier_destroy": ([C.c_void_p], C.c_int),
+    "hier_last_error": ([C.c_void_p], C.c_char_p),
+    "patch_add": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
+    "hier_finalize": ([C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)], C.c_int),
+    "patch_layout": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_int)], C.c_int),
+    "patch_current": ([C.c_void_p, C.c_int, C.POINTER(C.c_int)], C.c_int),
+    "hier_bind": ([C.c_void_p, C.c_void_p, C.c_size_t, C.c_void_p, C.c_size_t], C.c_int),
+    "level_ghost_fill": ([C.c_void_p, C.c_int, C.c_int], C.c_int),
+    "advance_level": ([C.c_void_p, C.c_int, C.c_double, C.c_int], C.c_int),
+    "restrict_level": ([C.c_void_p, C.c_int], C.c_int),
+    "sync_level": ([C.c_void_p, C.c_int], C.c_int),
+    "cfl_dt": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
+    "hier_step": ([C.c_void_p, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "hier_conservation": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
+    "hier_diag": ([C.c_void_p, C.POINTER(C.c_double), C.c_int], C.c_int),
+    "hier_debug_sources": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_longlong)], C.c_int),
+    "hier_debug_prolong_cells": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int], C.c_int),
+}
+
+
+def load_library(path=LIB_PATH):
+    """Load libamrx.so (raises if it has not been built: no fallback path exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"libamrx.so not built at {path}; run __graft_entry__.build()")
+    lib = C.CDLL(path)
+    for name, (args, res) in EXPORTS.items():
+        fn = getattr(lib, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = lib
+    return lib
+
+
+def _i3(v):
+    return (C.c_int * 3)(*[int(x) for x in v])
+
+
+class Hierarchy:
+    """A static patch hierarchy bound to device arenas allocated by PyTorch.
+
+    ``spec`` is any object with ``root_n`` and ``patches`` = [(level, lo, hi), ...].
+    With ``device=None`` only the host bookkeeping is built (no HIP call is made).
+    """
+
+    def __init__(self, spec, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, device="cuda:0", stream=None):
+        self.lib = load_library()
+        self.precision = precision
+        self.spec = spec
+        d = Desc()
+        d.root_n = _i3(spec.root_n)
+        levels = 1 + max(p[0] for p in spec.patches)
+        d.max_level = levels - 1
+        d.ratio, d.nghost = 2, G
+        d.gamma, d.cfl, d.precision = gamma, cfl, precision
+        self._torch = None
+        if device is not None:
+            import torch
+            self._torch = torch
+            if stream is None:
+                stream = torch.cuda.current_stream(torch.device(device))
+            self.stream = stream
+            d.stream = C.c_void_p(stream.cuda_stream)
+        else:
+            d.stream = None
+        h = C.c_void_p()
+        self._check(self.lib.hier_create(C.byref(d), C.byref(h)), None)
+        self.h = h
+        self.ids = []
+        for lv, lo, hi in spec.patches:
+            pid = C.c_int()
+            self._check(self.lib.patch_add(self.h, int(lv), _i3(lo), _i3(hi), C.byref(pid)))
+            self.ids.append(pid.value)
+        sb, cb = C.c_size_t(), C.c_size_t()
+        self._check(self.lib.hier_finalize(self.h, C.byref(sb), C.byref(cb)))
+        self.state_bytes, self.scratch_bytes = sb.value, cb.value
+        self.levels = levels
+        self.device = device
+        if device is not None:
+            torch = self._torch
+            self.state = torch.empty(self.state_bytes, dtype=torch.uint8, device=device)
+            self.scratch = torch.empty(self.scratch_bytes, dtype=torch.uint8, device=device)
+            self._check(self.lib.hier_bind(self.h, C.c_void_p(self.state.data_ptr()), self.state_bytes,
+                                           C.c_void_p(self.scratch.data_ptr()), self.scratch_bytes))
+            self.real = self.state.view(torch.float64 if precision == FP64 else torch.float32)
+
+    # ------------------------------------------------------------------ errors
+    def _check(self, rc, h=0):
+        if rc != 0:
+            hh = self.h if h == 0 else h
+            msg = self.lib.hier_last_error(hh).decode() if hh is not None else ""
+            raise AmrxError(rc, msg)
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None) is not None:
+                self.lib.hier_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ layout
+    def layout(self, pid, which):
+        offs = (C.c_size_t * 8)()
+        dims = (C.c_int * 3)()
+        self._check(self.lib.patch_layout(self.h, pid, which, offs, dims))
+        return list(offs), (dims[2], dims[1], dims[0])
+
+    def current(self, pid):
+        w = C.c_int()
+        self._check(self.lib.patch_current(self.h, pid, C.byref(w)))
+        return w.value
+
+    def _views(self, pid, which=None):
+        if which is None:
+            which = self.current(pid)
+        offs, shape = self.layout(pid, which)
+        esize = 8 if self.precision == FP64 else 4
+        vol = shape[0] * shape[1] * shape[2]
+        out = []
+        for m in range(8):
+            o = offs[m] // esize
+            out.append(self.real[o:o + vol].view(*shape))
+        return out
+
+    def upload(self, pid, cells, faces, which=None):
+        """Copy float64 host arrays (5, Z, Y, X) and [bx, by, bz] into a patch buffer (default: current)."""
+        torch = self._torch
+        views = self._views(pid, which)
+        dt = views[0].dtype
+        for m in range(5):
+            views[m].copy_(torch.from_numpy(np.ascontiguousarray(cells[m])).to(dt))
+        for d in range(3):
+            views[5 + d].copy_(torch.from_numpy(np.ascontiguousarray(faces[d])).to(dt))
+
+    def download(self, pid, which=None):
+        """(cells (5, Z, Y, X), [bx, by, bz]) of a patch as float64 NumPy arrays."""
+        views = self._views(pid, which)
+        arrs = [v.double().cpu().numpy() for v in views]
+        return np.stack(arrs[:5]), arrs[5:]
+
+    def set_field(self, field):
+        root = tuple(int(x) for x in self.spec.root_n)
+        for pid, (lv, lo, hi) in zip(self.ids, self.spec.patches):
+            st = field.patch(lv, root, tuple(lo), tuple(hi))
+            self.upload(pid, st.cells, st.faces)
+        self.synchronize()
+
+    def synchronize(self):
+        if self._torch is not None:
+            self.stream.synchronize()
+
+    # ------------------------------------------------------------------ operations
+    def ghost_fill(self, level, substep):
+        self._check(self.lib.level_ghost_fill(self.h, level, substep))
+
+    def advance(self, level, dt, substep):
+        self._check(self.lib.advance_level(self.h, level, float(dt), substep))
+
+    def restrict(self, fine_level):
+        self._check(self.lib.restrict_level(self.h, fine_level))
+
+    def sync(self, level):
+        self._check(self.lib.sync_level(self.h, level))
+
+    def cfl_dt(self):
+        v = C.c_double()
+        self._check(self.lib.cfl_dt(self.h, C.byref(v)))
+        return v.value
+
+    def step(self, mode=BATCHED, dt=0.0):
+        v = C.c_double(float(dt))
+        self._check(self.lib.hier_step(self.h, mode, C.byref(v)))
+        return v.value
+
+    def conservation(self):
+        s = (C.c_double * 8)()
+        c = (C.c_double * 8)()
+        self._check(self.lib.hier_conservation(self.h, s, c))
+        return np.array(list(s)), np.array(list(c))
+
+    def diag(self):
+        out = (C.c_double * 3)()
+        self._check(self.lib.hier_diag(self.h, out, 3))
+        return {"sync_flux_max": out[0], "sync_face_max": out[1], "phys_flag": out[2]}
+
+    # ------------------------------------------------------------------ bookkeeping exports
+    def debug_sources(self, pid, kind):
+        offs, shape = self.layout(pid, 0)
+        vol = shape[0] * shape[1] * shape[2]
+        out = (C.c_longlong * vol)()
+        self._check(self.lib.hier_debug_sources(self.h, pid, kind, out))
+        return np.ctypeslib.as_array(out).reshape(shape).copy()
+
+    def debug_prolong_cells(self, pid):
+        cnt = C.c_int()
+        self._check(self.lib.hier_debug_prolong_cells(self.h, pid, C.byref(cnt), None, 0))
+        n = cnt.value
+        buf = (C.c_int * max(1, 3 * n))()
+        self._check(self.lib.hier_debug_prolong_cells(self.h, pid, C.byref(cnt), buf, n))
+        return np.ctypeslib.as_array(buf)[:3 * n].reshape(n, 3).copy()

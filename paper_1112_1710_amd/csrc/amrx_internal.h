@@ -1,0 +1,177 @@
+// Internal layout shared by the host bookkeeping (hier.cpp) and the gfx950
+// kernels (kernels.hip).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define AMRX_G 4        // ghost width = ratio * stencil depth
+#define AMRX_R 2        // refinement ratio
+#define AMRX_NG 2       // stencil depth of one substep
+#define AMRX_MAXLEV 16
+#define AMRX_BLOCK 256  // threads per block of the stage kernels (4 wavefronts)
+
+// Number of real-valued intermediate arrays per patch (each of the patch's
+// node-padded volume) used by the staged advance.
+#define AMRX_NSCR 49
+enum {
+  SCR_W = 0,    // 8 primitives at t^n
+  SCR_EC = 8,   // 3 cell EMFs at t^n
+  SCR_DU = 11,  // 8 Hancock half-step increments
+  SCR_BH = 19,  // 3 face-normal fields at t^{n+1/2}
+  SCR_ER = 22,  // 3 cell reference EMFs at t^{n+1/2}
+  SCR_F = 25,   // 3 axes x 7: 5 cell fluxes, EMF along (d+2)%3, EMF along (d+1)%3
+  SCR_E = 46    // 3 edge EMFs
+};
+
+struct PatchDev {
+  int n[3];          // interior cells per axis
+  int dim[3];        // node-padded array dims (n + 2G + 1)
+  long long vol;     // dim[0]*dim[1]*dim[2]
+  long long st[2];   // element offsets of state buffers 0 / 1 (8 arrays of vol each)
+  long long scr;     // element offset of the AMRX_NSCR intermediate arrays
+  long long freg;    // register-element offset of fine face registers: blocks acc, lo, last
+  long long fsize;   // entries of one fine face register block
+  long long ereg;    // register-element offset of fine edge registers: blocks acc, lo
+  long long esize;   // entries of one fine edge register block
+  long long creg;    // coarse-side face registers (parent's fluxes on this patch's box surface)
+  long long cereg;   // coarse-side edge registers
+  long long cov;     // int offset of the coverage map (child id per padded cell), -1 if childless
+  int level;
+  int parent;
+  int lo[3];         // level index of the first interior cell
+  int has_children;
+  double dx;         // cell width
+};
+
+// A region of one patch processed by a stage kernel (padded indices, half-open).
+struct Task {
+  int patch;
+  int axis;
+  int lo[3];
+  int hi[3];
+};
+
+// A run of consecutive padded entries copied from a same-level patch.
+struct Run {
+  int dst_patch, dst_lin, src_patch, src_lin;
+  int len;   // <= 64
+  int kind;  // 0: the 5 cell arrays, 1..3: face array of axis kind-1
+};
+
+// One parent cell prolongated into a fine patch's ghost region.
+struct Pro {
+  int patch;   // fine patch
+  int c[3];    // coarse cell relative to the fine padded origin (fine padded index = 2*c)
+  int pidx;    // parent padded linear index of that coarse cell
+  int flags;   // bit 2*d+s: the coarse face (axis d, side s) already holds same-level fine data
+};
+
+// An entry of the correction lists of a parent patch.
+struct Corr {
+  int patch;   // parent
+  int axis;    // face axis (EMF correction), unused for cells
+  int lin;     // padded linear index of the cell / face
+};
+
+// A boundary face of patch a shared with patch b (same level, possibly a periodic image of a).
+struct SyncPair {
+  int a, b, axis, a_side;
+  int a_reg, b_reg;        // offsets inside one fine face register block (component 0)
+  int a_face, b_face;      // padded linear indices of the face in a and b
+  int a_cell;              // padded linear index of a's interior cell adjacent to the face
+};
+
+// ---------------------------------------------------------------------------
+// register layouts on a box surface (used with the fine sizes n or the coarse
+// sizes n/2); identical on host and device
+// ---------------------------------------------------------------------------
+__host__ __device__ inline void other_axes(int d, int& a1, int& a2) {
+  a1 = d == 0 ? 1 : 0;
+  a2 = d == 2 ? 1 : 2;
+}
+
+// Face register: axis d, side s (0 low, 1 high), component c (0..4), transverse t1 (along a1), t2 (along a2).
+__host__ __device__ inline long long face_reg_size(const int n[3]) {
+  return 10LL * (n[1] * (long long)n[2] + n[0] * (long long)n[2] + n[0] * (long long)n[1]);
+}
+__host__ __device__ inline long long face_reg_index(const int n[3], int d, int s, int c, int t1, int t2) {
+  long long base = 0;
+  for (int e = 0; e < d; ++e) {
+    int b1, b2;
+    other_axes(e, b1, b2);
+    base += 10LL * n[b1] * n[b2];
+  }
+  int a1, a2;
+  other_axes(d, a1, a2);
+  return base + ((long long)(s * 5 + c) * n[a2] + t2) * n[a1] + t1;
+}
+
+// Edge register for edges along e; (a, b) = ((e+1)%3, (e+2)%3).  Plane "pa": the
+// box face normal to a (side s), entries (ib in [0, n_b], ie in [0, n_e)); plane
+// "pb": the box face normal to b (side s), entries (ia in [0, n_a], ie).
+__host__ __device__ inline long long edge_reg_size(const int n[3]) {
+  long long t = 0;
+  for (int e = 0; e < 3; ++e) {
+    int a = (e + 1) % 3, b = (e + 2) % 3;
+    t += 2LL * n[e] * (n[a] + n[b] + 2);
+  }
+  return t;
+}
+__host__ __device__ inline long long edge_reg_base(const int n[3], int e) {
+  long long base = 0;
+  for (int f = 0; f < e; ++f) {
+    int a = (f + 1) % 3, b = (f + 2) % 3;
+    base += 2LL * n[f] * (n[a] + n[b] + 2);
+  }
+  return base;
+}
+__host__ __device__ inline long long edge_reg_pa(const int n[3], int e, int s, int ib, int ie) {
+  int b = (e + 2) % 3;
+  return edge_reg_base(n, e) + ((long long)s * (n[b] + 1) + ib) * n[e] + ie;
+}
+__host__ __device__ inline long long edge_reg_pb(const int n[3], int e, int s, int ia, int ie) {
+  int a = (e + 1) % 3, b = (e + 2) % 3;
+  return edge_reg_base(n, e) + 2LL * (n[b] + 1) * n[e] + ((long long)s * (n[a] + 1) + ia) * n[e] + ie;
+}
+
+// ---------------------------------------------------------------------------
+// kernel launchers (kernels.hip); all enqueue on `stream`, return hipError_t
+// ---------------------------------------------------------------------------
+struct DevCtx {
+  void* state;            // state arena
+  void* rscr;             // real intermediates
+  void* reg;              // registers (double for FP64 / mixed, float for FP32)
+  const PatchDev* patches;
+  const Task* tasks;
+  const int* blk;         // per-task first block (prefix)
+  const Run* runs;
+  const Pro* pros;
+  const Corr* corrs;
+  const SyncPair* syncs;
+  int* cov;               // coverage maps
+  unsigned long long* slots;  // reduction / diagnostic slots
+  double* partials;       // per-block conservation partials
+  int precision;
+  double gamma;
+  hipStream_t stream;
+};
+
+enum { STAGE_PRIM = 0, STAGE_PRED, STAGE_BHALF, STAGE_EREF, STAGE_FLUX, STAGE_EDGE, STAGE_UPDATE, NSTAGE };
+
+// slot indices in DevCtx::slots
+enum { SLOT_PHYS = 0, SLOT_SYNC_F = 1, SLOT_SYNC_B = 2, SLOT_SMAX = 8 /* + level */, NSLOT = 8 + AMRX_MAXLEV };
+
+hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, int blk_first, int nblk,
+                        int cur, int level, int substep, double dt);
+hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int cur);
+hipError_t launch_prolong(const DevCtx& c, int first, int n, int cur_fine, int old_parent);
+hipError_t launch_restrict(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk, int cur_fine,
+                           int cur_coarse);
+hipError_t launch_flux_corr(const DevCtx& c, int first, int n, int cur_coarse);
+hipError_t launch_emf_corr(const DevCtx& c, int first, int n, int cur_coarse);
+hipError_t launch_sync(const DevCtx& c, int first, int n, int cur);
+hipError_t launch_cfl(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk, int cur, int level);
+hipError_t launch_conservation(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk,
+                               const int* cur_of_level);
+hipError_t launch_clear_slots(const DevCtx& c);

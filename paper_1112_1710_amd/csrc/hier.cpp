@@ -1,0 +1,1039 @@
+// Host side of libamrx: hierarchy bookkeeping, index lists, memory layout and
+// the C ABI declared in include/amrx.h.
+//
+// The bookkeeping follows the paper's description of the AMR mesh (Sec. 2):
+// every patch has one parent on the next coarser level and exchanges data
+// with same-level neighbours, its parent and its children.  All lists are
+// built once when the (static) topology is frozen; nothing here runs on the
+// device except through the launchers of kernels.hip.
+
+#include <algorithm>
+#include <array>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "amrx_internal.h"
+#include "../../include/amrx.h"
+
+namespace {
+
+constexpr int G = AMRX_G;
+constexpr int R = AMRX_R;
+constexpr int NG = AMRX_NG;
+
+struct TaskList {
+  int first = 0, count = 0, nblk = 0;
+};
+struct Range {
+  int first = 0, count = 0;
+};
+
+struct HPatch {
+  int id = 0, level = 0;
+  int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, n[3] = {0, 0, 0};
+  int parent = -1;
+  std::vector<int> children;
+  int dim[3] = {0, 0, 0};
+  long long vol = 0;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct amrx_hier {
+  amrx_desc d{};
+  std::vector<HPatch> P;
+  std::vector<std::vector<int>> lev;
+  int nlev = 0;
+  bool frozen = false, bound = false;
+  std::string err;
+  size_t real_size = 8, reg_size = 8;
+
+  // host images of the device tables
+  std::vector<PatchDev> pdev;
+  std::vector<Task> tasks;
+  std::vector<int> blk;
+  std::vector<Run> runs;
+  std::vector<Pro> pros;
+  std::vector<Corr> fcorrs, ecorrs;
+  std::vector<SyncPair> syncs;
+  std::vector<int> cov;
+  // debug copies of the source maps: per patch, 4 arrays (cells, faces x/y/z) of vol entries
+  std::vector<std::array<std::vector<long long>, 4>> src;
+
+  // lists: batched (per level) and plain (per patch)
+  TaskList stage_b[AMRX_MAXLEV][2][NSTAGE];
+  std::vector<std::array<std::array<TaskList, NSTAGE>, 2>> stage_p;
+  Range copy_b[AMRX_MAXLEV];
+  std::vector<Range> copy_p;
+  Range pro_b[AMRX_MAXLEV];
+  std::vector<Range> pro_p;
+  TaskList restr_b[AMRX_MAXLEV];
+  std::vector<TaskList> restr_p;
+  Range fcorr_b[AMRX_MAXLEV], ecorr_b[AMRX_MAXLEV];
+  std::vector<Range> fcorr_p, ecorr_p;
+  Range sync_b[AMRX_MAXLEV];
+  std::vector<Range> sync_p;
+  TaskList cfl_b[AMRX_MAXLEV];
+  TaskList cons_all;
+
+  // layout
+  size_t state_bytes = 0, scratch_bytes = 0;
+  size_t off_pdev = 0, off_tasks = 0, off_blk = 0, off_runs = 0, off_pros = 0, off_fcorr = 0, off_ecorr = 0,
+         off_sync = 0, off_cov = 0, off_slots = 0, off_partials = 0, off_reg = 0, off_rscr = 0;
+  size_t meta_bytes = 0;
+
+  char* state = nullptr;
+  char* scratch = nullptr;
+  DevCtx ctx{};
+  int cur[AMRX_MAXLEV] = {0};
+};
+
+namespace {
+
+int fail(amrx_hier* h, int code, const std::string& msg) {
+  if (h) h->err = msg;
+  return code;
+}
+
+bool hip_ok(amrx_hier* h, hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  h->err = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+
+#define HIPCHK(expr, what)                                  \
+  do {                                                      \
+    if (!hip_ok(h, (expr), what)) return AMRX_EHIP;         \
+  } while (0)
+
+bool box_meet(const int alo[3], const int ahi[3], const int blo[3], const int bhi[3]) {
+  for (int a = 0; a < 3; ++a)
+    if (std::max(alo[a], blo[a]) >= std::min(ahi[a], bhi[a])) return false;
+  return true;
+}
+
+long long lin_of(const HPatch& p, int i, int j, int k) { return ((long long)k * p.dim[1] + j) * p.dim[0] + i; }
+
+int nl_of(const amrx_hier* h, int level, int a) { return h->d.root_n[a] << level; }
+
+void update_box(const HPatch& p, int substep, int lo[3], int hi[3]) {
+  const int g = p.level == 0 ? 0 : (R - 1 - substep) * NG;
+  for (int a = 0; a < 3; ++a) {
+    lo[a] = G - g;
+    hi[a] = G + p.n[a] + g;
+  }
+}
+
+// Append a task over [lo, hi) and return its block count.
+int add_task(amrx_hier* h, int patch, int axis, const int lo[3], const int hi[3], int blk_start) {
+  Task t;
+  t.patch = patch;
+  t.axis = axis;
+  long long v = 1;
+  for (int a = 0; a < 3; ++a) {
+    t.lo[a] = lo[a];
+    t.hi[a] = hi[a];
+    v *= std::max(0, hi[a] - lo[a]);
+  }
+  h->tasks.push_back(t);
+  h->blk.push_back(blk_start);
+  return (int)((v + AMRX_BLOCK - 1) / AMRX_BLOCK);
+}
+
+// Regions of the advance stages for update region [lo, hi).
+void stage_regions(int stage, int axis, const int lo[3], const int hi[3], int rlo[3], int rhi[3]) {
+  for (int a = 0; a < 3; ++a) {
+    switch (stage) {
+      case STAGE_PRIM: rlo[a] = lo[a] - 2; rhi[a] = hi[a] + 2; break;
+      case STAGE_PRED:
+      case STAGE_EREF: rlo[a] = lo[a] - 1; rhi[a] = hi[a] + 1; break;
+      case STAGE_BHALF: rlo[a] = lo[a] - 1; rhi[a] = hi[a] + 2; break;
+      case STAGE_FLUX:
+        if (a == axis) { rlo[a] = lo[a]; rhi[a] = hi[a] + 1; }
+        else { rlo[a] = lo[a] - 1; rhi[a] = hi[a] + 1; }
+        break;
+      case STAGE_EDGE:
+        if (a == axis) { rlo[a] = lo[a]; rhi[a] = hi[a]; }
+        else { rlo[a] = lo[a]; rhi[a] = hi[a] + 1; }
+        break;
+      case STAGE_UPDATE: rlo[a] = lo[a]; rhi[a] = hi[a] + 1; break;
+    }
+  }
+}
+
+// Same-level sources of every padded cell and face of patch p (lowest id wins, p itself first).
+void build_sources(amrx_hier* h, int pid) {
+  HPatch& p = h->P[pid];
+  auto& S = h->src[pid];
+  for (int k = 0; k < 4; ++k) S[k].assign(p.vol, -1);
+  std::vector<int> cands;
+  cands.push_back(pid);
+  for (int q : h->lev[p.level])
+    if (q != pid) cands.push_back(q);
+  int plo[3], phi[3];
+  for (int a = 0; a < 3; ++a) {
+    plo[a] = p.lo[a] - G;
+    phi[a] = p.hi[a] + G;
+  }
+  for (int q : cands) {
+    const HPatch& Q = h->P[q];
+    for (int sz = -1; sz <= 1; ++sz)
+      for (int sy = -1; sy <= 1; ++sy)
+        for (int sx = -1; sx <= 1; ++sx) {
+          const int s[3] = {sx * nl_of(h, p.level, 0), sy * nl_of(h, p.level, 1), sz * nl_of(h, p.level, 2)};
+          int qlo[3], qhi1[3];
+          for (int a = 0; a < 3; ++a) {
+            qlo[a] = Q.lo[a] + s[a];
+            qhi1[a] = Q.hi[a] + s[a] + 1;
+          }
+          // faces reach one entry further than cells along their normal: test the grown boxes
+          const int phi1[3] = {phi[0] + 1, phi[1] + 1, phi[2] + 1};
+          if (!box_meet(plo, phi1, qlo, qhi1)) continue;
+          // cells: [max(plo, qlo), min(phi, Q.hi + s))
+          for (int kind = 0; kind < 4; ++kind) {
+            int lo[3], hi[3];
+            bool empty = false;
+            for (int a = 0; a < 3; ++a) {
+              const int top_p = phi[a] + ((kind >= 1 && a == kind - 1) ? 1 : 0);
+              const int top_q = Q.hi[a] + s[a] + ((kind >= 1 && a == kind - 1) ? 1 : 0);
+              lo[a] = std::max(plo[a], qlo[a]);
+              hi[a] = std::min(top_p, top_q);
+              if (hi[a] <= lo[a]) empty = true;
+            }
+            if (empty) continue;
+            std::vector<long long>& arr = S[kind];
+            for (int z = lo[2]; z < hi[2]; ++z)
+              for (int y = lo[1]; y < hi[1]; ++y)
+                for (int x = lo[0]; x < hi[0]; ++x) {
+                  const long long pl = lin_of(p, x - plo[0], y - plo[1], z - plo[2]);
+                  if (arr[pl] >= 0) continue;
+                  const long long ql = lin_of(Q, x - s[0] - (Q.lo[0] - G), y - s[1] - (Q.lo[1] - G), z - s[2] - (Q.lo[2] - G));
+                  arr[pl] = ((long long)q << 32) + ql;
+                }
+          }
+        }
+  }
+}
+
+bool is_own(const HPatch& p, int kind, int i, int j, int k) {
+  const int idx[3] = {i, j, k};
+  for (int a = 0; a < 3; ++a) {
+    const int top = G + p.n[a] + ((kind >= 1 && a == kind - 1) ? 1 : 0);
+    if (idx[a] < G || idx[a] >= top) return false;
+  }
+  return true;
+}
+
+void build_runs(amrx_hier* h, int pid) {
+  const HPatch& p = h->P[pid];
+  const auto& S = h->src[pid];
+  for (int kind = 0; kind < 4; ++kind) {
+    const auto& arr = S[kind];
+    const int nx = p.dim[0] - ((kind == 1) ? 0 : 1);  // valid x extent of this array
+    const int ny = p.dim[1] - ((kind == 2) ? 0 : 1);
+    const int nz = p.dim[2] - ((kind == 3) ? 0 : 1);
+    for (int k = 0; k < nz; ++k)
+      for (int j = 0; j < ny; ++j) {
+        int i = 0;
+        while (i < nx) {
+          const long long l = lin_of(p, i, j, k);
+          if (arr[l] < 0 || is_own(p, kind, i, j, k)) {
+            ++i;
+            continue;
+          }
+          const int sp = (int)(arr[l] >> 32);
+          const long long sl = arr[l] & 0xffffffffLL;
+          int len = 1;
+          while (i + len < nx && len < 64) {
+            const long long l2 = l + len;
+            if (arr[l2] < 0 || is_own(p, kind, i + len, j, k)) break;
+            if ((int)(arr[l2] >> 32) != sp || (arr[l2] & 0xffffffffLL) != sl + len) break;
+            ++len;
+          }
+          Run r;
+          r.dst_patch = pid;
+          r.dst_lin = (int)l;
+          r.src_patch = sp;
+          r.src_lin = (int)sl;
+          r.len = len;
+          r.kind = kind;
+          h->runs.push_back(r);
+          i += len;
+        }
+      }
+  }
+}
+
+void build_pros(amrx_hier* h, int pid) {
+  const HPatch& p = h->P[pid];
+  const HPatch& m = h->P[p.parent];
+  const auto& S = h->src[pid];
+  const int nc[3] = {(p.n[0] + 2 * G) / 2, (p.n[1] + 2 * G) / 2, (p.n[2] + 2 * G) / 2};
+  for (int cz = 0; cz < nc[2]; ++cz)
+    for (int cy = 0; cy < nc[1]; ++cy)
+      for (int cx = 0; cx < nc[0]; ++cx) {
+        if (S[0][lin_of(p, 2 * cx, 2 * cy, 2 * cz)] >= 0) continue;
+        Pro pr;
+        pr.patch = pid;
+        pr.c[0] = cx;
+        pr.c[1] = cy;
+        pr.c[2] = cz;
+        const int gidx[3] = {(p.lo[0] - G) / 2 + cx, (p.lo[1] - G) / 2 + cy, (p.lo[2] - G) / 2 + cz};
+        int pi[3];
+        for (int a = 0; a < 3; ++a) pi[a] = gidx[a] - (m.lo[a] - G);
+        pr.pidx = (int)lin_of(m, pi[0], pi[1], pi[2]);
+        int flags = 0;
+        for (int d = 0; d < 3; ++d)
+          for (int s = 0; s < 2; ++s) {
+            int f[3] = {2 * cx, 2 * cy, 2 * cz};
+            f[d] += 2 * s;
+            if (S[1 + d][lin_of(p, f[0], f[1], f[2])] >= 0) flags |= 1 << (2 * d + s);
+          }
+        pr.flags = flags;
+        h->pros.push_back(pr);
+      }
+}
+
+// Coverage map and correction lists of a parent patch.
+void build_parent(amrx_hier* h, int mid, std::vector<int>& covmap) {
+  const HPatch& m = h->P[mid];
+  covmap.assign(m.vol, -1);
+  for (int c : m.children) {
+    const HPatch& C = h->P[c];
+    for (int z = C.lo[2] / 2; z < C.hi[2] / 2; ++z)
+      for (int y = C.lo[1] / 2; y < C.hi[1] / 2; ++y)
+        for (int x = C.lo[0] / 2; x < C.hi[0] / 2; ++x)
+          covmap[lin_of(m, x - (m.lo[0] - G), y - (m.lo[1] - G), z - (m.lo[2] - G))] = c;
+  }
+  const long long s[3] = {1, m.dim[0], (long long)m.dim[0] * m.dim[1]};
+  auto covered = [&](long long q) { return covmap[q] >= 0; };
+  // uncovered interior cells with a covered face neighbour
+  for (int k = G; k < G + m.n[2]; ++k)
+    for (int j = G; j < G + m.n[1]; ++j)
+      for (int i = G; i < G + m.n[0]; ++i) {
+        const long long q = lin_of(m, i, j, k);
+        if (covered(q)) continue;
+        bool nb = false;
+        for (int d = 0; d < 3; ++d) nb = nb || covered(q + s[d]) || covered(q - s[d]);
+        if (nb) h->fcorrs.push_back(Corr{mid, 0, (int)q});
+      }
+  // uncovered faces with a coverage-boundary edge on their perimeter
+  auto edge_boundary = [&](int e, long long q) {
+    const int A = (e + 1) % 3, C = (e + 2) % 3;
+    const bool c0 = covered(q - s[A] - s[C]), c1 = covered(q - s[C]), c2 = covered(q - s[A]), c3 = covered(q);
+    const bool any = c0 || c1 || c2 || c3, all = c0 && c1 && c2 && c3;
+    return any && !all;
+  };
+  for (int d = 0; d < 3; ++d) {
+    const int A = (d + 1) % 3, C = (d + 2) % 3;
+    for (int k = G; k < G + m.n[2] + (d == 2); ++k)
+      for (int j = G; j < G + m.n[1] + (d == 1); ++j)
+        for (int i = G; i < G + m.n[0] + (d == 0); ++i) {
+          const long long q = lin_of(m, i, j, k);
+          if (covered(q) || covered(q - s[d])) continue;
+          const bool b = edge_boundary(C, q) || edge_boundary(C, q + s[A]) || edge_boundary(A, q) ||
+                         edge_boundary(A, q + s[C]);
+          if (b) h->ecorrs.push_back(Corr{mid, d, (int)q});
+        }
+  }
+}
+
+void build_syncs(amrx_hier* h, int pid) {
+  const HPatch& p = h->P[pid];
+  for (int q : h->lev[p.level]) {
+    const HPatch& Q = h->P[q];
+    for (int sz = -1; sz <= 1; ++sz)
+      for (int sy = -1; sy <= 1; ++sy)
+        for (int sx = -1; sx <= 1; ++sx) {
+          if (q == pid && sx == 0 && sy == 0 && sz == 0) continue;
+          const int s[3] = {sx * nl_of(h, p.level, 0), sy * nl_of(h, p.level, 1), sz * nl_of(h, p.level, 2)};
+          for (int d = 0; d < 3; ++d) {
+            int a1, a2;
+            other_axes(d, a1, a2);
+            for (int side = 0; side < 2; ++side) {
+              const int plane = side == 0 ? p.lo[d] : p.hi[d];
+              const int qplane = (side == 0 ? Q.hi[d] : Q.lo[d]) + s[d];
+              if (plane != qplane) continue;
+              const int lo1 = std::max(p.lo[a1], Q.lo[a1] + s[a1]), hi1 = std::min(p.hi[a1], Q.hi[a1] + s[a1]);
+              const int lo2 = std::max(p.lo[a2], Q.lo[a2] + s[a2]), hi2 = std::min(p.hi[a2], Q.hi[a2] + s[a2]);
+              for (int t2 = lo2; t2 < hi2; ++t2)
+                for (int t1 = lo1; t1 < hi1; ++t1) {
+                  SyncPair sp;
+                  sp.a = pid;
+                  sp.b = q;
+                  sp.axis = d;
+                  sp.a_side = side;
+                  sp.a_reg = (int)face_reg_index(p.n, d, side, 0, t1 - p.lo[a1], t2 - p.lo[a2]);
+                  sp.b_reg = (int)face_reg_index(Q.n, d, 1 - side, 0, t1 - s[a1] - Q.lo[a1], t2 - s[a2] - Q.lo[a2]);
+                  int pa[3], qa[3];
+                  pa[d] = plane - (p.lo[d] - G);
+                  qa[d] = plane - s[d] - (Q.lo[d] - G);
+                  pa[a1] = t1 - (p.lo[a1] - G);
+                  pa[a2] = t2 - (p.lo[a2] - G);
+                  qa[a1] = t1 - s[a1] - (Q.lo[a1] - G);
+                  qa[a2] = t2 - s[a2] - (Q.lo[a2] - G);
+                  sp.a_face = (int)lin_of(p, pa[0], pa[1], pa[2]);
+                  sp.b_face = (int)lin_of(Q, qa[0], qa[1], qa[2]);
+                  int ca[3] = {pa[0], pa[1], pa[2]};
+                  if (side == 1) ca[d] -= 1;
+                  sp.a_cell = (int)lin_of(p, ca[0], ca[1], ca[2]);
+                  h->syncs.push_back(sp);
+                }
+            }
+          }
+        }
+  }
+}
+
+int finalize_impl(amrx_hier* h) {
+  // level-0 patches must tile the root grid
+  long long vol0 = 0;
+  for (int id : h->lev[0]) {
+    const HPatch& p = h->P[id];
+    vol0 += (long long)p.n[0] * p.n[1] * p.n[2];
+  }
+  if (h->lev[0].empty() || vol0 != (long long)h->d.root_n[0] * h->d.root_n[1] * h->d.root_n[2])
+    return fail(h, AMRX_ENEST, "level-0 patches must tile the root grid");
+  const int np = (int)h->P.size();
+  h->nlev = 0;
+  for (int l = 0; l < AMRX_MAXLEV; ++l)
+    if (!h->lev[l].empty()) h->nlev = l + 1;
+  for (auto& p : h->P) {
+    for (int a = 0; a < 3; ++a) p.dim[a] = p.n[a] + 2 * G + 1;
+    p.vol = (long long)p.dim[0] * p.dim[1] * p.dim[2];
+  }
+  h->src.assign(np, {});
+  h->stage_p.assign(np, {});
+  h->copy_p.assign(np, {});
+  h->pro_p.assign(np, {});
+  h->restr_p.assign(np, {});
+  h->fcorr_p.assign(np, {});
+  h->ecorr_p.assign(np, {});
+  h->sync_p.assign(np, {});
+  for (int id = 0; id < np; ++id) build_sources(h, id);
+
+  // state and register layout
+  h->pdev.assign(np, PatchDev{});
+  long long st = 0, reg = 0, rscr = 0, covoff = 0;
+  std::vector<std::vector<int>> covmaps(np);
+  for (int l = 0; l < h->nlev; ++l)
+    for (int id : h->lev[l]) {
+      HPatch& p = h->P[id];
+      PatchDev& d = h->pdev[id];
+      for (int a = 0; a < 3; ++a) {
+        d.n[a] = p.n[a];
+        d.dim[a] = p.dim[a];
+        d.lo[a] = p.lo[a];
+      }
+      d.vol = p.vol;
+      d.st[0] = st;
+      d.st[1] = st + 8 * p.vol;
+      st += 16 * p.vol;
+      d.scr = rscr;
+      rscr += (long long)AMRX_NSCR * p.vol;
+      d.fsize = face_reg_size(p.n);
+      d.esize = edge_reg_size(p.n);
+      d.freg = reg;
+      reg += 3 * d.fsize;
+      d.ereg = reg;
+      reg += 2 * d.esize;
+      if (p.parent >= 0) {
+        const int nc[3] = {p.n[0] / 2, p.n[1] / 2, p.n[2] / 2};
+        d.creg = reg;
+        reg += face_reg_size(nc);
+        d.cereg = reg;
+        reg += edge_reg_size(nc);
+      } else {
+        d.creg = d.cereg = -1;
+      }
+      d.level = p.level;
+      d.parent = p.parent;
+      d.has_children = p.children.empty() ? 0 : 1;
+      d.dx = 1.0 / (double)nl_of(h, p.level, 0);
+      if (!p.children.empty()) {
+        d.cov = covoff;
+        build_parent(h, id, covmaps[id]);
+        covoff += p.vol;
+      } else {
+        d.cov = -1;
+      }
+    }
+  // the correction lists were appended in level order above; record per-parent ranges
+  {
+    std::vector<Range> f(np), e(np);
+    for (size_t i = 0; i < h->fcorrs.size(); ++i) {
+      Range& r = f[h->fcorrs[i].patch];
+      if (r.count == 0) r.first = (int)i;
+      ++r.count;
+    }
+    for (size_t i = 0; i < h->ecorrs.size(); ++i) {
+      Range& r = e[h->ecorrs[i].patch];
+      if (r.count == 0) r.first = (int)i;
+      ++r.count;
+    }
+    h->fcorr_p = f;
+    h->ecorr_p = e;
+  }
+  h->cov.assign(covoff, -1);
+  for (int id = 0; id < np; ++id)
+    if (h->pdev[id].cov >= 0) std::copy(covmaps[id].begin(), covmaps[id].end(), h->cov.begin() + h->pdev[id].cov);
+
+  // per level lists
+  for (int l = 0; l < h->nlev; ++l) {
+    // ghost copy runs
+    h->copy_b[l].first = (int)h->runs.size();
+    for (int id : h->lev[l]) {
+      h->copy_p[id].first = (int)h->runs.size();
+      build_runs(h, id);
+      h->copy_p[id].count = (int)h->runs.size() - h->copy_p[id].first;
+    }
+    h->copy_b[l].count = (int)h->runs.size() - h->copy_b[l].first;
+    // prolongation
+    h->pro_b[l].first = (int)h->pros.size();
+    if (l > 0)
+      for (int id : h->lev[l]) {
+        h->pro_p[id].first = (int)h->pros.size();
+        build_pros(h, id);
+        h->pro_p[id].count = (int)h->pros.size() - h->pro_p[id].first;
+      }
+    h->pro_b[l].count = (int)h->pros.size() - h->pro_b[l].first;
+    // sync pairs
+    h->sync_b[l].first = (int)h->syncs.size();
+    for (int id : h->lev[l]) {
+      h->sync_p[id].first = (int)h->syncs.size();
+      build_syncs(h, id);
+      h->sync_p[id].count = (int)h->syncs.size() - h->sync_p[id].first;
+    }
+    h->sync_b[l].count = (int)h->syncs.size() - h->sync_b[l].first;
+    // correction ranges of the level's parents are contiguous (built in level order)
+    Range fb, eb;
+    bool fset = false, eset = false;
+    for (int id : h->lev[l]) {
+      if (h->fcorr_p[id].count) {
+        if (!fset) { fb.first = h->fcorr_p[id].first; fset = true; }
+        fb.count = h->fcorr_p[id].first + h->fcorr_p[id].count - fb.first;
+      }
+      if (h->ecorr_p[id].count) {
+        if (!eset) { eb.first = h->ecorr_p[id].first; eset = true; }
+        eb.count = h->ecorr_p[id].first + h->ecorr_p[id].count - eb.first;
+      }
+    }
+    h->fcorr_b[l] = fb;
+    h->ecorr_b[l] = eb;
+
+    // stage tasks
+    const int nsub = l == 0 ? 1 : R;
+    for (int s = 0; s < nsub; ++s)
+      for (int stg = 0; stg < NSTAGE; ++stg) {
+        const int naxes = (stg == STAGE_FLUX || stg == STAGE_EDGE) ? 3 : 1;
+        TaskList& B = h->stage_b[l][s][stg];
+        B.first = (int)h->tasks.size();
+        int nb = 0;
+        for (int id : h->lev[l]) {
+          int lo[3], hi[3];
+          update_box(h->P[id], s, lo, hi);
+          for (int ax = 0; ax < naxes; ++ax) {
+            int rlo[3], rhi[3];
+            stage_regions(stg, ax, lo, hi, rlo, rhi);
+            nb += add_task(h, id, ax, rlo, rhi, nb);
+          }
+        }
+        B.count = (int)h->tasks.size() - B.first;
+        B.nblk = nb;
+        for (int id : h->lev[l]) {
+          TaskList& T = h->stage_p[id][s][stg];
+          T.first = (int)h->tasks.size();
+          int lo[3], hi[3];
+          update_box(h->P[id], s, lo, hi);
+          int nbp = 0;
+          for (int ax = 0; ax < naxes; ++ax) {
+            int rlo[3], rhi[3];
+            stage_regions(stg, ax, lo, hi, rlo, rhi);
+            nbp += add_task(h, id, ax, rlo, rhi, nbp);
+          }
+          T.count = (int)h->tasks.size() - T.first;
+          T.nblk = nbp;
+        }
+      }
+    // restriction of level l onto l-1 (tasks per child: node box of its coarse box)
+    if (l > 0) {
+      TaskList& B = h->restr_b[l];
+      B.first = (int)h->tasks.size();
+      int nb = 0;
+      for (int id : h->lev[l]) {
+        const HPatch& p = h->P[id];
+        const int lo[3] = {0, 0, 0};
+        const int hi[3] = {p.n[0] / 2 + 1, p.n[1] / 2 + 1, p.n[2] / 2 + 1};
+        nb += add_task(h, id, 0, lo, hi, nb);
+      }
+      B.count = (int)h->tasks.size() - B.first;
+      B.nblk = nb;
+      for (int id : h->lev[l]) {
+        const HPatch& p = h->P[id];
+        TaskList& T = h->restr_p[id];
+        T.first = (int)h->tasks.size();
+        const int lo[3] = {0, 0, 0};
+        const int hi[3] = {p.n[0] / 2 + 1, p.n[1] / 2 + 1, p.n[2] / 2 + 1};
+        T.nblk = add_task(h, id, 0, lo, hi, 0);
+        T.count = 1;
+      }
+    }
+    // CFL over interiors
+    {
+      TaskList& B = h->cfl_b[l];
+      B.first = (int)h->tasks.size();
+      int nb = 0;
+      for (int id : h->lev[l]) {
+        const HPatch& p = h->P[id];
+        const int lo[3] = {G, G, G};
+        const int hi[3] = {G + p.n[0], G + p.n[1], G + p.n[2]};
+        nb += add_task(h, id, 0, lo, hi, nb);
+      }
+      B.count = (int)h->tasks.size() - B.first;
+      B.nblk = nb;
+    }
+  }
+  {
+    TaskList& B = h->cons_all;
+    B.first = (int)h->tasks.size();
+    int nb = 0;
+    for (int l = 0; l < h->nlev; ++l)
+      for (int id : h->lev[l]) {
+        const HPatch& p = h->P[id];
+        const int lo[3] = {G, G, G};
+        const int hi[3] = {G + p.n[0], G + p.n[1], G + p.n[2]};
+        nb += add_task(h, id, 0, lo, hi, nb);
+      }
+    B.count = (int)h->tasks.size() - B.first;
+    B.nblk = nb;
+  }
+
+  // host-side bounds checks of everything the kernels index
+  for (const Pro& pr : h->pros) {
+    const HPatch& p = h->P[pr.patch];
+    const HPatch& m = h->P[p.parent];
+    const long long sy = m.dim[0], sz = (long long)m.dim[0] * m.dim[1];
+    const long long lo = (long long)pr.pidx - 1 - sy - sz, hi = (long long)pr.pidx + 1 + sy + sz;
+    if (lo < 0 || hi >= m.vol) return fail(h, AMRX_ENEST, "prolongation stencil leaves the parent array");
+  }
+
+  // byte layout of the scratch arena
+  size_t o = 0;
+  h->off_pdev = o; o = align256(o + sizeof(PatchDev) * np);
+  h->off_tasks = o; o = align256(o + sizeof(Task) * h->tasks.size());
+  h->off_blk = o; o = align256(o + sizeof(int) * h->blk.size());
+  h->off_runs = o; o = align256(o + sizeof(Run) * h->runs.size());
+  h->off_pros = o; o = align256(o + sizeof(Pro) * h->pros.size());
+  h->off_fcorr = o; o = align256(o + sizeof(Corr) * h->fcorrs.size());
+  h->off_ecorr = o; o = align256(o + sizeof(Corr) * h->ecorrs.size());
+  h->off_sync = o; o = align256(o + sizeof(SyncPair) * h->syncs.size());
+  h->off_cov = o; o = align256(o + sizeof(int) * h->cov.size());
+  h->meta_bytes = o;
+  h->off_slots = o; o = align256(o + sizeof(unsigned long long) * NSLOT);
+  h->off_partials = o; o = align256(o + sizeof(double) * 16 * ((size_t)h->cons_all.nblk + 1));
+  h->off_reg = o; o = align256(o + h->reg_size * (size_t)reg);
+  h->off_rscr = o; o = align256(o + h->real_size * (size_t)rscr);
+  h->scratch_bytes = o;
+  h->state_bytes = align256(h->real_size * (size_t)st);
+  h->frozen = true;
+  return AMRX_OK;
+}
+
+DevCtx make_ctx(amrx_hier* h) {
+  DevCtx c{};
+  char* s = h->scratch;
+  c.state = h->state;
+  c.rscr = s + h->off_rscr;
+  c.reg = s + h->off_reg;
+  c.patches = (const PatchDev*)(s + h->off_pdev);
+  c.tasks = (const Task*)(s + h->off_tasks);
+  c.blk = (const int*)(s + h->off_blk);
+  c.runs = (const Run*)(s + h->off_runs);
+  c.pros = (const Pro*)(s + h->off_pros);
+  c.corrs = nullptr;
+  c.syncs = (const SyncPair*)(s + h->off_sync);
+  c.cov = (int*)(s + h->off_cov);
+  c.slots = (unsigned long long*)(s + h->off_slots);
+  c.partials = (double*)(s + h->off_partials);
+  c.precision = h->d.precision;
+  c.gamma = h->d.gamma;
+  c.stream = (hipStream_t)h->d.stream;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+// the level operations
+// ---------------------------------------------------------------------------
+int do_ghost_fill(amrx_hier* h, int level, int substep, bool plain) {
+  DevCtx& c = h->ctx;
+  const int cur = h->cur[level];
+  if (plain) {
+    for (int id : h->lev[level]) HIPCHK(launch_copy(c, h->copy_p[id].first, h->copy_p[id].count, cur), "ghost copy");
+  } else {
+    HIPCHK(launch_copy(c, h->copy_b[level].first, h->copy_b[level].count, cur), "ghost copy");
+  }
+  if (level > 0 && substep == 0) {
+    const int old_parent = 1 - h->cur[level - 1];
+    if (plain) {
+      for (int id : h->lev[level])
+        HIPCHK(launch_prolong(c, h->pro_p[id].first, h->pro_p[id].count, cur, old_parent), "prolongation");
+    } else {
+      HIPCHK(launch_prolong(c, h->pro_b[level].first, h->pro_b[level].count, cur, old_parent), "prolongation");
+    }
+  }
+  return AMRX_OK;
+}
+
+int do_advance(amrx_hier* h, int level, double dt, int substep, bool plain) {
+  DevCtx& c = h->ctx;
+  const int cur = h->cur[level];
+  for (int stg = 0; stg < NSTAGE; ++stg) {
+    if (plain) {
+      for (int id : h->lev[level]) {
+        const TaskList& T = h->stage_p[id][substep][stg];
+        HIPCHK(launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep, dt), "advance stage");
+      }
+    } else {
+      const TaskList& T = h->stage_b[level][substep][stg];
+      HIPCHK(launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep, dt), "advance stage");
+    }
+  }
+  h->cur[level] = 1 - cur;
+  return AMRX_OK;
+}
+
+int do_restrict(amrx_hier* h, int fine, bool plain) {
+  DevCtx& c = h->ctx;
+  const int cf = h->cur[fine], cc = h->cur[fine - 1];
+  if (plain) {
+    for (int id : h->lev[fine]) {
+      const TaskList& T = h->restr_p[id];
+      HIPCHK(launch_restrict(c, T.first, T.count, 0, T.nblk, cf, cc), "restriction");
+    }
+    for (int id : h->lev[fine - 1]) {
+      c.corrs = (const Corr*)(h->scratch + h->off_fcorr);
+      HIPCHK(launch_flux_corr(c, h->fcorr_p[id].first, h->fcorr_p[id].count, cc), "flux correction");
+      c.corrs = (const Corr*)(h->scratch + h->off_ecorr);
+      HIPCHK(launch_emf_corr(c, h->ecorr_p[id].first, h->ecorr_p[id].count, cc), "EMF correction");
+    }
+  } else {
+    const TaskList& T = h->restr_b[fine];
+    HIPCHK(launch_restrict(c, T.first, T.count, 0, T.nblk, cf, cc), "restriction");
+    c.corrs = (const Corr*)(h->scratch + h->off_fcorr);
+    HIPCHK(launch_flux_corr(c, h->fcorr_b[fine - 1].first, h->fcorr_b[fine - 1].count, cc), "flux correction");
+    c.corrs = (const Corr*)(h->scratch + h->off_ecorr);
+    HIPCHK(launch_emf_corr(c, h->ecorr_b[fine - 1].first, h->ecorr_b[fine - 1].count, cc), "EMF correction");
+  }
+  return AMRX_OK;
+}
+
+int do_sync(amrx_hier* h, int level, bool plain) {
+  DevCtx& c = h->ctx;
+  const int cur = h->cur[level];
+  if (plain) {
+    for (int id : h->lev[level]) HIPCHK(launch_sync(c, h->sync_p[id].first, h->sync_p[id].count, cur), "sync");
+  } else {
+    HIPCHK(launch_sync(c, h->sync_b[level].first, h->sync_b[level].count, cur), "sync");
+  }
+  return AMRX_OK;
+}
+
+int amr_recursive(amrx_hier* h, int level, double dt, bool plain) {
+  const int nsub = level == 0 ? 1 : R;
+  for (int s = 0; s < nsub; ++s) {
+    int rc = do_ghost_fill(h, level, s, plain);
+    if (rc) return rc;
+    rc = do_advance(h, level, dt, s, plain);
+    if (rc) return rc;
+    if (level + 1 < h->nlev) {
+      rc = amr_recursive(h, level + 1, dt / R, plain);
+      if (rc) return rc;
+      rc = do_restrict(h, level + 1, plain);
+      if (rc) return rc;
+    }
+    rc = do_sync(h, level, plain);
+    if (rc) return rc;
+  }
+  return AMRX_OK;
+}
+
+int read_slots(amrx_hier* h, unsigned long long* out) {
+  HIPCHK(hipMemcpyAsync(out, h->scratch + h->off_slots, sizeof(unsigned long long) * NSLOT, hipMemcpyDeviceToHost,
+                        (hipStream_t)h->d.stream),
+         "slot readback");
+  HIPCHK(hipStreamSynchronize((hipStream_t)h->d.stream), "stream synchronize");
+  return AMRX_OK;
+}
+
+double bits_to_double(unsigned long long b) {
+  double d;
+  std::memcpy(&d, &b, sizeof d);
+  return d;
+}
+
+int cfl_impl(amrx_hier* h, double* dt0) {
+  DevCtx& c = h->ctx;
+  HIPCHK(launch_clear_slots(c), "clear slots");
+  for (int l = 0; l < h->nlev; ++l) {
+    const TaskList& T = h->cfl_b[l];
+    HIPCHK(launch_cfl(c, T.first, T.count, 0, T.nblk, h->cur[l], l), "cfl");
+  }
+  unsigned long long sl[NSLOT];
+  int rc = read_slots(h, sl);
+  if (rc) return rc;
+  if (sl[SLOT_PHYS]) return fail(h, AMRX_EPHYS, "unphysical state (rho<=0, p<=0 or non-finite)");
+  double best = 1e300;
+  for (int l = 0; l < h->nlev; ++l) {
+    const double smax = bits_to_double(sl[SLOT_SMAX + l]);
+    if (smax > 0.0) best = std::min(best, (double)(1 << l) * h->d.cfl / smax);
+  }
+  *dt0 = best;
+  return AMRX_OK;
+}
+
+bool ready(amrx_hier* h) {
+  if (!h) return false;
+  if (!h->bound) {
+    h->err = "hierarchy not bound (call hier_finalize and hier_bind first)";
+    return false;
+  }
+  return true;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+int hier_create(const amrx_desc* desc, amrx_hier** out) {
+  if (!desc || !out) return AMRX_EINVAL;
+  *out = nullptr;
+  if (desc->ratio != R || desc->nghost != G) return AMRX_EINVAL;
+  if (desc->max_level < 0 || desc->max_level >= AMRX_MAXLEV) return AMRX_EINVAL;
+  if (desc->precision < 0 || desc->precision > 2) return AMRX_EINVAL;
+  if (!(desc->gamma > 1.0) || !(desc->cfl > 0.0)) return AMRX_EINVAL;
+  for (int a = 0; a < 3; ++a)
+    if (desc->root_n[a] < 1 || desc->root_n[a] > (1 << 20)) return AMRX_EINVAL;
+  if (!(desc->root_n[0] == desc->root_n[1] && desc->root_n[1] == desc->root_n[2])) return AMRX_EINVAL;
+  amrx_hier* h = new amrx_hier();
+  h->d = *desc;
+  h->lev.assign(AMRX_MAXLEV, {});
+  h->real_size = desc->precision == AMRX_FP64 ? 8 : 4;
+  h->reg_size = desc->precision == AMRX_FP32 ? 4 : 8;
+  *out = h;
+  return AMRX_OK;
+}
+
+int hier_destroy(amrx_hier* h) {
+  delete h;
+  return AMRX_OK;
+}
+
+const char* hier_last_error(const amrx_hier* h) { return h ? h->err.c_str() : "null hierarchy"; }
+
+int patch_add(amrx_hier* h, int level, const int lo[3], const int hi[3], int* patch_id) {
+  if (!h || !lo || !hi) return AMRX_EINVAL;
+  if (h->frozen) return fail(h, AMRX_ESTATE, "patch_add after hier_finalize");
+  if (level < 0 || level > h->d.max_level) return fail(h, AMRX_EINVAL, "level out of range");
+  for (int a = 0; a < 3; ++a)
+    if (hi[a] <= lo[a]) return fail(h, AMRX_EINVAL, "empty box");
+  int parent = -1;
+  if (level == 0) {
+    for (int a = 0; a < 3; ++a)
+      if (lo[a] < 0 || hi[a] > h->d.root_n[a]) return fail(h, AMRX_EINVAL, "root box outside the domain");
+  } else {
+    for (int a = 0; a < 3; ++a)
+      if ((lo[a] & 1) || (hi[a] & 1)) return fail(h, AMRX_ENEST, "box corners must be even");
+    int found = 0;
+    for (int q : h->lev[level - 1]) {
+      const HPatch& Q = h->P[q];
+      bool in = true;
+      for (int a = 0; a < 3; ++a) in = in && (lo[a] >= R * (Q.lo[a] + 1)) && (hi[a] <= R * (Q.hi[a] - 1));
+      if (in) {
+        ++found;
+        parent = q;
+      }
+    }
+    if (found != 1) return fail(h, AMRX_ENEST, "box must lie inside exactly one parent interior shrunk by one cell");
+  }
+  for (int q : h->lev[level])
+    if (box_meet(lo, hi, h->P[q].lo, h->P[q].hi)) return fail(h, AMRX_EOVERLAP, "box overlaps a same-level patch");
+  HPatch p;
+  p.id = (int)h->P.size();
+  p.level = level;
+  for (int a = 0; a < 3; ++a) {
+    p.lo[a] = lo[a];
+    p.hi[a] = hi[a];
+    p.n[a] = hi[a] - lo[a];
+  }
+  p.parent = parent;
+  h->P.push_back(p);
+  if (parent >= 0) h->P[parent].children.push_back(p.id);
+  h->lev[level].push_back(p.id);
+  if (patch_id) *patch_id = p.id;
+  return AMRX_OK;
+}
+
+int hier_finalize(amrx_hier* h, size_t* state_bytes, size_t* scratch_bytes) {
+  if (!h) return AMRX_EINVAL;
+  if (h->frozen) return fail(h, AMRX_ESTATE, "hier_finalize called twice");
+  const int rc = finalize_impl(h);
+  if (rc) return rc;
+  if (state_bytes) *state_bytes = h->state_bytes;
+  if (scratch_bytes) *scratch_bytes = h->scratch_bytes;
+  return AMRX_OK;
+}
+
+int patch_layout(const amrx_hier* h, int patch_id, int which, size_t offsets[8], int dims[3]) {
+  if (!h || !offsets || !dims) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  if (patch_id < 0 || patch_id >= (int)h->P.size() || which < 0 || which > 1) return AMRX_EINVAL;
+  const PatchDev& d = h->pdev[patch_id];
+  for (int m = 0; m < 8; ++m) offsets[m] = (size_t)(d.st[which] + m * d.vol) * h->real_size;
+  for (int a = 0; a < 3; ++a) dims[a] = d.dim[a];
+  return AMRX_OK;
+}
+
+int patch_current(const amrx_hier* h, int patch_id, int* which) {
+  if (!h || !which || patch_id < 0 || patch_id >= (int)h->P.size()) return AMRX_EINVAL;
+  *which = h->cur[h->P[patch_id].level];
+  return AMRX_OK;
+}
+
+int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size_t scratch_bytes) {
+  if (!h || !state || !scratch) return AMRX_EINVAL;
+  if (!h->frozen) return fail(h, AMRX_ESTATE, "hier_bind before hier_finalize");
+  if (state_bytes < h->state_bytes || scratch_bytes < h->scratch_bytes)
+    return fail(h, AMRX_ENOMEM, "bound arenas are smaller than hier_finalize reported");
+  if (((uintptr_t)state & 255) || ((uintptr_t)scratch & 255))
+    return fail(h, AMRX_EINVAL, "arenas must be 256-byte aligned");
+  h->state = (char*)state;
+  h->scratch = (char*)scratch;
+  // metadata image
+  std::vector<char> img(h->meta_bytes, 0);
+  auto put = [&](size_t off, const void* src, size_t n) {
+    if (n) std::memcpy(img.data() + off, src, n);
+  };
+  put(h->off_pdev, h->pdev.data(), sizeof(PatchDev) * h->pdev.size());
+  put(h->off_tasks, h->tasks.data(), sizeof(Task) * h->tasks.size());
+  put(h->off_blk, h->blk.data(), sizeof(int) * h->blk.size());
+  put(h->off_runs, h->runs.data(), sizeof(Run) * h->runs.size());
+  put(h->off_pros, h->pros.data(), sizeof(Pro) * h->pros.size());
+  put(h->off_fcorr, h->fcorrs.data(), sizeof(Corr) * h->fcorrs.size());
+  put(h->off_ecorr, h->ecorrs.data(), sizeof(Corr) * h->ecorrs.size());
+  put(h->off_sync, h->syncs.data(), sizeof(SyncPair) * h->syncs.size());
+  put(h->off_cov, h->cov.data(), sizeof(int) * h->cov.size());
+  hipStream_t s = (hipStream_t)h->d.stream;
+  HIPCHK(hipMemcpyAsync(h->scratch, img.data(), img.size(), hipMemcpyHostToDevice, s), "upload index lists");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  h->ctx = make_ctx(h);
+  HIPCHK(launch_clear_slots(h->ctx), "clear slots");
+  for (int l = 0; l < AMRX_MAXLEV; ++l) h->cur[l] = 0;
+  h->bound = true;
+  return AMRX_OK;
+}
+
+int level_ghost_fill(amrx_hier* h, int level, int substep) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (level < 0 || level >= h->nlev || substep < 0 || substep >= (level == 0 ? 1 : R)) return AMRX_EINVAL;
+  return do_ghost_fill(h, level, substep, false);
+}
+
+int advance_level(amrx_hier* h, int level, double dt_level, int substep) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (level < 0 || level >= h->nlev || substep < 0 || substep >= (level == 0 ? 1 : R) || !(dt_level > 0.0))
+    return AMRX_EINVAL;
+  return do_advance(h, level, dt_level, substep, false);
+}
+
+int restrict_level(amrx_hier* h, int fine_level) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (fine_level < 1 || fine_level >= h->nlev) return AMRX_EINVAL;
+  return do_restrict(h, fine_level, false);
+}
+
+int sync_level(amrx_hier* h, int level) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (level < 0 || level >= h->nlev) return AMRX_EINVAL;
+  return do_sync(h, level, false);
+}
+
+int cfl_dt(amrx_hier* h, double* dt0) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (!dt0) return AMRX_EINVAL;
+  return cfl_impl(h, dt0);
+}
+
+int hier_step(amrx_hier* h, int mode, double* dt0) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (!dt0 || mode < AMRX_PLAIN || mode > AMRX_GRAPH) return AMRX_EINVAL;
+  if (!(*dt0 > 0.0)) {
+    const int rc = cfl_impl(h, dt0);
+    if (rc) return rc;
+  }
+  const int rc = amr_recursive(h, 0, *dt0, mode == AMRX_PLAIN);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize((hipStream_t)h->d.stream), "stream synchronize");
+  return AMRX_OK;
+}
+
+int hier_conservation(amrx_hier* h, double sum[8], double comp[8]) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (!sum || !comp) return AMRX_EINVAL;
+  const TaskList& T = h->cons_all;
+  HIPCHK(launch_conservation(h->ctx, T.first, T.count, 0, T.nblk, h->cur), "conservation");
+  double buf[16];
+  HIPCHK(hipMemcpyAsync(buf, h->scratch + h->off_partials + sizeof(double) * 16 * (size_t)T.nblk, sizeof buf,
+                        hipMemcpyDeviceToHost, (hipStream_t)h->d.stream),
+         "conservation readback");
+  HIPCHK(hipStreamSynchronize((hipStream_t)h->d.stream), "stream synchronize");
+  for (int m = 0; m < 8; ++m) {
+    sum[m] = buf[m];
+    comp[m] = buf[8 + m];
+  }
+  return AMRX_OK;
+}
+
+int hier_diag(amrx_hier* h, double* out, int n) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (!out || n < 0 || n > 3) return AMRX_EINVAL;
+  unsigned long long sl[NSLOT];
+  const int rc = read_slots(h, sl);
+  if (rc) return rc;
+  const double v[3] = {bits_to_double(sl[SLOT_SYNC_F]), bits_to_double(sl[SLOT_SYNC_B]), sl[SLOT_PHYS] ? 1.0 : 0.0};
+  for (int i = 0; i < n; ++i) out[i] = v[i];
+  return AMRX_OK;
+}
+
+int hier_debug_sources(const amrx_hier* h, int patch_id, int kind, long long* out) {
+  if (!h || !out || kind < 0 || kind > 3) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  if (patch_id < 0 || patch_id >= (int)h->P.size()) return AMRX_EINVAL;
+  const auto& a = h->src[patch_id][kind];
+  std::copy(a.begin(), a.end(), out);
+  return AMRX_OK;
+}
+
+int hier_debug_prolong_cells(const amrx_hier* h, int patch_id, int* count, int* out, int cap) {
+  if (!h || !count) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  if (patch_id < 0 || patch_id >= (int)h->P.size()) return AMRX_EINVAL;
+  const Range r = h->pro_p[patch_id];
+  *count = r.count;
+  if (out) {
+    const HPatch& p = h->P[patch_id];
+    for (int i = 0; i < r.count && i < cap; ++i) {
+      const Pro& pr = h->pros[r.first + i];
+      for (int a = 0; a < 3; ++a) out[3 * i + a] = (p.lo[a] - G) / 2 + pr.c[a];
+    }
+  }
+  return AMRX_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,1237 @@
+// gfx950 kernels of the AMR MHD hot path.
+//
+// Advance of a ghost-padded patch by one substep (unsplit MUSCL-Hancock
+// predictor, HLLD fluxes after Miyoshi & Kusano 2005, upwinded CT-contact
+// edge EMFs after Gardiner & Stone 2005), staged through per-patch
+// intermediate arrays so that every quantity is computed once per cell,
+// face or edge of the region that needs it.  Stage regions follow the
+// extended-ghost rule of the paper (Sec. 2.3): for an update region W, the
+// primitives cover W grown by 2 cells, the half-step state W grown by 1, the
+// face fluxes the faces of W plus one transverse layer, the edge EMFs the
+// edges of W's faces.
+//
+// Every stage kernel walks a list of (patch, region) tasks: block b finds its
+// task by binary search over the tasks' first blocks, so one launch can cover
+// one patch (plain schedule) or all patches of a level substep (batched
+// schedule).  Threads map to region entries with x fastest, so consecutive
+// lanes touch consecutive addresses of the structure-of-arrays buffers.
+//
+// Precision: Real = double (FP64), float (FP32) or float with the pressure
+// recovered in double and flux/EMF registers kept in double with two-sum
+// compensation (FP32 mixed).  Registers are double except in plain FP32.
+
+#include <math.h>
+#include <stdint.h>
+
+#include "amrx_internal.h"
+
+namespace {
+
+// ---------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R mc_limit(R dm, R dp) {
+  // monotonised central: minmod(2 dm, 2 dp, (dm + dp)/2), zero unless dm, dp share a strict sign
+  if (!(dm * dp > R(0))) return R(0);
+  R a = fmin(fmin(R(2) * fabs(dm), R(2) * fabs(dp)), R(0.5) * fabs(dm + dp));
+  return dm > R(0) ? a : -a;
+}
+
+template <typename R>
+__device__ __forceinline__ R minmod2(R a, R b) {
+  if (!(a * b > R(0))) return R(0);
+  R m = fmin(fabs(a), fabs(b));
+  return a > R(0) ? m : -m;
+}
+
+template <typename R>
+__device__ __forceinline__ R upwind(R flux, R minus_val, R plus_val) {
+  if (flux > R(0)) return minus_val;
+  if (flux < R(0)) return plus_val;
+  return R(0.5) * (minus_val + plus_val);
+}
+
+// gas pressure from conserved variables; MIX evaluates it in double
+template <typename R, bool MIX>
+__device__ __forceinline__ R pressure(R rho, R mx, R my, R mz, R e, R bx, R by, R bz, R gm1) {
+  if (MIX) {
+    double r = rho;
+    double kin = 0.5 * ((double)mx * mx + (double)my * my + (double)mz * mz) / r;
+    double mag = 0.5 * ((double)bx * bx + (double)by * by + (double)bz * bz);
+    return (R)((double)gm1 * ((double)e - kin - mag));
+  } else {
+    R kin = R(0.5) * (mx * mx + my * my + mz * mz) / rho;
+    R mag = R(0.5) * (bx * bx + by * by + bz * bz);
+    return gm1 * (e - kin - mag);
+  }
+}
+
+template <typename R>
+__device__ __forceinline__ R fast_speed(R rho, R p, R b2, R bn2, R gamma) {
+  R a2 = gamma * p / rho;
+  R s = a2 + b2 / rho;
+  R disc = s * s - R(4) * a2 * bn2 / rho;
+  disc = disc > R(0) ? disc : R(0);
+  return sqrt(R(0.5) * (s + sqrt(disc)));
+}
+
+// primitive w = (rho, vx, vy, vz, p, Bx, By, Bz) -> physical flux along D (global component order)
+template <int D, typename R>
+__device__ __forceinline__ void phys_flux(const R* w, R gm1, R* f) {
+  const R rho = w[0], p = w[4];
+  const R v0 = w[1], v1 = w[2], v2 = w[3];
+  const R b0 = w[5], b1 = w[6], b2 = w[7];
+  const R un = w[1 + D], bn = w[5 + D];
+  const R bb = b0 * b0 + b1 * b1 + b2 * b2;
+  const R pt = p + R(0.5) * bb;
+  const R e = p / gm1 + R(0.5) * rho * (v0 * v0 + v1 * v1 + v2 * v2) + R(0.5) * bb;
+  const R vb = v0 * b0 + v1 * b1 + v2 * b2;
+  f[0] = rho * un;
+  f[1] = rho * v0 * un - b0 * bn;
+  f[2] = rho * v1 * un - b1 * bn;
+  f[3] = rho * v2 * un - b2 * bn;
+  f[1 + D] += pt;
+  f[4] = (e + pt) * un - bn * vb;
+  f[5] = b0 * un - bn * v0;
+  f[6] = b1 * un - bn * v1;
+  f[7] = b2 * un - bn * v2;
+  f[5 + D] = R(0);
+}
+
+// primitive state -> 8 conserved (rho, m, E, B)
+template <typename R>
+__device__ __forceinline__ void to_cons(const R* w, R gm1, R* u) {
+  u[0] = w[0];
+  u[1] = w[0] * w[1];
+  u[2] = w[0] * w[2];
+  u[3] = w[0] * w[3];
+  u[4] = w[4] / gm1 + R(0.5) * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) +
+         R(0.5) * (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]);
+  u[5] = w[5];
+  u[6] = w[6];
+  u[7] = w[7];
+}
+
+template <typename R, bool MIX>
+__device__ __forceinline__ void to_prim(const R* u, R gm1, R* w) {
+  w[0] = u[0];
+  w[1] = u[1] / u[0];
+  w[2] = u[2] / u[0];
+  w[3] = u[3] / u[0];
+  w[4] = pressure<R, MIX>(u[0], u[1], u[2], u[3], u[4], u[5], u[6], u[7], gm1);
+  w[5] = u[5];
+  w[6] = u[6];
+  w[7] = u[7];
+}
+
+// HLLD flux normal to D.  Normal field bn replaces both states' normal component.
+template <int D, typename R>
+__device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R* out) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const R gm1 = gamma - R(1);
+  const R rl = wl[0], ul = wl[1 + D], vl = wl[1 + T1], zl = wl[1 + T2], pl = wl[4], byl = wl[5 + T1], bzl = wl[5 + T2];
+  const R rr = wr[0], ur = wr[1 + D], vr = wr[1 + T1], zr = wr[1 + T2], pr = wr[4], byr = wr[5 + T1], bzr = wr[5 + T2];
+  const R bn2 = bn * bn;
+  const R b2l = bn2 + byl * byl + bzl * bzl;
+  const R b2r = bn2 + byr * byr + bzr * bzr;
+  const R cfl = fast_speed(rl, pl, b2l, bn2, gamma);
+  const R cfr = fast_speed(rr, pr, b2r, bn2, gamma);
+  const R cmax = fmax(cfl, cfr);
+  const R sl = fmin(ul, ur) - cmax;
+  const R sr = fmax(ul, ur) + cmax;
+  const R ptl = pl + R(0.5) * b2l;
+  const R ptr = pr + R(0.5) * b2r;
+  const R el = pl / gm1 + R(0.5) * rl * (ul * ul + vl * vl + zl * zl) + R(0.5) * b2l;
+  const R er = pr / gm1 + R(0.5) * rr * (ur * ur + vr * vr + zr * zr) + R(0.5) * b2r;
+  const R vbl = ul * bn + vl * byl + zl * bzl;
+  const R vbr = ur * bn + vr * byr + zr * bzr;
+
+  R f[7];
+  if (sl >= R(0)) {
+    f[0] = rl * ul;
+    f[1] = rl * ul * ul + ptl - bn2;
+    f[2] = rl * ul * vl - bn * byl;
+    f[3] = rl * ul * zl - bn * bzl;
+    f[4] = (el + ptl) * ul - bn * vbl;
+    f[5] = byl * ul - bn * vl;
+    f[6] = bzl * ul - bn * zl;
+  } else if (sr <= R(0) && !(sr >= R(0))) {
+    f[0] = rr * ur;
+    f[1] = rr * ur * ur + ptr - bn2;
+    f[2] = rr * ur * vr - bn * byr;
+    f[3] = rr * ur * zr - bn * bzr;
+    f[4] = (er + ptr) * ur - bn * vbr;
+    f[5] = byr * ur - bn * vr;
+    f[6] = bzr * ur - bn * zr;
+  } else {
+    const R sdl = sl - ul, sdr = sr - ur;
+    const R den = sdr * rr - sdl * rl;
+    const R sm = (sdr * rr * ur - sdl * rl * ul - ptr + ptl) / den;
+    const R pts = (sdr * rr * ptl - sdl * rl * ptr + rl * rr * sdr * sdl * (ur - ul)) / den;
+    // left star state
+    const R rls = rl * sdl / (sl - sm);
+    R vls, zls, byls, bzls;
+    {
+      const R dn = rl * sdl * (sl - sm) - bn2;
+      if (fabs(dn) <= R(1e-8) * rl * sdl * sdl) {
+        vls = vl; zls = zl; byls = byl; bzls = bzl;
+      } else {
+        const R num = rl * sdl * sdl - bn2;
+        vls = vl - bn * byl * (sm - ul) / dn;
+        zls = zl - bn * bzl * (sm - ul) / dn;
+        byls = byl * num / dn;
+        bzls = bzl * num / dn;
+      }
+    }
+    const R vbls = sm * bn + vls * byls + zls * bzls;
+    const R els = (sdl * el - ptl * ul + pts * sm + bn * (vbl - vbls)) / (sl - sm);
+    // right star state
+    const R rrs = rr * sdr / (sr - sm);
+    R vrs, zrs, byrs, bzrs;
+    {
+      const R dn = rr * sdr * (sr - sm) - bn2;
+      if (fabs(dn) <= R(1e-8) * rr * sdr * sdr) {
+        vrs = vr; zrs = zr; byrs = byr; bzrs = bzr;
+      } else {
+        const R num = rr * sdr * sdr - bn2;
+        vrs = vr - bn * byr * (sm - ur) / dn;
+        zrs = zr - bn * bzr * (sm - ur) / dn;
+        byrs = byr * num / dn;
+        bzrs = bzr * num / dn;
+      }
+    }
+    const R vbrs = sm * bn + vrs * byrs + zrs * bzrs;
+    const R ers = (sdr * er - ptr * ur + pts * sm + bn * (vbr - vbrs)) / (sr - sm);
+
+    const bool skip = bn2 <= R(1e-12) * (ptl + ptr);
+    const R sql = sqrt(rls), sqr = sqrt(rrs);
+    const R abn = fabs(bn);
+    const R ssl = skip ? sm : sm - abn / sql;
+    const R ssr = skip ? sm : sm + abn / sqr;
+    const bool left = sm >= R(0);
+    // star flux of the side that holds x/t = 0
+    R us[7], uo[7], fo[7], s_out;
+    if (left) {
+      us[0] = rls; us[1] = rls * sm; us[2] = rls * vls; us[3] = rls * zls; us[4] = els; us[5] = byls; us[6] = bzls;
+      uo[0] = rl; uo[1] = rl * ul; uo[2] = rl * vl; uo[3] = rl * zl; uo[4] = el; uo[5] = byl; uo[6] = bzl;
+      fo[0] = rl * ul; fo[1] = rl * ul * ul + ptl - bn2; fo[2] = rl * ul * vl - bn * byl; fo[3] = rl * ul * zl - bn * bzl;
+      fo[4] = (el + ptl) * ul - bn * vbl; fo[5] = byl * ul - bn * vl; fo[6] = bzl * ul - bn * zl;
+      s_out = sl;
+    } else {
+      us[0] = rrs; us[1] = rrs * sm; us[2] = rrs * vrs; us[3] = rrs * zrs; us[4] = ers; us[5] = byrs; us[6] = bzrs;
+      uo[0] = rr; uo[1] = rr * ur; uo[2] = rr * vr; uo[3] = rr * zr; uo[4] = er; uo[5] = byr; uo[6] = bzr;
+      fo[0] = rr * ur; fo[1] = rr * ur * ur + ptr - bn2; fo[2] = rr * ur * vr - bn * byr; fo[3] = rr * ur * zr - bn * bzr;
+      fo[4] = (er + ptr) * ur - bn * vbr; fo[5] = byr * ur - bn * vr; fo[6] = bzr * ur - bn * zr;
+      s_out = sr;
+    }
+    for (int q = 0; q < 7; ++q) f[q] = fo[q] + s_out * (us[q] - uo[q]);
+    const bool in_star = left ? (ssl >= R(0)) : !(ssr >= R(0));
+    if (!skip && !in_star) {
+      // double-star state of the same side
+      const R sgn = bn > R(0) ? R(1) : (bn < R(0) ? R(-1) : R(0));
+      const R inv = R(1) / (sql + sqr);
+      const R vss = (sql * vls + sqr * vrs + (byrs - byls) * sgn) * inv;
+      const R zss = (sql * zls + sqr * zrs + (bzrs - bzls) * sgn) * inv;
+      const R byss = (sql * byrs + sqr * byls + sql * sqr * (vrs - vls) * sgn) * inv;
+      const R bzss = (sql * bzrs + sqr * bzls + sql * sqr * (zrs - zls) * sgn) * inv;
+      const R vbss = sm * bn + vss * byss + zss * bzss;
+      R uss[7];
+      const R rs = left ? rls : rrs;
+      uss[0] = rs; uss[1] = rs * sm; uss[2] = rs * vss; uss[3] = rs * zss;
+      uss[4] = left ? els - sql * (vbls - vbss) * sgn : ers + sqr * (vbrs - vbss) * sgn;
+      uss[5] = byss; uss[6] = bzss;
+      const R ss = left ? ssl : ssr;
+      for (int q = 0; q < 7; ++q) f[q] = f[q] + ss * (uss[q] - us[q]);
+    }
+  }
+  out[0] = f[0];
+  out[1 + D] = f[1];
+  out[1 + T1] = f[2];
+  out[1 + T2] = f[3];
+  out[4] = f[4];
+  out[5 + D] = R(0);
+  out[5 + T1] = f[5];
+  out[5 + T2] = f[6];
+}
+
+__device__ __forceinline__ void atomic_max_pos(unsigned long long* slot, double v) {
+  // non-negative doubles order like their bit patterns
+  if (!(v >= 0.0)) v = 1.0e308;  // NaN: report as huge
+  atomicMax(slot, (unsigned long long)__double_as_longlong(v));
+}
+
+__device__ __forceinline__ void flag_phys(unsigned long long* slots) { atomicOr(&slots[SLOT_PHYS], 1ULL); }
+
+// ---------------------------------------------------------------------------
+// task lookup
+// ---------------------------------------------------------------------------
+struct Where {
+  int task;
+  int i, j, k;
+};
+
+__device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, Where& w) {
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (c.blk[first + mid] <= b) lo = mid; else hi = mid - 1;
+  }
+  const int t = first + lo;
+  const Task& T = c.tasks[t];
+  const long long ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
+  const long long local = (long long)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
+  if (local >= ex * ey * ez) return false;
+  w.task = t;
+  w.i = T.lo[0] + (int)(local % ex);
+  w.j = T.lo[1] + (int)((local / ex) % ey);
+  w.k = T.lo[2] + (int)(local / (ex * ey));
+  return true;
+}
+
+struct Strides {
+  long long s[3];
+  long long v;
+};
+__device__ __forceinline__ Strides strides(const PatchDev& p) {
+  Strides s;
+  s.s[0] = 1;
+  s.s[1] = p.dim[0];
+  s.s[2] = (long long)p.dim[0] * p.dim[1];
+  s.v = p.vol;
+  return s;
+}
+
+// register precision per mode
+template <typename R, bool MIX> struct RegOf { using T = double; };
+template <> struct RegOf<float, false> { using T = float; };
+
+// set (mode 0) or add (mode 1) a value into an (acc, lo) register pair
+template <typename Q, bool MIX>
+__device__ __forceinline__ void reg_put(Q* acc, Q* lo, long long idx, Q v, int mode) {
+  if (mode == 0) {
+    acc[idx] = v;
+    if (MIX) lo[idx] = Q(0);
+  } else if (MIX) {
+    const Q a = acc[idx];
+    const Q s = a + v;
+    const Q bb = s - a;
+    const Q err = (a - (s - bb)) + (v - bb);
+    acc[idx] = s;
+    lo[idx] = lo[idx] + err;
+  } else {
+    acc[idx] = acc[idx] + v;
+  }
+}
+template <typename Q, bool MIX>
+__device__ __forceinline__ Q reg_get(const Q* acc, const Q* lo, long long idx) {
+  return MIX ? acc[idx] + lo[idx] : acc[idx];
+}
+
+// ---------------------------------------------------------------------------
+// stage 1: primitives and cell EMFs at t^n   (cells of the region grown by 2)
+// ---------------------------------------------------------------------------
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_prim(DevCtx c, int first, int n, int cur) {
+  Where w;
+  if (!locate(c, first, n, w)) return;
+  const PatchDev& p = c.patches[c.tasks[w.task].patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  R* X = (R*)c.rscr + p.scr;
+  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+  const long long v = S.v;
+  const R gm1 = R(c.gamma) - R(1);
+  const R rho = U[q], mx = U[v + q], my = U[2 * v + q], mz = U[3 * v + q], e = U[4 * v + q];
+  const R bx = R(0.5) * (U[5 * v + q] + U[5 * v + q + 1]);
+  const R by = R(0.5) * (U[6 * v + q] + U[6 * v + q + S.s[1]]);
+  const R bz = R(0.5) * (U[7 * v + q] + U[7 * v + q + S.s[2]]);
+  const R vx = mx / rho, vy = my / rho, vz = mz / rho;
+  const R pr = pressure<R, MIX>(rho, mx, my, mz, e, bx, by, bz, gm1);
+  if (!(rho > R(0)) || !(pr > R(0)) || !isfinite(e)) flag_phys(c.slots);
+  R* W = X + SCR_W * v;
+  W[q] = rho;
+  W[v + q] = vx;
+  W[2 * v + q] = vy;
+  W[3 * v + q] = vz;
+  W[4 * v + q] = pr;
+  W[5 * v + q] = bx;
+  W[6 * v + q] = by;
+  W[7 * v + q] = bz;
+  R* E = X + SCR_EC * v;
+  E[q] = -(vy * bz - vz * by);
+  E[v + q] = -(vz * bx - vx * bz);
+  E[2 * v + q] = -(vx * by - vy * bx);
+}
+
+// ---------------------------------------------------------------------------
+// stage 2: limited slopes and the conservative Hancock half step (cells of the region grown by 1)
+// ---------------------------------------------------------------------------
+template <int D, typename R>
+__device__ __forceinline__ void hancock_axis(const R* W, long long v, long long q, long long sd, const R* w0, R gm1,
+                                             R half_dt_dx, R* du) {
+  R wp[8], wm[8], f1[8], f2[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const R s = mc_limit(w0[m] - W[m * v + q - sd], W[m * v + q + sd] - w0[m]);
+    wp[m] = w0[m] + R(0.5) * s;
+    wm[m] = w0[m] - R(0.5) * s;
+  }
+  phys_flux<D>(wp, gm1, f1);
+  phys_flux<D>(wm, gm1, f2);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) du[m] -= half_dt_dx * (f1[m] - f2[m]);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_pred(DevCtx c, int first, int n, int cur, double dt) {
+  Where w;
+  if (!locate(c, first, n, w)) return;
+  const PatchDev& p = c.patches[c.tasks[w.task].patch];
+  const Strides S = strides(p);
+  R* X = (R*)c.rscr + p.scr;
+  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+  const long long v = S.v;
+  const R* W = X + SCR_W * v;
+  const R gm1 = R(c.gamma) - R(1);
+  const R h = R(0.5 * dt / p.dx);
+  R w0[8], du[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    w0[m] = W[m * v + q];
+    du[m] = R(0);
+  }
+  hancock_axis<0>(W, v, q, S.s[0], w0, gm1, h, du);
+  hancock_axis<1>(W, v, q, S.s[1], w0, gm1, h, du);
+  hancock_axis<2>(W, v, q, S.s[2], w0, gm1, h, du);
+  R* DU = X + SCR_DU * v;
+#pragma unroll
+  for (int m = 0; m < 8; ++m) DU[m * v + q] = du[m];
+}
+
+// ---------------------------------------------------------------------------
+// stage 3: face-normal field at t^{n+1/2} (faces of the cells of the region grown by 1)
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R ebar(const R* ec_e, long long q, long long sa, long long sc) {
+  return R(0.25) * (ec_e[q] + ec_e[q - sa] + ec_e[q - sc] + ec_e[q - sa - sc]);
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void bhalf_axis(const R* U, R* X, const Strides& S, long long q, R half_dt_dx) {
+  constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
+  const long long v = S.v;
+  const R* EC = X + SCR_EC * v;
+  const R* ecC = EC + C * v;
+  const R* ecA = EC + A * v;
+  // edge-averaged cell EMFs: component C has in-plane axes (D, A); component A has (C, D)
+  const R eC0 = ebar(ecC, q, S.s[D], S.s[A]);
+  const R eC1 = ebar(ecC, q + S.s[A], S.s[D], S.s[A]);
+  const R eA0 = ebar(ecA, q, S.s[C], S.s[D]);
+  const R eA1 = ebar(ecA, q + S.s[C], S.s[C], S.s[D]);
+  const R curl = (eC1 - eC0) - (eA1 - eA0);
+  X[(SCR_BH + D) * v + q] = U[(5 + D) * v + q] - half_dt_dx * curl;
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_bhalf(DevCtx c, int first, int n, int cur, double dt) {
+  Where w;
+  if (!locate(c, first, n, w)) return;
+  const Task& T = c.tasks[w.task];
+  const PatchDev& p = c.patches[T.patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  R* X = (R*)c.rscr + p.scr;
+  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+  const R h = R(0.5 * dt / p.dx);
+  // the task region is the node box [lo, hi]; the cell box is [lo, hi - 1]
+  const bool ix = w.i < T.hi[0] - 1, iy = w.j < T.hi[1] - 1, iz = w.k < T.hi[2] - 1;
+  if (iy && iz) bhalf_axis<0>(U, X, S, q, h);
+  if (ix && iz) bhalf_axis<1>(U, X, S, q, h);
+  if (ix && iy) bhalf_axis<2>(U, X, S, q, h);
+}
+
+// ---------------------------------------------------------------------------
+// stage 4: cell reference EMF at t^{n+1/2} (cells of the region grown by 1)
+// ---------------------------------------------------------------------------
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_eref(DevCtx c, int first, int n, int cur) {
+  Where w;
+  if (!locate(c, first, n, w)) return;
+  const PatchDev& p = c.patches[c.tasks[w.task].patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  R* X = (R*)c.rscr + p.scr;
+  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+  const long long v = S.v;
+  const R* DU = X + SCR_DU * v;
+  const R* BH = X + SCR_BH * v;
+  const R rho = U[q] + DU[q];
+  const R vx = (U[v + q] + DU[v + q]) / rho;
+  const R vy = (U[2 * v + q] + DU[2 * v + q]) / rho;
+  const R vz = (U[3 * v + q] + DU[3 * v + q]) / rho;
+  const R bx = R(0.5) * (BH[q] + BH[q + 1]);
+  const R by = R(0.5) * (BH[v + q] + BH[v + q + S.s[1]]);
+  const R bz = R(0.5) * (BH[2 * v + q] + BH[2 * v + q + S.s[2]]);
+  R* ER = X + SCR_ER * v;
+  ER[q] = -(vy * bz - vz * by);
+  ER[v + q] = -(vz * bx - vx * bz);
+  ER[2 * v + q] = -(vx * by - vy * bx);
+}
+
+// ---------------------------------------------------------------------------
+// stage 5: HLLD fluxes through the faces normal to D, boundary registers
+// ---------------------------------------------------------------------------
+template <int D, typename R, bool MIX>
+__device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, const R* U, R* X, int i, int j, int k,
+                          int level, int substep, double dt) {
+  using Q = typename RegOf<R, MIX>::T;
+  constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
+  const long long v = S.v;
+  const long long sd = S.s[D];
+  const long long q = i + j * S.s[1] + k * S.s[2];
+  const R* W = X + SCR_W * v;
+  const R* DU = X + SCR_DU * v;
+  const R gamma = R(c.gamma);
+  const R gm1 = gamma - R(1);
+  R wl[8], wr[8], u[8];
+  // + state of the cell on the low side
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const R a = W[m * v + q - 2 * sd], b = W[m * v + q - sd], cc = W[m * v + q];
+    wl[m] = b + R(0.5) * mc_limit(b - a, cc - b);
+  }
+  to_cons(wl, gm1, u);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) u[m] += DU[m * v + q - sd];
+  to_prim<R, MIX>(u, gm1, wl);
+  // - state of the cell on the high side
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const R a = W[m * v + q - sd], b = W[m * v + q], cc = W[m * v + q + sd];
+    wr[m] = b - R(0.5) * mc_limit(b - a, cc - b);
+  }
+  to_cons(wr, gm1, u);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) u[m] += DU[m * v + q];
+  to_prim<R, MIX>(u, gm1, wr);
+  if (!(wl[0] > R(0)) || !(wl[4] > R(0)) || !(wr[0] > R(0)) || !(wr[4] > R(0))) flag_phys(c.slots);
+  const R bn = X[(SCR_BH + D) * v + q];
+  R f[8];
+  hlld<D>(wl, wr, bn, gamma, f);
+  R* F = X + (SCR_F + 7 * D) * v;
+  F[q] = f[0];
+  F[v + q] = f[1];
+  F[2 * v + q] = f[2];
+  F[3 * v + q] = f[3];
+  F[4 * v + q] = f[4];
+  F[5 * v + q] = -f[5 + A];   // EMF along C carried by this face
+  F[6 * v + q] = f[5 + C];    // EMF along A carried by this face
+
+  // registers ---------------------------------------------------------------
+  const int r[3] = {i - AMRX_G, j - AMRX_G, k - AMRX_G};
+  int a1, a2;
+  other_axes(D, a1, a2);
+  Q* regs = (Q*)c.reg;
+  const bool trans_in = r[a1] >= 0 && r[a1] < p.n[a1] && r[a2] >= 0 && r[a2] < p.n[a2];
+  if (trans_in && (r[D] == 0 || r[D] == p.n[D])) {
+    const int side = r[D] == 0 ? 0 : 1;
+    const int mode = (level > 0 && substep > 0) ? 1 : 0;
+    Q* acc = regs + p.freg;
+    Q* lo = acc + p.fsize;
+    Q* last = lo + p.fsize;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const long long idx = face_reg_index(p.n, D, side, m, r[a1], r[a2]);
+      const Q val = (Q)f[m] * (Q)dt;
+      reg_put<Q, MIX>(acc, lo, idx, val, mode);
+      last[idx] = val;
+    }
+  }
+  if (p.has_children) {
+    const int* cov = c.cov + p.cov;
+    const int cl = cov[q - sd], ch = cov[q];
+    if ((cl >= 0) != (ch >= 0)) {
+      const int child = cl >= 0 ? cl : ch;
+      const PatchDev& cp = c.patches[child];
+      const int side = ch >= 0 ? 0 : 1;
+      const int nc[3] = {cp.n[0] / 2, cp.n[1] / 2, cp.n[2] / 2};
+      const int g[3] = {i + p.lo[0] - AMRX_G, j + p.lo[1] - AMRX_G, k + p.lo[2] - AMRX_G};
+      const int t1 = g[a1] - cp.lo[a1] / 2, t2 = g[a2] - cp.lo[a2] / 2;
+#pragma unroll
+      for (int m = 0; m < 5; ++m) regs[cp.creg + face_reg_index(nc, D, side, m, t1, t2)] = (Q)f[m] * (Q)dt;
+    }
+  }
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n, int cur, int level, int substep,
+                                                      double dt) {
+  Where w;
+  if (!locate(c, first, n, w)) return;
+  const Task& T = c.tasks[w.task];
+  const PatchDev& p = c.patches[T.patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  R* X = (R*)c.rscr + p.scr;
+  if (T.axis == 0) flux_face<0, R, MIX>(c, p, S, U, X, w.i, w.j, w.k, level, substep, dt);
+  else if (T.axis == 1) flux_face<1, R, MIX>(c, p, S, U, X, w.i, w.j, w.k, level, substep, dt);
+  else flux_face<2, R, MIX>(c, p, S, U, X, w.i, w.j, w.k, level, substep, dt);
+}
+
+// ---------------------------------------------------------------------------
+// stage 6: upwinded CT-contact edge EMFs along E, boundary registers
+// ---------------------------------------------------------------------------
+template <int E, typename R, bool MIX>
+__device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R* X, int i, int j, int k, int level,
+                         int substep, double dt) {
+  using Q = typename RegOf<R, MIX>::T;
+  constexpr int A = (E + 1) % 3, C = (E + 2) % 3;
+  const long long v = S.v;
+  const long long q = i + j * S.s[1] + k * S.s[2];
+  const long long sa = S.s[A], sc = S.s[C];
+  const R* FA = X + (SCR_F + 7 * A) * v;
+  const R* FC = X + (SCR_F + 7 * C) * v;
+  const R* efa = FA + 5 * v;   // EMF along E on the faces normal to A
+  const R* efc = FC + 6 * v;   // EMF along E on the faces normal to C
+  const R* er = X + (SCR_ER + E) * v;
+  const R ea_bm = efa[q - sc], ea_b0 = efa[q];
+  const R eb_am = efc[q - sa], eb_a0 = efc[q];
+  const R r_mm = er[q - sa - sc], r_0m = er[q - sc], r_m0 = er[q - sa], r_00 = er[q];
+  const R d_b_upper = upwind(FA[q], r_m0 - eb_am, r_00 - eb_a0);
+  const R d_b_lower = upwind(FA[q - sc], eb_am - r_mm, eb_a0 - r_0m);
+  const R d_a_upper = upwind(FC[q], r_0m - ea_bm, r_00 - ea_b0);
+  const R d_a_lower = upwind(FC[q - sa], ea_bm - r_mm, ea_b0 - r_m0);
+  const R emf = R(0.25) * (ea_bm + ea_b0 + eb_am + eb_a0) + R(0.25) * (d_b_lower - d_b_upper) +
+                R(0.25) * (d_a_lower - d_a_upper);
+  X[(SCR_E + E) * v + q] = emf;
+
+  // registers on the patch's box surface --------------------------------------
+  Q* regs = (Q*)c.reg;
+  const int r[3] = {i - AMRX_G, j - AMRX_G, k - AMRX_G};
+  const Q val = (Q)emf * (Q)dt;
+  if (r[E] >= 0 && r[E] < p.n[E] && r[A] >= 0 && r[A] <= p.n[A] && r[C] >= 0 && r[C] <= p.n[C]) {
+    const int mode = (level > 0 && substep > 0) ? 1 : 0;
+    Q* acc = regs + p.ereg;
+    Q* lo = acc + p.esize;
+    if (r[A] == 0 || r[A] == p.n[A])
+      reg_put<Q, MIX>(acc, lo, edge_reg_pa(p.n, E, r[A] == 0 ? 0 : 1, r[C], r[E]), val, mode);
+    if (r[C] == 0 || r[C] == p.n[C])
+      reg_put<Q, MIX>(acc, lo, edge_reg_pb(p.n, E, r[C] == 0 ? 0 : 1, r[A], r[E]), val, mode);
+  }
+  if (p.has_children) {
+    const int* cov = c.cov + p.cov;
+    const int nb[4] = {cov[q - sa - sc], cov[q - sc], cov[q - sa], cov[q]};
+    const bool any = nb[0] >= 0 || nb[1] >= 0 || nb[2] >= 0 || nb[3] >= 0;
+    const bool all = nb[0] >= 0 && nb[1] >= 0 && nb[2] >= 0 && nb[3] >= 0;
+    if (any && !all) {
+      const int owner = nb[0] >= 0 ? nb[0] : (nb[1] >= 0 ? nb[1] : (nb[2] >= 0 ? nb[2] : nb[3]));
+      const PatchDev& cp = c.patches[owner];
+      const int nc[3] = {cp.n[0] / 2, cp.n[1] / 2, cp.n[2] / 2};
+      const int g[3] = {i + p.lo[0] - AMRX_G - cp.lo[0] / 2, j + p.lo[1] - AMRX_G - cp.lo[1] / 2,
+                        k + p.lo[2] - AMRX_G - cp.lo[2] / 2};
+      Q* cr = regs + cp.cereg;
+      if (g[A] == 0 || g[A] == nc[A]) cr[edge_reg_pa(nc, E, g[A] == 0 ? 0 : 1, g[C], g[E])] = val;
+      if (g[C] == 0 || g[C] == nc[C]) cr[edge_reg_pb(nc, E, g[C] == 0 ? 0 : 1, g[A], g[E])] = val;
+    }
+  }
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_edge(DevCtx c, int first, int n, int cur, int level, int substep,
+                                                      double dt) {
+  Where w;
+  if (!locate(c, first, n, w)) return;
+  const Task& T = c.tasks[w.task];
+  const PatchDev& p = c.patches[T.patch];
+  const Strides S = strides(p);
+  R* X = (R*)c.rscr + p.scr;
+  if (T.axis == 0) edge_emf<0, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else if (T.axis == 1) edge_emf<1, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else edge_emf<2, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+}
+
+// ---------------------------------------------------------------------------
+// stage 7: conservative cell update and Stokes face update into the next buffer
+// ---------------------------------------------------------------------------
+template <int D, typename R>
+__device__ __forceinline__ void face_update(const R* U, R* N, const R* X, const Strides& S, long long q, R dt_dx) {
+  constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
+  const long long v = S.v;
+  const R* EC = X + (SCR_E + C) * v;
+  const R* EA = X + (SCR_E + A) * v;
+  const R curl = (EC[q + S.s[A]] - EC[q]) - (EA[q + S.s[C]] - EA[q]);
+  N[(5 + D) * v + q] = U[(5 + D) * v + q] - dt_dx * curl;
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int n, int cur, double dt) {
+  Where w;
+  if (!locate(c, first, n, w)) return;
+  const Task& T = c.tasks[w.task];
+  const PatchDev& p = c.patches[T.patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  R* N = (R*)c.state + p.st[1 - cur];
+  const R* X = (const R*)c.rscr + p.scr;
+  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+  const long long v = S.v;
+  const R dt_dx = R(dt / p.dx);
+  const bool ix = w.i < T.hi[0] - 1, iy = w.j < T.hi[1] - 1, iz = w.k < T.hi[2] - 1;
+  if (ix && iy && iz) {
+    const R* FX = X + SCR_F * v;
+    const R* FY = X + (SCR_F + 7) * v;
+    const R* FZ = X + (SCR_F + 14) * v;
+#pragma unroll
+    for (int m = 0; m < 5; ++m) {
+      const R div = (FX[m * v + q + 1] - FX[m * v + q]) + (FY[m * v + q + S.s[1]] - FY[m * v + q]) +
+                    (FZ[m * v + q + S.s[2]] - FZ[m * v + q]);
+      N[m * v + q] = U[m * v + q] - dt_dx * div;
+    }
+  }
+  if (iy && iz) face_update<0>(U, N, X, S, q, dt_dx);
+  if (ix && iz) face_update<1>(U, N, X, S, q, dt_dx);
+  if (ix && iy) face_update<2>(U, N, X, S, q, dt_dx);
+}
+
+// ---------------------------------------------------------------------------
+// same-level ghost copy: 64 lanes per run (one wavefront)
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_copy(DevCtx c, int first, int n, int cur) {
+  const long long gid = (long long)blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  const long long run = gid >> 6;
+  const int lane = (int)(gid & 63);
+  if (run >= n) return;
+  const Run& r = c.runs[first + run];
+  if (lane >= r.len) return;
+  const PatchDev& dp = c.patches[r.dst_patch];
+  const PatchDev& sp = c.patches[r.src_patch];
+  R* dst = (R*)c.state + dp.st[cur];
+  const R* src = (const R*)c.state + sp.st[cur];
+  if (r.kind == 0) {
+#pragma unroll
+    for (int m = 0; m < 5; ++m) dst[m * dp.vol + r.dst_lin + lane] = src[m * sp.vol + r.src_lin + lane];
+  } else {
+    const int m = 4 + r.kind;
+    dst[m * dp.vol + r.dst_lin + lane] = src[m * sp.vol + r.src_lin + lane];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// prolongation of one parent cell into a fine ghost region
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_prolong(DevCtx c, int first, int n, int cur_fine, int old_parent) {
+  const int id = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  if (id >= n) return;
+  const Pro& pr = c.pros[first + id];
+  const PatchDev& fp = c.patches[pr.patch];
+  const PatchDev& mp = c.patches[fp.parent];
+  const Strides FS = strides(fp), MS = strides(mp);
+  const R* M = (const R*)c.state + mp.st[old_parent];
+  R* F = (R*)c.state + fp.st[cur_fine];
+  const long long P0 = pr.pidx;
+  const long long f0 = 2LL * pr.c[0] + 2LL * pr.c[1] * FS.s[1] + 2LL * pr.c[2] * FS.s[2];
+  // cells: conservative minmod-limited linear
+  for (int m = 0; m < 5; ++m) {
+    const R* u = M + m * MS.v;
+    const R u0 = u[P0];
+    const R sx = minmod2(u[P0 + MS.s[0]] - u0, u0 - u[P0 - MS.s[0]]);
+    const R sy = minmod2(u[P0 + MS.s[1]] - u0, u0 - u[P0 - MS.s[1]]);
+    const R sz = minmod2(u[P0 + MS.s[2]] - u0, u0 - u[P0 - MS.s[2]]);
+    for (int oz = 0; oz < 2; ++oz)
+      for (int oy = 0; oy < 2; ++oy)
+        for (int ox = 0; ox < 2; ++ox)
+          F[m * FS.v + f0 + ox + oy * FS.s[1] + oz * FS.s[2]] =
+              u0 + R(0.25) * (R(2 * ox - 1) * sx + R(2 * oy - 1) * sy + R(2 * oz - 1) * sz);
+  }
+  // faces: outer[d][s][t2][t1] with (t1, t2) the offsets along the two other axes in increasing order
+  R outer[3][2][2][2];
+  for (int d = 0; d < 3; ++d) {
+    int a1, a2;
+    other_axes(d, a1, a2);
+    const R* b = M + (5 + d) * MS.v;
+    R* fb = F + (5 + d) * FS.v;
+    for (int s = 0; s < 2; ++s) {
+      const long long fbase = f0 + 2LL * s * FS.s[d];
+      if (pr.flags & (1 << (2 * d + s))) {
+        for (int t2 = 0; t2 < 2; ++t2)
+          for (int t1 = 0; t1 < 2; ++t1) outer[d][s][t2][t1] = fb[fbase + t1 * FS.s[a1] + t2 * FS.s[a2]];
+      } else {
+        const long long pf = P0 + s * MS.s[d];
+        const R bc = b[pf];
+        const R s1 = minmod2(b[pf + MS.s[a1]] - bc, bc - b[pf - MS.s[a1]]);
+        const R s2 = minmod2(b[pf + MS.s[a2]] - bc, bc - b[pf - MS.s[a2]]);
+        for (int t2 = 0; t2 < 2; ++t2)
+          for (int t1 = 0; t1 < 2; ++t1) {
+            const R val = bc + R(0.25) * (R(2 * t1 - 1) * s1 + R(2 * t2 - 1) * s2);
+            outer[d][s][t2][t1] = val;
+            fb[fbase + t1 * FS.s[a1] + t2 * FS.s[a2]] = val;
+          }
+      }
+    }
+  }
+  // interior faces: mean of the aligned outer faces, then the least-norm divergence correction.
+  // Cell (o0, o1, o2) divergence (times h) = sum_d [high_d - low_d].  With interior guesses g,
+  // residual r = -div; phi = L^+ r for the cube graph Laplacian L (eigenvectors: Walsh functions
+  // chi_S(o) = (-1)^(S.o) with eigenvalue 2|S|); correction of the interior face of axis d at
+  // transverse offsets t: phi(o_d = 0, t) - phi(o_d = 1, t).
+  R inner[3][2][2];
+  for (int d = 0; d < 3; ++d)
+    for (int t2 = 0; t2 < 2; ++t2)
+      for (int t1 = 0; t1 < 2; ++t1) inner[d][t2][t1] = R(0.5) * (outer[d][0][t2][t1] + outer[d][1][t2][t1]);
+  R res[8];
+  for (int o = 0; o < 8; ++o) {
+    const int oo[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+    R div = R(0);
+    for (int d = 0; d < 3; ++d) {
+      int a1, a2;
+      other_axes(d, a1, a2);
+      const int t1 = oo[a1], t2 = oo[a2];
+      const R lowf = oo[d] == 0 ? outer[d][0][t2][t1] : inner[d][t2][t1];
+      const R highf = oo[d] == 0 ? inner[d][t2][t1] : outer[d][1][t2][t1];
+      div += highf - lowf;
+    }
+    res[o] = -div;
+  }
+  R phi[8];
+  for (int o = 0; o < 8; ++o) phi[o] = R(0);
+  for (int sm = 1; sm < 8; ++sm) {
+    const int nbits = (sm & 1) + ((sm >> 1) & 1) + ((sm >> 2) & 1);
+    R coef = R(0);
+    for (int o = 0; o < 8; ++o) coef += (__popc(sm & o) & 1) ? -res[o] : res[o];
+    coef *= R(1) / R(16 * nbits);  // (1/8) projection and 1/(2|S|)
+    for (int o = 0; o < 8; ++o) phi[o] += (__popc(sm & o) & 1) ? -coef : coef;
+  }
+  for (int d = 0; d < 3; ++d) {
+    int a1, a2;
+    other_axes(d, a1, a2);
+    R* fb = F + (5 + d) * FS.v;
+    for (int t2 = 0; t2 < 2; ++t2)
+      for (int t1 = 0; t1 < 2; ++t1) {
+        int o_lo = (t1 << a1) | (t2 << a2);
+        int o_hi = o_lo | (1 << d);
+        const R val = inner[d][t2][t1] + (phi[o_lo] - phi[o_hi]);
+        fb[f0 + FS.s[d] + t1 * FS.s[a1] + t2 * FS.s[a2]] = val;
+      }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// restriction of a child onto its parent: node box of the child's coarse box
+// ---------------------------------------------------------------------------
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_restrict(DevCtx c, int first, int n, int cur_fine, int cur_coarse) {
+  Where w;
+  if (!locate(c, first, n, w)) return;
+  const Task& T = c.tasks[w.task];
+  const PatchDev& fp = c.patches[T.patch];
+  const PatchDev& mp = c.patches[fp.parent];
+  const Strides FS = strides(fp), MS = strides(mp);
+  const R* F = (const R*)c.state + fp.st[cur_fine];
+  R* M = (R*)c.state + mp.st[cur_coarse];
+  const int I[3] = {w.i, w.j, w.k};
+  const int nc[3] = {fp.n[0] / 2, fp.n[1] / 2, fp.n[2] / 2};
+  long long pq = 0, fq = 0;
+  for (int a = 0; a < 3; ++a) {
+    pq += (long long)(fp.lo[a] / 2 - mp.lo[a] + AMRX_G + I[a]) * MS.s[a];
+    fq += (long long)(AMRX_G + 2 * I[a]) * FS.s[a];
+  }
+  const bool in[3] = {I[0] < nc[0], I[1] < nc[1], I[2] < nc[2]};
+  if (in[0] && in[1] && in[2]) {
+    for (int m = 0; m < 5; ++m) {
+      const R* u = F + m * FS.v;
+      R s = R(0);
+      for (int oz = 0; oz < 2; ++oz)
+        for (int oy = 0; oy < 2; ++oy)
+          for (int ox = 0; ox < 2; ++ox) s += u[fq + ox + oy * FS.s[1] + oz * FS.s[2]];
+      M[m * MS.v + pq] = R(0.125) * s;
+    }
+  }
+  for (int d = 0; d < 3; ++d) {
+    int a1, a2;
+    other_axes(d, a1, a2);
+    if (!(in[a1] && in[a2])) continue;
+    const R* b = F + (5 + d) * FS.v;
+    R s = R(0);
+    for (int t2 = 0; t2 < 2; ++t2)
+      for (int t1 = 0; t1 < 2; ++t1) s += b[fq + t1 * FS.s[a1] + t2 * FS.s[a2]];
+    M[(5 + d) * MS.v + pq] = R(0.25) * s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// flux correction of an uncovered parent cell next to the fine region
+// ---------------------------------------------------------------------------
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flux_corr(DevCtx c, int first, int n, int cur_coarse) {
+  using Q = typename RegOf<R, MIX>::T;
+  const int id = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  if (id >= n) return;
+  const Corr& e = c.corrs[first + id];
+  const PatchDev& mp = c.patches[e.patch];
+  const Strides S = strides(mp);
+  R* M = (R*)c.state + mp.st[cur_coarse];
+  const int* cov = c.cov + mp.cov;
+  const Q* regs = (const Q*)c.reg;
+  const long long q = e.lin;
+  const int ijk[3] = {(int)(q % S.s[1]), (int)((q / S.s[1]) % mp.dim[1]), (int)(q / S.s[2])};
+  double corr[5] = {0, 0, 0, 0, 0};
+  for (int d = 0; d < 3; ++d) {
+    int a1, a2;
+    other_axes(d, a1, a2);
+    for (int sg = -1; sg <= 1; sg += 2) {
+      const int ch = cov[q + sg * S.s[d]];
+      if (ch < 0) continue;
+      const PatchDev& cp = c.patches[ch];
+      const int nc[3] = {cp.n[0] / 2, cp.n[1] / 2, cp.n[2] / 2};
+      const int side = sg > 0 ? 0 : 1;
+      int g[3];
+      for (int a = 0; a < 3; ++a) g[a] = ijk[a] + mp.lo[a] - AMRX_G - cp.lo[a] / 2;
+      const int t1 = g[a1], t2 = g[a2];
+      const Q* acc = regs + cp.freg;
+      const Q* lo = acc + cp.fsize;
+      for (int m = 0; m < 5; ++m) {
+        Q fine = Q(0);
+        for (int u2 = 0; u2 < 2; ++u2)
+          for (int u1 = 0; u1 < 2; ++u1)
+            fine += reg_get<Q, MIX>(acc, lo, face_reg_index(cp.n, d, side, m, 2 * t1 + u1, 2 * t2 + u2));
+        const Q coarse = regs[cp.creg + face_reg_index(nc, d, side, m, t1, t2)];
+        const double delta = (double)(Q(0.25) * fine - coarse);
+        corr[m] += sg > 0 ? -delta : delta;
+      }
+    }
+  }
+  for (int m = 0; m < 5; ++m) M[m * S.v + q] = (R)((double)M[m * S.v + q] + corr[m] / mp.dx);
+}
+
+// EMF change (new - old, times dt) at a parent edge along e at node q, zero off the coverage boundary
+template <typename R, bool MIX>
+__device__ double emf_delta(const DevCtx& c, const PatchDev& mp, const Strides& S, const int* cov, int e,
+                            const int ijk[3]) {
+  using Q = typename RegOf<R, MIX>::T;
+  const int A = (e + 1) % 3, C = (e + 2) % 3;
+  const long long q = ijk[0] + ijk[1] * S.s[1] + ijk[2] * S.s[2];
+  const int nb[4] = {cov[q - S.s[A] - S.s[C]], cov[q - S.s[C]], cov[q - S.s[A]], cov[q]};
+  const bool any = nb[0] >= 0 || nb[1] >= 0 || nb[2] >= 0 || nb[3] >= 0;
+  const bool all = nb[0] >= 0 && nb[1] >= 0 && nb[2] >= 0 && nb[3] >= 0;
+  if (!any || all) return 0.0;
+  const int owner = nb[0] >= 0 ? nb[0] : (nb[1] >= 0 ? nb[1] : (nb[2] >= 0 ? nb[2] : nb[3]));
+  const PatchDev& cp = c.patches[owner];
+  const int nc[3] = {cp.n[0] / 2, cp.n[1] / 2, cp.n[2] / 2};
+  int g[3];
+  for (int a = 0; a < 3; ++a) g[a] = ijk[a] + mp.lo[a] - AMRX_G - cp.lo[a] / 2;
+  const Q* regs = (const Q*)c.reg;
+  const Q* acc = regs + cp.ereg;
+  const Q* lo = acc + cp.esize;
+  Q enew, eold;
+  if (g[A] == 0 || g[A] == nc[A]) {
+    const int s = g[A] == 0 ? 0 : 1;
+    eold = regs[cp.cereg + edge_reg_pa(nc, e, s, g[C], g[e])];
+    enew = Q(0.5) * (reg_get<Q, MIX>(acc, lo, edge_reg_pa(cp.n, e, s, 2 * g[C], 2 * g[e])) +
+                     reg_get<Q, MIX>(acc, lo, edge_reg_pa(cp.n, e, s, 2 * g[C], 2 * g[e] + 1)));
+  } else {
+    const int s = g[C] == 0 ? 0 : 1;
+    eold = regs[cp.cereg + edge_reg_pb(nc, e, s, g[A], g[e])];
+    enew = Q(0.5) * (reg_get<Q, MIX>(acc, lo, edge_reg_pb(cp.n, e, s, 2 * g[A], 2 * g[e])) +
+                     reg_get<Q, MIX>(acc, lo, edge_reg_pb(cp.n, e, s, 2 * g[A], 2 * g[e] + 1)));
+  }
+  return (double)(enew - eold);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_emf_corr(DevCtx c, int first, int n, int cur_coarse) {
+  const int id = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  if (id >= n) return;
+  const Corr& e = c.corrs[first + id];
+  const PatchDev& mp = c.patches[e.patch];
+  const Strides S = strides(mp);
+  R* M = (R*)c.state + mp.st[cur_coarse];
+  const int* cov = c.cov + mp.cov;
+  const long long q = e.lin;
+  const int d = e.axis;
+  const int A = (d + 1) % 3, C = (d + 2) % 3;
+  const int ijk[3] = {(int)(q % S.s[1]), (int)((q / S.s[1]) % mp.dim[1]), (int)(q / S.s[2])};
+  int nA[3] = {ijk[0], ijk[1], ijk[2]};
+  nA[A] += 1;
+  int nC[3] = {ijk[0], ijk[1], ijk[2]};
+  nC[C] += 1;
+  const double curl = (emf_delta<R, MIX>(c, mp, S, cov, C, nA) - emf_delta<R, MIX>(c, mp, S, cov, C, ijk)) -
+                      (emf_delta<R, MIX>(c, mp, S, cov, A, nC) - emf_delta<R, MIX>(c, mp, S, cov, A, ijk));
+  R* b = M + (5 + d) * S.v;
+  b[q] = (R)((double)b[q] - curl / mp.dx);
+}
+
+// ---------------------------------------------------------------------------
+// same-level synchronisation of shared boundary faces
+// ---------------------------------------------------------------------------
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_sync(DevCtx c, int first, int n, int cur) {
+  using Q = typename RegOf<R, MIX>::T;
+  const int id = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  if (id >= n) return;
+  const SyncPair& s = c.syncs[first + id];
+  const PatchDev& pa = c.patches[s.a];
+  const PatchDev& pb = c.patches[s.b];
+  const Q* regs = (const Q*)c.reg;
+  const Q* la = regs + pa.freg + 2 * pa.fsize;
+  const Q* lb = regs + pb.freg + 2 * pb.fsize;
+  double worst = 0.0;
+  double delta[5];
+  // component m of a face register sits m * (n_a2 * n_a1) entries after component 0
+  int a1, a2;
+  other_axes(s.axis, a1, a2);
+  const long long stride_a = (long long)pa.n[a1] * pa.n[a2];
+  const long long stride_b = (long long)pb.n[a1] * pb.n[a2];
+  for (int m = 0; m < 5; ++m) {
+    const double fa = la[s.a_reg + m * stride_a], fb = lb[s.b_reg + m * stride_b];
+    delta[m] = 0.5 * (fb - fa);
+    worst = fmax(worst, fabs(fb - fa));
+  }
+  atomic_max_pos(&c.slots[SLOT_SYNC_F], worst);
+  const R* Ua = (const R*)c.state + pa.st[cur];
+  const R* Ub = (const R*)c.state + pb.st[cur];
+  const double bd = fabs((double)Ua[(5 + s.axis) * pa.vol + s.a_face] - (double)Ub[(5 + s.axis) * pb.vol + s.b_face]);
+  atomic_max_pos(&c.slots[SLOT_SYNC_B], bd);
+  if (worst > 0.0) {
+    R* U = (R*)c.state + pa.st[cur];
+    for (int m = 0; m < 5; ++m) {
+      const double v = (s.a_side == 0 ? delta[m] : -delta[m]) / pa.dx;
+      atomicAdd(&U[m * pa.vol + s.a_cell], (R)v);
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// CFL signal speed: max over interior cells of sum_d (|v_d| + c_f,d) / dx
+// ---------------------------------------------------------------------------
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_cfl(DevCtx c, int first, int n, int cur, int level) {
+  Where w;
+  double s = 0.0;
+  if (locate(c, first, n, w)) {
+    const PatchDev& p = c.patches[c.tasks[w.task].patch];
+    const Strides S = strides(p);
+    const R* U = (const R*)c.state + p.st[cur];
+    const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+    const long long v = S.v;
+    const R gamma = R(c.gamma);
+    const R rho = U[q];
+    const R bx = R(0.5) * (U[5 * v + q] + U[5 * v + q + 1]);
+    const R by = R(0.5) * (U[6 * v + q] + U[6 * v + q + S.s[1]]);
+    const R bz = R(0.5) * (U[7 * v + q] + U[7 * v + q + S.s[2]]);
+    const R pr = pressure<R, MIX>(rho, U[v + q], U[2 * v + q], U[3 * v + q], U[4 * v + q], bx, by, bz, gamma - R(1));
+    const R b2 = bx * bx + by * by + bz * bz;
+    const R vx = U[v + q] / rho, vy = U[2 * v + q] / rho, vz = U[3 * v + q] / rho;
+    const R inv = R(1.0 / p.dx);
+    const R tot = (fabs(vx) + fast_speed(rho, pr, b2, bx * bx, gamma)) * inv +
+                  (fabs(vy) + fast_speed(rho, pr, b2, by * by, gamma)) * inv +
+                  (fabs(vz) + fast_speed(rho, pr, b2, bz * bz, gamma)) * inv;
+    s = (double)tot;
+    if (!(rho > R(0)) || !(pr > R(0)) || !isfinite(s)) flag_phys(c.slots);
+    if (!isfinite(s)) s = 1.0e308;
+  }
+  // wavefront max then one atomic per wavefront
+  for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off, 64));
+  if ((threadIdx.x & 63) == 0) atomic_max_pos(&c.slots[SLOT_SMAX + level], s);
+}
+
+// ---------------------------------------------------------------------------
+// conservation sums over leaf cells with compensated (two-sum) accumulation
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void two_sum(double a, double b, double& s, double& e) {
+  s = a + b;
+  const double bb = s - a;
+  e = (a - (s - bb)) + (b - bb);
+}
+
+struct Curs {
+  int c[AMRX_MAXLEV];
+};
+
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_cons(DevCtx c, int first, int n, Curs curs) {
+  __shared__ double sh_s[8][AMRX_BLOCK];
+  __shared__ double sh_e[8][AMRX_BLOCK];
+  Where w;
+  double x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (locate(c, first, n, w)) {
+    const PatchDev& p = c.patches[c.tasks[w.task].patch];
+    const Strides S = strides(p);
+    const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+    const bool leaf = !p.has_children || c.cov[p.cov + q] < 0;
+    if (leaf) {
+      const R* U = (const R*)c.state + p.st[curs.c[p.level]];
+      const long long v = S.v;
+      const double dv = p.dx * p.dx * p.dx;
+      for (int m = 0; m < 5; ++m) x[m] = (double)U[m * v + q] * dv;
+      x[5] = (double)(R(0.5) * (U[5 * v + q] + U[5 * v + q + 1])) * dv;
+      x[6] = (double)(R(0.5) * (U[6 * v + q] + U[6 * v + q + S.s[1]])) * dv;
+      x[7] = (double)(R(0.5) * (U[7 * v + q] + U[7 * v + q + S.s[2]])) * dv;
+    }
+  }
+  for (int m = 0; m < 8; ++m) {
+    sh_s[m][threadIdx.x] = x[m];
+    sh_e[m][threadIdx.x] = 0.0;
+  }
+  __syncthreads();
+  for (int half = AMRX_BLOCK / 2; half > 0; half >>= 1) {
+    if (threadIdx.x < half) {
+      for (int m = 0; m < 8; ++m) {
+        double s, e;
+        two_sum(sh_s[m][threadIdx.x], sh_s[m][threadIdx.x + half], s, e);
+        sh_s[m][threadIdx.x] = s;
+        sh_e[m][threadIdx.x] += sh_e[m][threadIdx.x + half] + e;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) {
+    c.partials[(long long)blockIdx.x * 16 + threadIdx.x] = sh_s[threadIdx.x][0];
+    c.partials[(long long)blockIdx.x * 16 + 8 + threadIdx.x] = sh_e[threadIdx.x][0];
+  }
+}
+
+__global__ __launch_bounds__(AMRX_BLOCK) void k_cons_final(DevCtx c, int nblk) {
+  __shared__ double sh_s[8][AMRX_BLOCK];
+  __shared__ double sh_e[8][AMRX_BLOCK];
+  double s[8], e[8];
+  for (int m = 0; m < 8; ++m) {
+    s[m] = 0.0;
+    e[m] = 0.0;
+  }
+  for (int b = threadIdx.x; b < nblk; b += AMRX_BLOCK) {
+    for (int m = 0; m < 8; ++m) {
+      double t, err;
+      two_sum(s[m], c.partials[(long long)b * 16 + m], t, err);
+      s[m] = t;
+      e[m] += err + c.partials[(long long)b * 16 + 8 + m];
+    }
+  }
+  for (int m = 0; m < 8; ++m) {
+    sh_s[m][threadIdx.x] = s[m];
+    sh_e[m][threadIdx.x] = e[m];
+  }
+  __syncthreads();
+  for (int half = AMRX_BLOCK / 2; half > 0; half >>= 1) {
+    if (threadIdx.x < half) {
+      for (int m = 0; m < 8; ++m) {
+        double t, err;
+        two_sum(sh_s[m][threadIdx.x], sh_s[m][threadIdx.x + half], t, err);
+        sh_s[m][threadIdx.x] = t;
+        sh_e[m][threadIdx.x] += sh_e[m][threadIdx.x + half] + err;
+      }
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x < 8) {
+    double t, err;
+    two_sum(sh_s[threadIdx.x][0], sh_e[threadIdx.x][0], t, err);
+    c.partials[(long long)nblk * 16 + threadIdx.x] = t;
+    c.partials[(long long)nblk * 16 + 8 + threadIdx.x] = err;
+  }
+}
+
+__global__ void k_clear_slots(DevCtx c) {
+  const int t = threadIdx.x;
+  if (t < NSLOT) c.slots[t] = 0ULL;
+}
+
+inline unsigned grid_of(long long n, int per) { return (unsigned)((n + per - 1) / per); }
+
+#define DISPATCH(KERNEL, GRID, ...)                                                              \
+  do {                                                                                           \
+    if (c.precision == 0) KERNEL<double, false><<<GRID, AMRX_BLOCK, 0, c.stream>>>(__VA_ARGS__); \
+    else if (c.precision == 1) KERNEL<float, false><<<GRID, AMRX_BLOCK, 0, c.stream>>>(__VA_ARGS__); \
+    else KERNEL<float, true><<<GRID, AMRX_BLOCK, 0, c.stream>>>(__VA_ARGS__);                    \
+  } while (0)
+
+#define DISPATCH_R(KERNEL, GRID, ...)                                                     \
+  do {                                                                                    \
+    if (c.precision == 0) KERNEL<double><<<GRID, AMRX_BLOCK, 0, c.stream>>>(__VA_ARGS__); \
+    else KERNEL<float><<<GRID, AMRX_BLOCK, 0, c.stream>>>(__VA_ARGS__);                   \
+  } while (0)
+
+}  // namespace
+
+hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, int blk_first, int nblk, int cur,
+                        int level, int substep, double dt) {
+  (void)blk_first;
+  if (ntask == 0 || nblk == 0) return hipSuccess;
+  const dim3 g(nblk);
+  switch (stage) {
+    case STAGE_PRIM: DISPATCH(k_prim, g, c, task_first, ntask, cur); break;
+    case STAGE_PRED: DISPATCH(k_pred, g, c, task_first, ntask, cur, dt); break;
+    case STAGE_BHALF: DISPATCH(k_bhalf, g, c, task_first, ntask, cur, dt); break;
+    case STAGE_EREF: DISPATCH(k_eref, g, c, task_first, ntask, cur); break;
+    case STAGE_FLUX: DISPATCH(k_flux, g, c, task_first, ntask, cur, level, substep, dt); break;
+    case STAGE_EDGE: DISPATCH(k_edge, g, c, task_first, ntask, cur, level, substep, dt); break;
+    case STAGE_UPDATE: DISPATCH(k_update, g, c, task_first, ntask, cur, dt); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int cur) {
+  if (nrun == 0) return hipSuccess;
+  DISPATCH_R(k_copy, dim3(grid_of((long long)nrun * 64, AMRX_BLOCK)), c, run_first, nrun, cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(const DevCtx& c, int first, int n, int cur_fine, int old_parent) {
+  if (n == 0) return hipSuccess;
+  DISPATCH_R(k_prolong, dim3(grid_of(n, AMRX_BLOCK)), c, first, n, cur_fine, old_parent);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk, int cur_fine,
+                           int cur_coarse) {
+  (void)blk_first;
+  if (ntask == 0 || nblk == 0) return hipSuccess;
+  DISPATCH_R(k_restrict, dim3(nblk), c, task_first, ntask, cur_fine, cur_coarse);
+  return hipGetLastError();
+}
+
+hipError_t launch_flux_corr(const DevCtx& c, int first, int n, int cur_coarse) {
+  if (n == 0) return hipSuccess;
+  DISPATCH(k_flux_corr, dim3(grid_of(n, AMRX_BLOCK)), c, first, n, cur_coarse);
+  return hipGetLastError();
+}
+
+hipError_t launch_emf_corr(const DevCtx& c, int first, int n, int cur_coarse) {
+  if (n == 0) return hipSuccess;
+  DISPATCH(k_emf_corr, dim3(grid_of(n, AMRX_BLOCK)), c, first, n, cur_coarse);
+  return hipGetLastError();
+}
+
+hipError_t launch_sync(const DevCtx& c, int first, int n, int cur) {
+  if (n == 0) return hipSuccess;
+  DISPATCH(k_sync, dim3(grid_of(n, AMRX_BLOCK)), c, first, n, cur);
+  return hipGetLastError();
+}
+
+hipError_t launch_cfl(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk, int cur, int level) {
+  (void)blk_first;
+  if (ntask == 0 || nblk == 0) return hipSuccess;
+  DISPATCH(k_cfl, dim3(nblk), c, task_first, ntask, cur, level);
+  return hipGetLastError();
+}
+
+hipError_t launch_conservation(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk,
+                               const int* cur_of_level) {
+  (void)blk_first;
+  Curs cs;
+  for (int l = 0; l < AMRX_MAXLEV; ++l) cs.c[l] = cur_of_level[l];
+  if (ntask > 0 && nblk > 0) DISPATCH_R(k_cons, dim3(nblk), c, task_first, ntask, cs);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  k_cons_final<<<1, AMRX_BLOCK, 0, c.stream>>>(c, nblk);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_slots(const DevCtx& c) {
+  k_clear_slots<<<1, 64, 0, c.stream>>>(c);
+  return hipGetLastError();
+}
