@@ -35,7 +35,7 @@
  *     and hier_diag(), which synchronise that stream.  Calls on one hierarchy
  *     must not run concurrently from several host threads.
  *
- * Memory layout of the state arena (hier_state_bytes() bytes)
+ * Memory layout of the state arena (size reported by hier_finalize)
  *   Every patch owns two state buffers (current and next; an advance writes
  *   the next buffer and then swaps).  A buffer holds 8 arrays of the patch's
  *   node-padded volume V = (nx+2G+1)(ny+2G+1)(nz+2G+1) real numbers, each
@@ -125,10 +125,11 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
 
 /* Ghost update of every patch of `level` before substep `substep`: copy the
  * interior (closure, for faces) of the same-level patch holding each ghost
- * value's periodic image (Sec. 2.1: data shared between neighbours of one
- * iteration); on levels >= 1 at substep 0, prolongate the parent's
- * pre-advance data into the ghost values no same-level patch holds (Sec. 2.2
- * "Prolongate initial (pre-advanced) data", Sec. 2.3). */
+ * value's periodic image (Sec. 2.1: between the first and last substep,
+ * ghost data come from same-level neighbours of the same iteration); on
+ * levels >= 1 at substep 0, fill the ghost values no same-level patch holds
+ * by prolongation of the parent's data from before the parent's advance
+ * (Sec. 2.2 P step, Sec. 2.3). */
 int level_ghost_fill(amrx_hier* h, int level, int substep);
 
 /* Advance every patch of `level` by dt_level (Sec. 2.2 "Advance"): substep s
@@ -137,16 +138,16 @@ int level_ghost_fill(amrx_hier* h, int level, int substep);
  * and synchronisation, then makes the written buffer current. */
 int advance_level(amrx_hier* h, int level, double dt_level, int substep);
 
-/* Restrict level fine_level onto its parents (Sec. 2.2 "Restrict"; "data and
- * fluxes are restricted and applied to their parent"): covered coarse cells
+/* Restrict level fine_level onto its parents (Sec. 2.2 R step: both the fine
+ * data and the fine fluxes are carried to the parent): covered coarse cells
  * and faces take the volume / area mean of the fine data; uncovered coarse
  * cells and faces next to the fine region are corrected so that the coarse
  * fluxes and EMFs across the coverage boundary equal the time and space
  * averages of the fine ones. */
 int restrict_level(amrx_hier* h, int fine_level);
 
-/* Synchronise fluxes through faces shared by patches of `level` (Sec. 2.2
- * "Synchronize fluxes between neighboring level l grids"): the two sides'
+/* Synchronise fluxes through faces shared by patches of `level` (Sec. 2.2 S
+ * step, flux agreement between adjacent grids of one level): the two sides'
  * fluxes of the last substep are compared, replaced by their mean and the
  * adjacent cells corrected; the largest difference seen is kept for hier_diag. */
 int sync_level(amrx_hier* h, int level);
@@ -171,6 +172,31 @@ int hier_conservation(amrx_hier* h, double sum[8], double comp[8]);
  * largest face-field mismatch on shared faces, out[2] = 1 if the device
  * flagged an unphysical state.  Synchronising.  n = number of slots (<= 3). */
 int hier_diag(amrx_hier* h, double* out, int n);
+
+/* Kernel classes reported by hier_timing_read (one slot each). */
+enum {
+  AMRX_K_PRIM = 0, AMRX_K_PRED, AMRX_K_BHALF, AMRX_K_EREF, AMRX_K_FLUX, AMRX_K_EDGE, AMRX_K_UPDATE,
+  AMRX_K_COPY, AMRX_K_PROLONG, AMRX_K_RESTRICT, AMRX_K_FLUXCORR, AMRX_K_EMFCORR, AMRX_K_SYNC,
+  AMRX_K_CFL, AMRX_K_CONS, AMRX_NKCLASS
+};
+
+/* Measurement support.  hier_timing_enable(h, 1) starts recording a HIP event
+ * before and after every kernel launch the library enqueues on desc.stream
+ * (discarding earlier records); hier_timing_enable(h, 0) stops recording.
+ * hier_timing_read synchronises the stream and returns, per kernel class
+ * (n <= AMRX_NKCLASS slots), the summed device time in ms between the
+ * events and the number of launches.  Recording adds two event records per
+ * launch. */
+int hier_timing_enable(amrx_hier* h, int on);
+int hier_timing_read(amrx_hier* h, int n, double* total_ms, int* launches);
+
+/* Work of one root step per kernel class (pure host, after hier_finalize):
+ * units[k] = number of entries the class processes (cells, faces, edges or
+ * nodes of the stage regions; copied elements for AMRX_K_COPY; parent cells
+ * for AMRX_K_PROLONG; coarse nodes for AMRX_K_RESTRICT; list entries for
+ * the corrections and synchronisation; interior cells for AMRX_K_CFL), and
+ * launches[k] = kernel launches of that class in the batched schedule. */
+int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
 
 /* Debug / test exports (pure host, after hier_finalize).  For every padded
  * cell (kind 0) or face normal to axis kind-1 (kind 1..3) of a patch, in

@@ -13,6 +13,9 @@ FP64, FP32, FP32_MIXED = 0, 1, 2
 PLAIN, BATCHED, GRAPH = 0, 1, 2
 G = 4
 
+KERNEL_CLASSES = ("prim", "pred", "bhalf", "eref", "flux", "edge", "update", "copy", "prolong", "restrict",
+                  "fluxcorr", "emfcorr", "sync", "cfl", "cons")
+
 _ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
 
 
@@ -46,6 +49,9 @@ EXPORTS = {
     "hier_step": ([C.c_void_p, C.c_int, C.POINTER(C.c_double)], C.c_int),
     "hier_conservation": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "hier_diag": ([C.c_void_p, C.POINTER(C.c_double), C.c_int], C.c_int),
+    "hier_timing_enable": ([C.c_void_p, C.c_int], C.c_int),
+    "hier_timing_read": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
+    "hier_step_work": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
     "hier_debug_sources": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_longlong)], C.c_int),
     "hier_debug_prolong_cells": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int], C.c_int),
 }
@@ -218,6 +224,24 @@ class Hierarchy:
         out = (C.c_double * 3)()
         self._check(self.lib.hier_diag(self.h, out, 3))
         return {"sync_flux_max": out[0], "sync_face_max": out[1], "phys_flag": out[2]}
+
+    # ------------------------------------------------------------------ measurement
+    def timing(self, on):
+        self._check(self.lib.hier_timing_enable(self.h, 1 if on else 0))
+
+    def timing_read(self):
+        n = len(KERNEL_CLASSES)
+        ms = (C.c_double * n)()
+        cnt = (C.c_int * n)()
+        self._check(self.lib.hier_timing_read(self.h, n, ms, cnt))
+        return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    def step_work(self):
+        n = len(KERNEL_CLASSES)
+        u = (C.c_double * n)()
+        cnt = (C.c_int * n)()
+        self._check(self.lib.hier_step_work(self.h, n, u, cnt))
+        return {k: (u[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
 
     # ------------------------------------------------------------------ bookkeeping exports
     def debug_sources(self, pid, kind):

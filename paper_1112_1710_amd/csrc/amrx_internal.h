@@ -52,11 +52,13 @@ struct Task {
   int hi[3];
 };
 
-// A run of consecutive padded entries copied from a same-level patch.
+// A run of consecutive padded entries (along x) copied from a same-level patch.
 struct Run {
   int dst_patch, dst_lin, src_patch, src_lin;
-  int len;   // <= 64
+  int len;   // entries in the run
   int kind;  // 0: the 5 cell arrays, 1..3: face array of axis kind-1
+  int off;   // first element of the run within its list (prefix sum of len)
+  int pad;
 };
 
 // One parent cell prolongated into a fine patch's ghost region.
@@ -146,6 +148,7 @@ struct DevCtx {
   const Task* tasks;
   const int* blk;         // per-task first block (prefix)
   const Run* runs;
+  const int* run_blk;     // per copy block: index (within the list) of the run holding its first element
   const Pro* pros;
   const Corr* corrs;
   const SyncPair* syncs;
@@ -164,7 +167,7 @@ enum { SLOT_PHYS = 0, SLOT_SYNC_F = 1, SLOT_SYNC_B = 2, SLOT_SMAX = 8 /* + level
 
 hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, int blk_first, int nblk,
                         int cur, int level, int substep, double dt);
-hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int cur);
+hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int blk_first, int nblk, int nelem, int cur);
 hipError_t launch_prolong(const DevCtx& c, int first, int n, int cur_fine, int old_parent);
 hipError_t launch_restrict(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk, int cur_fine,
                            int cur_coarse);

@@ -29,6 +29,10 @@ struct TaskList {
 struct Range {
   int first = 0, count = 0;
 };
+struct CopyList {
+  int first_run = 0, nrun = 0, first_blk = 0, nblk = 0, nelem = 0;
+  double comps = 0;  // copied array elements (cells count 5)
+};
 
 struct HPatch {
   int id = 0, level = 0;
@@ -67,8 +71,10 @@ struct amrx_hier {
   // lists: batched (per level) and plain (per patch)
   TaskList stage_b[AMRX_MAXLEV][2][NSTAGE];
   std::vector<std::array<std::array<TaskList, NSTAGE>, 2>> stage_p;
-  Range copy_b[AMRX_MAXLEV];
-  std::vector<Range> copy_p;
+  // ghost-copy lists per depth class (0: 4 ghost layers, 1: 2 ghost layers)
+  CopyList copy_b[AMRX_MAXLEV][2];
+  std::vector<std::array<CopyList, 2>> copy_p;
+  std::vector<int> run_blk;
   Range pro_b[AMRX_MAXLEV];
   std::vector<Range> pro_p;
   TaskList restr_b[AMRX_MAXLEV];
@@ -83,13 +89,22 @@ struct amrx_hier {
   // layout
   size_t state_bytes = 0, scratch_bytes = 0;
   size_t off_pdev = 0, off_tasks = 0, off_blk = 0, off_runs = 0, off_pros = 0, off_fcorr = 0, off_ecorr = 0,
-         off_sync = 0, off_cov = 0, off_slots = 0, off_partials = 0, off_reg = 0, off_rscr = 0;
+         off_sync = 0, off_cov = 0, off_slots = 0, off_partials = 0, off_reg = 0, off_rscr = 0, off_runblk = 0;
   size_t meta_bytes = 0;
 
   char* state = nullptr;
   char* scratch = nullptr;
   DevCtx ctx{};
   int cur[AMRX_MAXLEV] = {0};
+
+  // launch timing (measurement support)
+  bool timing = false;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
+  std::vector<std::pair<int, size_t>> ev_marks;  // (kernel class, index of the start event)
+  ~amrx_hier() {
+    for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
+  }
 };
 
 namespace {
@@ -109,6 +124,34 @@ bool hip_ok(amrx_hier* h, hipError_t e, const char* what) {
   do {                                                      \
     if (!hip_ok(h, (expr), what)) return AMRX_EHIP;         \
   } while (0)
+
+hipEvent_t next_event(amrx_hier* h) {
+  if (h->ev_used == h->ev_pool.size()) {
+    hipEvent_t e;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    h->ev_pool.push_back(e);
+  }
+  return h->ev_pool[h->ev_used++];
+}
+
+// Launch through `fn`, bracketing it with events when timing is on.
+template <typename F>
+hipError_t timed(amrx_hier* h, int cls, F fn) {
+  if (!h->timing) return fn();
+  const size_t i0 = h->ev_used;
+  hipEvent_t a = next_event(h), b = next_event(h);
+  if (!a || !b) return hipErrorOutOfMemory;
+  hipStream_t s = (hipStream_t)h->d.stream;
+  hipError_t e = hipEventRecord(a, s);
+  if (e != hipSuccess) return e;
+  e = fn();
+  if (e != hipSuccess) return e;
+  e = hipEventRecord(b, s);
+  h->ev_marks.push_back({cls, i0});
+  return e;
+}
+
+#define TIMED(cls, expr) timed(h, cls, [&]() { return (expr); })
 
 bool box_meet(const int alo[3], const int ahi[3], const int blo[3], const int bhi[3]) {
   for (int a = 0; a < 3; ++a)
@@ -228,18 +271,21 @@ bool is_own(const HPatch& p, int kind, int i, int j, int k) {
   return true;
 }
 
-void build_runs(amrx_hier* h, int pid) {
+// Copy runs (consecutive along x) of the ghost entries of p within `depth` layers of its interior.
+void build_runs(amrx_hier* h, int pid, int depth, int& nelem, double& comps) {
   const HPatch& p = h->P[pid];
   const auto& S = h->src[pid];
   for (int kind = 0; kind < 4; ++kind) {
     const auto& arr = S[kind];
-    const int nx = p.dim[0] - ((kind == 1) ? 0 : 1);  // valid x extent of this array
-    const int ny = p.dim[1] - ((kind == 2) ? 0 : 1);
-    const int nz = p.dim[2] - ((kind == 3) ? 0 : 1);
-    for (int k = 0; k < nz; ++k)
-      for (int j = 0; j < ny; ++j) {
-        int i = 0;
-        while (i < nx) {
+    int lo[3], hi[3];
+    for (int a = 0; a < 3; ++a) {
+      lo[a] = G - depth;
+      hi[a] = G + p.n[a] + depth + ((kind >= 1 && a == kind - 1) ? 1 : 0);
+    }
+    for (int k = lo[2]; k < hi[2]; ++k)
+      for (int j = lo[1]; j < hi[1]; ++j) {
+        int i = lo[0];
+        while (i < hi[0]) {
           const long long l = lin_of(p, i, j, k);
           if (arr[l] < 0 || is_own(p, kind, i, j, k)) {
             ++i;
@@ -248,7 +294,7 @@ void build_runs(amrx_hier* h, int pid) {
           const int sp = (int)(arr[l] >> 32);
           const long long sl = arr[l] & 0xffffffffLL;
           int len = 1;
-          while (i + len < nx && len < 64) {
+          while (i + len < hi[0]) {
             const long long l2 = l + len;
             if (arr[l2] < 0 || is_own(p, kind, i + len, j, k)) break;
             if ((int)(arr[l2] >> 32) != sp || (arr[l2] & 0xffffffffLL) != sl + len) break;
@@ -261,11 +307,35 @@ void build_runs(amrx_hier* h, int pid) {
           r.src_lin = (int)sl;
           r.len = len;
           r.kind = kind;
+          r.off = nelem;
+          r.pad = 0;
           h->runs.push_back(r);
+          nelem += len;
+          comps += (double)len * (kind == 0 ? 5 : 1);
           i += len;
         }
       }
   }
+}
+
+CopyList make_copy_list(amrx_hier* h, const std::vector<int>& pids, int depth) {
+  CopyList L;
+  L.first_run = (int)h->runs.size();
+  int nelem = 0;
+  double comps = 0;
+  for (int pid : pids) build_runs(h, pid, depth, nelem, comps);
+  L.nrun = (int)h->runs.size() - L.first_run;
+  L.nelem = nelem;
+  L.comps = comps;
+  L.first_blk = (int)h->run_blk.size();
+  L.nblk = (nelem + AMRX_BLOCK - 1) / AMRX_BLOCK;
+  int r = 0;
+  for (int b = 0; b < L.nblk; ++b) {
+    const int e0 = b * AMRX_BLOCK;
+    while (r + 1 < L.nrun && h->runs[L.first_run + r + 1].off <= e0) ++r;
+    h->run_blk.push_back(r);
+  }
+  return L;
 }
 
 void build_pros(amrx_hier* h, int pid) {
@@ -484,14 +554,13 @@ int finalize_impl(amrx_hier* h) {
 
   // per level lists
   for (int l = 0; l < h->nlev; ++l) {
-    // ghost copy runs
-    h->copy_b[l].first = (int)h->runs.size();
-    for (int id : h->lev[l]) {
-      h->copy_p[id].first = (int)h->runs.size();
-      build_runs(h, id);
-      h->copy_p[id].count = (int)h->runs.size() - h->copy_p[id].first;
+    // ghost copy runs: 4 layers before substep 0 of a refined level, else 2 layers
+    for (int cls = 0; cls < 2; ++cls) {
+      if (l == 0 && cls == 0) continue;
+      const int depth = cls == 0 ? G : NG;
+      h->copy_b[l][cls] = make_copy_list(h, h->lev[l], depth);
+      for (int id : h->lev[l]) h->copy_p[id][cls] = make_copy_list(h, std::vector<int>{id}, depth);
     }
-    h->copy_b[l].count = (int)h->runs.size() - h->copy_b[l].first;
     // prolongation
     h->pro_b[l].first = (int)h->pros.size();
     if (l > 0)
@@ -627,6 +696,7 @@ int finalize_impl(amrx_hier* h) {
   h->off_tasks = o; o = align256(o + sizeof(Task) * h->tasks.size());
   h->off_blk = o; o = align256(o + sizeof(int) * h->blk.size());
   h->off_runs = o; o = align256(o + sizeof(Run) * h->runs.size());
+  h->off_runblk = o; o = align256(o + sizeof(int) * h->run_blk.size());
   h->off_pros = o; o = align256(o + sizeof(Pro) * h->pros.size());
   h->off_fcorr = o; o = align256(o + sizeof(Corr) * h->fcorrs.size());
   h->off_ecorr = o; o = align256(o + sizeof(Corr) * h->ecorrs.size());
@@ -653,6 +723,7 @@ DevCtx make_ctx(amrx_hier* h) {
   c.tasks = (const Task*)(s + h->off_tasks);
   c.blk = (const int*)(s + h->off_blk);
   c.runs = (const Run*)(s + h->off_runs);
+  c.run_blk = (const int*)(s + h->off_runblk);
   c.pros = (const Pro*)(s + h->off_pros);
   c.corrs = nullptr;
   c.syncs = (const SyncPair*)(s + h->off_sync);
@@ -671,18 +742,23 @@ DevCtx make_ctx(amrx_hier* h) {
 int do_ghost_fill(amrx_hier* h, int level, int substep, bool plain) {
   DevCtx& c = h->ctx;
   const int cur = h->cur[level];
+  const int cls = (level > 0 && substep == 0) ? 0 : 1;
   if (plain) {
-    for (int id : h->lev[level]) HIPCHK(launch_copy(c, h->copy_p[id].first, h->copy_p[id].count, cur), "ghost copy");
+    for (int id : h->lev[level]) {
+      const CopyList& L = h->copy_p[id][cls];
+      HIPCHK(TIMED(AMRX_K_COPY, launch_copy(c, L.first_run, L.nrun, L.first_blk, L.nblk, L.nelem, cur)), "ghost copy");
+    }
   } else {
-    HIPCHK(launch_copy(c, h->copy_b[level].first, h->copy_b[level].count, cur), "ghost copy");
+    const CopyList& L = h->copy_b[level][cls];
+    HIPCHK(TIMED(AMRX_K_COPY, launch_copy(c, L.first_run, L.nrun, L.first_blk, L.nblk, L.nelem, cur)), "ghost copy");
   }
   if (level > 0 && substep == 0) {
     const int old_parent = 1 - h->cur[level - 1];
     if (plain) {
       for (int id : h->lev[level])
-        HIPCHK(launch_prolong(c, h->pro_p[id].first, h->pro_p[id].count, cur, old_parent), "prolongation");
+        HIPCHK(TIMED(AMRX_K_PROLONG, launch_prolong(c, h->pro_p[id].first, h->pro_p[id].count, cur, old_parent)), "prolongation");
     } else {
-      HIPCHK(launch_prolong(c, h->pro_b[level].first, h->pro_b[level].count, cur, old_parent), "prolongation");
+      HIPCHK(TIMED(AMRX_K_PROLONG, launch_prolong(c, h->pro_b[level].first, h->pro_b[level].count, cur, old_parent)), "prolongation");
     }
   }
   return AMRX_OK;
@@ -695,11 +771,11 @@ int do_advance(amrx_hier* h, int level, double dt, int substep, bool plain) {
     if (plain) {
       for (int id : h->lev[level]) {
         const TaskList& T = h->stage_p[id][substep][stg];
-        HIPCHK(launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep, dt), "advance stage");
+        HIPCHK(TIMED(AMRX_K_PRIM + stg, launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep, dt)), "advance stage");
       }
     } else {
       const TaskList& T = h->stage_b[level][substep][stg];
-      HIPCHK(launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep, dt), "advance stage");
+      HIPCHK(TIMED(AMRX_K_PRIM + stg, launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep, dt)), "advance stage");
     }
   }
   h->cur[level] = 1 - cur;
@@ -712,21 +788,21 @@ int do_restrict(amrx_hier* h, int fine, bool plain) {
   if (plain) {
     for (int id : h->lev[fine]) {
       const TaskList& T = h->restr_p[id];
-      HIPCHK(launch_restrict(c, T.first, T.count, 0, T.nblk, cf, cc), "restriction");
+      HIPCHK(TIMED(AMRX_K_RESTRICT, launch_restrict(c, T.first, T.count, 0, T.nblk, cf, cc)), "restriction");
     }
     for (int id : h->lev[fine - 1]) {
       c.corrs = (const Corr*)(h->scratch + h->off_fcorr);
-      HIPCHK(launch_flux_corr(c, h->fcorr_p[id].first, h->fcorr_p[id].count, cc), "flux correction");
+      HIPCHK(TIMED(AMRX_K_FLUXCORR, launch_flux_corr(c, h->fcorr_p[id].first, h->fcorr_p[id].count, cc)), "flux correction");
       c.corrs = (const Corr*)(h->scratch + h->off_ecorr);
-      HIPCHK(launch_emf_corr(c, h->ecorr_p[id].first, h->ecorr_p[id].count, cc), "EMF correction");
+      HIPCHK(TIMED(AMRX_K_EMFCORR, launch_emf_corr(c, h->ecorr_p[id].first, h->ecorr_p[id].count, cc)), "EMF correction");
     }
   } else {
     const TaskList& T = h->restr_b[fine];
-    HIPCHK(launch_restrict(c, T.first, T.count, 0, T.nblk, cf, cc), "restriction");
+    HIPCHK(TIMED(AMRX_K_RESTRICT, launch_restrict(c, T.first, T.count, 0, T.nblk, cf, cc)), "restriction");
     c.corrs = (const Corr*)(h->scratch + h->off_fcorr);
-    HIPCHK(launch_flux_corr(c, h->fcorr_b[fine - 1].first, h->fcorr_b[fine - 1].count, cc), "flux correction");
+    HIPCHK(TIMED(AMRX_K_FLUXCORR, launch_flux_corr(c, h->fcorr_b[fine - 1].first, h->fcorr_b[fine - 1].count, cc)), "flux correction");
     c.corrs = (const Corr*)(h->scratch + h->off_ecorr);
-    HIPCHK(launch_emf_corr(c, h->ecorr_b[fine - 1].first, h->ecorr_b[fine - 1].count, cc), "EMF correction");
+    HIPCHK(TIMED(AMRX_K_EMFCORR, launch_emf_corr(c, h->ecorr_b[fine - 1].first, h->ecorr_b[fine - 1].count, cc)), "EMF correction");
   }
   return AMRX_OK;
 }
@@ -735,9 +811,9 @@ int do_sync(amrx_hier* h, int level, bool plain) {
   DevCtx& c = h->ctx;
   const int cur = h->cur[level];
   if (plain) {
-    for (int id : h->lev[level]) HIPCHK(launch_sync(c, h->sync_p[id].first, h->sync_p[id].count, cur), "sync");
+    for (int id : h->lev[level]) HIPCHK(TIMED(AMRX_K_SYNC, launch_sync(c, h->sync_p[id].first, h->sync_p[id].count, cur)), "sync");
   } else {
-    HIPCHK(launch_sync(c, h->sync_b[level].first, h->sync_b[level].count, cur), "sync");
+    HIPCHK(TIMED(AMRX_K_SYNC, launch_sync(c, h->sync_b[level].first, h->sync_b[level].count, cur)), "sync");
   }
   return AMRX_OK;
 }
@@ -780,7 +856,7 @@ int cfl_impl(amrx_hier* h, double* dt0) {
   HIPCHK(launch_clear_slots(c), "clear slots");
   for (int l = 0; l < h->nlev; ++l) {
     const TaskList& T = h->cfl_b[l];
-    HIPCHK(launch_cfl(c, T.first, T.count, 0, T.nblk, h->cur[l], l), "cfl");
+    HIPCHK(TIMED(AMRX_K_CFL, launch_cfl(c, T.first, T.count, 0, T.nblk, h->cur[l], l)), "cfl");
   }
   unsigned long long sl[NSLOT];
   int rc = read_slots(h, sl);
@@ -924,6 +1000,7 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
   put(h->off_tasks, h->tasks.data(), sizeof(Task) * h->tasks.size());
   put(h->off_blk, h->blk.data(), sizeof(int) * h->blk.size());
   put(h->off_runs, h->runs.data(), sizeof(Run) * h->runs.size());
+  put(h->off_runblk, h->run_blk.data(), sizeof(int) * h->run_blk.size());
   put(h->off_pros, h->pros.data(), sizeof(Pro) * h->pros.size());
   put(h->off_fcorr, h->fcorrs.data(), sizeof(Corr) * h->fcorrs.size());
   put(h->off_ecorr, h->ecorrs.data(), sizeof(Corr) * h->ecorrs.size());
@@ -987,7 +1064,7 @@ int hier_conservation(amrx_hier* h, double sum[8], double comp[8]) {
   if (!ready(h)) return AMRX_ESTATE;
   if (!sum || !comp) return AMRX_EINVAL;
   const TaskList& T = h->cons_all;
-  HIPCHK(launch_conservation(h->ctx, T.first, T.count, 0, T.nblk, h->cur), "conservation");
+  HIPCHK(TIMED(AMRX_K_CONS, launch_conservation(h->ctx, T.first, T.count, 0, T.nblk, h->cur)), "conservation");
   double buf[16];
   HIPCHK(hipMemcpyAsync(buf, h->scratch + h->off_partials + sizeof(double) * 16 * (size_t)T.nblk, sizeof buf,
                         hipMemcpyDeviceToHost, (hipStream_t)h->d.stream),
@@ -1008,6 +1085,84 @@ int hier_diag(amrx_hier* h, double* out, int n) {
   if (rc) return rc;
   const double v[3] = {bits_to_double(sl[SLOT_SYNC_F]), bits_to_double(sl[SLOT_SYNC_B]), sl[SLOT_PHYS] ? 1.0 : 0.0};
   for (int i = 0; i < n; ++i) out[i] = v[i];
+  return AMRX_OK;
+}
+
+int hier_timing_enable(amrx_hier* h, int on) {
+  if (!h) return AMRX_EINVAL;
+  if (on) {
+    h->ev_used = 0;
+    h->ev_marks.clear();
+  }
+  h->timing = on != 0;
+  return AMRX_OK;
+}
+
+int hier_timing_read(amrx_hier* h, int n, double* total_ms, int* launches) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (!total_ms || !launches || n < 0 || n > AMRX_NKCLASS) return AMRX_EINVAL;
+  HIPCHK(hipStreamSynchronize((hipStream_t)h->d.stream), "stream synchronize");
+  for (int i = 0; i < n; ++i) {
+    total_ms[i] = 0.0;
+    launches[i] = 0;
+  }
+  for (const auto& m : h->ev_marks) {
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, h->ev_pool[m.second], h->ev_pool[m.second + 1]), "event elapsed time");
+    if (m.first < n) {
+      total_ms[m.first] += ms;
+      launches[m.first] += 1;
+    }
+  }
+  return AMRX_OK;
+}
+
+int hier_step_work(const amrx_hier* h, int n, double* units, int* launches) {
+  if (!h || !units || !launches || n < 0 || n > AMRX_NKCLASS) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  double u[AMRX_NKCLASS] = {0};
+  int nl[AMRX_NKCLASS] = {0};
+  auto task_units = [&](const TaskList& T) {
+    double v = 0;
+    for (int t = T.first; t < T.first + T.count; ++t) {
+      const Task& k = h->tasks[t];
+      v += (double)(k.hi[0] - k.lo[0]) * (k.hi[1] - k.lo[1]) * (k.hi[2] - k.lo[2]);
+    }
+    return v;
+  };
+  for (int l = 0; l < h->nlev; ++l) {
+    const int nsub = l == 0 ? 1 : R;
+    const double per_sub = l == 0 ? 1.0 : (double)(1 << (l - 1));  // executions of each substep
+    for (int s = 0; s < nsub; ++s) {
+      for (int stg = 0; stg < NSTAGE; ++stg) {
+        u[AMRX_K_PRIM + stg] += per_sub * task_units(h->stage_b[l][s][stg]);
+        nl[AMRX_K_PRIM + stg] += (int)per_sub;
+      }
+      const int cls = (l > 0 && s == 0) ? 0 : 1;
+      u[AMRX_K_COPY] += per_sub * h->copy_b[l][cls].comps;
+      nl[AMRX_K_COPY] += (int)per_sub;
+      if (l > 0 && s == 0) {
+        u[AMRX_K_PROLONG] += per_sub * h->pro_b[l].count;
+        nl[AMRX_K_PROLONG] += (int)per_sub;
+      }
+      if (l + 1 < h->nlev) {
+        u[AMRX_K_RESTRICT] += per_sub * task_units(h->restr_b[l + 1]);
+        u[AMRX_K_FLUXCORR] += per_sub * h->fcorr_b[l].count;
+        u[AMRX_K_EMFCORR] += per_sub * h->ecorr_b[l].count;
+        nl[AMRX_K_RESTRICT] += (int)per_sub;
+        nl[AMRX_K_FLUXCORR] += (int)per_sub;
+        nl[AMRX_K_EMFCORR] += (int)per_sub;
+      }
+      u[AMRX_K_SYNC] += per_sub * h->sync_b[l].count;
+      nl[AMRX_K_SYNC] += (int)per_sub;
+    }
+    u[AMRX_K_CFL] += task_units(h->cfl_b[l]);
+    nl[AMRX_K_CFL] += 1;
+  }
+  for (int i = 0; i < n; ++i) {
+    units[i] = u[i];
+    launches[i] = nl[i];
+  }
   return AMRX_OK;
 }
 

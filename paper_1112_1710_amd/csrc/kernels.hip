@@ -696,26 +696,32 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int 
 }
 
 // ---------------------------------------------------------------------------
-// same-level ghost copy: 64 lanes per run (one wavefront)
+// same-level ghost copy: one thread per copied entry; runs are consecutive
+// along x so neighbouring lanes read and write neighbouring addresses
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_copy(DevCtx c, int first, int n, int cur) {
-  const long long gid = (long long)blockIdx.x * AMRX_BLOCK + threadIdx.x;
-  const long long run = gid >> 6;
-  const int lane = (int)(gid & 63);
-  if (run >= n) return;
-  const Run& r = c.runs[first + run];
-  if (lane >= r.len) return;
+__global__ __launch_bounds__(AMRX_BLOCK) void k_copy(DevCtx c, int first, int n, int blk_first, int nelem, int cur) {
+  const int e = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  if (e >= nelem) return;
+  // the block's first run, then a binary search over the runs it can touch
+  int lo = c.run_blk[blk_first + blockIdx.x];
+  int hi = min(n - 1, lo + AMRX_BLOCK);
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (c.runs[first + mid].off <= e) lo = mid; else hi = mid - 1;
+  }
+  const Run& r = c.runs[first + lo];
+  const int k = e - r.off;
   const PatchDev& dp = c.patches[r.dst_patch];
   const PatchDev& sp = c.patches[r.src_patch];
   R* dst = (R*)c.state + dp.st[cur];
   const R* src = (const R*)c.state + sp.st[cur];
   if (r.kind == 0) {
 #pragma unroll
-    for (int m = 0; m < 5; ++m) dst[m * dp.vol + r.dst_lin + lane] = src[m * sp.vol + r.src_lin + lane];
+    for (int m = 0; m < 5; ++m) dst[m * dp.vol + r.dst_lin + k] = src[m * sp.vol + r.src_lin + k];
   } else {
     const int m = 4 + r.kind;
-    dst[m * dp.vol + r.dst_lin + lane] = src[m * sp.vol + r.src_lin + lane];
+    dst[m * dp.vol + r.dst_lin + k] = src[m * sp.vol + r.src_lin + k];
   }
 }
 
@@ -990,11 +996,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_sync(DevCtx c, int first, int n,
     delta[m] = 0.5 * (fb - fa);
     worst = fmax(worst, fabs(fb - fa));
   }
-  atomic_max_pos(&c.slots[SLOT_SYNC_F], worst);
+  if (!(worst == 0.0)) atomic_max_pos(&c.slots[SLOT_SYNC_F], worst);
   const R* Ua = (const R*)c.state + pa.st[cur];
   const R* Ub = (const R*)c.state + pb.st[cur];
   const double bd = fabs((double)Ua[(5 + s.axis) * pa.vol + s.a_face] - (double)Ub[(5 + s.axis) * pb.vol + s.b_face]);
-  atomic_max_pos(&c.slots[SLOT_SYNC_B], bd);
+  if (!(bd == 0.0)) atomic_max_pos(&c.slots[SLOT_SYNC_B], bd);
   if (worst > 0.0) {
     R* U = (R*)c.state + pa.st[cur];
     for (int m = 0; m < 5; ++m) {
@@ -1007,15 +1013,29 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_sync(DevCtx c, int first, int n,
 // ---------------------------------------------------------------------------
 // CFL signal speed: max over interior cells of sum_d (|v_d| + c_f,d) / dx
 // ---------------------------------------------------------------------------
+// Grid-stride over the list's blocks; one atomic per block on the level's slot.
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_cfl(DevCtx c, int first, int n, int cur, int level) {
-  Where w;
+__global__ __launch_bounds__(AMRX_BLOCK) void k_cfl(DevCtx c, int first, int n, int nblk, int cur, int level) {
+  __shared__ double red[AMRX_BLOCK / 64];
   double s = 0.0;
-  if (locate(c, first, n, w)) {
-    const PatchDev& p = c.patches[c.tasks[w.task].patch];
+  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (c.blk[first + mid] <= b) lo = mid; else hi = mid - 1;
+    }
+    const int t = first + lo;
+    const Task& T = c.tasks[t];
+    const long long ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
+    const long long local = (long long)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
+    if (local >= ex * ey * ez) continue;
+    const int i = T.lo[0] + (int)(local % ex);
+    const int j = T.lo[1] + (int)((local / ex) % ey);
+    const int k = T.lo[2] + (int)(local / (ex * ey));
+    const PatchDev& p = c.patches[T.patch];
     const Strides S = strides(p);
     const R* U = (const R*)c.state + p.st[cur];
-    const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+    const long long q = i + j * S.s[1] + k * S.s[2];
     const long long v = S.v;
     const R gamma = R(c.gamma);
     const R rho = U[q];
@@ -1029,13 +1049,19 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_cfl(DevCtx c, int first, int n, 
     const R tot = (fabs(vx) + fast_speed(rho, pr, b2, bx * bx, gamma)) * inv +
                   (fabs(vy) + fast_speed(rho, pr, b2, by * by, gamma)) * inv +
                   (fabs(vz) + fast_speed(rho, pr, b2, bz * bz, gamma)) * inv;
-    s = (double)tot;
-    if (!(rho > R(0)) || !(pr > R(0)) || !isfinite(s)) flag_phys(c.slots);
-    if (!isfinite(s)) s = 1.0e308;
+    double sv = (double)tot;
+    if (!(rho > R(0)) || !(pr > R(0)) || !isfinite(sv)) flag_phys(c.slots);
+    if (!isfinite(sv)) sv = 1.0e308;
+    s = fmax(s, sv);
   }
-  // wavefront max then one atomic per wavefront
   for (int off = 32; off > 0; off >>= 1) s = fmax(s, __shfl_xor(s, off, 64));
-  if ((threadIdx.x & 63) == 0) atomic_max_pos(&c.slots[SLOT_SMAX + level], s);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0];
+    for (int w = 1; w < AMRX_BLOCK / 64; ++w) m = fmax(m, red[w]);
+    if (m > 0.0) atomic_max_pos(&c.slots[SLOT_SMAX + level], m);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1174,9 +1200,9 @@ hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, i
   return hipGetLastError();
 }
 
-hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int cur) {
-  if (nrun == 0) return hipSuccess;
-  DISPATCH_R(k_copy, dim3(grid_of((long long)nrun * 64, AMRX_BLOCK)), c, run_first, nrun, cur);
+hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int blk_first, int nblk, int nelem, int cur) {
+  if (nrun == 0 || nblk == 0) return hipSuccess;
+  DISPATCH_R(k_copy, dim3(nblk), c, run_first, nrun, blk_first, nelem, cur);
   return hipGetLastError();
 }
 
@@ -1215,7 +1241,7 @@ hipError_t launch_sync(const DevCtx& c, int first, int n, int cur) {
 hipError_t launch_cfl(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk, int cur, int level) {
   (void)blk_first;
   if (ntask == 0 || nblk == 0) return hipSuccess;
-  DISPATCH(k_cfl, dim3(nblk), c, task_first, ntask, cur, level);
+  DISPATCH(k_cfl, dim3(nblk < 2048 ? nblk : 2048), c, task_first, ntask, nblk, cur, level);
   return hipGetLastError();
 }
 

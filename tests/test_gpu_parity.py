@@ -137,8 +137,20 @@ def _id_fields(o):
         p.faces = [base + lin + 0.5 + 0.0625 * d for d in range(3)]
 
 
+def _depth_mask(shape, n, depth, axis=None):
+    """Padded entries within `depth` ghost layers of the interior (closure along `axis` for faces)."""
+    m = np.zeros(shape, dtype=bool)
+    hi = [G + int(x) + depth for x in n]
+    if axis is not None:
+        hi[axis] += 1
+    m[G - depth:hi[2], G - depth:hi[1], G - depth:hi[0]] = True
+    return m
+
+
 @pytest.mark.parametrize("name", ["small_three_level", "root_tiled"])
 def test_ghost_copy_bit_exact(name):
+    """Same-level ghost copies equal the oracle's source maps bit for bit: 2 layers on level 0 and
+    before substep 1, all 4 layers before substep 0 of a refined level."""
     spec = getattr(H, name)()
     _say("ghost copy", name)
     o = amr.build(spec)
@@ -146,18 +158,29 @@ def test_ghost_copy_bit_exact(name):
     h = Hierarchy(spec, FP64)
     upload_oracle_state(h, o)
     for lv in range(o.nlevels):
-        s = 0 if lv == 0 else 1   # substep >= 1: same-level copies only (no prolongation)
+        s = 0 if lv == 0 else 1
         h.ghost_fill(lv, s)
         o.ghost_fill(lv, s)
     h.synchronize()
-    for pid, p in enumerate(o.patches):
-        cells, faces = h.download(pid)
-        csrc = o.cell_src[pid]
-        m = csrc >= 0
-        assert np.array_equal(cells[:, m], p.cells[:, m])
-        for d in range(3):
-            fm = o.face_src[pid][d] >= 0
-            assert np.array_equal(faces[d][fm], p.faces[d][fm])
+
+    def check(depth_of):
+        for pid, p in enumerate(o.patches):
+            depth = depth_of(p)
+            cells, faces = h.download(pid)
+            m = (o.cell_src[pid] >= 0) & _depth_mask(p.shape, p.n, depth)
+            assert np.array_equal(cells[:, m], p.cells[:, m])
+            for d in range(3):
+                fm = (o.face_src[pid][d] >= 0) & _depth_mask(p.shape, p.n, depth, d)
+                assert np.array_equal(faces[d][fm], p.faces[d][fm])
+
+    check(lambda p: 2)
+    if o.nlevels > 1:
+        for lv in range(1, o.nlevels):
+            h.ghost_fill(lv, 0)
+            for p in o.level_patches(lv):
+                o._copy_from_sources(p)
+        h.synchronize()
+        check(lambda p: 2 if p.level == 0 else 4)
 
 
 def test_prolongation_parity():
