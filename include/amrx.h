@@ -175,7 +175,7 @@ int hier_diag(amrx_hier* h, double* out, int n);
 
 /* Kernel classes reported by hier_timing_read (one slot each). */
 enum {
-  AMRX_K_PRIM = 0, AMRX_K_PRED, AMRX_K_BHALF, AMRX_K_EREF, AMRX_K_FLUX, AMRX_K_EDGE, AMRX_K_UPDATE,
+  AMRX_K_PRIM = 0, AMRX_K_BHALF, AMRX_K_PRED, AMRX_K_FLUX, AMRX_K_EDGE, AMRX_K_UPDATE,
   AMRX_K_COPY, AMRX_K_PROLONG, AMRX_K_RESTRICT, AMRX_K_FLUXCORR, AMRX_K_EMFCORR, AMRX_K_SYNC,
   AMRX_K_CFL, AMRX_K_CONS, AMRX_NKCLASS
 };

@@ -13,7 +13,7 @@ FP64, FP32, FP32_MIXED = 0, 1, 2
 PLAIN, BATCHED, GRAPH = 0, 1, 2
 G = 4
 
-KERNEL_CLASSES = ("prim", "pred", "bhalf", "eref", "flux", "edge", "update", "copy", "prolong", "restrict",
+KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
                   "fluxcorr", "emfcorr", "sync", "cfl", "cons")
 
 _ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
@@ -99,7 +99,9 @@ class Hierarchy:
             import torch
             self._torch = torch
             if stream is None:
-                stream = torch.cuda.current_stream(torch.device(device))
+                # a stream of its own (default priority): every library call and every
+                # upload/download of this hierarchy is ordered on it; graph capture needs it
+                stream = torch.cuda.Stream(device=torch.device(device))
             self.stream = stream
             d.stream = C.c_void_p(stream.cuda_stream)
         else:
@@ -169,15 +171,17 @@ class Hierarchy:
         torch = self._torch
         views = self._views(pid, which)
         dt = views[0].dtype
-        for m in range(5):
-            views[m].copy_(torch.from_numpy(np.ascontiguousarray(cells[m])).to(dt))
-        for d in range(3):
-            views[5 + d].copy_(torch.from_numpy(np.ascontiguousarray(faces[d])).to(dt))
+        with torch.cuda.stream(self.stream):
+            for m in range(5):
+                views[m].copy_(torch.from_numpy(np.ascontiguousarray(cells[m])).to(dt))
+            for d in range(3):
+                views[5 + d].copy_(torch.from_numpy(np.ascontiguousarray(faces[d])).to(dt))
 
     def download(self, pid, which=None):
         """(cells (5, Z, Y, X), [bx, by, bz]) of a patch as float64 NumPy arrays."""
         views = self._views(pid, which)
-        arrs = [v.double().cpu().numpy() for v in views]
+        with self._torch.cuda.stream(self.stream):
+            arrs = [v.double().cpu().numpy() for v in views]
         return np.stack(arrs[:5]), arrs[5:]
 
     def set_field(self, field):

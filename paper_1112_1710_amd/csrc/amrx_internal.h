@@ -11,17 +11,21 @@
 #define AMRX_MAXLEV 16
 #define AMRX_BLOCK 256  // threads per block of the stage kernels (4 wavefronts)
 
-// Number of real-valued intermediate arrays per patch (each of the patch's
-// node-padded volume) used by the staged advance.
+// Intermediates of the staged advance, per patch, in units of the patch's
+// node-padded volume V.  Quantities consumed as whole records are interleaved
+// per entry (read with 16-byte vector loads); quantities consumed one
+// component at a time are plain arrays.
 #define AMRX_NSCR 49
 enum {
-  SCR_W = 0,    // 8 primitives at t^n
-  SCR_EC = 8,   // 3 cell EMFs at t^n
-  SCR_DU = 11,  // 8 Hancock half-step increments
-  SCR_BH = 19,  // 3 face-normal fields at t^{n+1/2}
-  SCR_ER = 22,  // 3 cell reference EMFs at t^{n+1/2}
-  SCR_F = 25,   // 3 axes x 7: 5 cell fluxes, EMF along (d+2)%3, EMF along (d+1)%3
-  SCR_E = 46    // 3 edge EMFs
+  SCR_W = 0,     // 8 per cell, interleaved: primitives at t^n (rho, vx, vy, vz, p, Bx, By, Bz)
+  SCR_DU = 8,    // 8 per cell, interleaved: Hancock half-step increments of the 8 conserved components
+  SCR_F4 = 16,   // 3 axes x 4 per face, interleaved: momentum and energy fluxes (m_x, m_y, m_z, E)
+  SCR_F0 = 28,   // 3 arrays: mass flux through the faces normal to each axis
+  SCR_FE = 31,   // 3 axes x 2 arrays: face EMF along (d+2)%3, face EMF along (d+1)%3
+  SCR_EC = 37,   // 3 arrays: cell EMFs at t^n
+  SCR_BH = 40,   // 3 arrays: face-normal field at t^{n+1/2}
+  SCR_ER = 43,   // 3 arrays: cell reference EMFs at t^{n+1/2}
+  SCR_E = 46     // 3 arrays: edge EMFs
 };
 
 struct PatchDev {
@@ -160,13 +164,16 @@ struct DevCtx {
   hipStream_t stream;
 };
 
-enum { STAGE_PRIM = 0, STAGE_PRED, STAGE_BHALF, STAGE_EREF, STAGE_FLUX, STAGE_EDGE, STAGE_UPDATE, NSTAGE };
+enum { STAGE_PRIM = 0, STAGE_BHALF, STAGE_PRED, STAGE_FLUX, STAGE_EDGE, STAGE_UPDATE, NSTAGE };
 
 // slot indices in DevCtx::slots
-enum { SLOT_PHYS = 0, SLOT_SYNC_F = 1, SLOT_SYNC_B = 2, SLOT_SMAX = 8 /* + level */, NSLOT = 8 + AMRX_MAXLEV };
+// SLOT_DT holds the root time step dt0 (double bits); level l uses dt0 * 2^-l.
+enum { SLOT_PHYS = 0, SLOT_SYNC_F = 1, SLOT_SYNC_B = 2, SLOT_DT = 3, SLOT_SMAX = 8 /* + level */, NSLOT = 8 + AMRX_MAXLEV };
 
 hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, int blk_first, int nblk,
-                        int cur, int level, int substep, double dt);
+                        int cur, int level, int substep);
+hipError_t launch_set_dt(const DevCtx& c, double dt0);
+hipError_t launch_dt_from_cfl(const DevCtx& c, int nlev, double cfl);
 hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int blk_first, int nblk, int nelem, int cur);
 hipError_t launch_prolong(const DevCtx& c, int first, int n, int cur_fine, int old_parent);
 hipError_t launch_restrict(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk, int cur_fine,

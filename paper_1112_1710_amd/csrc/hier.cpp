@@ -8,9 +8,11 @@
 // device except through the launchers of kernels.hip.
 
 #include <algorithm>
+#include <cmath>
 #include <array>
 #include <cstdio>
 #include <cstring>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -32,6 +34,12 @@ struct Range {
 struct CopyList {
   int first_run = 0, nrun = 0, first_blk = 0, nblk = 0, nelem = 0;
   double comps = 0;  // copied array elements (cells count 5)
+};
+
+struct GraphEntry {
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  int cur_after[AMRX_MAXLEV] = {0};
 };
 
 struct HPatch {
@@ -97,12 +105,19 @@ struct amrx_hier {
   DevCtx ctx{};
   int cur[AMRX_MAXLEV] = {0};
 
+  // captured root steps of the graph schedule
+  std::map<unsigned, GraphEntry> graphs;
+
   // launch timing (measurement support)
   bool timing = false;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   std::vector<std::pair<int, size_t>> ev_marks;  // (kernel class, index of the start event)
   ~amrx_hier() {
+    for (auto& g : graphs) {
+      if (g.second.exec) (void)hipGraphExecDestroy(g.second.exec);
+      if (g.second.graph) (void)hipGraphDestroy(g.second.graph);
+    }
     for (hipEvent_t e : ev_pool) (void)hipEventDestroy(e);
   }
 };
@@ -192,8 +207,7 @@ void stage_regions(int stage, int axis, const int lo[3], const int hi[3], int rl
   for (int a = 0; a < 3; ++a) {
     switch (stage) {
       case STAGE_PRIM: rlo[a] = lo[a] - 2; rhi[a] = hi[a] + 2; break;
-      case STAGE_PRED:
-      case STAGE_EREF: rlo[a] = lo[a] - 1; rhi[a] = hi[a] + 1; break;
+      case STAGE_PRED: rlo[a] = lo[a] - 1; rhi[a] = hi[a] + 1; break;
       case STAGE_BHALF: rlo[a] = lo[a] - 1; rhi[a] = hi[a] + 2; break;
       case STAGE_FLUX:
         if (a == axis) { rlo[a] = lo[a]; rhi[a] = hi[a] + 1; }
@@ -504,7 +518,7 @@ int finalize_impl(amrx_hier* h) {
       d.st[1] = st + 8 * p.vol;
       st += 16 * p.vol;
       d.scr = rscr;
-      rscr += (long long)AMRX_NSCR * p.vol;
+      rscr += ((long long)AMRX_NSCR * p.vol + 7) / 8 * 8;  // keep every patch's records 32-byte aligned
       d.fsize = face_reg_size(p.n);
       d.esize = edge_reg_size(p.n);
       d.freg = reg;
@@ -765,17 +779,18 @@ int do_ghost_fill(amrx_hier* h, int level, int substep, bool plain) {
 }
 
 int do_advance(amrx_hier* h, int level, double dt, int substep, bool plain) {
+  (void)dt;  // the kernels read dt0 from the device slot and scale it by 2^-level
   DevCtx& c = h->ctx;
   const int cur = h->cur[level];
   for (int stg = 0; stg < NSTAGE; ++stg) {
     if (plain) {
       for (int id : h->lev[level]) {
         const TaskList& T = h->stage_p[id][substep][stg];
-        HIPCHK(TIMED(AMRX_K_PRIM + stg, launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep, dt)), "advance stage");
+        HIPCHK(TIMED(AMRX_K_PRIM + stg, launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep)), "advance stage");
       }
     } else {
       const TaskList& T = h->stage_b[level][substep][stg];
-      HIPCHK(TIMED(AMRX_K_PRIM + stg, launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep, dt)), "advance stage");
+      HIPCHK(TIMED(AMRX_K_PRIM + stg, launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep)), "advance stage");
     }
   }
   h->cur[level] = 1 - cur;
@@ -851,24 +866,95 @@ double bits_to_double(unsigned long long b) {
   return d;
 }
 
-int cfl_impl(amrx_hier* h, double* dt0) {
+// Enqueue: CFL reductions of every level and the device-side dt0 (slots must be clear).
+int enqueue_cfl(amrx_hier* h) {
   DevCtx& c = h->ctx;
-  HIPCHK(launch_clear_slots(c), "clear slots");
   for (int l = 0; l < h->nlev; ++l) {
     const TaskList& T = h->cfl_b[l];
     HIPCHK(TIMED(AMRX_K_CFL, launch_cfl(c, T.first, T.count, 0, T.nblk, h->cur[l], l)), "cfl");
   }
+  HIPCHK(launch_dt_from_cfl(c, h->nlev, h->d.cfl), "dt from cfl");
+  return AMRX_OK;
+}
+
+// Read dt0 and the unphysical-state flag after the stream drained.
+int finish_step(amrx_hier* h, double* dt0) {
   unsigned long long sl[NSLOT];
   int rc = read_slots(h, sl);
   if (rc) return rc;
+  if (dt0) *dt0 = bits_to_double(sl[SLOT_DT]);
   if (sl[SLOT_PHYS]) return fail(h, AMRX_EPHYS, "unphysical state (rho<=0, p<=0 or non-finite)");
-  double best = 1e300;
-  for (int l = 0; l < h->nlev; ++l) {
-    const double smax = bits_to_double(sl[SLOT_SMAX + l]);
-    if (smax > 0.0) best = std::min(best, (double)(1 << l) * h->d.cfl / smax);
-  }
-  *dt0 = best;
   return AMRX_OK;
+}
+
+int cfl_impl(amrx_hier* h, double* dt0) {
+  HIPCHK(launch_clear_slots(h->ctx), "clear slots");
+  int rc = enqueue_cfl(h);
+  if (rc) return rc;
+  return finish_step(h, dt0);
+}
+
+// Enqueue one root step; dt0 > 0 fixes the step, otherwise it comes from the CFL condition.
+int enqueue_step(amrx_hier* h, bool plain, double dt0) {
+  HIPCHK(launch_clear_slots(h->ctx), "clear slots");
+  if (dt0 > 0.0) {
+    HIPCHK(launch_set_dt(h->ctx, dt0), "set dt");
+  } else {
+    const int rc = enqueue_cfl(h);
+    if (rc) return rc;
+  }
+  return amr_recursive(h, 0, dt0, plain);
+}
+
+unsigned parity_key(const amrx_hier* h) {
+  unsigned k = 0;
+  for (int l = 0; l < h->nlev; ++l) k |= (unsigned)(h->cur[l] & 1) << l;
+  return k;
+}
+
+// Graph schedule: the batched root step captured once per (buffer parities, dt source) and replayed.
+int graph_step(amrx_hier* h, double* dt0) {
+  hipStream_t s = (hipStream_t)h->d.stream;
+  if (!s) return fail(h, AMRX_EINVAL, "the graph schedule needs a non-default stream");
+  const bool fixed = *dt0 > 0.0;
+  const unsigned key = parity_key(h) * 2u + (fixed ? 1u : 0u);
+  auto it = h->graphs.find(key);
+  if (it == h->graphs.end()) {
+    int cur_before[AMRX_MAXLEV];
+    std::memcpy(cur_before, h->cur, sizeof cur_before);
+    const bool timing = h->timing;
+    h->timing = false;
+    HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+    int rc = AMRX_OK;
+    if (fixed) {
+      // dt0 comes from the slot set before each replay
+      rc = amr_recursive(h, 0, 0.0, false);
+    } else {
+      rc = enqueue_step(h, false, 0.0);
+    }
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(s, &g);
+    h->timing = timing;
+    if (rc || ec != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      std::memcpy(h->cur, cur_before, sizeof cur_before);
+      if (rc) return rc;
+      return fail(h, AMRX_EHIP, std::string("end capture: ") + hipGetErrorString(ec));
+    }
+    GraphEntry e;
+    e.graph = g;
+    std::memcpy(e.cur_after, h->cur, sizeof e.cur_after);
+    std::memcpy(h->cur, cur_before, sizeof cur_before);
+    HIPCHK(hipGraphInstantiate(&e.exec, g, nullptr, nullptr, 0), "graph instantiate");
+    it = h->graphs.emplace(key, e).first;
+  }
+  if (fixed) {
+    HIPCHK(launch_clear_slots(h->ctx), "clear slots");
+    HIPCHK(launch_set_dt(h->ctx, *dt0), "set dt");
+  }
+  HIPCHK(hipGraphLaunch(it->second.exec, s), "graph launch");
+  std::memcpy(h->cur, it->second.cur_after, sizeof h->cur);
+  return finish_step(h, dt0);
 }
 
 bool ready(amrx_hier* h) {
@@ -1026,6 +1112,7 @@ int advance_level(amrx_hier* h, int level, double dt_level, int substep) {
   if (!ready(h)) return AMRX_ESTATE;
   if (level < 0 || level >= h->nlev || substep < 0 || substep >= (level == 0 ? 1 : R) || !(dt_level > 0.0))
     return AMRX_EINVAL;
+  HIPCHK(launch_set_dt(h->ctx, std::ldexp(dt_level, level)), "set dt");
   return do_advance(h, level, dt_level, substep, false);
 }
 
@@ -1050,14 +1137,11 @@ int cfl_dt(amrx_hier* h, double* dt0) {
 int hier_step(amrx_hier* h, int mode, double* dt0) {
   if (!ready(h)) return AMRX_ESTATE;
   if (!dt0 || mode < AMRX_PLAIN || mode > AMRX_GRAPH) return AMRX_EINVAL;
-  if (!(*dt0 > 0.0)) {
-    const int rc = cfl_impl(h, dt0);
-    if (rc) return rc;
-  }
-  const int rc = amr_recursive(h, 0, *dt0, mode == AMRX_PLAIN);
+  if (!(*dt0 > 0.0)) *dt0 = 0.0;
+  if (mode == AMRX_GRAPH) return graph_step(h, dt0);
+  const int rc = enqueue_step(h, mode == AMRX_PLAIN, *dt0);
   if (rc) return rc;
-  HIPCHK(hipStreamSynchronize((hipStream_t)h->d.stream), "stream synchronize");
-  return AMRX_OK;
+  return finish_step(h, dt0);
 }
 
 int hier_conservation(amrx_hier* h, double sum[8], double comp[8]) {

@@ -263,6 +263,11 @@ __device__ __forceinline__ void atomic_max_pos(unsigned long long* slot, double 
 
 __device__ __forceinline__ void flag_phys(unsigned long long* slots) { atomicOr(&slots[SLOT_PHYS], 1ULL); }
 
+// time step of a level: dt0 (device slot) * 2^-level, exact
+__device__ __forceinline__ double level_dt(const DevCtx& c, int level) {
+  return ldexp(__longlong_as_double((long long)c.slots[SLOT_DT]), -level);
+}
+
 // ---------------------------------------------------------------------------
 // task lookup
 // ---------------------------------------------------------------------------
@@ -271,8 +276,16 @@ struct Where {
   int i, j, k;
 };
 
+// Workgroups are handed to the 8 XCDs round-robin; renumber them so that each
+// XCD (with its own L2) works on one contiguous range of logical blocks, i.e.
+// on a compact slab of the region, and stencil neighbours stay in its L2.
+__device__ __forceinline__ int xcd_block(int b, int nb) {
+  const int x = b & 7, i = b >> 3, q = nb >> 3, r = nb & 7;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
+}
+
 __device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, Where& w) {
-  const int b = blockIdx.x;
+  const int b = xcd_block(blockIdx.x, gridDim.x);
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -329,6 +342,31 @@ __device__ __forceinline__ Q reg_get(const Q* acc, const Q* lo, long long idx) {
   return MIX ? acc[idx] + lo[idx] : acc[idx];
 }
 
+// 16-byte vector access to the interleaved intermediates (records of 4 or 8 reals)
+__device__ __forceinline__ void ld4(const float* p, float* o) {
+  const float4 a = *(const float4*)p;
+  o[0] = a.x; o[1] = a.y; o[2] = a.z; o[3] = a.w;
+}
+__device__ __forceinline__ void ld4(const double* p, double* o) {
+  const double2 a = ((const double2*)p)[0], b = ((const double2*)p)[1];
+  o[0] = a.x; o[1] = a.y; o[2] = b.x; o[3] = b.y;
+}
+template <typename R>
+__device__ __forceinline__ void ld8(const R* p, R* o) {
+  ld4(p, o);
+  ld4(p + 4, o + 4);
+}
+__device__ __forceinline__ void st4(float* p, const float* v) { *(float4*)p = make_float4(v[0], v[1], v[2], v[3]); }
+__device__ __forceinline__ void st4(double* p, const double* v) {
+  ((double2*)p)[0] = make_double2(v[0], v[1]);
+  ((double2*)p)[1] = make_double2(v[2], v[3]);
+}
+template <typename R>
+__device__ __forceinline__ void st8(R* p, const R* v) {
+  st4(p, v);
+  st4(p + 4, v + 4);
+}
+
 // ---------------------------------------------------------------------------
 // stage 1: primitives and cell EMFs at t^n   (cells of the region grown by 2)
 // ---------------------------------------------------------------------------
@@ -350,31 +388,70 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_prim(DevCtx c, int first, int n,
   const R vx = mx / rho, vy = my / rho, vz = mz / rho;
   const R pr = pressure<R, MIX>(rho, mx, my, mz, e, bx, by, bz, gm1);
   if (!(rho > R(0)) || !(pr > R(0)) || !isfinite(e)) flag_phys(c.slots);
-  R* W = X + SCR_W * v;
-  W[q] = rho;
-  W[v + q] = vx;
-  W[2 * v + q] = vy;
-  W[3 * v + q] = vz;
-  W[4 * v + q] = pr;
-  W[5 * v + q] = bx;
-  W[6 * v + q] = by;
-  W[7 * v + q] = bz;
-  R* E = X + SCR_EC * v;
-  E[q] = -(vy * bz - vz * by);
-  E[v + q] = -(vz * bx - vx * bz);
-  E[2 * v + q] = -(vx * by - vy * bx);
+  const R wv[8] = {rho, vx, vy, vz, pr, bx, by, bz};
+  st8(X + SCR_W * v + 8 * q, wv);
+  R* EC = X + SCR_EC * v;
+  EC[q] = -(vy * bz - vz * by);
+  EC[v + q] = -(vz * bx - vx * bz);
+  EC[2 * v + q] = -(vx * by - vy * bx);
 }
 
 // ---------------------------------------------------------------------------
-// stage 2: limited slopes and the conservative Hancock half step (cells of the region grown by 1)
+// stage 2: face-normal field at t^{n+1/2} (faces of the cells of the region grown by 1)
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R ebar(const R* ec, long long q, long long sa, long long sc) {
+  return R(0.25) * (ec[q] + ec[q - sa] + ec[q - sc] + ec[q - sa - sc]);
+}
+
+template <int D, typename R>
+__device__ __forceinline__ R bhalf_axis(const R* U, const R* EC, const Strides& S, long long q, R half_dt_dx) {
+  constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
+  // edge-averaged cell EMFs: component C has in-plane axes (D, A); component A has (C, D)
+  const R* ecC = EC + C * S.v;
+  const R* ecA = EC + A * S.v;
+  const R eC0 = ebar(ecC, q, S.s[D], S.s[A]);
+  const R eC1 = ebar(ecC, q + S.s[A], S.s[D], S.s[A]);
+  const R eA0 = ebar(ecA, q, S.s[C], S.s[D]);
+  const R eA1 = ebar(ecA, q + S.s[C], S.s[C], S.s[D]);
+  const R curl = (eC1 - eC0) - (eA1 - eA0);
+  return U[(5 + D) * S.v + q] - half_dt_dx * curl;
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_bhalf(DevCtx c, int first, int n, int cur, int level) {
+  const double dt = level_dt(c, level);
+  Where w;
+  if (!locate(c, first, n, w)) return;
+  const Task& T = c.tasks[w.task];
+  const PatchDev& p = c.patches[T.patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  R* X = (R*)c.rscr + p.scr;
+  const R* EC = X + SCR_EC * S.v;
+  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+  const R h = R(0.5 * dt / p.dx);
+  // the task region is the node box [lo, hi]; the cell box is [lo, hi - 1]
+  const bool ix = w.i < T.hi[0] - 1, iy = w.j < T.hi[1] - 1, iz = w.k < T.hi[2] - 1;
+  R* BH = X + SCR_BH * S.v;
+  if (iy && iz) BH[q] = bhalf_axis<0>(U, EC, S, q, h);
+  if (ix && iz) BH[S.v + q] = bhalf_axis<1>(U, EC, S, q, h);
+  if (ix && iy) BH[2 * S.v + q] = bhalf_axis<2>(U, EC, S, q, h);
+}
+
+// ---------------------------------------------------------------------------
+// stage 3: limited slopes, conservative Hancock half step and the cell
+// reference EMF at t^{n+1/2} (cells of the region grown by 1)
 // ---------------------------------------------------------------------------
 template <int D, typename R>
-__device__ __forceinline__ void hancock_axis(const R* W, long long v, long long q, long long sd, const R* w0, R gm1,
-                                             R half_dt_dx, R* du) {
-  R wp[8], wm[8], f1[8], f2[8];
+__device__ __forceinline__ void hancock_axis(const R* W, long long q, long long sd, const R* w0, R gm1, R half_dt_dx,
+                                             R* du) {
+  R wm[8], wp[8], f1[8], f2[8];
+  ld8(W + 8 * (q - sd), wm);
+  ld8(W + 8 * (q + sd), wp);
 #pragma unroll
   for (int m = 0; m < 8; ++m) {
-    const R s = mc_limit(w0[m] - W[m * v + q - sd], W[m * v + q + sd] - w0[m]);
+    const R s = mc_limit(w0[m] - wm[m], wp[m] - w0[m]);
     wp[m] = w0[m] + R(0.5) * s;
     wm[m] = w0[m] - R(0.5) * s;
   }
@@ -385,11 +462,13 @@ __device__ __forceinline__ void hancock_axis(const R* W, long long v, long long 
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_pred(DevCtx c, int first, int n, int cur, double dt) {
+__global__ __launch_bounds__(AMRX_BLOCK) void k_pred(DevCtx c, int first, int n, int cur, int level) {
+  const double dt = level_dt(c, level);
   Where w;
   if (!locate(c, first, n, w)) return;
   const PatchDev& p = c.patches[c.tasks[w.task].patch];
   const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
   R* X = (R*)c.rscr + p.scr;
   const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
   const long long v = S.v;
@@ -397,80 +476,19 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_pred(DevCtx c, int first, int n,
   const R gm1 = R(c.gamma) - R(1);
   const R h = R(0.5 * dt / p.dx);
   R w0[8], du[8];
+  ld8(W + 8 * q, w0);
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    w0[m] = W[m * v + q];
-    du[m] = R(0);
-  }
-  hancock_axis<0>(W, v, q, S.s[0], w0, gm1, h, du);
-  hancock_axis<1>(W, v, q, S.s[1], w0, gm1, h, du);
-  hancock_axis<2>(W, v, q, S.s[2], w0, gm1, h, du);
-  R* DU = X + SCR_DU * v;
-#pragma unroll
-  for (int m = 0; m < 8; ++m) DU[m * v + q] = du[m];
-}
-
-// ---------------------------------------------------------------------------
-// stage 3: face-normal field at t^{n+1/2} (faces of the cells of the region grown by 1)
-// ---------------------------------------------------------------------------
-template <typename R>
-__device__ __forceinline__ R ebar(const R* ec_e, long long q, long long sa, long long sc) {
-  return R(0.25) * (ec_e[q] + ec_e[q - sa] + ec_e[q - sc] + ec_e[q - sa - sc]);
-}
-
-template <int D, typename R>
-__device__ __forceinline__ void bhalf_axis(const R* U, R* X, const Strides& S, long long q, R half_dt_dx) {
-  constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
-  const long long v = S.v;
-  const R* EC = X + SCR_EC * v;
-  const R* ecC = EC + C * v;
-  const R* ecA = EC + A * v;
-  // edge-averaged cell EMFs: component C has in-plane axes (D, A); component A has (C, D)
-  const R eC0 = ebar(ecC, q, S.s[D], S.s[A]);
-  const R eC1 = ebar(ecC, q + S.s[A], S.s[D], S.s[A]);
-  const R eA0 = ebar(ecA, q, S.s[C], S.s[D]);
-  const R eA1 = ebar(ecA, q + S.s[C], S.s[C], S.s[D]);
-  const R curl = (eC1 - eC0) - (eA1 - eA0);
-  X[(SCR_BH + D) * v + q] = U[(5 + D) * v + q] - half_dt_dx * curl;
-}
-
-template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_bhalf(DevCtx c, int first, int n, int cur, double dt) {
-  Where w;
-  if (!locate(c, first, n, w)) return;
-  const Task& T = c.tasks[w.task];
-  const PatchDev& p = c.patches[T.patch];
-  const Strides S = strides(p);
-  const R* U = (const R*)c.state + p.st[cur];
-  R* X = (R*)c.rscr + p.scr;
-  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
-  const R h = R(0.5 * dt / p.dx);
-  // the task region is the node box [lo, hi]; the cell box is [lo, hi - 1]
-  const bool ix = w.i < T.hi[0] - 1, iy = w.j < T.hi[1] - 1, iz = w.k < T.hi[2] - 1;
-  if (iy && iz) bhalf_axis<0>(U, X, S, q, h);
-  if (ix && iz) bhalf_axis<1>(U, X, S, q, h);
-  if (ix && iy) bhalf_axis<2>(U, X, S, q, h);
-}
-
-// ---------------------------------------------------------------------------
-// stage 4: cell reference EMF at t^{n+1/2} (cells of the region grown by 1)
-// ---------------------------------------------------------------------------
-template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_eref(DevCtx c, int first, int n, int cur) {
-  Where w;
-  if (!locate(c, first, n, w)) return;
-  const PatchDev& p = c.patches[c.tasks[w.task].patch];
-  const Strides S = strides(p);
-  const R* U = (const R*)c.state + p.st[cur];
-  R* X = (R*)c.rscr + p.scr;
-  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
-  const long long v = S.v;
-  const R* DU = X + SCR_DU * v;
+  for (int m = 0; m < 8; ++m) du[m] = R(0);
+  hancock_axis<0>(W, q, S.s[0], w0, gm1, h, du);
+  hancock_axis<1>(W, q, S.s[1], w0, gm1, h, du);
+  hancock_axis<2>(W, q, S.s[2], w0, gm1, h, du);
+  st8(X + SCR_DU * v + 8 * q, du);
+  // half-step velocity and face-averaged half-step field -> reference EMF
   const R* BH = X + SCR_BH * v;
-  const R rho = U[q] + DU[q];
-  const R vx = (U[v + q] + DU[v + q]) / rho;
-  const R vy = (U[2 * v + q] + DU[2 * v + q]) / rho;
-  const R vz = (U[3 * v + q] + DU[3 * v + q]) / rho;
+  const R rho = U[q] + du[0];
+  const R vx = (U[v + q] + du[1]) / rho;
+  const R vy = (U[2 * v + q] + du[2]) / rho;
+  const R vz = (U[3 * v + q] + du[3]) / rho;
   const R bx = R(0.5) * (BH[q] + BH[q + 1]);
   const R by = R(0.5) * (BH[v + q] + BH[v + q + S.s[1]]);
   const R bz = R(0.5) * (BH[2 * v + q] + BH[2 * v + q + S.s[2]]);
@@ -481,11 +499,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_eref(DevCtx c, int first, int n,
 }
 
 // ---------------------------------------------------------------------------
-// stage 5: HLLD fluxes through the faces normal to D, boundary registers
+// stage 4: HLLD fluxes through the faces normal to D, boundary registers
 // ---------------------------------------------------------------------------
 template <int D, typename R, bool MIX>
-__device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, const R* U, R* X, int i, int j, int k,
-                          int level, int substep, double dt) {
+__device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, R* X, int i, int j, int k, int level,
+                          int substep, double dt) {
   using Q = typename RegOf<R, MIX>::T;
   constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
   const long long v = S.v;
@@ -495,39 +513,36 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
   const R* DU = X + SCR_DU * v;
   const R gamma = R(c.gamma);
   const R gm1 = gamma - R(1);
-  R wl[8], wr[8], u[8];
+  R a[8], b[8], cc[8], wl[8], wr[8], u[8], d[8];
+  ld8(W + 8 * (q - 2 * sd), a);
+  ld8(W + 8 * (q - sd), b);
+  ld8(W + 8 * q, cc);
   // + state of the cell on the low side
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const R a = W[m * v + q - 2 * sd], b = W[m * v + q - sd], cc = W[m * v + q];
-    wl[m] = b + R(0.5) * mc_limit(b - a, cc - b);
-  }
-  to_cons(wl, gm1, u);
-#pragma unroll
-  for (int m = 0; m < 8; ++m) u[m] += DU[m * v + q - sd];
-  to_prim<R, MIX>(u, gm1, wl);
+  for (int m = 0; m < 8; ++m) wl[m] = b[m] + R(0.5) * mc_limit(b[m] - a[m], cc[m] - b[m]);
+  ld8(W + 8 * (q + sd), a);
   // - state of the cell on the high side
 #pragma unroll
-  for (int m = 0; m < 8; ++m) {
-    const R a = W[m * v + q - sd], b = W[m * v + q], cc = W[m * v + q + sd];
-    wr[m] = b - R(0.5) * mc_limit(b - a, cc - b);
-  }
-  to_cons(wr, gm1, u);
+  for (int m = 0; m < 8; ++m) wr[m] = cc[m] - R(0.5) * mc_limit(cc[m] - b[m], a[m] - cc[m]);
+  to_cons(wl, gm1, u);
+  ld8(DU + 8 * (q - sd), d);
 #pragma unroll
-  for (int m = 0; m < 8; ++m) u[m] += DU[m * v + q];
+  for (int m = 0; m < 8; ++m) u[m] += d[m];
+  to_prim<R, MIX>(u, gm1, wl);
+  to_cons(wr, gm1, u);
+  ld8(DU + 8 * q, d);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) u[m] += d[m];
   to_prim<R, MIX>(u, gm1, wr);
   if (!(wl[0] > R(0)) || !(wl[4] > R(0)) || !(wr[0] > R(0)) || !(wr[4] > R(0))) flag_phys(c.slots);
   const R bn = X[(SCR_BH + D) * v + q];
   R f[8];
   hlld<D>(wl, wr, bn, gamma, f);
-  R* F = X + (SCR_F + 7 * D) * v;
-  F[q] = f[0];
-  F[v + q] = f[1];
-  F[2 * v + q] = f[2];
-  F[3 * v + q] = f[3];
-  F[4 * v + q] = f[4];
-  F[5 * v + q] = -f[5 + A];   // EMF along C carried by this face
-  F[6 * v + q] = f[5 + C];    // EMF along A carried by this face
+  const R rec[4] = {f[1], f[2], f[3], f[4]};
+  st4(X + (SCR_F4 + 4 * D) * v + 4 * q, rec);
+  X[(SCR_F0 + D) * v + q] = f[0];
+  X[(SCR_FE + 2 * D) * v + q] = -f[5 + A];     // EMF along C carried by this face
+  X[(SCR_FE + 2 * D + 1) * v + q] = f[5 + C];  // EMF along A carried by this face
 
   // registers ---------------------------------------------------------------
   const int r[3] = {i - AMRX_G, j - AMRX_G, k - AMRX_G};
@@ -566,22 +581,22 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n, int cur, int level, int substep,
-                                                      double dt) {
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n, int cur, int level, int substep) {
+  const double dt = level_dt(c, level);
   Where w;
   if (!locate(c, first, n, w)) return;
   const Task& T = c.tasks[w.task];
   const PatchDev& p = c.patches[T.patch];
   const Strides S = strides(p);
-  const R* U = (const R*)c.state + p.st[cur];
   R* X = (R*)c.rscr + p.scr;
-  if (T.axis == 0) flux_face<0, R, MIX>(c, p, S, U, X, w.i, w.j, w.k, level, substep, dt);
-  else if (T.axis == 1) flux_face<1, R, MIX>(c, p, S, U, X, w.i, w.j, w.k, level, substep, dt);
-  else flux_face<2, R, MIX>(c, p, S, U, X, w.i, w.j, w.k, level, substep, dt);
+  (void)cur;
+  if (T.axis == 0) flux_face<0, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else if (T.axis == 1) flux_face<1, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else flux_face<2, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
 }
 
 // ---------------------------------------------------------------------------
-// stage 6: upwinded CT-contact edge EMFs along E, boundary registers
+// stage 5: upwinded CT-contact edge EMFs along E, boundary registers
 // ---------------------------------------------------------------------------
 template <int E, typename R, bool MIX>
 __device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R* X, int i, int j, int k, int level,
@@ -591,18 +606,18 @@ __device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R
   const long long v = S.v;
   const long long q = i + j * S.s[1] + k * S.s[2];
   const long long sa = S.s[A], sc = S.s[C];
-  const R* FA = X + (SCR_F + 7 * A) * v;
-  const R* FC = X + (SCR_F + 7 * C) * v;
-  const R* efa = FA + 5 * v;   // EMF along E on the faces normal to A
-  const R* efc = FC + 6 * v;   // EMF along E on the faces normal to C
+  const R* efa = X + (SCR_FE + 2 * A) * v;      // faces normal to A: EMF along (A+2)%3 = E
+  const R* efc = X + (SCR_FE + 2 * C + 1) * v;  // faces normal to C: EMF along (C+1)%3 = E
+  const R* fa0 = X + (SCR_F0 + A) * v;
+  const R* fc0 = X + (SCR_F0 + C) * v;
   const R* er = X + (SCR_ER + E) * v;
   const R ea_bm = efa[q - sc], ea_b0 = efa[q];
   const R eb_am = efc[q - sa], eb_a0 = efc[q];
   const R r_mm = er[q - sa - sc], r_0m = er[q - sc], r_m0 = er[q - sa], r_00 = er[q];
-  const R d_b_upper = upwind(FA[q], r_m0 - eb_am, r_00 - eb_a0);
-  const R d_b_lower = upwind(FA[q - sc], eb_am - r_mm, eb_a0 - r_0m);
-  const R d_a_upper = upwind(FC[q], r_0m - ea_bm, r_00 - ea_b0);
-  const R d_a_lower = upwind(FC[q - sa], ea_bm - r_mm, ea_b0 - r_m0);
+  const R d_b_upper = upwind(fa0[q], r_m0 - eb_am, r_00 - eb_a0);
+  const R d_b_lower = upwind(fa0[q - sc], eb_am - r_mm, eb_a0 - r_0m);
+  const R d_a_upper = upwind(fc0[q], r_0m - ea_bm, r_00 - ea_b0);
+  const R d_a_lower = upwind(fc0[q - sa], ea_bm - r_mm, ea_b0 - r_m0);
   const R emf = R(0.25) * (ea_bm + ea_b0 + eb_am + eb_a0) + R(0.25) * (d_b_lower - d_b_upper) +
                 R(0.25) * (d_a_lower - d_a_upper);
   X[(SCR_E + E) * v + q] = emf;
@@ -639,34 +654,35 @@ __device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_edge(DevCtx c, int first, int n, int cur, int level, int substep,
-                                                      double dt) {
+__global__ __launch_bounds__(AMRX_BLOCK) void k_edge(DevCtx c, int first, int n, int cur, int level, int substep) {
+  const double dt = level_dt(c, level);
   Where w;
   if (!locate(c, first, n, w)) return;
   const Task& T = c.tasks[w.task];
   const PatchDev& p = c.patches[T.patch];
   const Strides S = strides(p);
   R* X = (R*)c.rscr + p.scr;
+  (void)cur;
   if (T.axis == 0) edge_emf<0, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
   else if (T.axis == 1) edge_emf<1, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
   else edge_emf<2, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
 }
 
 // ---------------------------------------------------------------------------
-// stage 7: conservative cell update and Stokes face update into the next buffer
+// stage 6: conservative cell update and Stokes face update into the next buffer
 // ---------------------------------------------------------------------------
 template <int D, typename R>
-__device__ __forceinline__ void face_update(const R* U, R* N, const R* X, const Strides& S, long long q, R dt_dx) {
+__device__ __forceinline__ void face_update(const R* U, R* N, const R* EE, const Strides& S, long long q, R dt_dx) {
   constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
-  const long long v = S.v;
-  const R* EC = X + (SCR_E + C) * v;
-  const R* EA = X + (SCR_E + A) * v;
-  const R curl = (EC[q + S.s[A]] - EC[q]) - (EA[q + S.s[C]] - EA[q]);
-  N[(5 + D) * v + q] = U[(5 + D) * v + q] - dt_dx * curl;
+  const R* eC = EE + C * S.v;
+  const R* eA = EE + A * S.v;
+  const R curl = (eC[q + S.s[A]] - eC[q]) - (eA[q + S.s[C]] - eA[q]);
+  N[(5 + D) * S.v + q] = U[(5 + D) * S.v + q] - dt_dx * curl;
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int n, int cur, double dt) {
+__global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int n, int cur, int level) {
+  const double dt = level_dt(c, level);
   Where w;
   if (!locate(c, first, n, w)) return;
   const Task& T = c.tasks[w.task];
@@ -680,19 +696,25 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int 
   const R dt_dx = R(dt / p.dx);
   const bool ix = w.i < T.hi[0] - 1, iy = w.j < T.hi[1] - 1, iz = w.k < T.hi[2] - 1;
   if (ix && iy && iz) {
-    const R* FX = X + SCR_F * v;
-    const R* FY = X + (SCR_F + 7) * v;
-    const R* FZ = X + (SCR_F + 14) * v;
+    R div[5] = {R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
-    for (int m = 0; m < 5; ++m) {
-      const R div = (FX[m * v + q + 1] - FX[m * v + q]) + (FY[m * v + q + S.s[1]] - FY[m * v + q]) +
-                    (FZ[m * v + q + S.s[2]] - FZ[m * v + q]);
-      N[m * v + q] = U[m * v + q] - dt_dx * div;
+    for (int d = 0; d < 3; ++d) {
+      const R* F4 = X + (SCR_F4 + 4 * d) * v;
+      const R* F0 = X + (SCR_F0 + d) * v;
+      R f0[4], f1[4];
+      ld4(F4 + 4 * q, f0);
+      ld4(F4 + 4 * (q + S.s[d]), f1);
+      div[0] += F0[q + S.s[d]] - F0[q];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) div[1 + m] += f1[m] - f0[m];
     }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) N[m * v + q] = U[m * v + q] - dt_dx * div[m];
   }
-  if (iy && iz) face_update<0>(U, N, X, S, q, dt_dx);
-  if (ix && iz) face_update<1>(U, N, X, S, q, dt_dx);
-  if (ix && iy) face_update<2>(U, N, X, S, q, dt_dx);
+  const R* EE = X + SCR_E * v;
+  if (iy && iz) face_update<0>(U, N, EE, S, q, dt_dx);
+  if (ix && iz) face_update<1>(U, N, EE, S, q, dt_dx);
+  if (ix && iy) face_update<2>(U, N, EE, S, q, dt_dx);
 }
 
 // ---------------------------------------------------------------------------
@@ -701,16 +723,21 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int 
 // ---------------------------------------------------------------------------
 template <typename R>
 __global__ __launch_bounds__(AMRX_BLOCK) void k_copy(DevCtx c, int first, int n, int blk_first, int nelem, int cur) {
+  __shared__ int offs[AMRX_BLOCK + 1];
+  // runs touched by this block: [r0, r1] (a run has >= 1 entry, so at most AMRX_BLOCK of them)
+  const int r0 = c.run_blk[blk_first + blockIdx.x];
+  const int r1 = blockIdx.x + 1 < gridDim.x ? c.run_blk[blk_first + blockIdx.x + 1] : n - 1;
+  const int nr = r1 - r0 + 1;
+  for (int t = threadIdx.x; t < nr; t += AMRX_BLOCK) offs[t] = c.runs[first + r0 + t].off;
+  __syncthreads();
   const int e = blockIdx.x * AMRX_BLOCK + threadIdx.x;
   if (e >= nelem) return;
-  // the block's first run, then a binary search over the runs it can touch
-  int lo = c.run_blk[blk_first + blockIdx.x];
-  int hi = min(n - 1, lo + AMRX_BLOCK);
+  int lo = 0, hi = nr - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
-    if (c.runs[first + mid].off <= e) lo = mid; else hi = mid - 1;
+    if (offs[mid] <= e) lo = mid; else hi = mid - 1;
   }
-  const Run& r = c.runs[first + lo];
+  const Run& r = c.runs[first + r0 + lo];
   const int k = e - r.off;
   const PatchDev& dp = c.patches[r.dst_patch];
   const PatchDev& sp = c.patches[r.src_patch];
@@ -1165,6 +1192,21 @@ __global__ void k_clear_slots(DevCtx c) {
   if (t < NSLOT) c.slots[t] = 0ULL;
 }
 
+__global__ void k_set_dt(DevCtx c, double dt0) {
+  if (threadIdx.x == 0) c.slots[SLOT_DT] = (unsigned long long)__double_as_longlong(dt0);
+}
+
+// dt0 = min over levels of 2^l * cfl / (max signal speed sum of level l)
+__global__ void k_dt_from_cfl(DevCtx c, int nlev, double cfl) {
+  if (threadIdx.x != 0) return;
+  double best = 1e300;
+  for (int l = 0; l < nlev; ++l) {
+    const double smax = __longlong_as_double((long long)c.slots[SLOT_SMAX + l]);
+    if (smax > 0.0) best = fmin(best, ldexp(cfl, l) / smax);
+  }
+  c.slots[SLOT_DT] = (unsigned long long)__double_as_longlong(best);
+}
+
 inline unsigned grid_of(long long n, int per) { return (unsigned)((n + per - 1) / per); }
 
 #define DISPATCH(KERNEL, GRID, ...)                                                              \
@@ -1183,18 +1225,17 @@ inline unsigned grid_of(long long n, int per) { return (unsigned)((n + per - 1) 
 }  // namespace
 
 hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, int blk_first, int nblk, int cur,
-                        int level, int substep, double dt) {
+                        int level, int substep) {
   (void)blk_first;
   if (ntask == 0 || nblk == 0) return hipSuccess;
   const dim3 g(nblk);
   switch (stage) {
     case STAGE_PRIM: DISPATCH(k_prim, g, c, task_first, ntask, cur); break;
-    case STAGE_PRED: DISPATCH(k_pred, g, c, task_first, ntask, cur, dt); break;
-    case STAGE_BHALF: DISPATCH(k_bhalf, g, c, task_first, ntask, cur, dt); break;
-    case STAGE_EREF: DISPATCH(k_eref, g, c, task_first, ntask, cur); break;
-    case STAGE_FLUX: DISPATCH(k_flux, g, c, task_first, ntask, cur, level, substep, dt); break;
-    case STAGE_EDGE: DISPATCH(k_edge, g, c, task_first, ntask, cur, level, substep, dt); break;
-    case STAGE_UPDATE: DISPATCH(k_update, g, c, task_first, ntask, cur, dt); break;
+    case STAGE_BHALF: DISPATCH(k_bhalf, g, c, task_first, ntask, cur, level); break;
+    case STAGE_PRED: DISPATCH(k_pred, g, c, task_first, ntask, cur, level); break;
+    case STAGE_FLUX: DISPATCH(k_flux, g, c, task_first, ntask, cur, level, substep); break;
+    case STAGE_EDGE: DISPATCH(k_edge, g, c, task_first, ntask, cur, level, substep); break;
+    case STAGE_UPDATE: DISPATCH(k_update, g, c, task_first, ntask, cur, level); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1259,5 +1300,15 @@ hipError_t launch_conservation(const DevCtx& c, int task_first, int ntask, int b
 
 hipError_t launch_clear_slots(const DevCtx& c) {
   k_clear_slots<<<1, 64, 0, c.stream>>>(c);
+  return hipGetLastError();
+}
+
+hipError_t launch_set_dt(const DevCtx& c, double dt0) {
+  k_set_dt<<<1, 64, 0, c.stream>>>(c, dt0);
+  return hipGetLastError();
+}
+
+hipError_t launch_dt_from_cfl(const DevCtx& c, int nlev, double cfl) {
+  k_dt_from_cfl<<<1, 64, 0, c.stream>>>(c, nlev, cfl);
   return hipGetLastError();
 }

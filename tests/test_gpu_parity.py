@@ -81,6 +81,19 @@ def test_hierarchy_root_step(name, precision):
     assert d["phys_flag"] == 0.0
 
 
+def _assert_same_interiors(spec, a, b):
+    """Bitwise equality of the interiors (cells) and interior closures (faces) of two runs."""
+    o = amr.build(spec)
+    for pid, p in enumerate(o.patches):
+        ca, fa = a.download(pid)
+        cb, fb = b.download(pid)
+        m = o._interior_mask(p)
+        assert np.array_equal(ca[:, m], cb[:, m]), pid
+        for d in range(3):
+            mk = o._closure_mask(p, d)
+            assert np.array_equal(fa[d][mk], fb[d][mk]), (pid, d)
+
+
 def test_plain_and_batched_schedules_are_bit_identical():
     spec = H.small_three_level()
     _say("plain vs batched")
@@ -92,12 +105,7 @@ def test_plain_and_batched_schedules_are_bit_identical():
     for _ in range(2):
         dt = a.step(PLAIN)
         b.step(BATCHED, dt)
-    for pid in range(len(spec.patches)):
-        ca, fa = a.download(pid)
-        cb, fb = b.download(pid)
-        assert np.array_equal(ca, cb)
-        for d in range(3):
-            assert np.array_equal(fa[d], fb[d])
+    _assert_same_interiors(spec, a, b)
 
 
 def test_conservation_and_divergence_on_gpu():
@@ -261,3 +269,21 @@ def test_low_beta_step():
         assert np.all(err <= 1e-5 * 44.72 / 0.1), dict(zip(FIELDS, err))
         _say("per-field rel-L1", prec, dict(zip(FIELDS, np.round(err, 9))))
         _say("pressure rel-L1", prec, _pressure_rel_l1(h, o))
+
+
+@pytest.mark.parametrize("fixed_dt", [False, True])
+def test_graph_schedule_is_bit_identical_to_batched(fixed_dt):
+    """Replays of the captured root step (both buffer parities) equal the batched schedule bit for bit."""
+    from paper_1112_1710_amd import GRAPH
+    spec = H.small_three_level()
+    _say("graph schedule", fixed_dt)
+    field = SmoothField(8)
+    a = Hierarchy(spec, FP64)
+    b = Hierarchy(spec, FP64)
+    a.set_field(field)
+    b.set_field(field)
+    for _ in range(3):
+        dt = a.step(BATCHED, 1.5e-3 if fixed_dt else 0.0)
+        dtg = b.step(GRAPH, 1.5e-3 if fixed_dt else 0.0)
+        assert dt == dtg
+        _assert_same_interiors(spec, a, b)
