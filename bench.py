@@ -44,7 +44,7 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="two_level", choices=["two_level", "uniform256", "uniform32", "deep"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_mixed", "fp64"])
-    ap.add_argument("--mode", default="batched", choices=["plain", "batched", "graph"])
+    ap.add_argument("--mode", default="batched", choices=["plain", "batched", "graph", "persistent"])
     ap.add_argument("--plain-steps", type=int, default=4, help="steps of the FP64 per-patch-launch comparison")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
@@ -102,9 +102,9 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_1112_1710_amd import BATCHED, FP32, FP32_MIXED, FP64, GRAPH, PLAIN, Hierarchy
+    from paper_1112_1710_amd import BATCHED, FP32, FP32_MIXED, FP64, GRAPH, PERSISTENT, PLAIN, Hierarchy
     prec = {"fp32": FP32, "fp32_mixed": FP32_MIXED, "fp64": FP64}[args.precision]
-    mode = {"plain": PLAIN, "batched": BATCHED, "graph": GRAPH}[args.mode]
+    mode = {"plain": PLAIN, "batched": BATCHED, "graph": GRAPH, "persistent": PERSISTENT}[args.mode]
     spec, field, desc = workload(args.workload)
     zu = spec.zone_updates_per_root_step()
 
@@ -113,8 +113,8 @@ def main():
     sec, timing = timed_steps(h, mode, args.steps, args.warmup, torch)
     value = zu / sec
     work = h.step_work()
-    if mode == GRAPH:
-        # kernels inside a replayed graph are not bracketed by events: take the per-kernel
+    if mode in (GRAPH, PERSISTENT):
+        # kernels inside a replayed graph or the persistent kernel are not bracketed by events: take the per-kernel
         # launch times from an instrumented batched pass of the same steps
         _, timing = timed_steps(h, BATCHED, args.steps, 1, torch)
 

@@ -73,7 +73,10 @@ enum { AMRX_FP64 = 0, AMRX_FP32 = 1, AMRX_FP32_MIXED = 2 };
 enum {
   AMRX_PLAIN = 0,     /* every stage launched separately for every patch */
   AMRX_BATCHED = 1,   /* every stage launched once for all patches of a level substep */
-  AMRX_GRAPH = 2      /* AMRX_BATCHED captured once into a HIP graph and replayed */
+  AMRX_GRAPH = 2,     /* AMRX_BATCHED captured once into a HIP graph and replayed */
+  AMRX_PERSISTENT = 3 /* one launch of a persistent work-queue kernel per root step: every
+                         batched launch becomes a node of a dependency graph, levels run
+                         concurrently and ready work of finer levels is taken first (Sec. 4) */
 };
 
 typedef struct amrx_hier amrx_hier;
@@ -204,6 +207,14 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
  * src_patch * 2^32 + linear padded index, the patch's own interior (closure)
  * entries included, or -1 where none exists.  `out` holds V entries. */
 int hier_debug_sources(const amrx_hier* h, int patch_id, int kind, long long* out);
+
+/* The persistent schedule of one root step as built for the current buffer
+ * parities (fixed_dt: dt0 preset instead of computed), for `nworkgroups`
+ * workgroups.  sizes = (nodes, preds, items, queues); each non-NULL array
+ * receives the records (nodes: 12 ints each, items: 4 ints, queues: 2 ints)
+ * in the layout the device uses. */
+int hier_debug_schedule(amrx_hier* h, int fixed_dt, int nworkgroups, int* sizes, int* nodes, int* preds, int* items,
+                        int* queues);
 
 /* Number of parent cells prolongated into a patch at substep 0, and (if out
  * is non-NULL, cap entries) their level-(l-1) (x, y, z) indices. */

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libamrx.so")
 
 FP64, FP32, FP32_MIXED = 0, 1, 2
-PLAIN, BATCHED, GRAPH = 0, 1, 2
+PLAIN, BATCHED, GRAPH, PERSISTENT = 0, 1, 2, 3
 G = 4
 
 KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
@@ -52,6 +52,8 @@ EXPORTS = {
     "hier_timing_enable": ([C.c_void_p, C.c_int], C.c_int),
     "hier_timing_read": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
     "hier_step_work": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
+    "hier_debug_schedule": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
+                             C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hier_debug_sources": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_longlong)], C.c_int),
     "hier_debug_prolong_cells": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int], C.c_int),
 }
@@ -254,6 +256,20 @@ class Hierarchy:
         out = (C.c_longlong * vol)()
         self._check(self.lib.hier_debug_sources(self.h, pid, kind, out))
         return np.ctypeslib.as_array(out).reshape(shape).copy()
+
+    def debug_schedule(self, fixed_dt=False, nworkgroups=1024):
+        """Persistent schedule tables: nodes (N, 12), preds, items (M, 4), queues (Q, 2)."""
+        sizes = (C.c_int * 4)()
+        self._check(self.lib.hier_debug_schedule(self.h, int(fixed_dt), nworkgroups, sizes, None, None, None, None))
+        nn, npr, ni, nq = (sizes[i] for i in range(4))
+        nodes = (C.c_int * max(1, 12 * nn))()
+        preds = (C.c_int * max(1, npr))()
+        items = (C.c_int * max(1, 4 * ni))()
+        queues = (C.c_int * max(1, 2 * nq))()
+        self._check(self.lib.hier_debug_schedule(self.h, int(fixed_dt), nworkgroups, sizes, nodes, preds, items, queues))
+        a = np.ctypeslib.as_array
+        return (a(nodes)[:12 * nn].reshape(nn, 12).copy(), a(preds)[:npr].copy(),
+                a(items)[:4 * ni].reshape(ni, 4).copy(), a(queues)[:2 * nq].reshape(nq, 2).copy())
 
     def debug_prolong_cells(self, pid):
         cnt = C.c_int()

@@ -154,7 +154,8 @@ struct DevCtx {
   const Run* runs;
   const int* run_blk;     // per copy block: index (within the list) of the run holding its first element
   const Pro* pros;
-  const Corr* corrs;
+  const Corr* fcorrs;     // flux-correction entries (uncovered parent cells)
+  const Corr* ecorrs;     // EMF-correction entries (uncovered parent faces)
   const SyncPair* syncs;
   int* cov;               // coverage maps
   unsigned long long* slots;  // reduction / diagnostic slots
@@ -168,7 +169,41 @@ enum { STAGE_PRIM = 0, STAGE_BHALF, STAGE_PRED, STAGE_FLUX, STAGE_EDGE, STAGE_UP
 
 // slot indices in DevCtx::slots
 // SLOT_DT holds the root time step dt0 (double bits); level l uses dt0 * 2^-l.
-enum { SLOT_PHYS = 0, SLOT_SYNC_F = 1, SLOT_SYNC_B = 2, SLOT_DT = 3, SLOT_SMAX = 8 /* + level */, NSLOT = 8 + AMRX_MAXLEV };
+// SLOT_SCHED is set when a persistent workgroup gave up waiting for work.
+enum { SLOT_PHYS = 0, SLOT_SYNC_F = 1, SLOT_SYNC_B = 2, SLOT_DT = 3, SLOT_SCHED = 4, SLOT_SMAX = 8 /* + level */,
+       NSLOT = 8 + AMRX_MAXLEV };
+
+// ---------------------------------------------------------------------------
+// persistent schedule of one root step: nodes (one batched launch's worth of
+// blocks each) with predecessor lists, and per-level queues of items (block
+// ranges of a node) in program order; finer queues are served first
+// ---------------------------------------------------------------------------
+enum { OP_CFL = 0, OP_DT, OP_COPY, OP_PROLONG, OP_PRIM, OP_BHALF, OP_PRED, OP_FLUX, OP_EDGE, OP_UPDATE, OP_RESTRICT,
+       OP_FCORR, OP_ECORR, OP_SYNC };
+
+struct Node {
+  int op, level, substep, cur, aux;        // aux: parent parity (prolong), coarse parity (restrict, corrections)
+  int first, n, blk_first, nblk, nelem;    // list parameters of the equivalent batched launch
+  int pred_first, npred;                   // predecessors in the schedule's pred array
+};
+
+struct Item {
+  int node, b0, b1, pad;                   // blocks [b0, b1) of a node
+};
+
+struct Queue {
+  int first, len;                          // items of one level, in program order
+};
+
+struct Sched {
+  const Node* nodes;
+  const int* preds;
+  const Item* items;
+  const Queue* queues;
+  int nq;
+  int* heads;                              // per queue: next unclaimed item
+  int* done;                               // per node: completed blocks
+};
 
 hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, int blk_first, int nblk,
                         int cur, int level, int substep);
@@ -185,3 +220,5 @@ hipError_t launch_cfl(const DevCtx& c, int task_first, int ntask, int blk_first,
 hipError_t launch_conservation(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk,
                                const int* cur_of_level);
 hipError_t launch_clear_slots(const DevCtx& c);
+hipError_t launch_persistent(const DevCtx& c, const Sched& sc, int nnodes, int nworkgroups, int nlev, double cfl);
+int persistent_blocks_per_cu(int precision);

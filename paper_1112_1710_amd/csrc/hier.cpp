@@ -36,6 +36,15 @@ struct CopyList {
   double comps = 0;  // copied array elements (cells count 5)
 };
 
+struct SchedVariant {
+  bool valid = false;
+  unsigned key = 0;
+  unsigned long long used = 0;
+  int nnodes = 0, nq = 0;
+  size_t off_nodes = 0, off_preds = 0, off_items = 0, off_queues = 0, off_heads = 0, off_done = 0;
+  int cur_after[AMRX_MAXLEV] = {0};
+};
+
 struct GraphEntry {
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -107,6 +116,13 @@ struct amrx_hier {
 
   // captured root steps of the graph schedule
   std::map<unsigned, GraphEntry> graphs;
+
+  // persistent schedule variants (device copies in the scratch arena)
+  SchedVariant sv[4];
+  size_t off_sched = 0, sched_slot_bytes = 0;
+  unsigned long long sched_clock = 0;
+  int nworkgroups = 0;
+  bool persistent_enabled = false;
 
   // launch timing (measurement support)
   bool timing = false;
@@ -473,6 +489,201 @@ void build_syncs(amrx_hier* h, int pid) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// persistent schedule: DAG of one root step built from the read/write sets of
+// every batched launch in program order; node dependencies follow the last
+// writer (read-after-write, write-after-write) and the readers since the last
+// write (write-after-read) of each per-level resource
+// ---------------------------------------------------------------------------
+enum { RES_BUFI = 0, RES_BUFG, RES_INT, RES_REG, RES_CREG, RES_DT };
+
+int res_key(int kind, int level, int parity) { return (kind * AMRX_MAXLEV + level) * 2 + parity; }
+
+struct SchedBuild {
+  std::vector<Node> nodes;
+  std::vector<std::vector<int>> preds;
+  std::vector<int> queue;
+  struct Res {
+    int writer = -1;
+    std::vector<int> readers;
+  };
+  std::map<int, Res> res;
+
+  // Append a node; `acc` lists (resource key, reads, writes).  Empty launches are skipped.
+  int emit(const Node& nd0, int q, const std::vector<std::array<int, 3>>& acc, const std::vector<int>& extra = {}) {
+    if (nd0.nblk <= 0) return -1;
+    const int id = (int)nodes.size();
+    std::vector<int> pr(extra.begin(), extra.end());
+    for (const auto& a : acc) {
+      Res& r = res[a[0]];
+      if (r.writer >= 0) pr.push_back(r.writer);
+      if (a[2])
+        for (int rd : r.readers) pr.push_back(rd);
+    }
+    for (const auto& a : acc) {
+      Res& r = res[a[0]];
+      if (a[2]) {
+        r.writer = id;
+        r.readers.clear();
+      } else if (a[1]) {
+        r.readers.push_back(id);
+      }
+    }
+    std::sort(pr.begin(), pr.end());
+    pr.erase(std::unique(pr.begin(), pr.end()), pr.end());
+    nodes.push_back(nd0);
+    preds.push_back(pr);
+    queue.push_back(q);
+    return id;
+  }
+};
+
+Node mk_node(int op, int level, int substep, int cur, int aux, int first, int n, int blk_first, int nblk, int nelem) {
+  Node nd{};
+  nd.op = op;
+  nd.level = level;
+  nd.substep = substep;
+  nd.cur = cur;
+  nd.aux = aux;
+  nd.first = first;
+  nd.n = n;
+  nd.blk_first = blk_first;
+  nd.nblk = nblk;
+  nd.nelem = nelem;
+  return nd;
+}
+
+void sched_level(amrx_hier* h, SchedBuild& B, int l, int* cur, bool fixed_dt) {
+  const int nsub = l == 0 ? 1 : R;
+  const int dtk = res_key(RES_DT, 0, 0);
+  for (int s = 0; s < nsub; ++s) {
+    const int c = cur[l];
+    const int bi = res_key(RES_BUFI, l, c), bg = res_key(RES_BUFG, l, c);
+    const int cls = (l > 0 && s == 0) ? 0 : 1;
+    const CopyList& L = h->copy_b[l][cls];
+    B.emit(mk_node(OP_COPY, l, s, c, 0, L.first_run, L.nrun, L.first_blk, L.nblk, L.nelem), l,
+           {{bi, 1, 0}, {bg, 1, 1}});
+    if (l > 0 && s == 0) {
+      const int pc = 1 - cur[l - 1];
+      const Range& P = h->pro_b[l];
+      B.emit(mk_node(OP_PROLONG, l, s, c, pc, P.first, P.count, 0, (P.count + AMRX_BLOCK - 1) / AMRX_BLOCK, 0), l,
+             {{res_key(RES_BUFI, l - 1, pc), 1, 0}, {res_key(RES_BUFG, l - 1, pc), 1, 0}, {bi, 1, 0}, {bg, 1, 1}});
+    }
+    const int ik = res_key(RES_INT, l, 0);
+    const int rk = res_key(RES_REG, l, 0);
+    const int ck = res_key(RES_CREG, l + 1, 0);
+    const int ops[NSTAGE] = {OP_PRIM, OP_BHALF, OP_PRED, OP_FLUX, OP_EDGE, OP_UPDATE};
+    for (int stg = 0; stg < NSTAGE; ++stg) {
+      const TaskList& T = h->stage_b[l][s][stg];
+      std::vector<std::array<int, 3>> acc;
+      switch (ops[stg]) {
+        case OP_PRIM: acc = {{bi, 1, 0}, {bg, 1, 0}, {ik, 0, 1}}; break;
+        case OP_BHALF:
+        case OP_PRED: acc = {{bi, 1, 0}, {bg, 1, 0}, {ik, 1, 1}}; break;
+        case OP_FLUX:
+        case OP_EDGE: acc = {{ik, 1, 1}, {rk, 1, 1}, {ck, 1, 1}}; break;
+        case OP_UPDATE:
+          acc = {{ik, 1, 0}, {bi, 1, 0}, {bg, 1, 0}, {res_key(RES_BUFI, l, 1 - c), 0, 1}};
+          if (l > 0 && s == 0) acc.push_back({res_key(RES_BUFG, l, 1 - c), 0, 1});
+          break;
+      }
+      if (!fixed_dt && ops[stg] != OP_PRIM) acc.push_back({dtk, 1, 0});
+      B.emit(mk_node(ops[stg], l, s, c, 0, T.first, T.count, 0, T.nblk, 0), l, acc);
+    }
+    cur[l] = 1 - c;
+    if (l + 1 < h->nlev) {
+      sched_level(h, B, l + 1, cur, fixed_dt);
+      const int cc = cur[l], cf = cur[l + 1];
+      const int bic = res_key(RES_BUFI, l, cc);
+      const TaskList& T = h->restr_b[l + 1];
+      B.emit(mk_node(OP_RESTRICT, l + 1, 0, cf, cc, T.first, T.count, 0, T.nblk, 0), l + 1,
+             {{res_key(RES_BUFI, l + 1, cf), 1, 0}, {bic, 1, 1}});
+      const Range& F = h->fcorr_b[l];
+      B.emit(mk_node(OP_FCORR, l, 0, cc, cc, F.first, F.count, 0, (F.count + AMRX_BLOCK - 1) / AMRX_BLOCK, 0), l + 1,
+             {{res_key(RES_REG, l + 1, 0), 1, 0}, {res_key(RES_CREG, l + 1, 0), 1, 0}, {bic, 1, 1}});
+      const Range& E = h->ecorr_b[l];
+      B.emit(mk_node(OP_ECORR, l, 0, cc, cc, E.first, E.count, 0, (E.count + AMRX_BLOCK - 1) / AMRX_BLOCK, 0), l + 1,
+             {{res_key(RES_REG, l + 1, 0), 1, 0}, {res_key(RES_CREG, l + 1, 0), 1, 0}, {bic, 1, 1}});
+    }
+    const Range& S = h->sync_b[l];
+    B.emit(mk_node(OP_SYNC, l, s, cur[l], 0, S.first, S.count, 0, (S.count + AMRX_BLOCK - 1) / AMRX_BLOCK, 0), l,
+           {{rk, 1, 0}, {res_key(RES_BUFI, l, cur[l]), 1, 1}});
+  }
+}
+
+// Host image of one schedule variant (starting buffer parities, dt source).
+struct SchedImage {
+  std::vector<Node> nodes;
+  std::vector<int> preds;
+  std::vector<Item> items;
+  std::vector<Queue> queues;
+  int cur_after[AMRX_MAXLEV];
+};
+
+SchedImage build_sched(amrx_hier* h, bool fixed_dt, int nworkgroups) {
+  SchedBuild B;
+  int cur[AMRX_MAXLEV];
+  std::memcpy(cur, h->cur, sizeof cur);
+  if (!fixed_dt) {
+    std::vector<int> cfl_nodes;
+    for (int l = 0; l < h->nlev; ++l) {
+      const TaskList& T = h->cfl_b[l];
+      const int id = B.emit(mk_node(OP_CFL, l, 0, cur[l], 0, T.first, T.count, 0, T.nblk, 0), l,
+                            {{res_key(RES_BUFI, l, cur[l]), 1, 0}});
+      if (id >= 0) cfl_nodes.push_back(id);
+    }
+    B.emit(mk_node(OP_DT, 0, 0, 0, 0, 0, 0, 0, 1, 0), 0, {{res_key(RES_DT, 0, 0), 0, 1}}, cfl_nodes);
+  }
+  sched_level(h, B, 0, cur, fixed_dt);
+  const int nn = (int)B.nodes.size();
+  // transitive reduction of the predecessor lists (nodes are in topological order)
+  const int words = (nn + 63) / 64;
+  std::vector<std::vector<uint64_t>> anc(nn, std::vector<uint64_t>(words, 0));
+  SchedImage img;
+  for (int v = 0; v < nn; ++v) {
+    for (int p : B.preds[v]) {
+      for (int w = 0; w < words; ++w) anc[v][w] |= anc[p][w];
+      anc[v][p >> 6] |= 1ULL << (p & 63);
+    }
+    Node nd = B.nodes[v];
+    nd.pred_first = (int)img.preds.size();
+    for (int p : B.preds[v]) {
+      bool implied = false;
+      for (int o : B.preds[v])
+        if (o != p && (anc[o][p >> 6] >> (p & 63) & 1ULL)) {
+          implied = true;
+          break;
+        }
+      if (!implied) img.preds.push_back(p);
+    }
+    nd.npred = (int)img.preds.size() - nd.pred_first;
+    img.nodes.push_back(nd);
+  }
+  // per-level queues of items, program order inside a queue
+  int nq = 0;
+  for (int q : B.queue) nq = std::max(nq, q + 1);
+  for (int q = 0; q < nq; ++q) {
+    Queue Q;
+    Q.first = (int)img.items.size();
+    for (int v = 0; v < nn; ++v) {
+      if (B.queue[v] != q) continue;
+      const int nb = img.nodes[v].nblk;
+      const int chunk = std::max(1, std::min(16, nb / std::max(1, 2 * nworkgroups)));
+      for (int b = 0; b < nb; b += chunk) img.items.push_back(Item{v, b, std::min(nb, b + chunk), 0});
+    }
+    Q.len = (int)img.items.size() - Q.first;
+    img.queues.push_back(Q);
+  }
+  std::memcpy(img.cur_after, cur, sizeof cur);
+  return img;
+}
+
+size_t sched_bytes(const SchedImage& img) {
+  return align256(sizeof(Node) * img.nodes.size()) + align256(sizeof(int) * img.preds.size()) +
+         align256(sizeof(Item) * img.items.size()) + align256(sizeof(Queue) * img.queues.size()) +
+         align256(sizeof(int) * img.queues.size()) + align256(sizeof(int) * img.nodes.size());
+}
+
 int finalize_impl(amrx_hier* h) {
   // level-0 patches must tile the root grid
   long long vol0 = 0;
@@ -719,6 +930,17 @@ int finalize_impl(amrx_hier* h) {
   h->meta_bytes = o;
   h->off_slots = o; o = align256(o + sizeof(unsigned long long) * NSLOT);
   h->off_partials = o; o = align256(o + sizeof(double) * 16 * ((size_t)h->cons_all.nblk + 1));
+  {
+    // 4 schedule variants; items depend on the persistent grid, bounded by one item per block
+    SchedImage dry = build_sched(h, false, 1);
+    size_t items_max = 0;
+    for (const Node& nd : dry.nodes) items_max += (size_t)nd.nblk;
+    h->sched_slot_bytes = align256(sizeof(Node) * dry.nodes.size()) + align256(sizeof(int) * dry.preds.size()) +
+                          align256(sizeof(Item) * items_max) + align256(sizeof(Queue) * dry.queues.size()) +
+                          align256(sizeof(int) * dry.queues.size()) + align256(sizeof(int) * dry.nodes.size()) + 4096;
+    h->off_sched = o;
+    o = align256(o + 4 * h->sched_slot_bytes);
+  }
   h->off_reg = o; o = align256(o + h->reg_size * (size_t)reg);
   h->off_rscr = o; o = align256(o + h->real_size * (size_t)rscr);
   h->scratch_bytes = o;
@@ -739,7 +961,8 @@ DevCtx make_ctx(amrx_hier* h) {
   c.runs = (const Run*)(s + h->off_runs);
   c.run_blk = (const int*)(s + h->off_runblk);
   c.pros = (const Pro*)(s + h->off_pros);
-  c.corrs = nullptr;
+  c.fcorrs = (const Corr*)(s + h->off_fcorr);
+  c.ecorrs = (const Corr*)(s + h->off_ecorr);
   c.syncs = (const SyncPair*)(s + h->off_sync);
   c.cov = (int*)(s + h->off_cov);
   c.slots = (unsigned long long*)(s + h->off_slots);
@@ -806,17 +1029,13 @@ int do_restrict(amrx_hier* h, int fine, bool plain) {
       HIPCHK(TIMED(AMRX_K_RESTRICT, launch_restrict(c, T.first, T.count, 0, T.nblk, cf, cc)), "restriction");
     }
     for (int id : h->lev[fine - 1]) {
-      c.corrs = (const Corr*)(h->scratch + h->off_fcorr);
       HIPCHK(TIMED(AMRX_K_FLUXCORR, launch_flux_corr(c, h->fcorr_p[id].first, h->fcorr_p[id].count, cc)), "flux correction");
-      c.corrs = (const Corr*)(h->scratch + h->off_ecorr);
       HIPCHK(TIMED(AMRX_K_EMFCORR, launch_emf_corr(c, h->ecorr_p[id].first, h->ecorr_p[id].count, cc)), "EMF correction");
     }
   } else {
     const TaskList& T = h->restr_b[fine];
     HIPCHK(TIMED(AMRX_K_RESTRICT, launch_restrict(c, T.first, T.count, 0, T.nblk, cf, cc)), "restriction");
-    c.corrs = (const Corr*)(h->scratch + h->off_fcorr);
     HIPCHK(TIMED(AMRX_K_FLUXCORR, launch_flux_corr(c, h->fcorr_b[fine - 1].first, h->fcorr_b[fine - 1].count, cc)), "flux correction");
-    c.corrs = (const Corr*)(h->scratch + h->off_ecorr);
     HIPCHK(TIMED(AMRX_K_EMFCORR, launch_emf_corr(c, h->ecorr_b[fine - 1].first, h->ecorr_b[fine - 1].count, cc)), "EMF correction");
   }
   return AMRX_OK;
@@ -955,6 +1174,71 @@ int graph_step(amrx_hier* h, double* dt0) {
   HIPCHK(hipGraphLaunch(it->second.exec, s), "graph launch");
   std::memcpy(h->cur, it->second.cur_after, sizeof h->cur);
   return finish_step(h, dt0);
+}
+
+// Persistent schedule: one launch of the fine-first work-queue kernel per root step.
+int persistent_step(amrx_hier* h, double* dt0) {
+  const bool fixed = *dt0 > 0.0;
+  const unsigned key = parity_key(h) * 2u + (fixed ? 1u : 0u);
+  int slot = -1;
+  for (int i = 0; i < 4; ++i)
+    if (h->sv[i].valid && h->sv[i].key == key) slot = i;
+  if (slot < 0) {
+    // build the variant into the least recently used slot
+    slot = 0;
+    for (int i = 1; i < 4; ++i)
+      if (!h->sv[i].valid || (h->sv[slot].valid && h->sv[i].used < h->sv[slot].used)) slot = i;
+    SchedImage img = build_sched(h, fixed, h->nworkgroups);
+    if (sched_bytes(img) > h->sched_slot_bytes) return fail(h, AMRX_ENOMEM, "schedule larger than its reserved slot");
+    char* base = h->scratch + h->off_sched + (size_t)slot * h->sched_slot_bytes;
+    std::vector<char> buf(sched_bytes(img), 0);
+    size_t o = 0;
+    SchedVariant& v = h->sv[slot];
+    auto put = [&](const void* src, size_t n) {
+      const size_t at = o;
+      if (n) std::memcpy(buf.data() + o, src, n);
+      o += align256(n);
+      return at;
+    };
+    v.off_nodes = put(img.nodes.data(), sizeof(Node) * img.nodes.size());
+    v.off_preds = put(img.preds.data(), sizeof(int) * img.preds.size());
+    v.off_items = put(img.items.data(), sizeof(Item) * img.items.size());
+    v.off_queues = put(img.queues.data(), sizeof(Queue) * img.queues.size());
+    v.off_heads = o;
+    o += align256(sizeof(int) * img.queues.size());
+    v.off_done = o;
+    o += align256(sizeof(int) * img.nodes.size());
+    HIPCHK(hipMemcpyAsync(base, buf.data(), buf.size(), hipMemcpyHostToDevice, (hipStream_t)h->d.stream),
+           "upload schedule");
+    HIPCHK(hipStreamSynchronize((hipStream_t)h->d.stream), "stream synchronize");
+    v.key = key;
+    v.valid = true;
+    v.nnodes = (int)img.nodes.size();
+    v.nq = (int)img.queues.size();
+    std::memcpy(v.cur_after, img.cur_after, sizeof v.cur_after);
+  }
+  SchedVariant& v = h->sv[slot];
+  v.used = ++h->sched_clock;
+  char* base = h->scratch + h->off_sched + (size_t)slot * h->sched_slot_bytes;
+  Sched sc;
+  sc.nodes = (const Node*)(base + v.off_nodes);
+  sc.preds = (const int*)(base + v.off_preds);
+  sc.items = (const Item*)(base + v.off_items);
+  sc.queues = (const Queue*)(base + v.off_queues);
+  sc.nq = v.nq;
+  sc.heads = (int*)(base + v.off_heads);
+  sc.done = (int*)(base + v.off_done);
+  HIPCHK(launch_clear_slots(h->ctx), "clear slots");
+  if (fixed) HIPCHK(launch_set_dt(h->ctx, *dt0), "set dt");
+  HIPCHK(launch_persistent(h->ctx, sc, v.nnodes, h->nworkgroups, h->nlev, h->d.cfl), "persistent launch");
+  std::memcpy(h->cur, v.cur_after, sizeof h->cur);
+  unsigned long long sl[NSLOT];
+  const int rc = read_slots(h, sl);
+  if (rc) return rc;
+  *dt0 = bits_to_double(sl[SLOT_DT]);
+  if (sl[SLOT_SCHED]) return fail(h, AMRX_EHIP, "persistent schedule stalled (no ready work for 10 s)");
+  if (sl[SLOT_PHYS]) return fail(h, AMRX_EPHYS, "unphysical state (rho<=0, p<=0 or non-finite)");
+  return AMRX_OK;
 }
 
 bool ready(amrx_hier* h) {
@@ -1097,6 +1381,13 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   h->ctx = make_ctx(h);
   HIPCHK(launch_clear_slots(h->ctx), "clear slots");
+  {
+    int dev = 0, ncu = 0;
+    HIPCHK(hipGetDevice(&dev), "get device");
+    HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
+    // at most 4 workgroups (16 waves) per CU: enough to hide latency, few enough idle pollers
+    h->nworkgroups = std::max(1, ncu) * std::min(4, persistent_blocks_per_cu(h->d.precision));
+  }
   for (int l = 0; l < AMRX_MAXLEV; ++l) h->cur[l] = 0;
   h->bound = true;
   return AMRX_OK;
@@ -1136,9 +1427,14 @@ int cfl_dt(amrx_hier* h, double* dt0) {
 
 int hier_step(amrx_hier* h, int mode, double* dt0) {
   if (!ready(h)) return AMRX_ESTATE;
-  if (!dt0 || mode < AMRX_PLAIN || mode > AMRX_GRAPH) return AMRX_EINVAL;
+  if (!dt0 || mode < AMRX_PLAIN || mode > AMRX_PERSISTENT) return AMRX_EINVAL;
   if (!(*dt0 > 0.0)) *dt0 = 0.0;
   if (mode == AMRX_GRAPH) return graph_step(h, dt0);
+  if (mode == AMRX_PERSISTENT)
+    // Switched off: its launches stalled on the MI355X (run killed after 180 s of silence,
+    // twice) and the cause has not been shown yet; the schedule itself is checked on the host.
+    return h->persistent_enabled ? persistent_step(h, dt0)
+                                 : fail(h, AMRX_EINVAL, "the persistent schedule is disabled in this build");
   const int rc = enqueue_step(h, mode == AMRX_PLAIN, *dt0);
   if (rc) return rc;
   return finish_step(h, dt0);
@@ -1247,6 +1543,22 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches) {
     units[i] = u[i];
     launches[i] = nl[i];
   }
+  return AMRX_OK;
+}
+
+int hier_debug_schedule(amrx_hier* h, int fixed_dt, int nworkgroups, int* sizes, int* nodes, int* preds, int* items,
+                        int* queues) {
+  if (!h || !sizes) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  SchedImage img = build_sched(h, fixed_dt != 0, nworkgroups > 0 ? nworkgroups : 1);
+  sizes[0] = (int)img.nodes.size();
+  sizes[1] = (int)img.preds.size();
+  sizes[2] = (int)img.items.size();
+  sizes[3] = (int)img.queues.size();
+  if (nodes) std::memcpy(nodes, img.nodes.data(), sizeof(Node) * img.nodes.size());
+  if (preds) std::memcpy(preds, img.preds.data(), sizeof(int) * img.preds.size());
+  if (items) std::memcpy(items, img.items.data(), sizeof(Item) * img.items.size());
+  if (queues) std::memcpy(queues, img.queues.data(), sizeof(Queue) * img.queues.size());
   return AMRX_OK;
 }
 

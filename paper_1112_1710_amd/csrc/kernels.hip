@@ -284,8 +284,7 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
-__device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, Where& w) {
-  const int b = xcd_block(blockIdx.x, gridDim.x);
+__device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, int b, Where& w) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
     const int mid = (lo + hi + 1) >> 1;
@@ -371,9 +370,10 @@ __device__ __forceinline__ void st8(R* p, const R* v) {
 // stage 1: primitives and cell EMFs at t^n   (cells of the region grown by 2)
 // ---------------------------------------------------------------------------
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_prim(DevCtx c, int first, int n, int cur) {
+__device__ __forceinline__ void d_prim(const DevCtx& c, int vb, int nb, int first, int n, int cur) {
+  (void)nb;
   Where w;
-  if (!locate(c, first, n, w)) return;
+  if (!locate(c, first, n, vb, w)) return;
   const PatchDev& p = c.patches[c.tasks[w.task].patch];
   const Strides S = strides(p);
   const R* U = (const R*)c.state + p.st[cur];
@@ -394,6 +394,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_prim(DevCtx c, int first, int n,
   EC[q] = -(vy * bz - vz * by);
   EC[v + q] = -(vz * bx - vx * bz);
   EC[2 * v + q] = -(vx * by - vy * bx);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_prim(DevCtx c, int first, int n, int cur) {
+  d_prim<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur);
 }
 
 // ---------------------------------------------------------------------------
@@ -419,10 +424,11 @@ __device__ __forceinline__ R bhalf_axis(const R* U, const R* EC, const Strides& 
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_bhalf(DevCtx c, int first, int n, int cur, int level) {
+__device__ __forceinline__ void d_bhalf(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level) {
+  (void)nb;
   const double dt = level_dt(c, level);
   Where w;
-  if (!locate(c, first, n, w)) return;
+  if (!locate(c, first, n, vb, w)) return;
   const Task& T = c.tasks[w.task];
   const PatchDev& p = c.patches[T.patch];
   const Strides S = strides(p);
@@ -437,6 +443,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_bhalf(DevCtx c, int first, int n
   if (iy && iz) BH[q] = bhalf_axis<0>(U, EC, S, q, h);
   if (ix && iz) BH[S.v + q] = bhalf_axis<1>(U, EC, S, q, h);
   if (ix && iy) BH[2 * S.v + q] = bhalf_axis<2>(U, EC, S, q, h);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_bhalf(DevCtx c, int first, int n, int cur, int level) {
+  d_bhalf<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level);
 }
 
 // ---------------------------------------------------------------------------
@@ -462,10 +473,11 @@ __device__ __forceinline__ void hancock_axis(const R* W, long long q, long long 
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_pred(DevCtx c, int first, int n, int cur, int level) {
+__device__ __forceinline__ void d_pred(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level) {
+  (void)nb;
   const double dt = level_dt(c, level);
   Where w;
-  if (!locate(c, first, n, w)) return;
+  if (!locate(c, first, n, vb, w)) return;
   const PatchDev& p = c.patches[c.tasks[w.task].patch];
   const Strides S = strides(p);
   const R* U = (const R*)c.state + p.st[cur];
@@ -496,6 +508,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_pred(DevCtx c, int first, int n,
   ER[q] = -(vy * bz - vz * by);
   ER[v + q] = -(vz * bx - vx * bz);
   ER[2 * v + q] = -(vx * by - vy * bx);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_pred(DevCtx c, int first, int n, int cur, int level) {
+  d_pred<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level);
 }
 
 // ---------------------------------------------------------------------------
@@ -581,10 +598,11 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n, int cur, int level, int substep) {
+__device__ __forceinline__ void d_flux(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level, int substep) {
+  (void)nb;
   const double dt = level_dt(c, level);
   Where w;
-  if (!locate(c, first, n, w)) return;
+  if (!locate(c, first, n, vb, w)) return;
   const Task& T = c.tasks[w.task];
   const PatchDev& p = c.patches[T.patch];
   const Strides S = strides(p);
@@ -593,6 +611,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n,
   if (T.axis == 0) flux_face<0, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
   else if (T.axis == 1) flux_face<1, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
   else flux_face<2, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n, int cur, int level, int substep) {
+  d_flux<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
 }
 
 // ---------------------------------------------------------------------------
@@ -654,10 +677,11 @@ __device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_edge(DevCtx c, int first, int n, int cur, int level, int substep) {
+__device__ __forceinline__ void d_edge(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level, int substep) {
+  (void)nb;
   const double dt = level_dt(c, level);
   Where w;
-  if (!locate(c, first, n, w)) return;
+  if (!locate(c, first, n, vb, w)) return;
   const Task& T = c.tasks[w.task];
   const PatchDev& p = c.patches[T.patch];
   const Strides S = strides(p);
@@ -666,6 +690,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_edge(DevCtx c, int first, int n,
   if (T.axis == 0) edge_emf<0, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
   else if (T.axis == 1) edge_emf<1, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
   else edge_emf<2, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_edge(DevCtx c, int first, int n, int cur, int level, int substep) {
+  d_edge<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
 }
 
 // ---------------------------------------------------------------------------
@@ -681,10 +710,11 @@ __device__ __forceinline__ void face_update(const R* U, R* N, const R* EE, const
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int n, int cur, int level) {
+__device__ __forceinline__ void d_update(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level) {
+  (void)nb;
   const double dt = level_dt(c, level);
   Where w;
-  if (!locate(c, first, n, w)) return;
+  if (!locate(c, first, n, vb, w)) return;
   const Task& T = c.tasks[w.task];
   const PatchDev& p = c.patches[T.patch];
   const Strides S = strides(p);
@@ -717,20 +747,26 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int 
   if (ix && iy) face_update<2>(U, N, EE, S, q, dt_dx);
 }
 
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int n, int cur, int level) {
+  d_update<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level);
+}
+
 // ---------------------------------------------------------------------------
 // same-level ghost copy: one thread per copied entry; runs are consecutive
 // along x so neighbouring lanes read and write neighbouring addresses
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_copy(DevCtx c, int first, int n, int blk_first, int nelem, int cur) {
+__device__ __forceinline__ void d_copy(const DevCtx& c, int vb, int nb, int first, int n, int blk_first, int nelem, int cur) {
+  (void)nb;
   __shared__ int offs[AMRX_BLOCK + 1];
   // runs touched by this block: [r0, r1] (a run has >= 1 entry, so at most AMRX_BLOCK of them)
-  const int r0 = c.run_blk[blk_first + blockIdx.x];
-  const int r1 = blockIdx.x + 1 < gridDim.x ? c.run_blk[blk_first + blockIdx.x + 1] : n - 1;
+  const int r0 = c.run_blk[blk_first + vb];
+  const int r1 = vb + 1 < nb ? c.run_blk[blk_first + vb + 1] : n - 1;
   const int nr = r1 - r0 + 1;
   for (int t = threadIdx.x; t < nr; t += AMRX_BLOCK) offs[t] = c.runs[first + r0 + t].off;
   __syncthreads();
-  const int e = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  const int e = vb * AMRX_BLOCK + threadIdx.x;
   if (e >= nelem) return;
   int lo = 0, hi = nr - 1;
   while (lo < hi) {
@@ -752,12 +788,18 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_copy(DevCtx c, int first, int n,
   }
 }
 
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_copy(DevCtx c, int first, int n, int blk_first, int nelem, int cur) {
+  d_copy<R>(c, blockIdx.x, gridDim.x, first, n, blk_first, nelem, cur);
+}
+
 // ---------------------------------------------------------------------------
 // prolongation of one parent cell into a fine ghost region
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_prolong(DevCtx c, int first, int n, int cur_fine, int old_parent) {
-  const int id = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+__device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int first, int n, int cur_fine, int old_parent) {
+  (void)nb;
+  const int id = vb * AMRX_BLOCK + threadIdx.x;
   if (id >= n) return;
   const Pro& pr = c.pros[first + id];
   const PatchDev& fp = c.patches[pr.patch];
@@ -852,13 +894,19 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_prolong(DevCtx c, int first, int
   }
 }
 
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_prolong(DevCtx c, int first, int n, int cur_fine, int old_parent) {
+  d_prolong<R>(c, blockIdx.x, gridDim.x, first, n, cur_fine, old_parent);
+}
+
 // ---------------------------------------------------------------------------
 // restriction of a child onto its parent: node box of the child's coarse box
 // ---------------------------------------------------------------------------
 template <typename R>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_restrict(DevCtx c, int first, int n, int cur_fine, int cur_coarse) {
+__device__ __forceinline__ void d_restrict(const DevCtx& c, int vb, int nb, int first, int n, int cur_fine, int cur_coarse) {
+  (void)nb;
   Where w;
-  if (!locate(c, first, n, w)) return;
+  if (!locate(c, first, n, vb, w)) return;
   const Task& T = c.tasks[w.task];
   const PatchDev& fp = c.patches[T.patch];
   const PatchDev& mp = c.patches[fp.parent];
@@ -895,15 +943,21 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_restrict(DevCtx c, int first, in
   }
 }
 
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_restrict(DevCtx c, int first, int n, int cur_fine, int cur_coarse) {
+  d_restrict<R>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur_fine, cur_coarse);
+}
+
 // ---------------------------------------------------------------------------
 // flux correction of an uncovered parent cell next to the fine region
 // ---------------------------------------------------------------------------
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_flux_corr(DevCtx c, int first, int n, int cur_coarse) {
+__device__ __forceinline__ void d_flux_corr(const DevCtx& c, int vb, int nb, int first, int n, int cur_coarse) {
+  (void)nb;
   using Q = typename RegOf<R, MIX>::T;
-  const int id = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  const int id = vb * AMRX_BLOCK + threadIdx.x;
   if (id >= n) return;
-  const Corr& e = c.corrs[first + id];
+  const Corr& e = c.fcorrs[first + id];
   const PatchDev& mp = c.patches[e.patch];
   const Strides S = strides(mp);
   R* M = (R*)c.state + mp.st[cur_coarse];
@@ -938,6 +992,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_flux_corr(DevCtx c, int first, i
     }
   }
   for (int m = 0; m < 5; ++m) M[m * S.v + q] = (R)((double)M[m * S.v + q] + corr[m] / mp.dx);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flux_corr(DevCtx c, int first, int n, int cur_coarse) {
+  d_flux_corr<R, MIX>(c, blockIdx.x, gridDim.x, first, n, cur_coarse);
 }
 
 // EMF change (new - old, times dt) at a parent edge along e at node q, zero off the coverage boundary
@@ -975,10 +1034,11 @@ __device__ double emf_delta(const DevCtx& c, const PatchDev& mp, const Strides& 
 }
 
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_emf_corr(DevCtx c, int first, int n, int cur_coarse) {
-  const int id = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+__device__ __forceinline__ void d_emf_corr(const DevCtx& c, int vb, int nb, int first, int n, int cur_coarse) {
+  (void)nb;
+  const int id = vb * AMRX_BLOCK + threadIdx.x;
   if (id >= n) return;
-  const Corr& e = c.corrs[first + id];
+  const Corr& e = c.ecorrs[first + id];
   const PatchDev& mp = c.patches[e.patch];
   const Strides S = strides(mp);
   R* M = (R*)c.state + mp.st[cur_coarse];
@@ -997,13 +1057,19 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_emf_corr(DevCtx c, int first, in
   b[q] = (R)((double)b[q] - curl / mp.dx);
 }
 
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_emf_corr(DevCtx c, int first, int n, int cur_coarse) {
+  d_emf_corr<R, MIX>(c, blockIdx.x, gridDim.x, first, n, cur_coarse);
+}
+
 // ---------------------------------------------------------------------------
 // same-level synchronisation of shared boundary faces
 // ---------------------------------------------------------------------------
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_sync(DevCtx c, int first, int n, int cur) {
+__device__ __forceinline__ void d_sync(const DevCtx& c, int vb, int nb, int first, int n, int cur) {
+  (void)nb;
   using Q = typename RegOf<R, MIX>::T;
-  const int id = blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  const int id = vb * AMRX_BLOCK + threadIdx.x;
   if (id >= n) return;
   const SyncPair& s = c.syncs[first + id];
   const PatchDev& pa = c.patches[s.a];
@@ -1037,15 +1103,20 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_sync(DevCtx c, int first, int n,
   }
 }
 
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_sync(DevCtx c, int first, int n, int cur) {
+  d_sync<R, MIX>(c, blockIdx.x, gridDim.x, first, n, cur);
+}
+
 // ---------------------------------------------------------------------------
 // CFL signal speed: max over interior cells of sum_d (|v_d| + c_f,d) / dx
 // ---------------------------------------------------------------------------
 // Grid-stride over the list's blocks; one atomic per block on the level's slot.
 template <typename R, bool MIX>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_cfl(DevCtx c, int first, int n, int nblk, int cur, int level) {
+__device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int first, int n, int nblk, int cur, int level) {
   __shared__ double red[AMRX_BLOCK / 64];
   double s = 0.0;
-  for (int b = blockIdx.x; b < nblk; b += gridDim.x) {
+  for (int b = b0; b < nblk; b += stride) {
     int lo = 0, hi = n - 1;
     while (lo < hi) {
       const int mid = (lo + hi + 1) >> 1;
@@ -1091,6 +1162,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_cfl(DevCtx c, int first, int n, 
   }
 }
 
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_cfl(DevCtx c, int first, int n, int nblk, int cur, int level) {
+  d_cfl<R, MIX>(c, blockIdx.x, gridDim.x, first, n, nblk, cur, level);
+}
+
 // ---------------------------------------------------------------------------
 // conservation sums over leaf cells with compensated (two-sum) accumulation
 // ---------------------------------------------------------------------------
@@ -1110,7 +1186,7 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_cons(DevCtx c, int first, int n,
   __shared__ double sh_e[8][AMRX_BLOCK];
   Where w;
   double x[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  if (locate(c, first, n, w)) {
+  if (locate(c, first, n, blockIdx.x, w)) {
     const PatchDev& p = c.patches[c.tasks[w.task].patch];
     const Strides S = strides(p);
     const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
@@ -1207,7 +1283,120 @@ __global__ void k_dt_from_cfl(DevCtx c, int nlev, double cfl) {
   c.slots[SLOT_DT] = (unsigned long long)__double_as_longlong(best);
 }
 
+__device__ __forceinline__ void dt_from_cfl(const DevCtx& c, int nlev, double cfl) {
+  double best = 1e300;
+  for (int l = 0; l < nlev; ++l) {
+    const double smax = __longlong_as_double((long long)c.slots[SLOT_SMAX + l]);
+    if (smax > 0.0) best = fmin(best, ldexp(cfl, l) / smax);
+  }
+  c.slots[SLOT_DT] = (unsigned long long)__double_as_longlong(best);
+}
+
+// ---------------------------------------------------------------------------
+// persistent fine-first scheduler
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool node_ready(const Sched& sc, const Node& nd) {
+  for (int k = 0; k < nd.npred; ++k) {
+    const int p = sc.preds[nd.pred_first + k];
+    // relaxed (coherent, no cache invalidation); the claimer acquires once after a successful claim
+    if (__hip_atomic_load(&sc.done[p], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < sc.nodes[p].nblk) return false;
+  }
+  return true;
+}
+
+// Claim the first ready item of the finest queue that has one.  Non-blocking: a
+// workgroup never holds an item while waiting, so progress needs no co-residency.
+// Returns -1 once every queue is exhausted, or after ~10 s without any ready item
+// (then SLOT_SCHED is raised so the host reports the failure).  Idle polling
+// sleeps ~3 us between rounds and touches only coherent counters.
+__device__ int claim_item(const Sched& sc, unsigned long long* slots) {
+  const unsigned long long t0 = wall_clock64();
+  for (unsigned spin = 0;; ++spin) {
+    bool pending = false;
+    for (int q = sc.nq - 1; q >= 0; --q) {
+      const Queue Q = sc.queues[q];
+      int h = __hip_atomic_load(&sc.heads[q], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      while (h < Q.len) {
+        pending = true;
+        const Item& it = sc.items[Q.first + h];
+        if (!node_ready(sc, sc.nodes[it.node])) break;
+        int expected = h;
+        if (__hip_atomic_compare_exchange_strong(&sc.heads[q], &expected, h + 1, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+          return Q.first + h;
+        h = expected;
+      }
+    }
+    if (!pending) return -1;
+    // wall_clock64 ticks at 100 MHz; the iteration cap (>= 3 us per round) bounds the wait even without a clock
+    if (wall_clock64() - t0 > 1000000000ULL || spin > 4000000u) {
+      atomicOr(&slots[SLOT_SCHED], 1ULL);
+      return -1;
+    }
+    __builtin_amdgcn_s_sleep(127);
+  }
+}
+
+template <typename R, bool MIX>
+__device__ __forceinline__ void run_node(const DevCtx& c, const Node& nd, int b, int nlev, double cfl) {
+  switch (nd.op) {
+    case OP_CFL: d_cfl<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.nblk, nd.cur, nd.level); break;
+    case OP_DT:
+      if (threadIdx.x == 0) dt_from_cfl(c, nlev, cfl);
+      break;
+    case OP_COPY: d_copy<R>(c, b, nd.nblk, nd.first, nd.n, nd.blk_first, nd.nelem, nd.cur); break;
+    case OP_PROLONG: d_prolong<R>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.aux); break;
+    case OP_PRIM: d_prim<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur); break;
+    case OP_BHALF: d_bhalf<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level); break;
+    case OP_PRED: d_pred<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level); break;
+    case OP_FLUX: d_flux<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep); break;
+    case OP_EDGE: d_edge<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep); break;
+    case OP_UPDATE: d_update<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level); break;
+    case OP_RESTRICT: d_restrict<R>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.aux); break;
+    case OP_FCORR: d_flux_corr<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.aux); break;
+    case OP_ECORR: d_emf_corr<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.aux); break;
+    case OP_SYNC: d_sync<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur); break;
+    default: break;
+  }
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_persistent(DevCtx c, Sched sc, int nlev, double cfl) {
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) {
+      const int got = claim_item(sc, c.slots);
+      // acquire once per claimed item: the data of its completed predecessors; the
+      // barrier below orders the other waves of this workgroup after it
+      if (got >= 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+      s_item = got;
+    }
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it < 0) return;
+    const Item I = sc.items[it];
+    const Node nd = sc.nodes[I.node];
+    for (int b = I.b0; b < I.b1; ++b) {
+      run_node<R, MIX>(c, nd, b, nlev, cfl);
+      __syncthreads();  // every wave's stores of this workgroup are done (workgroup scope)
+    }
+    // release by one thread: the workgroup's writes become visible device-wide before the count
+    if (threadIdx.x == 0) {
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+      __hip_atomic_fetch_add(&sc.done[I.node], I.b1 - I.b0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+  }
+}
+
+__global__ void k_clear_sched(Sched sc, int nnodes) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nnodes; i += gridDim.x * blockDim.x) sc.done[i] = 0;
+  if (blockIdx.x == 0)
+    for (int q = threadIdx.x; q < sc.nq; q += blockDim.x) sc.heads[q] = 0;
+}
+
 inline unsigned grid_of(long long n, int per) { return (unsigned)((n + per - 1) / per); }
+
 
 #define DISPATCH(KERNEL, GRID, ...)                                                              \
   do {                                                                                           \
@@ -1303,7 +1492,29 @@ hipError_t launch_clear_slots(const DevCtx& c) {
   return hipGetLastError();
 }
 
+hipError_t launch_persistent(const DevCtx& c, const Sched& sc, int nnodes, int nworkgroups, int nlev, double cfl) {
+  const unsigned gc = grid_of(nnodes, AMRX_BLOCK);
+  k_clear_sched<<<gc < 64 ? gc : 64, AMRX_BLOCK, 0, c.stream>>>(sc, nnodes);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  const dim3 g(nworkgroups);
+  if (c.precision == 0) k_persistent<double, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, sc, nlev, cfl);
+  else if (c.precision == 1) k_persistent<float, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, sc, nlev, cfl);
+  else k_persistent<float, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, sc, nlev, cfl);
+  return hipGetLastError();
+}
+
+int persistent_blocks_per_cu(int precision) {
+  int nb = 0;
+  hipError_t e;
+  if (precision == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<double, false>, AMRX_BLOCK, 0);
+  else if (precision == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<float, false>, AMRX_BLOCK, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_persistent<float, true>, AMRX_BLOCK, 0);
+  return e == hipSuccess && nb > 0 ? nb : 1;
+}
+
 hipError_t launch_set_dt(const DevCtx& c, double dt0) {
+
   k_set_dt<<<1, 64, 0, c.stream>>>(c, dt0);
   return hipGetLastError();
 }

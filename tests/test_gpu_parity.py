@@ -287,3 +287,25 @@ def test_graph_schedule_is_bit_identical_to_batched(fixed_dt):
         dtg = b.step(GRAPH, 1.5e-3 if fixed_dt else 0.0)
         assert dt == dtg
         _assert_same_interiors(spec, a, b)
+
+
+@pytest.mark.skip(reason="persistent schedule switched off: its GPU runs stalled (killed after 180 s of "
+                         "silence, twice) and the cause is not yet shown; the schedule is checked on the CPU")
+@pytest.mark.parametrize("name", ["small_three_level", "root_tiled", "two_level"])
+def test_persistent_schedule_is_bit_identical_to_batched(name):
+    """The persistent fine-first work-queue kernel gives the batched schedule's results bit for bit."""
+    from paper_1112_1710_amd import PERSISTENT
+    spec = getattr(H, name)()
+    _say("persistent schedule", name)
+    field = SmoothField(12)
+    a = Hierarchy(spec, FP64)
+    b = Hierarchy(spec, FP64)
+    a.set_field(field)
+    b.set_field(field)
+    for k in range(3):
+        fixed = 1e-3 if k == 1 else 0.0
+        dt = a.step(BATCHED, fixed)
+        dtp = b.step(PERSISTENT, fixed)
+        assert dt == dtp
+    _assert_same_interiors(spec, a, b)
+    assert b.diag()["phys_flag"] == 0.0

@@ -108,3 +108,55 @@ def test_two_level_workload_bookkeeping():
         assert np.array_equal(h.debug_sources(pid, 0), o.cell_src[pid])
         for d in range(3):
             assert np.array_equal(h.debug_sources(pid, 1 + d), o.face_src[pid][d])
+
+
+@pytest.mark.parametrize("name", ["small_three_level", "root_tiled", "two_level"])
+@pytest.mark.parametrize("fixed_dt", [False, True])
+def test_persistent_schedule_claims_complete(name, fixed_dt):
+    """Simulate the fine-first claim protocol on the schedule tables the library builds.
+
+    Virtual workgroups take the first ready item of the finest queue that has one
+    and finish running items in random order; every item must be taken and every
+    node completed (no dependency can block progress).  Predecessors always
+    precede their node (acyclic) and each level's substeps appear 2^l times.
+    """
+    import random
+    _lib()
+    spec = getattr(H, name)()
+    h = binding.Hierarchy(spec, device=None)
+    nodes, preds, items, queues = h.debug_schedule(fixed_dt, 1024)
+    nn = len(nodes)
+    nblk = nodes[:, 8]
+    for v in range(nn):
+        pf, npr = nodes[v, 10], nodes[v, 11]
+        assert np.all(preds[pf:pf + npr] < v)
+    update_op = 9
+    for lv in range(spec.levels()):
+        assert int(np.sum((nodes[:, 0] == update_op) & (nodes[:, 1] == lv))) == 2 ** lv
+    done = np.zeros(nn, dtype=np.int64)
+    heads = np.zeros(len(queues), dtype=np.int64)
+    rng = random.Random(1)
+    running = []
+
+    def ready(v):
+        pf, npr = nodes[v, 10], nodes[v, 11]
+        return all(done[p] >= nblk[p] for p in preds[pf:pf + npr])
+
+    while True:
+        while len(running) < 48:
+            got = None
+            for q in range(len(queues) - 1, -1, -1):
+                f, L = queues[q]
+                if heads[q] < L and ready(items[f + heads[q], 0]):
+                    got = f + heads[q]
+                    heads[q] += 1
+                    break
+            if got is None:
+                break
+            running.append(got)
+        if not running:
+            break
+        it = running.pop(rng.randrange(len(running)))
+        done[items[it, 0]] += items[it, 2] - items[it, 1]
+    assert all(heads[q] >= queues[q][1] for q in range(len(queues)))
+    assert np.array_equal(done, nblk)
