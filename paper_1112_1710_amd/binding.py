@@ -186,6 +186,14 @@ class Hierarchy:
             arrs = [v.double().cpu().numpy() for v in views]
         return np.stack(arrs[:5]), arrs[5:]
 
+    def download_box(self, pid, lo, hi, which=None):
+        """Entries [lo, hi) (padded (x, y, z) indices, node box) of a patch buffer as float64 arrays."""
+        views = self._views(pid, which)
+        sl = (slice(lo[2], hi[2]), slice(lo[1], hi[1]), slice(lo[0], hi[0]))
+        with self._torch.cuda.stream(self.stream):
+            arrs = [v[sl].double().cpu().numpy() for v in views]
+        return np.stack(arrs[:5]), arrs[5:]
+
     def set_field(self, field):
         root = tuple(int(x) for x in self.spec.root_n)
         for pid, (lv, lo, hi) in zip(self.ids, self.spec.patches):
