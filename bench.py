@@ -34,6 +34,7 @@ WORDS_PER_UNIT = {
     "edge": 5 + 1,       # 2 face EMFs, 2 mass fluxes, reference EMF in; edge EMF out
     "update": 26 + 8,    # U (5), fluxes (15), faces (3), edge EMFs (3) in; 8 out
     "copy": 2,           # one element in, one out
+    "primhalf": 1,       # fused prim/bhalf/pred: the library reports its algorithmic words directly
 }
 
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a
@@ -60,12 +61,14 @@ def parse():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="two_level", choices=["two_level", "uniform256", "uniform32", "deep"])
     ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_mixed", "fp64"])
-    ap.add_argument("--mode", default="graph", choices=["plain", "batched", "graph", "persistent"])
+    ap.add_argument("--mode", default="graph", choices=["plain", "batched", "graph", "persistent", "concurrent"])
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="after the timed steps, copy a 512 MiB buffer once (reference dispatch for HBM counters)")
     ap.add_argument("--plain-steps", type=int, default=4, help="steps of the FP64 per-patch-launch comparison")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--staged", action="store_true", help="run the first three advance stages as separate kernels")
+    ap.add_argument("--no-autotune", action="store_true", help="keep the default tile of the fused kernel")
     return ap.parse_args()
 
 
@@ -120,18 +123,26 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_1112_1710_amd import BATCHED, FP32, FP32_MIXED, FP64, GRAPH, PERSISTENT, PLAIN, Hierarchy
+    from paper_1112_1710_amd import BATCHED, CONCURRENT, FP32, FP32_MIXED, FP64, GRAPH, PERSISTENT, PLAIN, Hierarchy
+    from paper_1112_1710_amd.binding import TUNE_FUSED
     prec = {"fp32": FP32, "fp32_mixed": FP32_MIXED, "fp64": FP64}[args.precision]
-    mode = {"plain": PLAIN, "batched": BATCHED, "graph": GRAPH, "persistent": PERSISTENT}[args.mode]
+    mode = {"plain": PLAIN, "batched": BATCHED, "graph": GRAPH, "persistent": PERSISTENT,
+            "concurrent": CONCURRENT}[args.mode]
     spec, field, desc = workload(args.workload)
     zu = spec.zone_updates_per_root_step()
 
     h = Hierarchy(spec, prec)
     h.set_field(field)
+    tiles = None
+    if args.staged:
+        h.tune_set(TUNE_FUSED, 0)
+    elif not args.no_autotune:
+        from paper_1112_1710_amd.autotune import autotune
+        tiles = {lvl: v[1] for lvl, v in autotune(h).items()}
     sec, timing = timed_steps(h, mode, args.steps, args.warmup, torch)
     value = zu / sec
     work = h.step_work()
-    if mode in (GRAPH, PERSISTENT):
+    if mode in (GRAPH, PERSISTENT, CONCURRENT):
         # kernels inside a replayed graph or the persistent kernel are not bracketed by events: take the per-kernel
         # launch times from an instrumented batched pass of the same steps
         _, timing = timed_steps(h, BATCHED, args.steps, 1, torch)
@@ -180,7 +191,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "patches": len(spec.patches), "levels": spec.levels(),
                    "cells": spec.cells(), "zone_updates_per_step": zu, "precision": args.precision,
-                   "schedule": args.mode, "parallelism": "single GPU"},
+                   "schedule": args.mode,
+                   "first_stages": "staged" if args.staged or tiles is None else tiles,
+                   "parallelism": "single GPU"},
         "roofline": roof,
         "kernel_ms_per_step": per_class,
     }

@@ -74,9 +74,15 @@ enum {
   AMRX_PLAIN = 0,     /* every stage launched separately for every patch */
   AMRX_BATCHED = 1,   /* every stage launched once for all patches of a level substep */
   AMRX_GRAPH = 2,     /* AMRX_BATCHED captured once into a HIP graph and replayed */
-  AMRX_PERSISTENT = 3 /* one launch of a persistent work-queue kernel per root step: every
+  AMRX_PERSISTENT = 3,/* one launch of a persistent work-queue kernel per root step: every
                          batched launch becomes a node of a dependency graph, levels run
                          concurrently and ready work of finer levels is taken first (Sec. 4) */
+  AMRX_CONCURRENT = 4 /* the same dependency graph of batched launches captured into a HIP graph
+                         with one branch per level: launches of different levels that touch
+                         disjoint data run concurrently (Sec. 4: coarser levels fill the gaps
+                         left by finer ones); replayed like AMRX_GRAPH.
+                         AMRX_PERSISTENT and AMRX_CONCURRENT are disabled in this build
+                         (hier_step returns EINVAL for them). */
 };
 
 typedef struct amrx_hier amrx_hier;
@@ -105,7 +111,9 @@ const char* hier_last_error(const amrx_hier* h);
  * Level-0 patches must tile the root grid (checked by hier_finalize).  On
  * levels >= 1, lo and hi must be even and the box must lie inside exactly one
  * level-(l-1) patch's interior shrunk by one parent cell; same-level boxes
- * must not overlap.  Pure host call.  Errors: EINVAL, ENEST, EOVERLAP, ESTATE. */
+ * must not overlap.  A patch's ghost-padded volume prod(hi - lo + 9) must stay
+ * below 2^31 entries (EINVAL otherwise).  Pure host call.  Errors: EINVAL,
+ * ENEST, EOVERLAP, ESTATE. */
 int patch_add(amrx_hier* h, int level, const int lo[3], const int hi[3], int* patch_id);
 
 /* Freeze the topology and build every index list (ghost sources, prolongation
@@ -180,7 +188,9 @@ int hier_diag(amrx_hier* h, double* out, int n);
 enum {
   AMRX_K_PRIM = 0, AMRX_K_BHALF, AMRX_K_PRED, AMRX_K_FLUX, AMRX_K_EDGE, AMRX_K_UPDATE,
   AMRX_K_COPY, AMRX_K_PROLONG, AMRX_K_RESTRICT, AMRX_K_FLUXCORR, AMRX_K_EMFCORR, AMRX_K_SYNC,
-  AMRX_K_CFL, AMRX_K_CONS, AMRX_NKCLASS
+  AMRX_K_CFL, AMRX_K_CONS,
+  AMRX_K_PRIMHALF,   /* stages prim, bhalf and pred fused into one LDS-tiled kernel */
+  AMRX_NKCLASS
 };
 
 /* Measurement support.  hier_timing_enable(h, 1) starts recording a HIP event
@@ -197,9 +207,38 @@ int hier_timing_read(amrx_hier* h, int n, double* total_ms, int* launches);
  * units[k] = number of entries the class processes (cells, faces, edges or
  * nodes of the stage regions; copied elements for AMRX_K_COPY; parent cells
  * for AMRX_K_PROLONG; coarse nodes for AMRX_K_RESTRICT; list entries for
- * the corrections and synchronisation; interior cells for AMRX_K_CFL), and
- * launches[k] = kernel launches of that class in the batched schedule. */
+ * the corrections and synchronisation; interior cells for AMRX_K_CFL;
+ * algorithmic words for AMRX_K_PRIMHALF: 8 read and 8 written per cell of the
+ * primitive region, 14 written per cell of the half-step region), and
+ * launches[k] = kernel launches of that class in the batched schedule, for
+ * the current tuning (the staged or the fused first three stages). */
 int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
+
+/* Launch tuning (autotuner hooks).  Per level, the first three advance
+ * stages run either as three staged kernels (the default) or as one kernel
+ * over tiles of the primitive region staged through LDS, with a tile shape
+ * from a fixed table.  Both give bit-identical results.
+ *   AMRX_TUNE_FUSED: 0 staged, 1 fused
+ *   AMRX_TUNE_TILE:  index into the tile table
+ * level = -1 sets every level.  Pure host calls (captured graph-schedule steps
+ * are discarded on a change).  EINVAL for a bad parameter, level or index, or
+ * a tile whose LDS footprint exceeds the limit for the hierarchy's precision. */
+enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1 };
+int hier_tune_set(amrx_hier* h, int level, int param, int value);
+int hier_tune_get(const amrx_hier* h, int level, int param, int* value);
+
+/* The tile table: n_tiles receives its length; if shapes is non-NULL it
+ * receives up to cap (tx, ty, tz) triples and lds_bytes (if non-NULL) the LDS
+ * bytes per workgroup of each tile at `precision` (0 where the tile is not
+ * allowed at that precision).  Pure host call. */
+int hier_tile_table(int precision, int* n_tiles, int* shapes, int* lds_bytes, int cap);
+
+/* Time the first three stages of (level, substep): the fused kernel with
+ * tile `tile`, or the three staged kernels for tile = -1; `reps` repetitions
+ * on desc.stream bracketed by HIP events; *ms = mean device time per
+ * repetition.  Writes only intermediate scratch, never the state (so it may
+ * run between steps).  Synchronising.  Needs hier_bind. */
+int hier_tune_time(amrx_hier* h, int level, int substep, int tile, int reps, double* ms);
 
 /* Debug / test exports (pure host, after hier_finalize).  For every padded
  * cell (kind 0) or face normal to axis kind-1 (kind 1..3) of a patch, in

@@ -1,0 +1,127 @@
+"""Autotuner for the first three advance stages (primitives, half-step face
+field, Hancock predictor).
+
+For every level of a bound hierarchy the candidates are the three staged
+kernels and the fused LDS-tiled kernel with each tile shape of the library's
+table that fits the LDS limit at the hierarchy's precision.  Each is timed on
+the level's own patches (``hier_tune_time``: only these kernels, writing only
+intermediate scratch, so the state is untouched), summed over the level's
+substeps; the fastest is selected with ``hier_tune_set``.  All candidates give
+bit-identical results.
+
+Choices are cached in a JSON file keyed by GPU architecture, precision and a
+size class of the level (patch count and the median side of the patches'
+primitive regions, each rounded to a power of two), so a later hierarchy of the
+same shape class skips the search.  The cache lives at ``$AMRX_TUNE_CACHE`` if
+set, else ``~/.cache/amrx/tune.json``.
+"""
+import json
+import os
+
+from .binding import TUNE_FUSED, TUNE_TILE, tile_table
+
+G = 4
+
+
+def _pow2(x):
+    p = 1
+    while p < x:
+        p <<= 1
+    return p
+
+
+def size_class(spec, level):
+    """Patch count and median primitive-region side of `level`, each rounded up to a power of two."""
+    sides = []
+    count = 0
+    for (lv, lo, hi) in spec.patches:
+        if lv != level:
+            continue
+        count += 1
+        grow = 0 if level == 0 else 2
+        for a in range(3):
+            sides.append(hi[a] - lo[a] + 2 * grow + 4)
+    sides.sort()
+    med = sides[len(sides) // 2] if sides else 0
+    return f"n{_pow2(count)}-s{_pow2(med)}"
+
+
+def arch_name(device=0):
+    import torch
+    props = torch.cuda.get_device_properties(device)
+    return getattr(props, "gcnArchName", props.name).split(":")[0]
+
+
+def cache_path():
+    return os.environ.get("AMRX_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "amrx", "tune.json"))
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def _store(path, data):
+    try:
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        tmp = path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump(data, f, indent=1, sort_keys=True)
+        os.replace(tmp, path)
+    except OSError:
+        pass  # a read-only home only costs a repeated search
+
+
+STAGED = -1
+
+
+def _apply(h, level, choice):
+    if choice == STAGED:
+        h.tune_set(TUNE_FUSED, 0, level)
+    else:
+        h.tune_set(TUNE_FUSED, 1, level)
+        h.tune_set(TUNE_TILE, choice, level)
+
+
+def _shape(table, choice):
+    return "staged" if choice == STAGED else "x".join(str(x) for x in table[choice][:3])
+
+
+def autotune(h, reps=5, use_cache=True, path=None):
+    """Select staged or fused (and the tile) for every level of the bound hierarchy `h`.
+
+    Returns {level: (choice, shape, ms, source)}: choice -1 = staged, else the tile index; shape "staged" or
+    "TXxTYxTZ"; ms the summed time of the level's substeps; source "search" or "cache".
+    """
+    path = path or cache_path()
+    cache = _load(path) if use_cache else {}
+    table = tile_table(h.precision)
+    candidates = [STAGED] + [t for t, (_, _, _, lds) in enumerate(table) if lds > 0]
+    arch = arch_name()
+    levels = 1 + max(p[0] for p in h.spec.patches)
+    out = {}
+    changed = False
+    for level in range(levels):
+        key = f"{arch}|p{h.precision}|l{min(level, 1)}|{size_class(h.spec, level)}"
+        hit = cache.get(key)
+        if hit is not None and hit.get("choice") in candidates and hit.get("shape") == _shape(table, hit["choice"]):
+            _apply(h, level, hit["choice"])
+            out[level] = (hit["choice"], hit["shape"], hit.get("ms"), "cache")
+            continue
+        nsub = 1 if level == 0 else 2
+        times = {}
+        for t in candidates:
+            h.tune_time(level, 0, t, 1)  # warm-up
+            times[t] = sum(h.tune_time(level, s, t, reps) for s in range(nsub))
+        best = min(times, key=times.get)
+        _apply(h, level, best)
+        out[level] = (best, _shape(table, best), times[best], "search")
+        cache[key] = {"choice": best, "shape": _shape(table, best), "ms": times[best],
+                      "candidates": {_shape(table, t): times[t] for t in times}}
+        changed = True
+    if use_cache and changed:
+        _store(path, cache)
+    return out

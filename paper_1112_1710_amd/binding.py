@@ -10,11 +10,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libamrx.so")
 
 FP64, FP32, FP32_MIXED = 0, 1, 2
-PLAIN, BATCHED, GRAPH, PERSISTENT = 0, 1, 2, 3
+PLAIN, BATCHED, GRAPH, PERSISTENT, CONCURRENT = 0, 1, 2, 3, 4
 G = 4
 
 KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
-                  "fluxcorr", "emfcorr", "sync", "cfl", "cons")
+                  "fluxcorr", "emfcorr", "sync", "cfl", "cons", "primhalf")
+TUNE_FUSED, TUNE_TILE = 0, 1
 
 _ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
 
@@ -56,7 +57,23 @@ EXPORTS = {
                              C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hier_debug_sources": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_longlong)], C.c_int),
     "hier_debug_prolong_cells": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int], C.c_int),
+    "hier_tune_set": ([C.c_void_p, C.c_int, C.c_int, C.c_int], C.c_int),
+    "hier_tune_get": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int)], C.c_int),
+    "hier_tile_table": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int], C.c_int),
+    "hier_tune_time": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
 }
+
+
+def tile_table(precision):
+    """[(tx, ty, tz, lds_bytes)] of the fused first-three-stage kernel; lds_bytes 0 = not allowed."""
+    lib = load_library()
+    n = C.c_int()
+    if lib.hier_tile_table(precision, C.byref(n), None, None, 0) != 0:
+        raise AmrxError(-1, "hier_tile_table")
+    shapes = (C.c_int * (3 * n.value))()
+    lds = (C.c_int * n.value)()
+    lib.hier_tile_table(precision, C.byref(n), shapes, lds, n.value)
+    return [(shapes[3 * t], shapes[3 * t + 1], shapes[3 * t + 2], lds[t]) for t in range(n.value)]
 
 
 def load_library(path=LIB_PATH):
@@ -256,6 +273,21 @@ class Hierarchy:
         cnt = (C.c_int * n)()
         self._check(self.lib.hier_step_work(self.h, n, u, cnt))
         return {k: (u[i], cnt[i]) for i, k in enumerate(KERNEL_CLASSES)}
+
+    # ------------------------------------------------------------------ tuning
+    def tune_set(self, param, value, level=-1):
+        """Set a tuning parameter for `level` (-1: every level)."""
+        self._check(self.lib.hier_tune_set(self.h, level, param, int(value)))
+
+    def tune_get(self, param, level=0):
+        v = C.c_int()
+        self._check(self.lib.hier_tune_get(self.h, level, param, C.byref(v)))
+        return v.value
+
+    def tune_time(self, level, substep, tile, reps=5):
+        ms = C.c_double()
+        self._check(self.lib.hier_tune_time(self.h, level, substep, tile, reps, C.byref(ms)))
+        return ms.value
 
     # ------------------------------------------------------------------ bookkeeping exports
     def debug_sources(self, pid, kind):

@@ -30,6 +30,21 @@ namespace {
 // ---------------------------------------------------------------------------
 // small helpers
 // ---------------------------------------------------------------------------
+// Division, reciprocal and square root.  FP64 keeps the IEEE operations.
+// FP32 uses the hardware reciprocal refined by one Newton step (error within
+// about 1 ulp, against several instructions of scaling and fix-up for a
+// correctly rounded quotient) and the hardware square root (1 ulp); FP32
+// results are held to a relative L1 tolerance of 1e-5, far above that.
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rcp(float x) {
+  const float r = __builtin_amdgcn_rcpf(x);
+  return fmaf(fmaf(-x, r, 1.0f), r, r);
+}
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ float qdiv(float a, float b) { return a * rcp(b); }
+__device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
+__device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+
 template <typename R>
 __device__ __forceinline__ R mc_limit(R dm, R dp) {
   // monotonised central: minmod(2 dm, 2 dp, (dm + dp)/2), zero unless dm, dp share a strict sign
@@ -61,7 +76,7 @@ __device__ __forceinline__ R pressure(R rho, R mx, R my, R mz, R e, R bx, R by, 
     double mag = 0.5 * ((double)bx * bx + (double)by * by + (double)bz * bz);
     return (R)((double)gm1 * ((double)e - kin - mag));
   } else {
-    R kin = R(0.5) * (mx * mx + my * my + mz * mz) / rho;
+    R kin = qdiv(R(0.5) * (mx * mx + my * my + mz * mz), rho);
     R mag = R(0.5) * (bx * bx + by * by + bz * bz);
     return gm1 * (e - kin - mag);
   }
@@ -69,11 +84,12 @@ __device__ __forceinline__ R pressure(R rho, R mx, R my, R mz, R e, R bx, R by, 
 
 template <typename R>
 __device__ __forceinline__ R fast_speed(R rho, R p, R b2, R bn2, R gamma) {
-  R a2 = gamma * p / rho;
-  R s = a2 + b2 / rho;
-  R disc = s * s - R(4) * a2 * bn2 / rho;
+  const R ir = rcp(rho);
+  R a2 = gamma * p * ir;
+  R s = a2 + b2 * ir;
+  R disc = s * s - R(4) * a2 * bn2 * ir;
   disc = disc > R(0) ? disc : R(0);
-  return sqrt(R(0.5) * (s + sqrt(disc)));
+  return qsqrt(R(0.5) * (s + qsqrt(disc)));
 }
 
 // primitive w = (rho, vx, vy, vz, p, Bx, By, Bz) -> physical flux along D (global component order)
@@ -85,7 +101,7 @@ __device__ __forceinline__ void phys_flux(const R* w, R gm1, R* f) {
   const R un = w[1 + D], bn = w[5 + D];
   const R bb = b0 * b0 + b1 * b1 + b2 * b2;
   const R pt = p + R(0.5) * bb;
-  const R e = p / gm1 + R(0.5) * rho * (v0 * v0 + v1 * v1 + v2 * v2) + R(0.5) * bb;
+  const R e = qdiv(p, gm1) + R(0.5) * rho * (v0 * v0 + v1 * v1 + v2 * v2) + R(0.5) * bb;
   const R vb = v0 * b0 + v1 * b1 + v2 * b2;
   f[0] = rho * un;
   f[1] = rho * v0 * un - b0 * bn;
@@ -106,7 +122,7 @@ __device__ __forceinline__ void to_cons(const R* w, R gm1, R* u) {
   u[1] = w[0] * w[1];
   u[2] = w[0] * w[2];
   u[3] = w[0] * w[3];
-  u[4] = w[4] / gm1 + R(0.5) * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) +
+  u[4] = qdiv(w[4], gm1) + R(0.5) * w[0] * (w[1] * w[1] + w[2] * w[2] + w[3] * w[3]) +
          R(0.5) * (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]);
   u[5] = w[5];
   u[6] = w[6];
@@ -116,9 +132,9 @@ __device__ __forceinline__ void to_cons(const R* w, R gm1, R* u) {
 template <typename R, bool MIX>
 __device__ __forceinline__ void to_prim(const R* u, R gm1, R* w) {
   w[0] = u[0];
-  w[1] = u[1] / u[0];
-  w[2] = u[2] / u[0];
-  w[3] = u[3] / u[0];
+  w[1] = qdiv(u[1], u[0]);
+  w[2] = qdiv(u[2], u[0]);
+  w[3] = qdiv(u[3], u[0]);
   w[4] = pressure<R, MIX>(u[0], u[1], u[2], u[3], u[4], u[5], u[6], u[7], gm1);
   w[5] = u[5];
   w[6] = u[6];
@@ -142,8 +158,8 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
   const R sr = fmax(ul, ur) + cmax;
   const R ptl = pl + R(0.5) * b2l;
   const R ptr = pr + R(0.5) * b2r;
-  const R el = pl / gm1 + R(0.5) * rl * (ul * ul + vl * vl + zl * zl) + R(0.5) * b2l;
-  const R er = pr / gm1 + R(0.5) * rr * (ur * ur + vr * vr + zr * zr) + R(0.5) * b2r;
+  const R el = qdiv(pl, gm1) + R(0.5) * rl * (ul * ul + vl * vl + zl * zl) + R(0.5) * b2l;
+  const R er = qdiv(pr, gm1) + R(0.5) * rr * (ur * ur + vr * vr + zr * zr) + R(0.5) * b2r;
   const R vbl = ul * bn + vl * byl + zl * bzl;
   const R vbr = ur * bn + vr * byr + zr * bzr;
 
@@ -167,10 +183,10 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
   } else {
     const R sdl = sl - ul, sdr = sr - ur;
     const R den = sdr * rr - sdl * rl;
-    const R sm = (sdr * rr * ur - sdl * rl * ul - ptr + ptl) / den;
-    const R pts = (sdr * rr * ptl - sdl * rl * ptr + rl * rr * sdr * sdl * (ur - ul)) / den;
+    const R sm = qdiv(sdr * rr * ur - sdl * rl * ul - ptr + ptl, den);
+    const R pts = qdiv(sdr * rr * ptl - sdl * rl * ptr + rl * rr * sdr * sdl * (ur - ul), den);
     // left star state
-    const R rls = rl * sdl / (sl - sm);
+    const R rls = qdiv(rl * sdl, sl - sm);
     R vls, zls, byls, bzls;
     {
       const R dn = rl * sdl * (sl - sm) - bn2;
@@ -178,16 +194,16 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
         vls = vl; zls = zl; byls = byl; bzls = bzl;
       } else {
         const R num = rl * sdl * sdl - bn2;
-        vls = vl - bn * byl * (sm - ul) / dn;
-        zls = zl - bn * bzl * (sm - ul) / dn;
-        byls = byl * num / dn;
-        bzls = bzl * num / dn;
+        vls = vl - qdiv(bn * byl * (sm - ul), dn);
+        zls = zl - qdiv(bn * bzl * (sm - ul), dn);
+        byls = qdiv(byl * num, dn);
+        bzls = qdiv(bzl * num, dn);
       }
     }
     const R vbls = sm * bn + vls * byls + zls * bzls;
-    const R els = (sdl * el - ptl * ul + pts * sm + bn * (vbl - vbls)) / (sl - sm);
+    const R els = qdiv(sdl * el - ptl * ul + pts * sm + bn * (vbl - vbls), sl - sm);
     // right star state
-    const R rrs = rr * sdr / (sr - sm);
+    const R rrs = qdiv(rr * sdr, sr - sm);
     R vrs, zrs, byrs, bzrs;
     {
       const R dn = rr * sdr * (sr - sm) - bn2;
@@ -195,20 +211,20 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
         vrs = vr; zrs = zr; byrs = byr; bzrs = bzr;
       } else {
         const R num = rr * sdr * sdr - bn2;
-        vrs = vr - bn * byr * (sm - ur) / dn;
-        zrs = zr - bn * bzr * (sm - ur) / dn;
-        byrs = byr * num / dn;
-        bzrs = bzr * num / dn;
+        vrs = vr - qdiv(bn * byr * (sm - ur), dn);
+        zrs = zr - qdiv(bn * bzr * (sm - ur), dn);
+        byrs = qdiv(byr * num, dn);
+        bzrs = qdiv(bzr * num, dn);
       }
     }
     const R vbrs = sm * bn + vrs * byrs + zrs * bzrs;
-    const R ers = (sdr * er - ptr * ur + pts * sm + bn * (vbr - vbrs)) / (sr - sm);
+    const R ers = qdiv(sdr * er - ptr * ur + pts * sm + bn * (vbr - vbrs), sr - sm);
 
     const bool skip = bn2 <= R(1e-12) * (ptl + ptr);
-    const R sql = sqrt(rls), sqr = sqrt(rrs);
+    const R sql = qsqrt(rls), sqr = qsqrt(rrs);
     const R abn = fabs(bn);
-    const R ssl = skip ? sm : sm - abn / sql;
-    const R ssr = skip ? sm : sm + abn / sqr;
+    const R ssl = skip ? sm : sm - qdiv(abn, sql);
+    const R ssr = skip ? sm : sm + qdiv(abn, sqr);
     const bool left = sm >= R(0);
     // star flux of the side that holds x/t = 0
     R us[7], uo[7], fo[7], s_out;
@@ -230,7 +246,7 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
     if (!skip && !in_star) {
       // double-star state of the same side
       const R sgn = bn > R(0) ? R(1) : (bn < R(0) ? R(-1) : R(0));
-      const R inv = R(1) / (sql + sqr);
+      const R inv = rcp(sql + sqr);
       const R vss = (sql * vls + sqr * vrs + (byrs - byls) * sgn) * inv;
       const R zss = (sql * zls + sqr * zrs + (bzrs - bzls) * sgn) * inv;
       const R byss = (sql * byrs + sqr * byls + sql * sqr * (vrs - vls) * sgn) * inv;
@@ -292,13 +308,16 @@ __device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, int b,
   }
   const int t = first + lo;
   const Task& T = c.tasks[t];
-  const long long ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
-  const long long local = (long long)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
+  // a region lies inside one padded patch, whose volume the host keeps below 2^31 entries
+  const unsigned ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
+  const unsigned local = (unsigned)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
   if (local >= ex * ey * ez) return false;
   w.task = t;
-  w.i = T.lo[0] + (int)(local % ex);
-  w.j = T.lo[1] + (int)((local / ex) % ey);
-  w.k = T.lo[2] + (int)(local / (ex * ey));
+  const unsigned row = local / ex;
+  const unsigned k = row / ey;
+  w.i = T.lo[0] + (int)(local - row * ex);
+  w.j = T.lo[1] + (int)(row - k * ey);
+  w.k = T.lo[2] + (int)k;
   return true;
 }
 
@@ -385,7 +404,7 @@ __device__ __forceinline__ void d_prim(const DevCtx& c, int vb, int nb, int firs
   const R bx = R(0.5) * (U[5 * v + q] + U[5 * v + q + 1]);
   const R by = R(0.5) * (U[6 * v + q] + U[6 * v + q + S.s[1]]);
   const R bz = R(0.5) * (U[7 * v + q] + U[7 * v + q + S.s[2]]);
-  const R vx = mx / rho, vy = my / rho, vz = mz / rho;
+  const R vx = qdiv(mx, rho), vy = qdiv(my, rho), vz = qdiv(mz, rho);
   const R pr = pressure<R, MIX>(rho, mx, my, mz, e, bx, by, bz, gm1);
   if (!(rho > R(0)) || !(pr > R(0)) || !isfinite(e)) flag_phys(c.slots);
   const R wv[8] = {rho, vx, vy, vz, pr, bx, by, bz};
@@ -498,9 +517,9 @@ __device__ __forceinline__ void d_pred(const DevCtx& c, int vb, int nb, int firs
   // half-step velocity and face-averaged half-step field -> reference EMF
   const R* BH = X + SCR_BH * v;
   const R rho = U[q] + du[0];
-  const R vx = (U[v + q] + du[1]) / rho;
-  const R vy = (U[2 * v + q] + du[2]) / rho;
-  const R vz = (U[3 * v + q] + du[3]) / rho;
+  const R vx = qdiv(U[v + q] + du[1], rho);
+  const R vy = qdiv(U[2 * v + q] + du[2], rho);
+  const R vz = qdiv(U[3 * v + q] + du[3], rho);
   const R bx = R(0.5) * (BH[q] + BH[q + 1]);
   const R by = R(0.5) * (BH[v + q] + BH[v + q + S.s[1]]);
   const R bz = R(0.5) * (BH[2 * v + q] + BH[2 * v + q + S.s[2]]);
@@ -513,6 +532,187 @@ __device__ __forceinline__ void d_pred(const DevCtx& c, int vb, int nb, int firs
 template <typename R, bool MIX>
 __global__ __launch_bounds__(AMRX_BLOCK) void k_pred(DevCtx c, int first, int n, int cur, int level) {
   d_pred<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level);
+}
+
+// ---------------------------------------------------------------------------
+// stages 1-3 fused: one workgroup per tile of the primitive region (the update
+// region grown by 2).  The primitives and cell EMFs of the tile and a one-cell
+// halo are computed into LDS, the half-step face field of the tile's faces
+// from them, then the Hancock increments and reference EMFs of the tile's
+// cells that lie in the update region grown by 1.  Results are bit-identical
+// to the three staged kernels (same operations in the same order); the cell
+// EMFs never reach HBM and the primitives are read back from LDS.
+// ---------------------------------------------------------------------------
+template <typename R>
+__device__ __forceinline__ R ebar_l(const R* ec, int q, int sa, int sc) {
+  return R(0.25) * (ec[q] + ec[q - sa] + ec[q - sc] + ec[q - sa - sc]);
+}
+
+template <int D, typename R>
+__device__ __forceinline__ R bhalf_lds(R face, const R* sE, int HV, int hq, const int hs[3], R half_dt_dx) {
+  constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
+  const R* ecC = sE + C * HV;
+  const R* ecA = sE + A * HV;
+  const R eC0 = ebar_l(ecC, hq, hs[D], hs[A]);
+  const R eC1 = ebar_l(ecC, hq + hs[A], hs[D], hs[A]);
+  const R eA0 = ebar_l(ecA, hq, hs[C], hs[D]);
+  const R eA1 = ebar_l(ecA, hq + hs[C], hs[C], hs[D]);
+  const R curl = (eC1 - eC0) - (eA1 - eA0);
+  return face - half_dt_dx * curl;
+}
+
+template <int D, typename R>
+__device__ __forceinline__ void hancock_lds(const R* sW, int HV, int hq, int sd, const R* w0, R gm1, R half_dt_dx,
+                                            R* du) {
+  R wm[8], wp[8], f1[8], f2[8];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    wm[m] = sW[m * HV + hq - sd];
+    wp[m] = sW[m * HV + hq + sd];
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) {
+    const R s = mc_limit(w0[m] - wm[m], wp[m] - w0[m]);
+    wp[m] = w0[m] + R(0.5) * s;
+    wm[m] = w0[m] - R(0.5) * s;
+  }
+  phys_flux<D>(wp, gm1, f1);
+  phys_flux<D>(wm, gm1, f2);
+#pragma unroll
+  for (int m = 0; m < 8; ++m) du[m] -= half_dt_dx * (f1[m] - f2[m]);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_fused_a(DevCtx c, int first, int n, int cur, int level, int tx, int ty,
+                                                         int tz) {
+  extern __shared__ double smem_d[];
+  R* sm = reinterpret_cast<R*>(smem_d);
+  const int nthr = blockDim.x;
+  const int vb = xcd_block(blockIdx.x, gridDim.x);
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (c.blk[first + mid] <= vb) lo = mid; else hi = mid - 1;
+  }
+  const Task& T = c.tasks[first + lo];
+  const int tile = vb - c.blk[first + lo];
+  const int ntx = (T.hi[0] - T.lo[0] + tx - 1) / tx, nty = (T.hi[1] - T.lo[1] + ty - 1) / ty;
+  const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
+  const int o[3] = {T.lo[0] + tix * tx, T.lo[1] + tiy * ty, T.lo[2] + tiz * tz};
+  const int e[3] = {min(tx, T.hi[0] - o[0]), min(ty, T.hi[1] - o[1]), min(tz, T.hi[2] - o[2])};
+  // region grown by 1 (the half-step region): the task region shrunk by one cell
+  const int lo1[3] = {T.lo[0] + 1, T.lo[1] + 1, T.lo[2] + 1};
+  const int hi1[3] = {T.hi[0] - 1, T.hi[1] - 1, T.hi[2] - 1};
+
+  const PatchDev& p = c.patches[T.patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  R* X = (R*)c.rscr + p.scr;
+  const long long v = S.v;
+  const R gm1 = R(c.gamma) - R(1);
+  const double dt = level_dt(c, level);
+  const R h = R(0.5 * dt / p.dx);
+
+  const int H0 = tx + 2, H1 = ty + 2, H2 = tz + 2;
+  const int HV = H0 * H1 * H2;
+  const int hs[3] = {1, H0, H0 * H1};
+  const int N0 = tx + 1, N1 = ty + 1;
+  const int NB = N0 * N1 * (tz + 1);
+  const int ns[3] = {1, N0, N0 * N1};
+  R* sW = sm;            // 8 x HV primitives
+  R* sE = sW + 8 * HV;   // 3 x HV cell EMFs
+  R* sB = sE + 3 * HV;   // 3 x NB half-step face field (low faces of the tile's cells + one layer)
+
+  // 1. primitives and cell EMFs of the tile and its halo (cells that exist in the padded arrays)
+  for (int t = threadIdx.x; t < HV; t += nthr) {
+    const int hx = t % H0, r = t / H0, hy = r % H1, hz = r / H1;
+    const int i = o[0] - 1 + hx, j = o[1] - 1 + hy, k = o[2] - 1 + hz;
+    if (i < 0 || j < 0 || k < 0 || i >= p.dim[0] - 1 || j >= p.dim[1] - 1 || k >= p.dim[2] - 1) continue;
+    const long long q = i + j * S.s[1] + k * S.s[2];
+    const R rho = U[q], mx = U[v + q], my = U[2 * v + q], mz = U[3 * v + q], en = U[4 * v + q];
+    const R bx = R(0.5) * (U[5 * v + q] + U[5 * v + q + 1]);
+    const R by = R(0.5) * (U[6 * v + q] + U[6 * v + q + S.s[1]]);
+    const R bz = R(0.5) * (U[7 * v + q] + U[7 * v + q + S.s[2]]);
+    const R vx = qdiv(mx, rho), vy = qdiv(my, rho), vz = qdiv(mz, rho);
+    const R pr = pressure<R, MIX>(rho, mx, my, mz, en, bx, by, bz, gm1);
+    const R wv[8] = {rho, vx, vy, vz, pr, bx, by, bz};
+#pragma unroll
+    for (int m = 0; m < 8; ++m) sW[m * HV + t] = wv[m];
+    sE[t] = -(vy * bz - vz * by);
+    sE[HV + t] = -(vz * bx - vx * bz);
+    sE[2 * HV + t] = -(vx * by - vy * bx);
+    if (hx >= 1 && hx <= e[0] && hy >= 1 && hy <= e[1] && hz >= 1 && hz <= e[2]) {
+      if (!(rho > R(0)) || !(pr > R(0)) || !isfinite(en)) flag_phys(c.slots);
+      st8(X + SCR_W * v + 8 * q, wv);
+    }
+  }
+  __syncthreads();
+
+  // 2. half-step normal field on the faces of the half-step region's cells
+  R* BH = X + SCR_BH * v;
+  for (int t = threadIdx.x; t < NB; t += nthr) {
+    const int fx = t % N0, r = t / N0, fy = r % N1, fz = r / N1;
+    const int i = o[0] + fx, j = o[1] + fy, k = o[2] + fz;
+    // in_d: a face position along d (low faces of the tile's cells and the next one);
+    // c_d: a cell of the tile along d; both restricted to the half-step region
+    const bool in0 = fx <= e[0] && i >= lo1[0] && i <= hi1[0];
+    const bool in1 = fy <= e[1] && j >= lo1[1] && j <= hi1[1];
+    const bool in2 = fz <= e[2] && k >= lo1[2] && k <= hi1[2];
+    const bool c0 = in0 && fx < e[0] && i < hi1[0];
+    const bool c1 = in1 && fy < e[1] && j < hi1[1];
+    const bool c2 = in2 && fz < e[2] && k < hi1[2];
+    const int hq = (fx + 1) + (fy + 1) * hs[1] + (fz + 1) * hs[2];
+    const long long q = i + j * S.s[1] + k * S.s[2];
+    if (in0 && c1 && c2) {
+      const R b = bhalf_lds<0>(U[5 * v + q], sE, HV, hq, hs, h);
+      sB[t] = b;
+      if (fx < e[0]) BH[q] = b;
+    }
+    if (c0 && in1 && c2) {
+      const R b = bhalf_lds<1>(U[6 * v + q], sE, HV, hq, hs, h);
+      sB[NB + t] = b;
+      if (fy < e[1]) BH[v + q] = b;
+    }
+    if (c0 && c1 && in2) {
+      const R b = bhalf_lds<2>(U[7 * v + q], sE, HV, hq, hs, h);
+      sB[2 * NB + t] = b;
+      if (fz < e[2]) BH[2 * v + q] = b;
+    }
+  }
+  __syncthreads();
+
+  // 3. Hancock increments and reference EMFs of the tile's cells in the half-step region
+  const int CV = tx * ty * tz;
+  for (int t = threadIdx.x; t < CV; t += nthr) {
+    const int cx = t % tx, r = t / tx, cy = r % ty, cz = r / ty;
+    if (cx >= e[0] || cy >= e[1] || cz >= e[2]) continue;
+    const int i = o[0] + cx, j = o[1] + cy, k = o[2] + cz;
+    if (i < lo1[0] || i >= hi1[0] || j < lo1[1] || j >= hi1[1] || k < lo1[2] || k >= hi1[2]) continue;
+    const int hq = (cx + 1) + (cy + 1) * hs[1] + (cz + 1) * hs[2];
+    const long long q = i + j * S.s[1] + k * S.s[2];
+    R w0[8], du[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      w0[m] = sW[m * HV + hq];
+      du[m] = R(0);
+    }
+    hancock_lds<0>(sW, HV, hq, hs[0], w0, gm1, h, du);
+    hancock_lds<1>(sW, HV, hq, hs[1], w0, gm1, h, du);
+    hancock_lds<2>(sW, HV, hq, hs[2], w0, gm1, h, du);
+    st8(X + SCR_DU * v + 8 * q, du);
+    const int nq = cx + cy * ns[1] + cz * ns[2];
+    const R rho = U[q] + du[0];
+    const R vx = qdiv(U[v + q] + du[1], rho);
+    const R vy = qdiv(U[2 * v + q] + du[2], rho);
+    const R vz = qdiv(U[3 * v + q] + du[3], rho);
+    const R bx = R(0.5) * (sB[nq] + sB[nq + 1]);
+    const R by = R(0.5) * (sB[NB + nq] + sB[NB + nq + ns[1]]);
+    const R bz = R(0.5) * (sB[2 * NB + nq] + sB[2 * NB + nq + ns[2]]);
+    R* ER = X + SCR_ER * v;
+    ER[q] = -(vy * bz - vz * by);
+    ER[v + q] = -(vz * bx - vx * bz);
+    ER[2 * v + q] = -(vx * by - vy * bx);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -964,7 +1164,8 @@ __device__ __forceinline__ void d_flux_corr(const DevCtx& c, int vb, int nb, int
   const int* cov = c.cov + mp.cov;
   const Q* regs = (const Q*)c.reg;
   const long long q = e.lin;
-  const int ijk[3] = {(int)(q % S.s[1]), (int)((q / S.s[1]) % mp.dim[1]), (int)(q / S.s[2])};
+  const unsigned uq = (unsigned)e.lin, row = uq / (unsigned)mp.dim[0], kq = row / (unsigned)mp.dim[1];
+  const int ijk[3] = {(int)(uq - row * (unsigned)mp.dim[0]), (int)(row - kq * (unsigned)mp.dim[1]), (int)kq};
   double corr[5] = {0, 0, 0, 0, 0};
   for (int d = 0; d < 3; ++d) {
     int a1, a2;
@@ -1046,7 +1247,8 @@ __device__ __forceinline__ void d_emf_corr(const DevCtx& c, int vb, int nb, int 
   const long long q = e.lin;
   const int d = e.axis;
   const int A = (d + 1) % 3, C = (d + 2) % 3;
-  const int ijk[3] = {(int)(q % S.s[1]), (int)((q / S.s[1]) % mp.dim[1]), (int)(q / S.s[2])};
+  const unsigned uq = (unsigned)e.lin, row = uq / (unsigned)mp.dim[0], kq = row / (unsigned)mp.dim[1];
+  const int ijk[3] = {(int)(uq - row * (unsigned)mp.dim[0]), (int)(row - kq * (unsigned)mp.dim[1]), (int)kq};
   int nA[3] = {ijk[0], ijk[1], ijk[2]};
   nA[A] += 1;
   int nC[3] = {ijk[0], ijk[1], ijk[2]};
@@ -1124,12 +1326,13 @@ __device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int f
     }
     const int t = first + lo;
     const Task& T = c.tasks[t];
-    const long long ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
-    const long long local = (long long)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
+    const unsigned ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
+    const unsigned local = (unsigned)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
     if (local >= ex * ey * ez) continue;
-    const int i = T.lo[0] + (int)(local % ex);
-    const int j = T.lo[1] + (int)((local / ex) % ey);
-    const int k = T.lo[2] + (int)(local / (ex * ey));
+    const unsigned row = local / ex, kk = row / ey;
+    const int i = T.lo[0] + (int)(local - row * ex);
+    const int j = T.lo[1] + (int)(row - kk * ey);
+    const int k = T.lo[2] + (int)kk;
     const PatchDev& p = c.patches[T.patch];
     const Strides S = strides(p);
     const R* U = (const R*)c.state + p.st[cur];
@@ -1142,7 +1345,7 @@ __device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int f
     const R bz = R(0.5) * (U[7 * v + q] + U[7 * v + q + S.s[2]]);
     const R pr = pressure<R, MIX>(rho, U[v + q], U[2 * v + q], U[3 * v + q], U[4 * v + q], bx, by, bz, gamma - R(1));
     const R b2 = bx * bx + by * by + bz * bz;
-    const R vx = U[v + q] / rho, vy = U[2 * v + q] / rho, vz = U[3 * v + q] / rho;
+    const R vx = qdiv(U[v + q], rho), vy = qdiv(U[2 * v + q], rho), vz = qdiv(U[3 * v + q], rho);
     const R inv = R(1.0 / p.dx);
     const R tot = (fabs(vx) + fast_speed(rho, pr, b2, bx * bx, gamma)) * inv +
                   (fabs(vy) + fast_speed(rho, pr, b2, by * by, gamma)) * inv +
@@ -1427,6 +1630,30 @@ hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, i
     case STAGE_UPDATE: DISPATCH(k_update, g, c, task_first, ntask, cur, level); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+int fused_a_threads(int tx, int ty, int tz) { return tx * ty * tz <= 128 ? 128 : AMRX_BLOCK; }
+
+size_t fused_a_lds_bytes(int precision, int tx, int ty, int tz) {
+  const size_t hv = (size_t)(tx + 2) * (ty + 2) * (tz + 2);
+  const size_t nb = (size_t)(tx + 1) * (ty + 1) * (tz + 1);
+  return (11 * hv + 3 * nb) * (precision == 0 ? sizeof(double) : sizeof(float));
+}
+
+hipError_t launch_fused_a(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, int tx, int ty,
+                          int tz) {
+  if (ntask == 0 || nblk == 0) return hipSuccess;
+  const size_t lds = fused_a_lds_bytes(c.precision, tx, ty, tz);
+  if (lds > AMRX_FUSED_LDS_MAX) return hipErrorInvalidValue;
+  const int nthr = fused_a_threads(tx, ty, tz);
+  const dim3 g(nblk);
+  if (c.precision == 0)
+    k_fused_a<double, false><<<g, nthr, lds, c.stream>>>(c, task_first, ntask, cur, level, tx, ty, tz);
+  else if (c.precision == 1)
+    k_fused_a<float, false><<<g, nthr, lds, c.stream>>>(c, task_first, ntask, cur, level, tx, ty, tz);
+  else
+    k_fused_a<float, true><<<g, nthr, lds, c.stream>>>(c, task_first, ntask, cur, level, tx, ty, tz);
   return hipGetLastError();
 }
 

@@ -1,0 +1,176 @@
+"""The LDS-tiled kernel that fuses the first three advance stages, and its autotuner.
+
+The fused kernel performs the staged kernels' operations in the same order,
+so whole root steps must agree with the staged schedule bit for bit, for
+every tile shape (ragged tiles included: the primitive regions of these
+hierarchies are not multiples of any tile) and every precision.  Parity of
+the fused path with the oracle is covered by the parity tests, which run the
+default (fused) configuration.
+"""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+from oracle import amr  # noqa: E402
+from paper_1112_1710_amd import BATCHED, FP32, FP32_MIXED, FP64, GRAPH, PLAIN, Hierarchy  # noqa: E402
+from paper_1112_1710_amd import binding  # noqa: E402
+from workloads import hierarchies as H  # noqa: E402
+from workloads.fields import SmoothField  # noqa: E402
+
+
+def _say(*a):
+    print(*a, flush=True)
+
+
+def _same_interiors(spec, a, b):
+    o = amr.build(spec)
+    for pid, p in enumerate(o.patches):
+        ca, fa = a.download(pid)
+        cb, fb = b.download(pid)
+        m = o._interior_mask(p)
+        assert np.array_equal(ca[:, m], cb[:, m]), pid
+        for d in range(3):
+            mk = o._closure_mask(p, d)
+            assert np.array_equal(fa[d][mk], fb[d][mk]), (pid, d)
+
+
+def _allowed(prec):
+    return [t for t, row in enumerate(binding.tile_table(prec)) if row[3] > 0]
+
+
+def _cases():
+    try:
+        return [(prec, t) for prec in (FP64, FP32, FP32_MIXED) for t in _allowed(prec)]
+    except ImportError:  # library not built: nothing to parametrize (the CPU suite only collects)
+        return []
+
+
+CASES = _cases()
+
+
+@pytest.mark.parametrize("prec,tile", CASES)
+def test_fused_matches_staged_bit_for_bit(prec, tile):
+    spec = H.small_three_level()
+    _say("fused vs staged", prec, tile, binding.tile_table(prec)[tile][:3])
+    field = SmoothField(21)
+    a = Hierarchy(spec, prec)
+    b = Hierarchy(spec, prec)
+    a.tune_set(binding.TUNE_FUSED, 0)
+    b.tune_set(binding.TUNE_FUSED, 1)
+    for lvl in range(spec.levels()):
+        b.tune_set(binding.TUNE_TILE, tile, level=lvl)
+    a.set_field(field)
+    b.set_field(field)
+    for _ in range(2):
+        dt = a.step(BATCHED)
+        dtb = b.step(BATCHED)
+        assert dt == dtb
+    _same_interiors(spec, a, b)
+    assert b.diag()["phys_flag"] == 0
+
+
+@pytest.mark.parametrize("name", ["root_tiled", "single32"])
+def test_fused_plain_and_graph_schedules(name):
+    spec = H.single_patch(32) if name == "single32" else getattr(H, name)()
+    _say("fused plain/graph", name)
+    field = SmoothField(22)
+    ref = Hierarchy(spec, FP32)
+    ref.tune_set(binding.TUNE_FUSED, 0)
+    pl = Hierarchy(spec, FP32)
+    gr = Hierarchy(spec, FP32)
+    for h in (pl, gr):
+        h.tune_set(binding.TUNE_FUSED, 1)
+        h.tune_set(binding.TUNE_TILE, 7)  # 24x8x2: ragged in x on these patches
+    for h in (ref, pl, gr):
+        h.set_field(field)
+    for _ in range(3):
+        dt = ref.step(BATCHED)
+        assert pl.step(PLAIN) == dt
+        assert gr.step(GRAPH) == dt
+    _same_interiors(spec, ref, pl)
+    _same_interiors(spec, ref, gr)
+
+
+def test_autotune_selects_allowed_tiles_and_keeps_results(tmp_path):
+    from paper_1112_1710_amd.autotune import autotune
+    spec = H.small_three_level()
+    _say("autotune")
+    field = SmoothField(23)
+    a = Hierarchy(spec, FP32)
+    b = Hierarchy(spec, FP32)
+    a.tune_set(binding.TUNE_FUSED, 0)
+    a.set_field(field)
+    b.set_field(field)
+    cache = str(tmp_path / "tune.json")
+    chosen = autotune(b, reps=2, path=cache)
+    allowed = _allowed(FP32)
+    assert sorted(chosen) == list(range(spec.levels()))
+    for lvl, (t, shape, ms, src) in chosen.items():
+        assert (t == -1 or t in allowed) and src == "search" and ms > 0
+        assert b.tune_get(binding.TUNE_FUSED, level=lvl) == (0 if t == -1 else 1)
+        if t >= 0:
+            assert b.tune_get(binding.TUNE_TILE, level=lvl) == t
+    again = autotune(b, reps=2, path=cache)
+    assert all(v[3] == "cache" and v[0] == chosen[k][0] for k, v in again.items())
+    # timing runs touch only intermediates: the state still gives the staged result
+    for _ in range(2):
+        assert a.step(BATCHED) == b.step(GRAPH)
+    _same_interiors(spec, a, b)
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32])
+def test_fused_path_matches_oracle(prec):
+    """One root step with every level fused against the oracle (per-field relative L1, as the parity tests)."""
+    from ._common import FIELDS, oracle_from, rel_l1, upload_oracle_state
+    spec = H.small_three_level()
+    _say("fused vs oracle", prec)
+    o = oracle_from(spec, SmoothField(24), round32=prec != FP64)
+    h = Hierarchy(spec, prec)
+    h.tune_set(binding.TUNE_FUSED, 1)
+    upload_oracle_state(h, o)
+    dt = o.cfl_dt()
+    o.root_step(dt)
+    h.step(BATCHED, dt)
+    err = rel_l1(h, o)
+    assert np.all(err <= (1e-12 if prec == FP64 else 1e-5)), dict(zip(FIELDS, err))
+
+
+@pytest.mark.skip(reason="concurrent schedule switched off: its first GPU capture ended the test process with a "
+                         "segmentation fault and the cause is not yet shown")
+@pytest.mark.parametrize("name,fused", [("small_three_level", False), ("small_three_level", True),
+                                        ("root_tiled", False), ("two_level", False), ("two_level", True)])
+@pytest.mark.parametrize("fixed_dt", [False, True])
+def test_concurrent_schedule_is_bit_identical_to_batched(name, fused, fixed_dt):
+    """Replays of the per-level-branch graph equal the batched schedule bit for bit over several root steps."""
+    from paper_1112_1710_amd import CONCURRENT
+    spec = getattr(H, name)()
+    _say("concurrent schedule", name, fused, fixed_dt)
+    field = SmoothField(25)
+    prec = FP32 if name == "two_level" else FP64
+    a = Hierarchy(spec, prec)
+    b = Hierarchy(spec, prec)
+    if fused:
+        b.tune_set(binding.TUNE_FUSED, 1)
+    a.set_field(field)
+    b.set_field(field)
+    for _ in range(3):
+        dt = a.step(BATCHED, 1e-3 if fixed_dt else 0.0)
+        assert b.step(CONCURRENT, 1e-3 if fixed_dt else 0.0) == dt
+    _same_interiors(spec, a, b)
+    d = b.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+
+
+def test_disabled_schedules_report_einval():
+    """The switched-off schedules are refused before any launch."""
+    from paper_1112_1710_amd import CONCURRENT, PERSISTENT, AmrxError
+    spec = H.small_three_level()
+    h = Hierarchy(spec, FP64)
+    h.set_field(SmoothField(26))
+    for mode in (PERSISTENT, CONCURRENT):
+        with pytest.raises(AmrxError) as ei:
+            h.step(mode)
+        assert ei.value.code == -1
+    h.step(BATCHED)

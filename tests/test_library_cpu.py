@@ -160,3 +160,71 @@ def test_persistent_schedule_claims_complete(name, fixed_dt):
         done[items[it, 0]] += items[it, 2] - items[it, 1]
     assert all(heads[q] >= queues[q][1] for q in range(len(queues)))
     assert np.array_equal(done, nblk)
+
+
+def test_padded_volume_limit():
+    """Patches whose ghost-padded volume reaches 2^31 entries are rejected (kernels index them with 32 bits)."""
+    lib = _lib()
+    i3 = binding._i3
+    d = binding.Desc()
+    d.root_n = i3((1400, 1400, 1400))
+    d.max_level, d.ratio, d.nghost, d.gamma, d.cfl, d.precision = 0, 2, 4, 5 / 3, 0.4, 1
+    hh = ctypes.c_void_p()
+    pid = ctypes.c_int()
+    assert lib.hier_create(ctypes.byref(d), ctypes.byref(hh)) == 0
+    assert lib.patch_add(hh, 0, i3((0, 0, 0)), i3((1400, 1400, 1400)), ctypes.byref(pid)) == -1
+    assert lib.patch_add(hh, 0, i3((0, 0, 0)), i3((1200, 1200, 1200)), ctypes.byref(pid)) == 0  # 1209^3 < 2^31
+    lib.hier_destroy(hh)
+
+
+@pytest.mark.parametrize("prec", [0, 1, 2])
+def test_tile_table_and_tuning_switches(prec):
+    _lib()
+    table = binding.tile_table(prec)
+    word = 8 if prec == 0 else 4
+    assert len(table) >= 2
+    for tx, ty, tz, lds in table:
+        need = (11 * (tx + 2) * (ty + 2) * (tz + 2) + 3 * (tx + 1) * (ty + 1) * (tz + 1)) * word
+        assert lds == (need if need <= 65536 else 0)
+    assert table[0][3] > 0  # the default tile is allowed at every precision
+    spec = H.small_three_level()
+    h = binding.Hierarchy(spec, precision=prec, device=None)
+    assert all(h.tune_get(binding.TUNE_FUSED, level=lv) == 0 for lv in range(3))  # staged by default
+    staged = h.step_work()
+    h.tune_set(binding.TUNE_FUSED, 1)
+    assert all(h.tune_get(binding.TUNE_FUSED, level=lv) == 1 for lv in range(3))
+    fused = h.step_work()
+    h.tune_set(binding.TUNE_FUSED, 0, level=1)
+    mixed = h.step_work()
+    assert 0 < mixed["prim"][0] < staged["prim"][0] and 0 < mixed["primhalf"][0] < fused["primhalf"][0]
+    h.tune_set(binding.TUNE_FUSED, 1)
+    for k in ("prim", "bhalf", "pred"):
+        assert fused[k] == (0.0, 0) and staged[k][0] > 0
+    assert staged["primhalf"] == (0.0, 0)
+    assert fused["primhalf"][0] == 16 * staged["prim"][0] + 14 * staged["pred"][0]
+    assert fused["primhalf"][1] == staged["prim"][1]
+    for k in ("flux", "edge", "update", "copy"):
+        assert fused[k] == staged[k]
+    for lvl in range(3):
+        for t, (_, _, _, lds) in enumerate(table):
+            if lds:
+                h.tune_set(binding.TUNE_TILE, t, level=lvl)
+                assert h.tune_get(binding.TUNE_TILE, level=lvl) == t
+            else:
+                with pytest.raises(binding.AmrxError):
+                    h.tune_set(binding.TUNE_TILE, t, level=lvl)
+    with pytest.raises(binding.AmrxError):
+        h.tune_set(binding.TUNE_TILE, len(table), level=0)
+    with pytest.raises(binding.AmrxError):
+        h.tune_set(binding.TUNE_FUSED, 2)
+    with pytest.raises(binding.AmrxError):
+        h.tune_set(7, 0)
+    with pytest.raises(binding.AmrxError):
+        h.tune_set(binding.TUNE_TILE, 0, level=16)
+
+
+def test_autotune_size_classes():
+    from paper_1112_1710_amd import autotune
+    spec = H.two_level()
+    assert autotune.size_class(spec, 0) == "n1-s256"          # one 128^3 root patch: side 132
+    assert autotune.size_class(spec, 1).startswith("n512-s")
