@@ -21,8 +21,14 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
-FP32_VALU_TFLOPS = 78.6        # 256 CU x 128 FP32 FMA-flops/clk (unpacked) x 2.4 GHz
-FP64_VALU_TFLOPS = 78.6
+# vector ALU peaks: 256 CU x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  FP32 reaches 157.3 TFLOP/s only with
+# packed two-wide FP32 instructions, which this build does not emit; FP64 runs at the same 78.6.
+VALU_PEAK_TFLOPS = 78.6
+
+# Kernel classes bound by vector arithmetic rather than HBM, with their algorithmic floating-point operations per
+# processed entry (add, multiply, divide, square root, min/max each count one; a fused multiply-add two).
+# flux: MUSCL reconstruction of both face states (about 260) + HLLD on its double-star path (about 310).
+ALU_BOUND = {"flux": 570}
 
 # Algorithmic words moved per processed entry of each kernel class (reads + writes of
 # distinct values, neighbour re-reads not counted); see DESIGN.md "Kernels and rooflines".
@@ -59,8 +65,12 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="two_level", choices=["two_level", "uniform256", "uniform32", "deep"])
-    ap.add_argument("--precision", default="fp32", choices=["fp32", "fp32_mixed", "fp64"])
+    ap.add_argument("--workload", default="two_level",
+                    choices=["two_level", "uniform256", "uniform32", "deep", "lowbeta"])
+    ap.add_argument("--report-steps", type=int, default=3,
+                    help="root steps of the low-beta precision report (workload lowbeta)")
+    ap.add_argument("--precision", default=None, choices=["fp32", "fp32_mixed", "fp64"],
+                    help="default fp32 (fp32_mixed for the low-beta workload)")
     ap.add_argument("--mode", default="graph", choices=["plain", "batched", "graph", "persistent", "concurrent"])
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="after the timed steps, copy a 512 MiB buffer once (reference dispatch for HBM counters)")
@@ -81,22 +91,139 @@ def workload(name):
         return H.single_patch(256), SmoothField(1710), "single periodic 256^3 patch, smooth field"
     if name == "uniform32":
         return H.single_patch(32), SmoothField(1112), "single periodic 32^3 patch, smooth field"
+    if name == "lowbeta":
+        from workloads.fields import low_beta
+        return H.two_level(), low_beta(5), "two-level 128^3 root + 512 refined patches, low beta (1e-3), 1% density noise"
     spec, centre, _ = H.deep_blast_target()
     return spec, Blast(centre), "deep 8-level hierarchy (64^3 root, ~40M cells), off-centre blast"
 
 
-def timed_steps(h, mode, steps, warmup, torch):
+def _interior_fields(h, spec, gamma=5.0 / 3.0):
+    """Per patch: float64 interior arrays of rho, mx, my, mz, E, p and the three face fields (interior closures)."""
+    import numpy as np
+    G = 4
+    out = []
+    for pid, (_, lo, hi) in enumerate(spec.patches):
+        cells, faces = h.download(pid)
+        n = [hi[a] - lo[a] for a in range(3)]
+        sl = (slice(G, G + n[2]), slice(G, G + n[1]), slice(G, G + n[0]))
+        c = [cells[m][sl].astype(np.float64) for m in range(5)]
+        bc = []
+        fs = []
+        for d in range(3):
+            f = faces[d].astype(np.float64)
+            up = [slice(G, G + n[2]), slice(G, G + n[1]), slice(G, G + n[0])]
+            up[2 - d] = slice(G + 1, G + n[d] + 1)
+            bc.append(0.5 * (f[sl] + f[tuple(up)]))
+            cl = [slice(G, G + n[2]), slice(G, G + n[1]), slice(G, G + n[0])]
+            cl[2 - d] = slice(G, G + n[d] + 1)
+            fs.append(f[tuple(cl)])
+        pr = (gamma - 1.0) * (c[4] - 0.5 * (c[1] ** 2 + c[2] ** 2 + c[3] ** 2) / c[0]
+                              - 0.5 * (bc[0] ** 2 + bc[1] ** 2 + bc[2] ** 2))
+        out.append(c + [pr] + fs)
+    return out
+
+
+def lowbeta_report(spec, field, steps, torch):
+    """Per-field relative L1 of FP32 with FP64 pressure recovery and of plain FP32 against the FP64 path (the
+    FP64 GPU path, itself held to 1e-12 of the oracle), after each of `steps` root steps taken with the FP64
+    path's time steps, and the conservation drift |sum U(t) - sum U(0)| / |sum U(0)| of each precision."""
+    import numpy as np
+    from paper_1112_1710_amd import FP32, FP32_MIXED, FP64, GRAPH, Hierarchy
+    names = ("rho", "mx", "my", "mz", "E", "p", "bx", "by", "bz")
+
+    class Rounded:
+        """The field with every value rounded to float32: the FP32 runs' exact input, in float64."""
+
+        def patch(self, level, root_n, lo, hi):
+            st = field.patch(level, root_n, lo, hi)
+            st.cells = st.cells.astype(np.float32).astype(np.float64)
+            st.faces = [f.astype(np.float32).astype(np.float64) for f in st.faces]
+            return st
+
+    hs = {}
+    for key, prec, fld in (("fp64", FP64, Rounded()), ("fp64_unrounded", FP64, field),
+                           ("fp32_mixed", FP32_MIXED, field), ("fp32", FP32, field)):
+        h = Hierarchy(spec, prec)
+        h.set_field(fld)
+        hs[key] = h
+    tot0 = {k: sum(h.conservation()) for k, h in hs.items()}
+    pairs = (("fp32_mixed", "fp64"), ("fp32", "fp64"), ("fp32_mixed", "fp64_unrounded"), ("fp64", "fp64_unrounded"))
+    rel = {f"{a}_vs_{b}": {n: [] for n in names} for a, b in pairs}
+    drift = {k: [] for k in hs}
+    for _ in range(steps):
+        dt = hs["fp64"].step(GRAPH)
+        for k in ("fp64_unrounded", "fp32_mixed", "fp32"):
+            hs[k].step(GRAPH, dt)
+        fields = {k: _interior_fields(h, spec) for k, h in hs.items()}
+        for a, b in pairs:
+            got, ref = fields[a], fields[b]
+            for i, n in enumerate(names):
+                num = sum(float(np.sum(np.abs(g[i] - r[i]))) for g, r in zip(got, ref))
+                den = sum(float(np.sum(np.abs(r[i]))) for r in ref)
+                rel[f"{a}_vs_{b}"][n].append(num / den)
+        del fields
+        for k, h in hs.items():
+            t = sum(h.conservation())
+            d = [float(abs(t[q] - tot0[k][q])) for q in range(5)]
+            # the momentum totals start near zero: their drift is reported in absolute terms only
+            drift[k].append({"abs": d, "rel_mass": d[0] / abs(tot0[k][0]), "rel_energy": d[4] / abs(tot0[k][4])})
+    for h in hs.values():
+        del h
+    hs.clear()
+    torch.cuda.empty_cache()
+    return {"steps": steps,
+            "reference": "fp64 GPU path from the float32-rounded input (fp64) or from the exact input "
+                         "(fp64_unrounded); the fp64 path is held to 1e-12 of the oracle",
+            "rel_l1": rel,
+            "conservation_drift": {k: {"per_step": v, "order": ["mass", "mx", "my", "mz", "energy"]}
+                                   for k, v in drift.items()}}
+
+
+def timed_steps(h, mode, steps, warmup, torch, reset=None):
+    """Mean wall time of one root step.  With `reset`, the initial state is restored before every step,
+    outside the timed region, and each step is bracketed by device synchronisations on its own."""
     for _ in range(warmup):
+        if reset is not None:
+            reset()
         h.step(mode)
     torch.cuda.synchronize()
     h.timing(True)
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        h.step(mode)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    if reset is None:
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            h.step(mode)
+        torch.cuda.synchronize()
+        total = time.perf_counter() - t0
+    else:
+        total = 0.0
+        for _ in range(steps):
+            reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            h.step(mode)
+            torch.cuda.synchronize()
+            total += time.perf_counter() - t0
     h.timing(False)
-    return (t1 - t0) / steps, h.timing_read()
+    return total / steps, h.timing_read()
+
+
+def state_reset(h, spec, field, precision):
+    """A callable that re-uploads the initial state (generated once, kept on the host in the state's dtype)."""
+    import numpy as np
+    from paper_1112_1710_amd import FP64
+    dt = np.float64 if precision == FP64 else np.float32
+    root = tuple(int(x) for x in spec.root_n)
+    cache = []
+    for (lv, lo, hi) in spec.patches:
+        st = field.patch(lv, root, tuple(lo), tuple(hi))
+        cache.append((st.cells.astype(dt), [f.astype(dt) for f in st.faces]))
+
+    def reset():
+        for pid, (cells, faces) in zip(h.ids, cache):
+            h.upload(pid, cells, faces)
+        h.synchronize()
+    return reset
 
 
 def cpu_baseline():
@@ -117,6 +244,8 @@ def cpu_baseline():
 
 def main():
     args = parse()
+    if args.precision is None:
+        args.precision = "fp32_mixed" if args.workload == "lowbeta" else "fp32"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         sys.stderr.write("bench.py measures one GPU only: this build has no multi-GPU path "
                          "(run with --gpus 1).\n")
@@ -132,20 +261,28 @@ def main():
     zu = spec.zone_updates_per_root_step()
 
     h = Hierarchy(spec, prec)
-    h.set_field(field)
+    reset = None
+    steps_from_t0 = args.workload == "deep"
+    if steps_from_t0:
+        # the blast's second root step fails the scheme's physical-state check (negative reconstructed
+        # pressure at the strong shock, in FP64 as in FP32): every timed step restarts from t = 0
+        reset = state_reset(h, spec, field, prec)
+        reset()
+    else:
+        h.set_field(field)
     tiles = None
     if args.staged:
         h.tune_set(TUNE_FUSED, 0)
     elif not args.no_autotune:
         from paper_1112_1710_amd.autotune import autotune
         tiles = {lvl: v[1] for lvl, v in autotune(h).items()}
-    sec, timing = timed_steps(h, mode, args.steps, args.warmup, torch)
+    sec, timing = timed_steps(h, mode, args.steps, args.warmup, torch, reset)
     value = zu / sec
     work = h.step_work()
     if mode in (GRAPH, PERSISTENT, CONCURRENT):
         # kernels inside a replayed graph or the persistent kernel are not bracketed by events: take the per-kernel
         # launch times from an instrumented batched pass of the same steps
-        _, timing = timed_steps(h, BATCHED, args.steps, 1, torch)
+        _, timing = timed_steps(h, BATCHED, args.steps, 1, torch, reset)
 
     # dominant kernel class and its roofline
     dom = max(timing, key=lambda k: timing[k][0])
@@ -161,11 +298,21 @@ def main():
         traffic = None
         if meas is not None and meas["sources"] == sources_hash():
             traffic = round(meas["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
-        roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(bytes_per_launch),
-                "traffic_bytes_per_launch": None if traffic is None else int(meas["bytes_per_launch"])}
+        hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+               "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(bytes_per_launch),
+               "traffic_bytes_per_launch": None if traffic is None else int(meas["bytes_per_launch"])}
+        if dom in ALU_BOUND:
+            flops_per_launch = units_per_step * ALU_BOUND[dom] / max(launches_per_step, 1)
+            tf = flops_per_launch / (avg_ms * 1e-3) / 1e12
+            roof = {"bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": round(tf / VALU_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": dom,
+                    "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": int(flops_per_launch),
+                    "hbm": {k: hbm[k] for k in ("achieved", "peak", "unit", "frac", "bytes_per_launch")}}
+        else:
+            roof = hbm
     per_class = {k: round(v[0] / args.steps, 4) for k, v in timing.items() if v[1]}
+    reset = None  # the closure holds the hierarchy
     del h
     torch.cuda.empty_cache()
     if args.pmc_calibration:
@@ -192,6 +339,7 @@ def main():
         "config": {"workload": desc, "patches": len(spec.patches), "levels": spec.levels(),
                    "cells": spec.cells(), "zone_updates_per_step": zu, "precision": args.precision,
                    "schedule": args.mode,
+                   "steps_from": "t=0 state before every step" if steps_from_t0 else "consecutive steps",
                    "first_stages": "staged" if args.staged or tiles is None else tiles,
                    "parallelism": "single GPU"},
         "roofline": roof,
@@ -200,12 +348,21 @@ def main():
 
     if not args.skip_plain:
         hp = Hierarchy(spec, FP64)
-        hp.set_field(field)
-        psec, _ = timed_steps(hp, PLAIN, args.plain_steps, 1, torch)
+        preset = None
+        if steps_from_t0:
+            preset = state_reset(hp, spec, field, FP64)
+            preset()
+        else:
+            hp.set_field(field)
+        psec, _ = timed_steps(hp, PLAIN, args.plain_steps, 1, torch, preset)
+        del preset
         out["fp64_plain_value"] = round(zu / psec, 1)
         out["speedup_vs_fp64_plain"] = round(value / (zu / psec), 3)
         del hp
         torch.cuda.empty_cache()
+
+    if args.workload == "lowbeta":
+        out["lowbeta_report"] = lowbeta_report(spec, field, args.report_steps, torch)
 
     if not args.skip_cpu:
         out["cpu_baseline"] = cpu_baseline()

@@ -148,3 +148,85 @@ def test_uniform_256_sampled_windows():
         for d in range(3):
             fsel = mhd._face_sel(region, d)
             assert _rel_l1(got_f[d][fsel], ref.faces[d][fsel]) <= 1e-5, (c, d)
+
+
+def _deep_samples(spec, centre):
+    """Patch ids: two level-3 patches nearest the blast surface (|x - c| = 0.1) and the largest finest patch."""
+    root = spec.root_n[0]
+    pick3 = []
+    finest = spec.levels() - 1
+    best_f, best_v = None, -1
+    for pid, (lv, lo, hi) in enumerate(spec.patches):
+        n = root << lv
+        if lv == 3:
+            ctr = [(lo[a] + hi[a]) / 2 / n for a in range(3)]
+            r = sum(((ctr[a] - centre[a] + 0.5) % 1.0 - 0.5) ** 2 for a in range(3)) ** 0.5
+            pick3.append((abs(r - 0.1), pid))
+        if lv == finest:
+            v = (hi[0] - lo[0]) * (hi[1] - lo[1]) * (hi[2] - lo[2])
+            if v > best_v:
+                best_f, best_v = pid, v
+    pick3.sort()
+    return [pick3[0][1], pick3[1][1], best_f]
+
+
+def test_deep_hierarchy_sampled_patches():
+    """Deep 8-level blast hierarchy (64^3 root, ~40M cells), autotuned, FP32: the first-substep chain of a
+    root step (ghost fill + advance of every level in turn) and the oracle's advance of sampled patches
+    from the GPU's own ghost-filled input."""
+    from paper_1112_1710_amd.autotune import autotune
+    from workloads.fields import Blast
+    spec, centre, _ = H.deep_blast_target()
+    _say("deep hierarchy, sampled patches", len(spec.patches), "patches")
+    h = Hierarchy(spec, FP32)
+    h.set_field(Blast(centre))
+    autotune(h, reps=2, use_cache=False)
+    samples = _deep_samples(spec, centre)
+    by_level = {}
+    for pid in samples:
+        by_level.setdefault(spec.patches[pid][0], []).append(pid)
+    o = amr.Hierarchy(spec.root_n)
+    dt0 = h.cfl_dt()
+    assert dt0 > 0
+    pre = {}
+    for lv in range(spec.levels()):
+        h.ghost_fill(lv, 0)
+        if lv in by_level:
+            h.synchronize()
+            for pid in by_level[lv]:
+                pre[pid] = h.download(pid)
+        h.advance(lv, dt0 / 2 ** lv, 0)
+    h.synchronize()
+    for pid in samples:
+        lv, lo, hi = spec.patches[pid]
+        cells, faces = pre[pid]
+        n = [hi[a] - lo[a] for a in range(3)]
+        reg = amr.update_box((G, G, G), tuple(G + n[a] for a in range(3)), lv, 0)
+        dx = o.dx(lv)
+        ref = mhd.advance(cells, faces, [dx] * 3, dt0 / 2 ** lv, reg, 5.0 / 3.0)
+        got_c, got_f = h.download(pid)
+        sel = mhd._sel(reg)
+        for m in range(5):
+            assert _rel_l1(got_c[m][sel], ref.cells[m][sel]) <= 1e-5, (pid, lv, m)
+        for d in range(3):
+            fsel = mhd._face_sel(reg, d)
+            assert _rel_l1(got_f[d][fsel], ref.faces[d][fsel]) <= 1e-5, (pid, lv, d)
+
+
+def test_deep_hierarchy_root_step_properties():
+    """One graph-replayed FP32 root step of the deep blast hierarchy: bit-zero sync, no unphysical state,
+    composite conservation to float32 round-off."""
+    from workloads.fields import Blast
+    spec, centre, _ = H.deep_blast_target()
+    _say("deep hierarchy, root-step properties")
+    h = Hierarchy(spec, FP32)
+    h.set_field(Blast(centre))
+    s0, c0 = h.conservation()
+    h.step(GRAPH)
+    s1, c1 = h.conservation()
+    d = h.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+    tot0, tot1 = s0 + c0, s1 + c1
+    for q in range(5):
+        scale = max(abs(tot0[q]), 0.05 * abs(tot0[4]))
+        assert abs(tot1[q] - tot0[q]) <= 1e-5 * scale, (q, tot0[q], tot1[q])
