@@ -23,6 +23,8 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "amrx_internal.h"
 
 namespace {
@@ -35,15 +37,44 @@ namespace {
 // about 1 ulp, against several instructions of scaling and fix-up for a
 // correctly rounded quotient) and the hardware square root (1 ulp); FP32
 // results are held to a relative L1 tolerance of 1e-5, far above that.
+#ifndef AMRX_FAST_FP32
+#define AMRX_FAST_FP32 1
+#endif
 __device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
+__device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
+#if AMRX_FAST_FP32
 __device__ __forceinline__ float rcp(float x) {
   const float r = __builtin_amdgcn_rcpf(x);
   return fmaf(fmaf(-x, r, 1.0f), r, r);
 }
-__device__ __forceinline__ double qdiv(double a, double b) { return a / b; }
 __device__ __forceinline__ float qdiv(float a, float b) { return a * rcp(b); }
-__device__ __forceinline__ double qsqrt(double x) { return sqrt(x); }
 __device__ __forceinline__ float qsqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+#else
+__device__ __forceinline__ float rcp(float x) { return 1.0f / x; }
+__device__ __forceinline__ float qdiv(float a, float b) { return a / b; }
+__device__ __forceinline__ float qsqrt(float x) { return sqrtf(x); }
+#endif
+
+// FD selects, for double, the hardware reciprocal refined by two Newton steps and a
+// corrected quotient (within about 1 ulp) instead of the IEEE division sequence; used by
+// the FP32_MIXED mode's double-precision Riemann solver.  The FP64 mode keeps IEEE.
+template <bool FD, typename R>
+__device__ __forceinline__ R rcp_t(R x) { return rcp(x); }
+template <>
+__device__ __forceinline__ double rcp_t<true, double>(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  r = fma(fma(-x, r, 1.0), r, r);
+  return fma(fma(-x, r, 1.0), r, r);
+}
+template <bool FD, typename R>
+__device__ __forceinline__ R qdiv_t(R a, R b) { return qdiv(a, b); }
+template <>
+__device__ __forceinline__ double qdiv_t<true, double>(double a, double b) {
+  const double r = rcp_t<true>(b);
+  const double q = a * r;
+  return fma(fma(-b, q, a), r, q);
+}
 
 template <typename R>
 __device__ __forceinline__ R mc_limit(R dm, R dp) {
@@ -82,9 +113,9 @@ __device__ __forceinline__ R pressure(R rho, R mx, R my, R mz, R e, R bx, R by, 
   }
 }
 
-template <typename R>
+template <typename R, bool FD = false>
 __device__ __forceinline__ R fast_speed(R rho, R p, R b2, R bn2, R gamma) {
-  const R ir = rcp(rho);
+  const R ir = rcp_t<FD>(rho);
   R a2 = gamma * p * ir;
   R s = a2 + b2 * ir;
   R disc = s * s - R(4) * a2 * bn2 * ir;
@@ -141,8 +172,27 @@ __device__ __forceinline__ void to_prim(const R* u, R gm1, R* w) {
   w[7] = u[7];
 }
 
+// Transverse star-state velocity and field of one side (Miyoshi & Kusano 2005, their
+// eqs. 44-47): with dn = rho sd (s - sm) - bn^2 and num = rho sd^2 - bn^2 (sd = s - u),
+// v* = v - bn by (sm - u) / dn and by* = by num / dn; a degenerate dn keeps v and B.
+template <bool FD, typename R>
+__device__ __forceinline__ void star_transverse(R r, R sd, R s, R sm, R u, R v, R z, R by, R bz, R bn, R& vs, R& zs,
+                                                R& bys, R& bzs) {
+  const R dn = r * sd * (s - sm) - bn * bn;
+  if (fabs(dn) <= R(1e-8) * r * sd * sd) {
+    vs = v; zs = z; bys = by; bzs = bz;
+  } else {
+    const R num = r * sd * sd - bn * bn;
+    const R dsm = sm - u;
+    vs = v - qdiv_t<FD>(bn * by * dsm, dn);
+    zs = z - qdiv_t<FD>(bn * bz * dsm, dn);
+    bys = qdiv_t<FD>(by * num, dn);
+    bzs = qdiv_t<FD>(bz * num, dn);
+  }
+}
+
 // HLLD flux normal to D.  Normal field bn replaces both states' normal component.
-template <int D, typename R>
+template <int D, typename R, bool FD = false>
 __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R* out) {
   constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
   const R gm1 = gamma - R(1);
@@ -151,15 +201,15 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
   const R bn2 = bn * bn;
   const R b2l = bn2 + byl * byl + bzl * bzl;
   const R b2r = bn2 + byr * byr + bzr * bzr;
-  const R cfl = fast_speed(rl, pl, b2l, bn2, gamma);
-  const R cfr = fast_speed(rr, pr, b2r, bn2, gamma);
+  const R cfl = fast_speed<R, FD>(rl, pl, b2l, bn2, gamma);
+  const R cfr = fast_speed<R, FD>(rr, pr, b2r, bn2, gamma);
   const R cmax = fmax(cfl, cfr);
   const R sl = fmin(ul, ur) - cmax;
   const R sr = fmax(ul, ur) + cmax;
   const R ptl = pl + R(0.5) * b2l;
   const R ptr = pr + R(0.5) * b2r;
-  const R el = qdiv(pl, gm1) + R(0.5) * rl * (ul * ul + vl * vl + zl * zl) + R(0.5) * b2l;
-  const R er = qdiv(pr, gm1) + R(0.5) * rr * (ur * ur + vr * vr + zr * zr) + R(0.5) * b2r;
+  const R el = qdiv_t<FD>(pl, gm1) + R(0.5) * rl * (ul * ul + vl * vl + zl * zl) + R(0.5) * b2l;
+  const R er = qdiv_t<FD>(pr, gm1) + R(0.5) * rr * (ur * ur + vr * vr + zr * zr) + R(0.5) * b2r;
   const R vbl = ul * bn + vl * byl + zl * bzl;
   const R vbr = ur * bn + vr * byr + zr * bzr;
 
@@ -183,48 +233,26 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
   } else {
     const R sdl = sl - ul, sdr = sr - ur;
     const R den = sdr * rr - sdl * rl;
-    const R sm = qdiv(sdr * rr * ur - sdl * rl * ul - ptr + ptl, den);
-    const R pts = qdiv(sdr * rr * ptl - sdl * rl * ptr + rl * rr * sdr * sdl * (ur - ul), den);
+    const R sm = qdiv_t<FD>(sdr * rr * ur - sdl * rl * ul - ptr + ptl, den);
+    const R pts = qdiv_t<FD>(sdr * rr * ptl - sdl * rl * ptr + rl * rr * sdr * sdl * (ur - ul), den);
     // left star state
-    const R rls = qdiv(rl * sdl, sl - sm);
+    const R rls = qdiv_t<FD>(rl * sdl, sl - sm);
     R vls, zls, byls, bzls;
-    {
-      const R dn = rl * sdl * (sl - sm) - bn2;
-      if (fabs(dn) <= R(1e-8) * rl * sdl * sdl) {
-        vls = vl; zls = zl; byls = byl; bzls = bzl;
-      } else {
-        const R num = rl * sdl * sdl - bn2;
-        vls = vl - qdiv(bn * byl * (sm - ul), dn);
-        zls = zl - qdiv(bn * bzl * (sm - ul), dn);
-        byls = qdiv(byl * num, dn);
-        bzls = qdiv(bzl * num, dn);
-      }
-    }
+    star_transverse<FD>(rl, sdl, sl, sm, ul, vl, zl, byl, bzl, bn, vls, zls, byls, bzls);
     const R vbls = sm * bn + vls * byls + zls * bzls;
-    const R els = qdiv(sdl * el - ptl * ul + pts * sm + bn * (vbl - vbls), sl - sm);
+    const R els = qdiv_t<FD>(sdl * el - ptl * ul + pts * sm + bn * (vbl - vbls), sl - sm);
     // right star state
-    const R rrs = qdiv(rr * sdr, sr - sm);
+    const R rrs = qdiv_t<FD>(rr * sdr, sr - sm);
     R vrs, zrs, byrs, bzrs;
-    {
-      const R dn = rr * sdr * (sr - sm) - bn2;
-      if (fabs(dn) <= R(1e-8) * rr * sdr * sdr) {
-        vrs = vr; zrs = zr; byrs = byr; bzrs = bzr;
-      } else {
-        const R num = rr * sdr * sdr - bn2;
-        vrs = vr - qdiv(bn * byr * (sm - ur), dn);
-        zrs = zr - qdiv(bn * bzr * (sm - ur), dn);
-        byrs = qdiv(byr * num, dn);
-        bzrs = qdiv(bzr * num, dn);
-      }
-    }
+    star_transverse<FD>(rr, sdr, sr, sm, ur, vr, zr, byr, bzr, bn, vrs, zrs, byrs, bzrs);
     const R vbrs = sm * bn + vrs * byrs + zrs * bzrs;
-    const R ers = qdiv(sdr * er - ptr * ur + pts * sm + bn * (vbr - vbrs), sr - sm);
+    const R ers = qdiv_t<FD>(sdr * er - ptr * ur + pts * sm + bn * (vbr - vbrs), sr - sm);
 
     const bool skip = bn2 <= R(1e-12) * (ptl + ptr);
     const R sql = qsqrt(rls), sqr = qsqrt(rrs);
     const R abn = fabs(bn);
-    const R ssl = skip ? sm : sm - qdiv(abn, sql);
-    const R ssr = skip ? sm : sm + qdiv(abn, sqr);
+    const R ssl = skip ? sm : sm - qdiv_t<FD>(abn, sql);
+    const R ssr = skip ? sm : sm + qdiv_t<FD>(abn, sqr);
     const bool left = sm >= R(0);
     // star flux of the side that holds x/t = 0
     R us[7], uo[7], fo[7], s_out;
@@ -246,7 +274,7 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
     if (!skip && !in_star) {
       // double-star state of the same side
       const R sgn = bn > R(0) ? R(1) : (bn < R(0) ? R(-1) : R(0));
-      const R inv = rcp(sql + sqr);
+      const R inv = rcp_t<FD>(sql + sqr);
       const R vss = (sql * vls + sqr * vrs + (byrs - byls) * sgn) * inv;
       const R zss = (sql * zls + sqr * zrs + (bzrs - bzls) * sgn) * inv;
       const R byss = (sql * byrs + sqr * byls + sql * sqr * (vrs - vls) * sgn) * inv;
@@ -754,7 +782,30 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
   if (!(wl[0] > R(0)) || !(wl[4] > R(0)) || !(wr[0] > R(0)) || !(wr[4] > R(0))) flag_phys(c.slots);
   const R bn = X[(SCR_BH + D) * v + q];
   R f[8];
-  hlld<D>(wl, wr, bn, gamma, f);
+  // FP32_MIXED at low-beta faces (beta = 2p/B^2 < 0.1 on either side): the Riemann solver in
+  // double.  With a strong field the star states approach the degenerate limit
+  // rho (S - u)^2 ~ Bn^2, where float32 rounding of the wave speeds and of
+  // rho (S - u)(S - S_M) - Bn^2 decides between branches.
+  bool low_beta = false;
+  if (MIX) {
+    const R bn2 = bn * bn;
+    const R b2l = bn2 + wl[5 + (D + 1) % 3] * wl[5 + (D + 1) % 3] + wl[5 + (D + 2) % 3] * wl[5 + (D + 2) % 3];
+    const R b2r = bn2 + wr[5 + (D + 1) % 3] * wr[5 + (D + 1) % 3] + wr[5 + (D + 2) % 3] * wr[5 + (D + 2) % 3];
+    low_beta = R(20) * fmin(wl[4], wr[4]) < fmax(b2l, b2r);
+  }
+  if (low_beta) {
+    double wld[8], wrd[8], fd[8];
+#pragma unroll
+    for (int m = 0; m < 8; ++m) {
+      wld[m] = wl[m];
+      wrd[m] = wr[m];
+    }
+    hlld<D, double, true>(wld, wrd, (double)bn, c.gamma, fd);
+#pragma unroll
+    for (int m = 0; m < 8; ++m) f[m] = (R)fd[m];
+  } else {
+    hlld<D, R>(wl, wr, bn, gamma, f);
+  }
   const R rec[4] = {f[1], f[2], f[3], f[4]};
   st4(X + (SCR_F4 + 4 * D) * v + 4 * q, rec);
   X[(SCR_F0 + D) * v + q] = f[0];

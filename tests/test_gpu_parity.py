@@ -261,12 +261,16 @@ def test_low_beta_step():
         o.root_step(dt)
         h.step(BATCHED, dt)
         err = rel_l1(h, o)
-        # rho, E and the guide-field component meet the FP32 bar; the transverse field and
-        # momentum (|dB| = 0.1 under |B0| = 44.7) carry float32 round-off of the guide-field
-        # fluxes, so they are held to the bar relative to the guide-field magnitude instead
-        for q in (0, 4, 5):
-            assert err[q] <= 1e-5, dict(zip(FIELDS, err))
-        assert np.all(err <= 1e-5 * 44.72 / 0.1), dict(zip(FIELDS, err))
+        if prec == FP32_MIXED:
+            # the Riemann solver and the pressure recovery in double: every field meets the bar
+            assert np.all(err <= 1e-5), dict(zip(FIELDS, err))
+        else:
+            # plain FP32: rho, E and the guide-field component meet the bar; the transverse field
+            # and momentum (|dB| = 0.1 under |B0| = 44.7) carry the float32 HLLD's error near its
+            # degenerate limit (rho (S - u)^2 ~ Bn^2), held to the bar relative to the guide field
+            for q in (0, 4, 5):
+                assert err[q] <= 1e-5, dict(zip(FIELDS, err))
+            assert np.all(err <= 1e-5 * 44.72 / 0.1), dict(zip(FIELDS, err))
         _say("per-field rel-L1", prec, dict(zip(FIELDS, np.round(err, 9))))
         _say("pressure rel-L1", prec, _pressure_rel_l1(h, o))
 
