@@ -220,10 +220,16 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
  * from a fixed table.  Both give bit-identical results.
  *   AMRX_TUNE_FUSED: 0 staged, 1 fused
  *   AMRX_TUNE_TILE:  index into the tile table
+ *   AMRX_TUNE_EXTEND_ALL: 1 = the substep-0 update region of every refined patch
+ *     extends over all six sides (every grid treated as isolated, Sec. 2.3);
+ *     0 (default) = only over sides whose extended ghost layers lack a
+ *     same-level source somewhere (elsewhere the next substep's ghost copy
+ *     replaces those values, so interiors are bit-identical either way).
+ *     Level ignored; only before hier_finalize (ESTATE after).
  * level = -1 sets every level.  Pure host calls (captured graph-schedule steps
  * are discarded on a change).  EINVAL for a bad parameter, level or index, or
  * a tile whose LDS footprint exceeds the limit for the hierarchy's precision. */
-enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1 };
+enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1, AMRX_TUNE_EXTEND_ALL = 2 };
 int hier_tune_set(amrx_hier* h, int level, int param, int value);
 int hier_tune_get(const amrx_hier* h, int level, int param, int* value);
 
@@ -254,6 +260,9 @@ int hier_debug_sources(const amrx_hier* h, int patch_id, int kind, long long* ou
  * in the layout the device uses. */
 int hier_debug_schedule(amrx_hier* h, int fixed_dt, int nworkgroups, int* sizes, int* nodes, int* preds, int* items,
                         int* queues);
+
+/* The update region [lo, hi) (padded cell indices) of a patch at `substep`. */
+int hier_debug_update_box(const amrx_hier* h, int patch_id, int substep, int lo[3], int hi[3]);
 
 /* Number of parent cells prolongated into a patch at substep 0, and (if out
  * is non-NULL, cap entries) their level-(l-1) (x, y, z) indices. */

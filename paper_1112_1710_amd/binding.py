@@ -15,7 +15,7 @@ G = 4
 
 KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
                   "fluxcorr", "emfcorr", "sync", "cfl", "cons", "primhalf")
-TUNE_FUSED, TUNE_TILE = 0, 1
+TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL = 0, 1, 2
 
 _ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
 
@@ -61,6 +61,7 @@ EXPORTS = {
     "hier_tune_get": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int)], C.c_int),
     "hier_tile_table": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int], C.c_int),
     "hier_tune_time": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "hier_debug_update_box": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
 }
 
 
@@ -101,9 +102,12 @@ class Hierarchy:
 
     ``spec`` is any object with ``root_n`` and ``patches`` = [(level, lo, hi), ...].
     With ``device=None`` only the host bookkeeping is built (no HIP call is made).
+    ``extend_all=True`` extends the substep-0 update region of refined patches over every side
+    (each grid treated as isolated) instead of only over sides lacking same-level cover.
     """
 
-    def __init__(self, spec, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, device="cuda:0", stream=None):
+    def __init__(self, spec, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, device="cuda:0", stream=None,
+                 extend_all=False):
         self.lib = load_library()
         self.precision = precision
         self.spec = spec
@@ -133,6 +137,8 @@ class Hierarchy:
             pid = C.c_int()
             self._check(self.lib.patch_add(self.h, int(lv), _i3(lo), _i3(hi), C.byref(pid)))
             self.ids.append(pid.value)
+        if extend_all:
+            self._check(self.lib.hier_tune_set(self.h, 0, TUNE_EXTEND_ALL, 1))
         sb, cb = C.c_size_t(), C.c_size_t()
         self._check(self.lib.hier_finalize(self.h, C.byref(sb), C.byref(cb)))
         self.state_bytes, self.scratch_bytes = sb.value, cb.value
@@ -290,6 +296,12 @@ class Hierarchy:
         return ms.value
 
     # ------------------------------------------------------------------ bookkeeping exports
+    def update_box(self, pid, substep):
+        """The update region ((lo), (hi)) in padded cell indices of a patch at `substep`."""
+        lo, hi = (C.c_int * 3)(), (C.c_int * 3)()
+        self._check(self.lib.hier_debug_update_box(self.h, pid, substep, lo, hi))
+        return tuple(lo), tuple(hi)
+
     def debug_sources(self, pid, kind):
         offs, shape = self.layout(pid, 0)
         vol = shape[0] * shape[1] * shape[2]

@@ -63,6 +63,9 @@ struct GraphEntry {
 
 struct HPatch {
   int id = 0, level = 0;
+  // per side (2 * axis + high): the substep-0 update region of a refined patch extends over
+  // this side's ghost layers (false: every ghost entry there has a same-level source)
+  bool ext[6] = {true, true, true, true, true, true};
   int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, n[3] = {0, 0, 0};
   int parent = -1;
   std::vector<int> children;
@@ -102,6 +105,7 @@ struct amrx_hier {
   TaskList fa_b[AMRX_MAXLEV][2][NTILE];
   std::vector<std::array<std::array<TaskList, NTILE>, 2>> fa_p;
   bool fused[AMRX_MAXLEV] = {false};  // per level: fused (true) or staged first three stages
+  bool extend_all = false;            // extend every side of refined patches (set before finalize)
   int tile[AMRX_MAXLEV] = {0};
   // ghost-copy lists per depth class (0: 4 ghost layers, 1: 2 ghost layers)
   CopyList copy_b[AMRX_MAXLEV][2];
@@ -216,11 +220,47 @@ long long lin_of(const HPatch& p, int i, int j, int k) { return ((long long)k * 
 
 int nl_of(const amrx_hier* h, int level, int a) { return h->d.root_n[a] << level; }
 
+// Update region of a substep (Sec. 2.3): a refined patch's interior grown by (R - 1 - s) n_g
+// cells on the sides that need its own advance of the extended ghost layers.
 void update_box(const HPatch& p, int substep, int lo[3], int hi[3]) {
   const int g = p.level == 0 ? 0 : (R - 1 - substep) * NG;
   for (int a = 0; a < 3; ++a) {
-    lo[a] = G - g;
-    hi[a] = G + p.n[a] + g;
+    lo[a] = G - (p.ext[2 * a] ? g : 0);
+    hi[a] = G + p.n[a] + (p.ext[2 * a + 1] ? g : 0);
+  }
+}
+
+// Sides of a refined patch whose extended ghost layers (every entry the later substeps'
+// ghost copies refresh: depth (R - 1) n_g, cells and the three face kinds) all have a
+// same-level source.  The paper notes that only isolated grids need extended ghosts;
+// there, copies from the neighbours replace the self-advanced values anyway.
+void mark_sides(amrx_hier* h, int pid) {
+  HPatch& p = h->P[pid];
+  const int D = (R - 1) * NG;
+  const auto& S = h->src[pid];
+  for (int side = 0; side < 6; ++side) {
+    const int d = side / 2, hiside = side % 2;
+    bool covered = true;
+    for (int kind = 0; kind < 4 && covered; ++kind) {
+      int lo[3], hi[3];
+      for (int a = 0; a < 3; ++a) {
+        const int plus = (kind >= 1 && a == kind - 1) ? 1 : 0;
+        lo[a] = G - D;
+        hi[a] = G + p.n[a] + D + plus;
+        if (a == d) {
+          if (hiside) lo[a] = G + p.n[a] + plus;
+          else hi[a] = G;
+        }
+      }
+      for (int k = lo[2]; k < hi[2] && covered; ++k)
+        for (int j = lo[1]; j < hi[1] && covered; ++j)
+          for (int i = lo[0]; i < hi[0]; ++i)
+            if (S[kind][lin_of(p, i, j, k)] < 0) {
+              covered = false;
+              break;
+            }
+    }
+    p.ext[side] = !covered;
   }
 }
 
@@ -758,6 +798,8 @@ int finalize_impl(amrx_hier* h) {
   h->ecorr_p.assign(np, {});
   h->sync_p.assign(np, {});
   for (int id = 0; id < np; ++id) build_sources(h, id);
+  for (int id = 0; id < np; ++id)
+    if (h->P[id].level > 0 && !h->extend_all) mark_sides(h, id);
 
   // state and register layout
   h->pdev.assign(np, PatchDev{});
@@ -1678,6 +1720,11 @@ int hier_tune_set(amrx_hier* h, int level, int param, int value) {
       changed = changed || h->fused[l] != (value == 1);
       h->fused[l] = value == 1;
     }
+  } else if (param == AMRX_TUNE_EXTEND_ALL) {
+    if (value != 0 && value != 1) return fail(h, AMRX_EINVAL, "AMRX_TUNE_EXTEND_ALL takes 0 or 1");
+    if (h->frozen) return fail(h, AMRX_ESTATE, "AMRX_TUNE_EXTEND_ALL must be set before hier_finalize");
+    h->extend_all = value == 1;
+    return AMRX_OK;
   } else if (param == AMRX_TUNE_TILE) {
     if (!tile_allowed(h->d.precision, value)) return fail(h, AMRX_EINVAL, "tile index out of range or too large");
     for (int l = l0; l < l1; ++l) {
@@ -1699,6 +1746,10 @@ int hier_tune_set(amrx_hier* h, int level, int param, int value) {
 
 int hier_tune_get(const amrx_hier* h, int level, int param, int* value) {
   if (!h || !value) return AMRX_EINVAL;
+  if (param == AMRX_TUNE_EXTEND_ALL) {
+    *value = h->extend_all ? 1 : 0;
+    return AMRX_OK;
+  }
   if (level < 0 || level >= AMRX_MAXLEV) return AMRX_EINVAL;
   if (param == AMRX_TUNE_FUSED) {
     *value = h->fused[level] ? 1 : 0;
@@ -1707,6 +1758,14 @@ int hier_tune_get(const amrx_hier* h, int level, int param, int* value) {
   } else {
     return AMRX_EINVAL;
   }
+  return AMRX_OK;
+}
+
+int hier_debug_update_box(const amrx_hier* h, int patch_id, int substep, int lo[3], int hi[3]) {
+  if (!h || !lo || !hi) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  if (patch_id < 0 || patch_id >= (int)h->P.size() || substep < 0 || substep >= R) return AMRX_EINVAL;
+  update_box(h->P[patch_id], substep, lo, hi);
   return AMRX_OK;
 }
 

@@ -84,8 +84,12 @@ def test_two_level_sampled_patches(precision):
     for pid in samples:
         p = o.patches[pid]
         cells, faces = pre[pid]
-        reg = amr.update_box(p.interior_box()[0], p.interior_box()[1], 1, 0)
-        ref = mhd.advance(cells, faces, [o.dx(1)] * 3, dt / 2, reg, o.gamma)
+        # the oracle advances the fully extended region; the library's region is that region
+        # shrunk on sides whose ghost layers are covered by siblings (compared there)
+        full = amr.update_box(p.interior_box()[0], p.interior_box()[1], 1, 0)
+        ref = mhd.advance(cells, faces, [o.dx(1)] * 3, dt / 2, full, o.gamma)
+        reg = h.update_box(pid, 0)
+        assert all(full[0][a] <= reg[0][a] and reg[1][a] <= full[1][a] for a in range(3))
         got_c, got_f = h.download(pid)
         sel = (slice(None),) + mhd._sel(reg)
         for m in range(5):
@@ -201,7 +205,7 @@ def test_deep_hierarchy_sampled_patches():
         lv, lo, hi = spec.patches[pid]
         cells, faces = pre[pid]
         n = [hi[a] - lo[a] for a in range(3)]
-        reg = amr.update_box((G, G, G), tuple(G + n[a] for a in range(3)), lv, 0)
+        reg = h.update_box(pid, 0)
         dx = o.dx(lv)
         ref = mhd.advance(cells, faces, [dx] * 3, dt0 / 2 ** lv, reg, 5.0 / 3.0)
         got_c, got_f = h.download(pid)

@@ -174,3 +174,24 @@ def test_disabled_schedules_report_einval():
             h.step(mode)
         assert ei.value.code == -1
     h.step(BATCHED)
+
+
+@pytest.mark.parametrize("name,prec", [("block_two_level", FP64), ("two_level", FP32)])
+def test_sibling_covered_sides_skip_extended_update(name, prec):
+    """Refined patches advance their extended ghost layers only on sides not covered by siblings;
+    the interiors equal, bit for bit, those of the run that treats every patch as isolated."""
+    spec = getattr(H, name)()
+    _say("per-side extended regions", name)
+    field = SmoothField(27)
+    a = Hierarchy(spec, prec, extend_all=True)
+    b = Hierarchy(spec, prec)
+    shrunk = sum(1 for pid, (lv, _, _) in enumerate(spec.patches) if lv > 0 and a.update_box(pid, 0) != b.update_box(pid, 0))
+    assert shrunk > 0
+    a.set_field(field)
+    b.set_field(field)
+    for k in range(3):
+        dt = a.step(BATCHED)
+        assert b.step(GRAPH if k else BATCHED) == dt
+    _same_interiors(spec, a, b)
+    d = b.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0

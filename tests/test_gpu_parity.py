@@ -65,7 +65,7 @@ def test_uniform_32_cube_ten_steps_fp64():
         assert np.all(err <= 1e-12), (step, dict(zip(FIELDS, err)))
 
 
-@pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "root_tiled"])
+@pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "root_tiled", "block_two_level"])
 @pytest.mark.parametrize("precision", [FP64, FP32])
 def test_hierarchy_root_step(name, precision):
     spec = getattr(H, name)()

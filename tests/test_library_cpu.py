@@ -228,3 +228,51 @@ def test_autotune_size_classes():
     spec = H.two_level()
     assert autotune.size_class(spec, 0) == "n1-s256"          # one 128^3 root patch: side 132
     assert autotune.size_class(spec, 1).startswith("n512-s")
+
+
+def _covered_sides(o, pid, depth=2, G=4):
+    """Per side (2*axis + high): every ghost entry of the side's extended layers has a same-level source."""
+    p = o.patches[pid]
+    n = [p.hi[a] - p.lo[a] for a in range(3)]
+    maps = [o.cell_src[pid]] + [o.face_src[pid][d] for d in range(3)]
+    out = []
+    for side in range(6):
+        d, high = divmod(side, 2)
+        ok = True
+        for kind, arr in enumerate(maps):
+            sl = []
+            for a in range(3):
+                plus = 1 if (kind >= 1 and a == kind - 1) else 0
+                lo, hi = G - depth, G + n[a] + depth + plus
+                if a == d:
+                    lo, hi = (G + n[a] + plus, hi) if high else (lo, G)
+                sl.append(slice(lo, hi))
+            ok = ok and bool(np.all(arr[sl[2], sl[1], sl[0]] >= 0))
+        out.append(ok)
+    return out
+
+
+@pytest.mark.parametrize("name", ["block_two_level", "small_three_level", "two_level"])
+def test_update_regions_follow_sibling_cover(name):
+    """The substep-0 update region of a refined patch skips exactly the sides whose extended ghost
+    layers are all covered by same-level sources (checked against the oracle's source maps)."""
+    _lib()
+    spec = getattr(H, name)()
+    h = binding.Hierarchy(spec, device=None)
+    full = binding.Hierarchy(spec, device=None, extend_all=True)
+    o = amr.build(spec)
+    pids = [pid for pid, (lv, _, _) in enumerate(spec.patches) if lv > 0]
+    if len(pids) > 60:
+        pids = pids[::9]
+    for pid in pids:
+        lv, lo, hi = spec.patches[pid]
+        n = [hi[a] - lo[a] for a in range(3)]
+        cov = _covered_sides(o, pid)
+        blo, bhi = h.update_box(pid, 0)
+        for a in range(3):
+            assert blo[a] == (4 if cov[2 * a] else 2), (pid, a)
+            assert bhi[a] == 4 + n[a] + (0 if cov[2 * a + 1] else 2), (pid, a)
+        assert full.update_box(pid, 0) == ((2, 2, 2), tuple(6 + x for x in n))
+        assert h.update_box(pid, 1) == ((4, 4, 4), tuple(4 + x for x in n))
+    if name == "block_two_level":
+        assert h.update_box(14, 0) == ((4, 4, 4), (12, 12, 12))  # the centre patch: covered on all sides

@@ -168,6 +168,23 @@ def small_two_level(root=16):
     return spec
 
 
+def block_two_level(root=16, k=3, side=8, start=2, wide=2):
+    """Root plus a k x k x k block of adjacent level-1 patches of `side` fine cells (the last
+    layer along each axis `wide` cells wider), so that the block's inner patch sides are
+    covered by siblings and its outer sides are not."""
+    spec = HierarchySpec(root_n=(root,) * 3, name=f"block two-level {root}^3, {k}^3 patches")
+    spec.patches.append((0, (0, 0, 0), (root,) * 3))
+    edges = [start + side * i for i in range(k + 1)]
+    edges[-1] += wide
+    for kz in range(k):
+        for ky in range(k):
+            for kx in range(k):
+                lo = (edges[kx], edges[ky], edges[kz])
+                hi = (edges[kx + 1], edges[ky + 1], edges[kz + 1])
+                spec.patches.append((1, lo, hi))
+    return spec
+
+
 def small_three_level(root=16):
     """Tiny hierarchy for tests: three levels with adjacent siblings and a grandchild."""
     spec = HierarchySpec(root_n=(root,) * 3, name=f"small three-level {root}^3")
