@@ -379,16 +379,20 @@ bool is_own(const HPatch& p, int kind, int i, int j, int k) {
   return true;
 }
 
-// Copy runs (consecutive along x) of the ghost entries of p within `depth` layers of its interior.
-void build_runs(amrx_hier* h, int pid, int depth, int& nelem, double& comps) {
+// Copy runs (consecutive along x) of the ghost entries of p within `depth` layers of its
+// interior; with `by_side`, sides that do not extend the substep-0 update region (their
+// ghosts feed only the stencil of the interior) take n_g layers instead.
+void build_runs(amrx_hier* h, int pid, int depth, bool by_side, int& nelem, double& comps) {
   const HPatch& p = h->P[pid];
   const auto& S = h->src[pid];
   for (int kind = 0; kind < 4; ++kind) {
     const auto& arr = S[kind];
     int lo[3], hi[3];
     for (int a = 0; a < 3; ++a) {
-      lo[a] = G - depth;
-      hi[a] = G + p.n[a] + depth + ((kind >= 1 && a == kind - 1) ? 1 : 0);
+      const int dlo = (by_side && !p.ext[2 * a]) ? NG : depth;
+      const int dhi = (by_side && !p.ext[2 * a + 1]) ? NG : depth;
+      lo[a] = G - dlo;
+      hi[a] = G + p.n[a] + dhi + ((kind >= 1 && a == kind - 1) ? 1 : 0);
     }
     for (int k = lo[2]; k < hi[2]; ++k)
       for (int j = lo[1]; j < hi[1]; ++j) {
@@ -426,12 +430,12 @@ void build_runs(amrx_hier* h, int pid, int depth, int& nelem, double& comps) {
   }
 }
 
-CopyList make_copy_list(amrx_hier* h, const std::vector<int>& pids, int depth) {
+CopyList make_copy_list(amrx_hier* h, const std::vector<int>& pids, int depth, bool by_side) {
   CopyList L;
   L.first_run = (int)h->runs.size();
   int nelem = 0;
   double comps = 0;
-  for (int pid : pids) build_runs(h, pid, depth, nelem, comps);
+  for (int pid : pids) build_runs(h, pid, depth, by_side, nelem, comps);
   L.nrun = (int)h->runs.size() - L.first_run;
   L.nelem = nelem;
   L.comps = comps;
@@ -869,12 +873,13 @@ int finalize_impl(amrx_hier* h) {
 
   // per level lists
   for (int l = 0; l < h->nlev; ++l) {
-    // ghost copy runs: 4 layers before substep 0 of a refined level, else 2 layers
+    // ghost copy runs: before substep 0 of a refined level the region its stencil reads
+    // (4 layers on sides it extends, 2 elsewhere), else 2 layers
     for (int cls = 0; cls < 2; ++cls) {
       if (l == 0 && cls == 0) continue;
       const int depth = cls == 0 ? G : NG;
-      h->copy_b[l][cls] = make_copy_list(h, h->lev[l], depth);
-      for (int id : h->lev[l]) h->copy_p[id][cls] = make_copy_list(h, std::vector<int>{id}, depth);
+      h->copy_b[l][cls] = make_copy_list(h, h->lev[l], depth, cls == 0);
+      for (int id : h->lev[l]) h->copy_p[id][cls] = make_copy_list(h, std::vector<int>{id}, depth, cls == 0);
     }
     // prolongation
     h->pro_b[l].first = (int)h->pros.size();

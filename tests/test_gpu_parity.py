@@ -155,10 +155,21 @@ def _depth_mask(shape, n, depth, axis=None):
     return m
 
 
-@pytest.mark.parametrize("name", ["small_three_level", "root_tiled"])
+def _box_mask(shape, lo, hi, axis=None):
+    """Padded entries of the cell box [lo, hi) (x, y, z order; faces: one more along `axis`)."""
+    m = np.zeros(shape, dtype=bool)
+    top = list(hi)
+    if axis is not None:
+        top[axis] += 1
+    m[lo[2]:top[2], lo[1]:top[1], lo[0]:top[0]] = True
+    return m
+
+
+@pytest.mark.parametrize("name", ["small_three_level", "root_tiled", "block_two_level"])
 def test_ghost_copy_bit_exact(name):
     """Same-level ghost copies equal the oracle's source maps bit for bit: 2 layers on level 0 and
-    before substep 1, all 4 layers before substep 0 of a refined level."""
+    before substep 1; before substep 0 of a refined level the region its stencil reads (the update
+    region grown by 2: 4 layers on sides that extend it, 2 on sides covered by siblings)."""
     spec = getattr(H, name)()
     _say("ghost copy", name)
     o = amr.build(spec)
@@ -171,24 +182,28 @@ def test_ghost_copy_bit_exact(name):
         o.ghost_fill(lv, s)
     h.synchronize()
 
-    def check(depth_of):
+    def check(box_of):
         for pid, p in enumerate(o.patches):
-            depth = depth_of(p)
+            lo, hi = box_of(pid, p)
             cells, faces = h.download(pid)
-            m = (o.cell_src[pid] >= 0) & _depth_mask(p.shape, p.n, depth)
+            m = (o.cell_src[pid] >= 0) & _box_mask(p.shape, lo, hi)
             assert np.array_equal(cells[:, m], p.cells[:, m])
             for d in range(3):
-                fm = (o.face_src[pid][d] >= 0) & _depth_mask(p.shape, p.n, depth, d)
+                fm = (o.face_src[pid][d] >= 0) & _box_mask(p.shape, lo, hi, d)
                 assert np.array_equal(faces[d][fm], p.faces[d][fm])
 
-    check(lambda p: 2)
+    def grown(pid, p, substep, g):
+        lo, hi = h.update_box(pid, substep) if p.level > 0 else ((G,) * 3, tuple(G + int(x) for x in p.n))
+        return tuple(x - g for x in lo), tuple(x + g for x in hi)
+
+    check(lambda pid, p: grown(pid, p, 1, 2))
     if o.nlevels > 1:
         for lv in range(1, o.nlevels):
             h.ghost_fill(lv, 0)
             for p in o.level_patches(lv):
                 o._copy_from_sources(p)
         h.synchronize()
-        check(lambda p: 2 if p.level == 0 else 4)
+        check(lambda pid, p: grown(pid, p, 0, 2) if p.level > 0 else grown(pid, p, 0, 2))
 
 
 def test_prolongation_parity():
