@@ -111,8 +111,8 @@ const char* hier_last_error(const amrx_hier* h);
  * Level-0 patches must tile the root grid (checked by hier_finalize).  On
  * levels >= 1, lo and hi must be even and the box must lie inside exactly one
  * level-(l-1) patch's interior shrunk by one parent cell; same-level boxes
- * must not overlap.  A patch's ghost-padded volume prod(hi - lo + 9) must stay
- * below 2^31 entries (EINVAL otherwise).  Pure host call.  Errors: EINVAL,
+ * must not overlap.  A patch's ghost-padded extents hi - lo + 9 must stay
+ * below 2^20 per axis and their product below 2^31 entries (EINVAL otherwise).  Pure host call.  Errors: EINVAL,
  * ENEST, EOVERLAP, ESTATE. */
 int patch_add(amrx_hier* h, int level, const int lo[3], const int hi[3], int* patch_id);
 

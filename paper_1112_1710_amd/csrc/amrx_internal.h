@@ -54,6 +54,7 @@ struct Task {
   int axis;
   int lo[3];
   int hi[3];
+  double inv0, inv1;  // 1 / (hi[0] - lo[0]) and 1 / (hi[1] - lo[1]): entry index -> (i, j, k) without integer division
 };
 
 // A run of consecutive padded entries (along x) copied from a same-level patch.

@@ -275,6 +275,8 @@ int add_task(amrx_hier* h, int patch, int axis, const int lo[3], const int hi[3]
     t.hi[a] = hi[a];
     v *= std::max(0, hi[a] - lo[a]);
   }
+  t.inv0 = 1.0 / std::max(1, hi[0] - lo[0]);
+  t.inv1 = 1.0 / std::max(1, hi[1] - lo[1]);
   h->tasks.push_back(t);
   h->blk.push_back(blk_start);
   return (int)((v + AMRX_BLOCK - 1) / AMRX_BLOCK);
@@ -285,6 +287,8 @@ int add_task_tiles(amrx_hier* h, int patch, const int lo[3], const int hi[3], in
   Task t;
   t.patch = patch;
   t.axis = 0;
+  t.inv0 = 1.0 / std::max(1, hi[0] - lo[0]);
+  t.inv1 = 1.0 / std::max(1, hi[1] - lo[1]);
   long long nt = 1;
   for (int a = 0; a < 3; ++a) {
     t.lo[a] = lo[a];
@@ -1525,9 +1529,14 @@ int patch_add(amrx_hier* h, int level, const int lo[3], const int hi[3], int* pa
   for (int a = 0; a < 3; ++a)
     if (hi[a] <= lo[a]) return fail(h, AMRX_EINVAL, "empty box");
   {
-    // kernels index one patch's padded arrays with 32-bit entry counts
+    // kernels index one patch's padded arrays with 32-bit entry counts and split entry
+    // indices with double reciprocals of the padded extents (exact below 2^20 per axis)
     long long padded = 1;
-    for (int a = 0; a < 3; ++a) padded *= (long long)(hi[a] - lo[a]) + 2 * G + 1;
+    for (int a = 0; a < 3; ++a) {
+      const long long e = (long long)(hi[a] - lo[a]) + 2 * G + 1;
+      if (e >= (1LL << 20)) return fail(h, AMRX_EINVAL, "patch too large: padded extent must stay below 2^20 per axis");
+      padded *= e;
+    }
     if (padded >= (1LL << 31)) return fail(h, AMRX_EINVAL, "patch too large: padded volume must stay below 2^31 entries");
   }
   int parent = -1;

@@ -328,6 +328,20 @@ __device__ __forceinline__ int xcd_block(int b, int nb) {
   return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + i;
 }
 
+// q = n / d and r = n % d for n < 2^31 and 1 <= d < 2^20, from a double reciprocal of d: the
+// product is within 2^-20 of n / d, so its truncation is the quotient or one less (when n / d is
+// an integer and 1/d rounded down), fixed by one comparison.
+__device__ __forceinline__ void split_index(unsigned n, unsigned d, double inv, unsigned& q, int& r) {
+  unsigned qq = (unsigned)((double)n * inv);
+  unsigned rr = n - qq * d;
+  if (rr >= d) {
+    ++qq;
+    rr -= d;
+  }
+  q = qq;
+  r = (int)rr;
+}
+
 __device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, int b, Where& w) {
   int lo = 0, hi = n - 1;
   while (lo < hi) {
@@ -341,10 +355,11 @@ __device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, int b,
   const unsigned local = (unsigned)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
   if (local >= ex * ey * ez) return false;
   w.task = t;
-  const unsigned row = local / ex;
-  const unsigned k = row / ey;
-  w.i = T.lo[0] + (int)(local - row * ex);
-  w.j = T.lo[1] + (int)(row - k * ey);
+  unsigned row, k;
+  split_index(local, ex, T.inv0, row, w.i);
+  split_index(row, ey, T.inv1, k, w.j);
+  w.i += T.lo[0];
+  w.j += T.lo[1];
   w.k = T.lo[2] + (int)k;
   return true;
 }
@@ -571,6 +586,32 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_pred(DevCtx c, int first, int n,
 // to the three staged kernels (same operations in the same order); the cell
 // EMFs never reach HBM and the primitives are read back from LDS.
 // ---------------------------------------------------------------------------
+// Walk over a box nx x ny x nz in steps of `step` linear entries (x fastest) without a
+// division per entry: the coordinates of the start and of the step are split once and
+// then added with carries.
+struct Walk3 {
+  int x, y, z, dx, dy, dz, nx, ny;
+  __device__ __forceinline__ Walk3(int t, int step, int nx_, int ny_) : nx(nx_), ny(ny_) {
+    int r = t / nx;
+    x = t - r * nx;
+    y = r % ny;
+    z = r / ny;
+    r = step / nx;
+    dx = step - r * nx;
+    dy = r % ny;
+    dz = r / ny;
+  }
+  __device__ __forceinline__ void next() {
+    x += dx;
+    const int cx = x >= nx ? 1 : 0;
+    x -= cx * nx;
+    y += dy + cx;
+    const int cy = y >= ny ? 1 : 0;
+    y -= cy * ny;
+    z += dz + cy;
+  }
+};
+
 template <typename R>
 __device__ __forceinline__ R ebar_l(const R* ec, int q, int sa, int sc) {
   return R(0.25) * (ec[q] + ec[q - sa] + ec[q - sc] + ec[q - sa - sc]);
@@ -652,8 +693,9 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_fused_a(DevCtx c, int first, int
   R* sB = sE + 3 * HV;   // 3 x NB half-step face field (low faces of the tile's cells + one layer)
 
   // 1. primitives and cell EMFs of the tile and its halo (cells that exist in the padded arrays)
-  for (int t = threadIdx.x; t < HV; t += nthr) {
-    const int hx = t % H0, r = t / H0, hy = r % H1, hz = r / H1;
+  Walk3 w1(threadIdx.x, nthr, H0, H1);
+  for (int t = threadIdx.x; t < HV; t += nthr, w1.next()) {
+    const int hx = w1.x, hy = w1.y, hz = w1.z;
     const int i = o[0] - 1 + hx, j = o[1] - 1 + hy, k = o[2] - 1 + hz;
     if (i < 0 || j < 0 || k < 0 || i >= p.dim[0] - 1 || j >= p.dim[1] - 1 || k >= p.dim[2] - 1) continue;
     const long long q = i + j * S.s[1] + k * S.s[2];
@@ -678,8 +720,9 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_fused_a(DevCtx c, int first, int
 
   // 2. half-step normal field on the faces of the half-step region's cells
   R* BH = X + SCR_BH * v;
-  for (int t = threadIdx.x; t < NB; t += nthr) {
-    const int fx = t % N0, r = t / N0, fy = r % N1, fz = r / N1;
+  Walk3 w2(threadIdx.x, nthr, N0, N1);
+  for (int t = threadIdx.x; t < NB; t += nthr, w2.next()) {
+    const int fx = w2.x, fy = w2.y, fz = w2.z;
     const int i = o[0] + fx, j = o[1] + fy, k = o[2] + fz;
     // in_d: a face position along d (low faces of the tile's cells and the next one);
     // c_d: a cell of the tile along d; both restricted to the half-step region
@@ -711,8 +754,9 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_fused_a(DevCtx c, int first, int
 
   // 3. Hancock increments and reference EMFs of the tile's cells in the half-step region
   const int CV = tx * ty * tz;
-  for (int t = threadIdx.x; t < CV; t += nthr) {
-    const int cx = t % tx, r = t / tx, cy = r % ty, cz = r / ty;
+  Walk3 w3(threadIdx.x, nthr, tx, ty);
+  for (int t = threadIdx.x; t < CV; t += nthr, w3.next()) {
+    const int cx = w3.x, cy = w3.y, cz = w3.z;
     if (cx >= e[0] || cy >= e[1] || cz >= e[2]) continue;
     const int i = o[0] + cx, j = o[1] + cy, k = o[2] + cz;
     if (i < lo1[0] || i >= hi1[0] || j < lo1[1] || j >= hi1[1] || k < lo1[2] || k >= hi1[2]) continue;
@@ -1380,9 +1424,12 @@ __device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int f
     const unsigned ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
     const unsigned local = (unsigned)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
     if (local >= ex * ey * ez) continue;
-    const unsigned row = local / ex, kk = row / ey;
-    const int i = T.lo[0] + (int)(local - row * ex);
-    const int j = T.lo[1] + (int)(row - kk * ey);
+    unsigned row, kk;
+    int i, j;
+    split_index(local, ex, T.inv0, row, i);
+    split_index(row, ey, T.inv1, kk, j);
+    i += T.lo[0];
+    j += T.lo[1];
     const int k = T.lo[2] + (int)kk;
     const PatchDev& p = c.patches[T.patch];
     const Strides S = strides(p);
