@@ -211,7 +211,10 @@ int hier_timing_read(amrx_hier* h, int n, double* total_ms, int* launches);
  * algorithmic words for AMRX_K_PRIMHALF: 8 read and 8 written per cell of the
  * primitive region, 14 written per cell of the half-step region), and
  * launches[k] = kernel launches of that class in the batched schedule, for
- * the current tuning (the staged or the fused first three stages). */
+ * the current tuning (the staged or the fused first three stages).  In the
+ * batched schedule the flux and EMF corrections run inside the restriction's
+ * launch (AMRX_K_FLUXCORR / AMRX_K_EMFCORR report entries but no launches) and
+ * the CFL reductions of all levels share one launch. */
 int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
 
 /* Launch tuning (autotuner hooks).  Per level, the first three advance

@@ -228,5 +228,17 @@ hipError_t launch_cfl(const DevCtx& c, int task_first, int ntask, int blk_first,
 hipError_t launch_conservation(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk,
                                const int* cur_of_level);
 hipError_t launch_clear_slots(const DevCtx& c);
+// every level's CFL reduction in one launch; level l takes blocks [grid0[l], grid0[l + 1])
+struct CflLevels {
+  int nlev;
+  int first[AMRX_MAXLEV], n[AMRX_MAXLEV], nblk[AMRX_MAXLEV], cur[AMRX_MAXLEV];
+  int grid0[AMRX_MAXLEV + 1];
+};
+// blocks of one level's CFL reduction (a grid-stride loop covers the rest; one atomic per block)
+inline int cfl_grid(int nblk) { return nblk < 2048 ? nblk : 2048; }
+hipError_t launch_cfl_all(const DevCtx& c, const CflLevels& L);
+// restriction of a fine level with both corrections of its parents, one launch
+hipError_t launch_restrict_corr(const DevCtx& c, int rfirst, int rn, int rnblk, int ffirst, int fn, int efirst, int en,
+                                int cur_fine, int cur_coarse);
 hipError_t launch_persistent(const DevCtx& c, const Sched& sc, int nnodes, int nworkgroups, int nlev, double cfl);
 int persistent_blocks_per_cu(int precision);

@@ -1173,10 +1173,13 @@ int do_restrict(amrx_hier* h, int fine, bool plain) {
       HIPCHK(TIMED(AMRX_K_EMFCORR, launch_emf_corr(c, h->ecorr_p[id].first, h->ecorr_p[id].count, cc)), "EMF correction");
     }
   } else {
+    // one launch: restriction and the two corrections write disjoint data
     const TaskList& T = h->restr_b[fine];
-    HIPCHK(TIMED(AMRX_K_RESTRICT, launch_restrict(c, T.first, T.count, 0, T.nblk, cf, cc)), "restriction");
-    HIPCHK(TIMED(AMRX_K_FLUXCORR, launch_flux_corr(c, h->fcorr_b[fine - 1].first, h->fcorr_b[fine - 1].count, cc)), "flux correction");
-    HIPCHK(TIMED(AMRX_K_EMFCORR, launch_emf_corr(c, h->ecorr_b[fine - 1].first, h->ecorr_b[fine - 1].count, cc)), "EMF correction");
+    const Range& F = h->fcorr_b[fine - 1];
+    const Range& E = h->ecorr_b[fine - 1];
+    HIPCHK(TIMED(AMRX_K_RESTRICT, launch_restrict_corr(c, T.first, T.count, T.nblk, F.first, F.count, E.first, E.count,
+                                                       cf, cc)),
+           "restriction and corrections");
   }
   return AMRX_OK;
 }
@@ -1228,10 +1231,18 @@ double bits_to_double(unsigned long long b) {
 // Enqueue: CFL reductions of every level and the device-side dt0 (slots must be clear).
 int enqueue_cfl(amrx_hier* h) {
   DevCtx& c = h->ctx;
+  CflLevels L{};
+  L.nlev = h->nlev;
+  L.grid0[0] = 0;
   for (int l = 0; l < h->nlev; ++l) {
     const TaskList& T = h->cfl_b[l];
-    HIPCHK(TIMED(AMRX_K_CFL, launch_cfl(c, T.first, T.count, 0, T.nblk, h->cur[l], l)), "cfl");
+    L.first[l] = T.first;
+    L.n[l] = T.count;
+    L.nblk[l] = T.nblk;
+    L.cur[l] = h->cur[l];
+    L.grid0[l + 1] = L.grid0[l] + (T.count > 0 && T.nblk > 0 ? cfl_grid(T.nblk) : 0);
   }
+  HIPCHK(TIMED(AMRX_K_CFL, launch_cfl_all(c, L)), "cfl");
   HIPCHK(launch_dt_from_cfl(c, h->nlev, h->d.cfl), "dt from cfl");
   return AMRX_OK;
 }
@@ -1900,16 +1911,14 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches) {
         u[AMRX_K_RESTRICT] += per_sub * task_units(h->restr_b[l + 1]);
         u[AMRX_K_FLUXCORR] += per_sub * h->fcorr_b[l].count;
         u[AMRX_K_EMFCORR] += per_sub * h->ecorr_b[l].count;
-        nl[AMRX_K_RESTRICT] += (int)per_sub;
-        nl[AMRX_K_FLUXCORR] += (int)per_sub;
-        nl[AMRX_K_EMFCORR] += (int)per_sub;
+        nl[AMRX_K_RESTRICT] += (int)per_sub;  // the corrections run inside the restriction's launch
       }
       u[AMRX_K_SYNC] += per_sub * h->sync_b[l].count;
       nl[AMRX_K_SYNC] += (int)per_sub;
     }
     u[AMRX_K_CFL] += task_units(h->cfl_b[l]);
-    nl[AMRX_K_CFL] += 1;
   }
+  nl[AMRX_K_CFL] = 1;  // all levels in one launch
   for (int i = 0; i < n; ++i) {
     units[i] = u[i];
     launches[i] = nl[i];

@@ -1359,6 +1359,24 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_emf_corr(DevCtx c, int first, in
   d_emf_corr<R, MIX>(c, blockIdx.x, gridDim.x, first, n, cur_coarse);
 }
 
+// Restriction of a fine level and both corrections of its parents in one launch: they write
+// disjoint data (covered cells and closure faces; uncovered cells next to the coverage
+// boundary; uncovered faces around its edges) and read only fine data and registers.
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_restrict_corr(DevCtx c, int rfirst, int rn, int rnblk, int ffirst,
+                                                               int fn, int efirst, int en, int cur_fine,
+                                                               int cur_coarse) {
+  const int b = blockIdx.x;
+  const int fnblk = (fn + AMRX_BLOCK - 1) / AMRX_BLOCK;
+  if (b < rnblk) {
+    d_restrict<R>(c, b, rnblk, rfirst, rn, cur_fine, cur_coarse);
+  } else if (b < rnblk + fnblk) {
+    d_flux_corr<R, MIX>(c, b - rnblk, fnblk, ffirst, fn, cur_coarse);
+  } else {
+    d_emf_corr<R, MIX>(c, b - rnblk - fnblk, (en + AMRX_BLOCK - 1) / AMRX_BLOCK, efirst, en, cur_coarse);
+  }
+}
+
 // ---------------------------------------------------------------------------
 // same-level synchronisation of shared boundary faces
 // ---------------------------------------------------------------------------
@@ -1466,6 +1484,15 @@ __device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int f
 template <typename R, bool MIX>
 __global__ __launch_bounds__(AMRX_BLOCK) void k_cfl(DevCtx c, int first, int n, int nblk, int cur, int level) {
   d_cfl<R, MIX>(c, blockIdx.x, gridDim.x, first, n, nblk, cur, level);
+}
+
+// All levels' CFL reductions in one launch: block ranges [grid0[l], grid0[l + 1]) serve level l.
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_cfl_all(DevCtx c, CflLevels L) {
+  int l = 0;
+  while (l + 1 < L.nlev && L.grid0[l + 1] <= (int)blockIdx.x) ++l;
+  const int stride = L.grid0[l + 1] - L.grid0[l];
+  d_cfl<R, MIX>(c, blockIdx.x - L.grid0[l], stride, L.first[l], L.n[l], L.nblk[l], L.cur[l], l);
 }
 
 // ---------------------------------------------------------------------------
@@ -1793,10 +1820,25 @@ hipError_t launch_sync(const DevCtx& c, int first, int n, int cur) {
   return hipGetLastError();
 }
 
+hipError_t launch_cfl_all(const DevCtx& c, const CflLevels& L) {
+  const int g = L.grid0[L.nlev];
+  if (g == 0) return hipSuccess;
+  DISPATCH(k_cfl_all, dim3(g), c, L);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict_corr(const DevCtx& c, int rfirst, int rn, int rnblk, int ffirst, int fn, int efirst, int en,
+                                int cur_fine, int cur_coarse) {
+  const int g = (rn > 0 ? rnblk : 0) + (fn + AMRX_BLOCK - 1) / AMRX_BLOCK + (en + AMRX_BLOCK - 1) / AMRX_BLOCK;
+  if (g == 0) return hipSuccess;
+  DISPATCH(k_restrict_corr, dim3(g), c, rfirst, rn, rn > 0 ? rnblk : 0, ffirst, fn, efirst, en, cur_fine, cur_coarse);
+  return hipGetLastError();
+}
+
 hipError_t launch_cfl(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk, int cur, int level) {
   (void)blk_first;
   if (ntask == 0 || nblk == 0) return hipSuccess;
-  DISPATCH(k_cfl, dim3(nblk < 2048 ? nblk : 2048), c, task_first, ntask, nblk, cur, level);
+  DISPATCH(k_cfl, dim3(cfl_grid(nblk)), c, task_first, ntask, nblk, cur, level);
   return hipGetLastError();
 }
 
