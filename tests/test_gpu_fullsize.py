@@ -236,3 +236,40 @@ def test_deep_hierarchy_root_step_properties():
     for q in range(5):
         scale = max(abs(tot0[q]), 0.05 * abs(tot0[4]))
         assert abs(tot1[q] - tot0[q]) <= 1e-5 * scale, (q, tot0[q], tot1[q])
+
+
+def test_uniform_512_sampled_windows_far_corner():
+    """A 512^3 patch (521^3 padded entries: 64-bit intermediate offsets beyond 2^32 bytes), FP32: windows of
+    one advance, including the far corner, recomputed by the oracle from the GPU's ghost-filled input."""
+    from workloads.fields import LinearWave
+    n = 512
+    spec = H.single_patch(n)
+    _say("uniform 512^3 sampled windows")
+    k = np.array([1, 2, 3])
+    rng = np.random.default_rng(5)
+    vec = rng.standard_normal(8)
+    vec[5:8] -= k * (vec[5:8] @ k) / (k @ k)
+    gam = 5.0 / 3.0
+    rho, v, p, b = 1.0, np.array([0.1, 0.05, 0.0]), 1.0, np.array([1.0, 0.5, 0.2])
+    u0 = np.concatenate([[rho], rho * v, [p / (gam - 1) + 0.5 * rho * v @ v + 0.5 * b @ b], b])
+    h = Hierarchy(spec, FP32)
+    h.set_field(LinearWave(u0, vec, 0.05, k))
+    h.ghost_fill(0, 0)
+    h.synchronize()
+    w, halo = 8, 4
+    centres = [np.array([G, G, G]), np.array([G + n - w] * 3), np.array([G + n - w, G, G + n - w]),
+               G + rng.integers(0, n - w, 3)]
+    pre = [h.download_box(0, c - halo, c + w + halo + 1) for c in centres]
+    dt = 2.0e-4
+    h.advance(0, dt, 0)
+    h.synchronize()
+    for c, (cells, faces) in zip(centres, pre):
+        region = ((halo,) * 3, (halo + w,) * 3)
+        ref = mhd.advance(cells, faces, [1.0 / n] * 3, dt, region, gam)
+        got_c, got_f = h.download_box(0, c - halo, c + w + halo + 1)
+        sel = mhd._sel(region)
+        for m in range(5):
+            assert _rel_l1(got_c[m][sel], ref.cells[m][sel]) <= 1e-5, (c, m)
+        for d in range(3):
+            fsel = mhd._face_sel(region, d)
+            assert _rel_l1(got_f[d][fsel], ref.faces[d][fsel]) <= 1e-5, (c, d)
