@@ -236,7 +236,8 @@ struct CflLevels {
 };
 // blocks of one level's CFL reduction (a grid-stride loop covers the rest; one atomic per block)
 inline int cfl_grid(int nblk) { return nblk < 2048 ? nblk : 2048; }
-hipError_t launch_cfl_all(const DevCtx& c, const CflLevels& L);
+// CFL of all levels (block maxima into the partials) followed by the dt0 reduction into SLOT_DT
+hipError_t launch_cfl_all(const DevCtx& c, const CflLevels& L, double cfl);
 // restriction of a fine level with both corrections of its parents, one launch
 hipError_t launch_restrict_corr(const DevCtx& c, int rfirst, int rn, int rnblk, int ffirst, int fn, int efirst, int en,
                                 int cur_fine, int cur_coarse);

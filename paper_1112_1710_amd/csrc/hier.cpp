@@ -1052,7 +1052,14 @@ int finalize_impl(amrx_hier* h) {
   h->off_cov = o; o = align256(o + sizeof(int) * h->cov.size());
   h->meta_bytes = o;
   h->off_slots = o; o = align256(o + sizeof(unsigned long long) * NSLOT);
-  h->off_partials = o; o = align256(o + sizeof(double) * 16 * ((size_t)h->cons_all.nblk + 1));
+  {
+    // conservation: 16 doubles per block; CFL: one double per block of every level's reduction
+    size_t cfl_blocks = 0;
+    for (int l = 0; l < h->nlev; ++l) cfl_blocks += (size_t)cfl_grid(h->cfl_b[l].nblk);
+    const size_t n = std::max((size_t)16 * ((size_t)h->cons_all.nblk + 1), cfl_blocks + 1);
+    h->off_partials = o;
+    o = align256(o + sizeof(double) * n);
+  }
   {
     // 4 schedule variants; items depend on the persistent grid, bounded by one item per block
     SchedImage dry = build_sched(h, false, 1);
@@ -1242,8 +1249,7 @@ int enqueue_cfl(amrx_hier* h) {
     L.cur[l] = h->cur[l];
     L.grid0[l + 1] = L.grid0[l] + (T.count > 0 && T.nblk > 0 ? cfl_grid(T.nblk) : 0);
   }
-  HIPCHK(TIMED(AMRX_K_CFL, launch_cfl_all(c, L)), "cfl");
-  HIPCHK(launch_dt_from_cfl(c, h->nlev, h->d.cfl), "dt from cfl");
+  HIPCHK(TIMED(AMRX_K_CFL, launch_cfl_all(c, L, h->d.cfl)), "cfl");
   return AMRX_OK;
 }
 

@@ -1428,7 +1428,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_sync(DevCtx c, int first, int n,
 // ---------------------------------------------------------------------------
 // Grid-stride over the list's blocks; one atomic per block on the level's slot.
 template <typename R, bool MIX>
-__device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int first, int n, int nblk, int cur, int level) {
+// Largest signal-speed sum over the cells of the blocks b0, b0 + stride, ... of a level's CFL list:
+// the block maximum goes to out[b0] when out is given (reduced by a later kernel, no atomics),
+// else into the level's slot with one atomic per block.
+__device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int first, int n, int nblk, int cur, int level,
+                                      double* out = nullptr) {
   __shared__ double red[AMRX_BLOCK / 64];
   double s = 0.0;
   for (int b = b0; b < nblk; b += stride) {
@@ -1477,7 +1481,8 @@ __device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int f
   if (threadIdx.x == 0) {
     double m = red[0];
     for (int w = 1; w < AMRX_BLOCK / 64; ++w) m = fmax(m, red[w]);
-    if (m > 0.0) atomic_max_pos(&c.slots[SLOT_SMAX + level], m);
+    if (out) out[b0] = m;
+    else if (m > 0.0) atomic_max_pos(&c.slots[SLOT_SMAX + level], m);
   }
 }
 
@@ -1492,7 +1497,30 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_cfl_all(DevCtx c, CflLevels L) {
   int l = 0;
   while (l + 1 < L.nlev && L.grid0[l + 1] <= (int)blockIdx.x) ++l;
   const int stride = L.grid0[l + 1] - L.grid0[l];
-  d_cfl<R, MIX>(c, blockIdx.x - L.grid0[l], stride, L.first[l], L.n[l], L.nblk[l], L.cur[l], l);
+  d_cfl<R, MIX>(c, blockIdx.x - L.grid0[l], stride, L.first[l], L.n[l], L.nblk[l], L.cur[l], l,
+                c.partials + L.grid0[l]);
+}
+
+// dt0 = min over levels of 2^l C / (largest signal-speed sum of level l), from the per-block
+// maxima the CFL launch left in the partials; also records each level's maximum in its slot.
+__global__ __launch_bounds__(AMRX_BLOCK) void k_dt_from_partials(DevCtx c, CflLevels L, double cfl) {
+  __shared__ double red[AMRX_BLOCK / 64];
+  double best = 1e300;
+  for (int l = 0; l < L.nlev; ++l) {
+    double m = 0.0;
+    for (int i = L.grid0[l] + threadIdx.x; i < L.grid0[l + 1]; i += AMRX_BLOCK) m = fmax(m, c.partials[i]);
+    for (int off = 32; off > 0; off >>= 1) m = fmax(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = m;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double mm = red[0];
+      for (int w = 1; w < AMRX_BLOCK / 64; ++w) mm = fmax(mm, red[w]);
+      c.slots[SLOT_SMAX + l] = (unsigned long long)__double_as_longlong(mm);
+      if (mm > 0.0) best = fmin(best, ldexp(cfl, l) / mm);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c.slots[SLOT_DT] = (unsigned long long)__double_as_longlong(best);
 }
 
 // ---------------------------------------------------------------------------
@@ -1820,10 +1848,10 @@ hipError_t launch_sync(const DevCtx& c, int first, int n, int cur) {
   return hipGetLastError();
 }
 
-hipError_t launch_cfl_all(const DevCtx& c, const CflLevels& L) {
+hipError_t launch_cfl_all(const DevCtx& c, const CflLevels& L, double cfl) {
   const int g = L.grid0[L.nlev];
-  if (g == 0) return hipSuccess;
-  DISPATCH(k_cfl_all, dim3(g), c, L);
+  if (g > 0) DISPATCH(k_cfl_all, dim3(g), c, L);
+  k_dt_from_partials<<<1, AMRX_BLOCK, 0, c.stream>>>(c, L, cfl);
   return hipGetLastError();
 }
 
