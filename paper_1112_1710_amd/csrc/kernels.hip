@@ -10,6 +10,10 @@
 // face fluxes the faces of W plus one transverse layer, the edge EMFs the
 // edges of W's faces.
 //
+// The first three stages (primitives, half-step face field, Hancock
+// predictor) also exist fused in one LDS-tiled kernel with bit-identical
+// results; which one runs, and its tile shape, is chosen per level.
+//
 // Every stage kernel walks a list of (patch, region) tasks: block b finds its
 // task by binary search over the tasks' first blocks, so one launch can cover
 // one patch (plain schedule) or all patches of a level substep (batched
@@ -17,8 +21,9 @@
 // lanes touch consecutive addresses of the structure-of-arrays buffers.
 //
 // Precision: Real = double (FP64), float (FP32) or float with the pressure
-// recovered in double and flux/EMF registers kept in double with two-sum
-// compensation (FP32 mixed).  Registers are double except in plain FP32.
+// recovered in double, the Riemann problem solved in double at low-beta
+// faces and flux/EMF registers kept in double with two-sum compensation
+// (FP32 mixed).  Registers are double except in plain FP32.
 
 #include <math.h>
 #include <stdint.h>

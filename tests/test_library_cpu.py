@@ -276,3 +276,45 @@ def test_update_regions_follow_sibling_cover(name):
         assert h.update_box(pid, 1) == ((4, 4, 4), tuple(4 + x for x in n))
     if name == "block_two_level":
         assert h.update_box(14, 0) == ((4, 4, 4), (12, 12, 12))  # the centre patch: covered on all sides
+
+
+class _FakeTuned:
+    """Stands in for a bound hierarchy: records tuning calls, times candidates from a table."""
+
+    def __init__(self, spec, precision, times):
+        self.spec, self.precision, self.times, self.calls = spec, precision, times, []
+
+    def tune_set(self, param, value, level=-1):
+        self.calls.append((param, value, level))
+
+    def tune_time(self, level, substep, tile, reps=5):
+        return self.times[(level, tile)]
+
+
+def test_autotune_search_and_cache(tmp_path, monkeypatch):
+    """The autotuner keeps the fastest candidate per level (staged = -1 or a tile), caches it, and a
+    second run applies the cached choice without timing."""
+    _lib()
+    from paper_1112_1710_amd import autotune as at
+    monkeypatch.setattr(at, "arch_name", lambda device=0: "gfx950")
+    spec = H.small_two_level()
+    table = binding.tile_table(1)
+    allowed = [t for t, row in enumerate(table) if row[3] > 0]
+    times = {(lv, t): 1.0 + 0.01 * (t + 1) for lv in range(2) for t in [-1] + allowed}
+    times[(0, -1)] = 0.5           # level 0: staged fastest
+    times[(1, allowed[2])] = 0.1   # level 1: one tile fastest
+    fake = _FakeTuned(spec, 1, times)
+    path = str(tmp_path / "tune.json")
+    out = at.autotune(fake, reps=1, path=path)
+    assert out[0][0] == -1 and out[0][1] == "staged" and out[0][3] == "search"
+    assert out[1][0] == allowed[2] and out[1][3] == "search"
+    assert (binding.TUNE_FUSED, 0, 0) in fake.calls
+    assert (binding.TUNE_FUSED, 1, 1) in fake.calls and (binding.TUNE_TILE, allowed[2], 1) in fake.calls
+
+    def no_timing(*a, **k):
+        raise AssertionError("timed although cached")
+    fake2 = _FakeTuned(spec, 1, times)
+    fake2.tune_time = no_timing
+    out2 = at.autotune(fake2, reps=1, path=path)
+    assert all(v[3] == "cache" for v in out2.values())
+    assert [v[0] for v in out2.values()] == [v[0] for v in out.values()]
