@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--staged", action="store_true", help="run the first three advance stages as separate kernels")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile of the fused kernel")
+    ap.add_argument("--pair", action="store_true",
+                    help="share launches between a level's advance and the finer level's first substep")
     return ap.parse_args()
 
 
@@ -253,7 +255,7 @@ def main():
     import torch
 
     from paper_1112_1710_amd import BATCHED, CONCURRENT, FP32, FP32_MIXED, FP64, GRAPH, PERSISTENT, PLAIN, Hierarchy
-    from paper_1112_1710_amd.binding import TUNE_FUSED
+    from paper_1112_1710_amd.binding import TUNE_FUSED, TUNE_PAIR
     prec = {"fp32": FP32, "fp32_mixed": FP32_MIXED, "fp64": FP64}[args.precision]
     mode = {"plain": PLAIN, "batched": BATCHED, "graph": GRAPH, "persistent": PERSISTENT,
             "concurrent": CONCURRENT}[args.mode]
@@ -271,6 +273,8 @@ def main():
     else:
         h.set_field(field)
     tiles = None
+    if args.pair:
+        h.tune_set(TUNE_PAIR, 1)
     if args.staged:
         h.tune_set(TUNE_FUSED, 0)
     elif not args.no_autotune:

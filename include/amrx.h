@@ -229,10 +229,16 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
  *     same-level source somewhere (elsewhere the next substep's ghost copy
  *     replaces those values, so interiors are bit-identical either way).
  *     Level ignored; only before hier_finalize (ESTATE after).
+ *   AMRX_TUNE_PAIR: 1 = in the batched and graph schedules, a level's staged
+ *     advance shares its launches with the next finer level's first-substep
+ *     ghost fill and staged advance (which read only the coarser level's
+ *     pre-advance buffer), two batched launches per grid; 0 (default) = one
+ *     after the other.  Levels running the fused first stages are not paired;
+ *     launches are not paired while launch timing is on.  Level ignored.
  * level = -1 sets every level.  Pure host calls (captured graph-schedule steps
  * are discarded on a change).  EINVAL for a bad parameter, level or index, or
  * a tile whose LDS footprint exceeds the limit for the hierarchy's precision. */
-enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1, AMRX_TUNE_EXTEND_ALL = 2 };
+enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1, AMRX_TUNE_EXTEND_ALL = 2, AMRX_TUNE_PAIR = 3 };
 int hier_tune_set(amrx_hier* h, int level, int param, int value);
 int hier_tune_get(const amrx_hier* h, int level, int param, int* value);
 

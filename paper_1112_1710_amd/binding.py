@@ -15,7 +15,7 @@ G = 4
 
 KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
                   "fluxcorr", "emfcorr", "sync", "cfl", "cons", "primhalf")
-TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL = 0, 1, 2
+TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL, TUNE_PAIR = 0, 1, 2, 3
 
 _ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
 

@@ -242,4 +242,7 @@ hipError_t launch_cfl_all(const DevCtx& c, const CflLevels& L, double cfl);
 hipError_t launch_restrict_corr(const DevCtx& c, int rfirst, int rn, int rnblk, int ffirst, int fn, int efirst, int en,
                                 int cur_fine, int cur_coarse);
 hipError_t launch_persistent(const DevCtx& c, const Sched& sc, int nnodes, int nworkgroups, int nlev, double cfl);
+// two independent batched launches in one grid (supported combinations only)
+bool pair_supported(int op_a, int op_b);
+hipError_t launch_pair(const DevCtx& c, const Node& a, const Node& b);
 int persistent_blocks_per_cu(int precision);

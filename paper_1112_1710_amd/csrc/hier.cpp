@@ -106,6 +106,7 @@ struct amrx_hier {
   std::vector<std::array<std::array<TaskList, NTILE>, 2>> fa_p;
   bool fused[AMRX_MAXLEV] = {false};  // per level: fused (true) or staged first three stages
   bool extend_all = false;            // extend every side of refined patches (set before finalize)
+  bool pair_levels = false;           // share launches between a level's advance and the finer level's first substep
   int tile[AMRX_MAXLEV] = {0};
   // ghost-copy lists per depth class (0: 4 ghost layers, 1: 2 ghost layers)
   CopyList copy_b[AMRX_MAXLEV][2];
@@ -1202,15 +1203,76 @@ int do_sync(amrx_hier* h, int level, bool plain) {
   return AMRX_OK;
 }
 
-int amr_recursive(amrx_hier* h, int level, double dt, bool plain) {
+hipError_t launch_node(amrx_hier* h, const Node& nd, hipStream_t s);
+
+// Batched launches of one level substep's ghost fill (copy, then prolongation from the
+// parent's buffer `old_parent` at substep 0 of a refined level) and of its staged advance.
+void ghost_nodes(amrx_hier* h, int l, int s, int cur, int old_parent, std::vector<Node>& out) {
+  const int cls = (l > 0 && s == 0) ? 0 : 1;
+  const CopyList& L = h->copy_b[l][cls];
+  out.push_back(mk_node(OP_COPY, l, s, cur, 0, L.first_run, L.nrun, L.first_blk, L.nrun ? L.nblk : 0, L.nelem));
+  if (l > 0 && s == 0) {
+    const Range& P = h->pro_b[l];
+    out.push_back(mk_node(OP_PROLONG, l, s, cur, old_parent, P.first, P.count, 0, (P.count + AMRX_BLOCK - 1) / AMRX_BLOCK, 0));
+  }
+}
+void advance_nodes(amrx_hier* h, int l, int s, int cur, std::vector<Node>& out) {
+  const int ops[NSTAGE] = {OP_PRIM, OP_BHALF, OP_PRED, OP_FLUX, OP_EDGE, OP_UPDATE};
+  for (int stg = 0; stg < NSTAGE; ++stg) {
+    const TaskList& T = h->stage_b[l][s][stg];
+    out.push_back(mk_node(ops[stg], l, s, cur, 0, T.first, T.count, 0, T.count ? T.nblk : 0, 0));
+  }
+}
+
+// Advance of (level, s) with the ghost fill and first-substep advance of level + 1 beside it:
+// the finer level reads only the coarser level's pre-advance buffer (Sec. 2.3), so the two
+// chains share launches, the i-th launch of each in one grid where the pair is supported.
+int paired_advance(amrx_hier* h, int level, int s) {
+  const int cl = h->cur[level], cf = h->cur[level + 1];
+  std::vector<Node> A, B;
+  advance_nodes(h, level, s, cl, A);
+  ghost_nodes(h, level + 1, 0, cf, cl, B);
+  advance_nodes(h, level + 1, 0, cf, B);
+  const hipStream_t st = (hipStream_t)h->d.stream;
+  const size_t n = std::max(A.size(), B.size());
+  for (size_t i = 0; i < n; ++i) {
+    const bool ha = i < A.size() && A[i].nblk > 0, hb = i < B.size() && B[i].nblk > 0;
+    if (ha && hb && pair_supported(A[i].op, B[i].op)) {
+      HIPCHK(launch_pair(h->ctx, A[i], B[i]), "paired launch");
+    } else {
+      if (ha) HIPCHK(launch_node(h, A[i], st), "advance launch");
+      if (hb) HIPCHK(launch_node(h, B[i], st), "finer-level launch");
+    }
+  }
+  h->cur[level] = 1 - cl;
+  h->cur[level + 1] = 1 - cf;
+  return AMRX_OK;
+}
+
+bool can_pair(const amrx_hier* h, int level, bool plain) {
+  return h->pair_levels && !plain && !h->timing && level + 1 < h->nlev && !h->fused[level] && !h->fused[level + 1];
+}
+
+// AMR(l) of Sec. 2.2 for one step of level `level`; with `first_done` the ghost fill and
+// advance of its first substep were already enqueued (paired with the parent's advance).
+int amr_recursive(amrx_hier* h, int level, double dt, bool plain, bool first_done) {
   const int nsub = level == 0 ? 1 : R;
   for (int s = 0; s < nsub; ++s) {
-    int rc = do_ghost_fill(h, level, s, plain);
-    if (rc) return rc;
-    rc = do_advance(h, level, dt, s, plain);
-    if (rc) return rc;
+    int rc;
+    bool child_done = false;
+    if (!(s == 0 && first_done)) {
+      rc = do_ghost_fill(h, level, s, plain);
+      if (rc) return rc;
+      if (can_pair(h, level, plain)) {
+        rc = paired_advance(h, level, s);
+        child_done = true;
+      } else {
+        rc = do_advance(h, level, dt, s, plain);
+      }
+      if (rc) return rc;
+    }
     if (level + 1 < h->nlev) {
-      rc = amr_recursive(h, level + 1, dt / R, plain);
+      rc = amr_recursive(h, level + 1, dt / R, plain, child_done);
       if (rc) return rc;
       rc = do_restrict(h, level + 1, plain);
       if (rc) return rc;
@@ -1220,6 +1282,7 @@ int amr_recursive(amrx_hier* h, int level, double dt, bool plain) {
   }
   return AMRX_OK;
 }
+int amr_recursive(amrx_hier* h, int level, double dt, bool plain) { return amr_recursive(h, level, dt, plain, false); }
 
 int read_slots(amrx_hier* h, unsigned long long* out) {
   HIPCHK(hipMemcpyAsync(out, h->scratch + h->off_slots, sizeof(unsigned long long) * NSLOT, hipMemcpyDeviceToHost,
@@ -1751,6 +1814,10 @@ int hier_tune_set(amrx_hier* h, int level, int param, int value) {
       changed = changed || h->fused[l] != (value == 1);
       h->fused[l] = value == 1;
     }
+  } else if (param == AMRX_TUNE_PAIR) {
+    if (value != 0 && value != 1) return fail(h, AMRX_EINVAL, "AMRX_TUNE_PAIR takes 0 or 1");
+    changed = h->pair_levels != (value == 1);
+    h->pair_levels = value == 1;
   } else if (param == AMRX_TUNE_EXTEND_ALL) {
     if (value != 0 && value != 1) return fail(h, AMRX_EINVAL, "AMRX_TUNE_EXTEND_ALL takes 0 or 1");
     if (h->frozen) return fail(h, AMRX_ESTATE, "AMRX_TUNE_EXTEND_ALL must be set before hier_finalize");
@@ -1779,6 +1846,10 @@ int hier_tune_get(const amrx_hier* h, int level, int param, int* value) {
   if (!h || !value) return AMRX_EINVAL;
   if (param == AMRX_TUNE_EXTEND_ALL) {
     *value = h->extend_all ? 1 : 0;
+    return AMRX_OK;
+  }
+  if (param == AMRX_TUNE_PAIR) {
+    *value = h->pair_levels ? 1 : 0;
     return AMRX_OK;
   }
   if (level < 0 || level >= AMRX_MAXLEV) return AMRX_EINVAL;

@@ -1750,6 +1750,48 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_persistent(DevCtx c, Sched sc, i
   }
 }
 
+// ---------------------------------------------------------------------------
+// paired launches: two independent batched launches (one level's advance stage
+// and the next finer level's ghost fill or advance stage of its first substep,
+// which reads only the coarse level's pre-advance buffer) in one grid, so that
+// their blocks share the GPU (e.g. arithmetic-bound fluxes beside
+// memory-bound stages).  Block ranges [0, pa) and [pa, pa + pb) serve a and b.
+// ---------------------------------------------------------------------------
+template <int OP, typename R, bool MIX>
+__device__ __forceinline__ void run_op(const DevCtx& c, const Node& nd, int vb) {
+  if constexpr (OP == OP_COPY) d_copy<R>(c, vb, nd.nblk, nd.first, nd.n, nd.blk_first, nd.nelem, nd.cur);
+  else if constexpr (OP == OP_PROLONG) d_prolong<R>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.aux);
+  else if constexpr (OP == OP_PRIM) d_prim<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur);
+  else if constexpr (OP == OP_BHALF) d_bhalf<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level);
+  else if constexpr (OP == OP_PRED) d_pred<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level);
+  else if constexpr (OP == OP_FLUX) d_flux<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep);
+  else if constexpr (OP == OP_EDGE) d_edge<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep);
+  else if constexpr (OP == OP_UPDATE) d_update<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level);
+}
+
+template <int OP>
+__device__ __forceinline__ int pair_block(int local, int padded) {
+  // ghost copies and prolongation index their lists directly; stage kernels use the XCD remap
+  return (OP == OP_COPY || OP == OP_PROLONG) ? local : xcd_block(local, padded);
+}
+
+template <int OA, int OB, typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_pair(DevCtx c, Node a, Node b, int pa, int pb) {
+  // groups of 8 consecutive blocks (one per XCD) alternate between a and b in proportion to
+  // their sizes, so both run side by side through the whole launch; a block keeps its XCD
+  const long long ga = pa >> 3, gt = (pa + pb) >> 3;
+  const long long g = blockIdx.x >> 3;
+  const int lane = blockIdx.x & 7;
+  const long long ka = g * ga / gt, ka1 = (g + 1) * ga / gt;  // a-groups before group g, and through it
+  if (ka1 > ka) {
+    const int vb = pair_block<OA>((int)(ka * 8 + lane), pa);
+    if (vb < a.nblk) run_op<OA, R, MIX>(c, a, vb);
+  } else {
+    const int vb = pair_block<OB>((int)((g - ka) * 8 + lane), pb);
+    if (vb < b.nblk) run_op<OB, R, MIX>(c, b, vb);
+  }
+}
+
 __global__ void k_clear_sched(Sched sc, int nnodes) {
   for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < nnodes; i += gridDim.x * blockDim.x) sc.done[i] = 0;
   if (blockIdx.x == 0)
@@ -1851,6 +1893,40 @@ hipError_t launch_sync(const DevCtx& c, int first, int n, int cur) {
   if (n == 0) return hipSuccess;
   DISPATCH(k_sync, dim3(grid_of(n, AMRX_BLOCK)), c, first, n, cur);
   return hipGetLastError();
+}
+
+template <int OA, int OB>
+hipError_t launch_pair_t(const DevCtx& c, const Node& a, const Node& b) {
+  // pad each range to a multiple of the 8 XCDs so that both remaps see whole rounds
+  const int pa = (a.nblk + 7) & ~7, pb = (b.nblk + 7) & ~7;
+  if (pa + pb == 0) return hipSuccess;
+  const dim3 g(pa + pb);
+  if (c.precision == 0)
+    k_pair<OA, OB, double, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, a, b, pa, pb);
+  else if (c.precision == 1)
+    k_pair<OA, OB, float, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, a, b, pa, pb);
+  else
+    k_pair<OA, OB, float, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, a, b, pa, pb);
+  return hipGetLastError();
+}
+
+#define PAIR_CASES(X)                                                                                \
+  X(OP_PRIM, OP_COPY) X(OP_BHALF, OP_PROLONG) X(OP_PRED, OP_PRIM) X(OP_FLUX, OP_BHALF) X(OP_EDGE, OP_PRED) \
+  X(OP_UPDATE, OP_FLUX)
+
+bool pair_supported(int op_a, int op_b) {
+#define PAIR_TEST(A, B) if (op_a == A && op_b == B) return true;
+  PAIR_CASES(PAIR_TEST)
+#undef PAIR_TEST
+  return false;
+}
+
+hipError_t launch_pair(const DevCtx& c, const Node& a, const Node& b) {
+#define PAIR_LAUNCH(A, B) \
+  if (a.op == A && b.op == B) return launch_pair_t<A, B>(c, a, b);
+  PAIR_CASES(PAIR_LAUNCH)
+#undef PAIR_LAUNCH
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_cfl_all(const DevCtx& c, const CflLevels& L, double cfl) {

@@ -195,3 +195,28 @@ def test_sibling_covered_sides_skip_extended_update(name, prec):
     _same_interiors(spec, a, b)
     d = b.diag()
     assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+
+
+@pytest.mark.parametrize("name,prec", [("small_three_level", FP64), ("block_two_level", FP64), ("two_level", FP32)])
+def test_paired_levels_bit_identical(name, prec):
+    """A level's advance sharing launches with the finer level's first substep gives the sequential
+    schedule's results bit for bit (batched and graph-captured)."""
+    spec = getattr(H, name)()
+    _say("paired levels", name)
+    field = SmoothField(28)
+    a = Hierarchy(spec, prec)
+    b = Hierarchy(spec, prec)
+    g = Hierarchy(spec, prec)
+    for x in (b, g):
+        x.tune_set(binding.TUNE_PAIR, 1)
+        assert x.tune_get(binding.TUNE_PAIR) == 1
+    for x in (a, b, g):
+        x.set_field(field)
+    for _ in range(3):
+        dt = a.step(BATCHED)
+        assert b.step(BATCHED) == dt
+        assert g.step(GRAPH) == dt
+    _same_interiors(spec, a, b)
+    _same_interiors(spec, a, g)
+    d = g.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
