@@ -47,7 +47,13 @@ WORDS_PER_UNIT = {
 # 512 MiB copy's readings), keyed by (workload, precision, kernel class); valid only for the kernel sources whose
 # hash is stored beside it, null otherwise.
 MEASURED_TRAFFIC = {
-    ("two_level", "fp32", "flux"): {"bytes_per_launch": 644.3e6, "sources": "5475637a2375dbc1:7c1c234338ed33f0"},
+    ("two_level", "fp32", "flux"): {"bytes_per_launch": 644.1e6, "sources": "4c7c0789838554e0:3c521936618967fa"},
+}
+
+# Fraction of the dominant kernel's vector-ALU issue slots used (SQ_INSTS_VALU against 256 CUs x one
+# wave-instruction per cycle x 2.4 GHz over its mean duration), from rocprofv3 counters, same validity rule.
+MEASURED_VALU_ISSUE = {
+    ("two_level", "fp32", "flux"): {"frac": 0.66, "sources": "4c7c0789838554e0:3c521936618967fa"},
 }
 
 
@@ -309,8 +315,11 @@ def main():
         if dom in ALU_BOUND:
             flops_per_launch = units_per_step * ALU_BOUND[dom] / max(launches_per_step, 1)
             tf = flops_per_launch / (avg_ms * 1e-3) / 1e12
+            issue = MEASURED_VALU_ISSUE.get((args.workload, args.precision, dom))
+            issue = issue["frac"] if issue is not None and issue["sources"] == sources_hash() else None
             roof = {"bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(tf / VALU_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": dom,
+                    "valu_issue_frac": issue,
                     "avg_launch_ms": round(avg_ms, 4), "flops_per_launch": int(flops_per_launch),
                     "hbm": {k: hbm[k] for k in ("achieved", "peak", "unit", "frac", "bytes_per_launch")}}
         else:
