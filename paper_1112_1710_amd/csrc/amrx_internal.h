@@ -152,6 +152,8 @@ struct DevCtx {
   const PatchDev* patches;
   const Task* tasks;
   const int* blk;         // per-task first block (prefix)
+  const int* tbl;         // per task list (indexed by its first task): offset of the list's block table in b2t
+  const int* b2t;         // block tables: task of every block of a list (one entry per block)
   const Run* runs;
   const int* run_blk;     // per copy block: index (within the list) of the run holding its first element
   const Pro* pros;

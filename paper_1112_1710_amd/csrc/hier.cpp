@@ -11,6 +11,7 @@
 #include <cmath>
 #include <array>
 #include <cstdio>
+#include <climits>
 #include <cstring>
 #include <map>
 #include <string>
@@ -125,6 +126,8 @@ struct amrx_hier {
 
   // layout
   size_t state_bytes = 0, scratch_bytes = 0;
+  std::vector<int> tbl, b2t;  // block tables of the task lists (see build_block_tables)
+  size_t off_tbl = 0, off_b2t = 0;
   size_t off_pdev = 0, off_tasks = 0, off_blk = 0, off_runs = 0, off_pros = 0, off_fcorr = 0, off_ecorr = 0,
          off_sync = 0, off_cov = 0, off_slots = 0, off_partials = 0, off_reg = 0, off_rscr = 0, off_runblk = 0;
   size_t meta_bytes = 0;
@@ -299,6 +302,25 @@ int add_task_tiles(amrx_hier* h, int patch, const int lo[3], const int hi[3], in
   h->tasks.push_back(t);
   h->blk.push_back(blk_start);
   return (int)nt;
+}
+
+// Block table of one task list: the task of each of its blocks, so a kernel finds its task with
+// one lookup instead of a search over the block prefix.  Lists without blocks get none.
+bool add_block_table(amrx_hier* h, const TaskList& L) {
+  if (L.count <= 0 || L.nblk <= 0) return true;
+  const size_t at = h->b2t.size();
+  h->tbl[L.first] = (int)at;
+  for (int t = L.first; t < L.first + L.count; ++t) {
+    const int b1 = t + 1 < L.first + L.count ? h->blk[t + 1] : L.nblk;
+    for (int b = h->blk[t]; b < b1; ++b) h->b2t.push_back(t);
+  }
+  // one entry per block, each the last task whose first block is <= b
+  if (h->blk[L.first] != 0 || h->b2t.size() - at != (size_t)L.nblk) return false;
+  for (int b = 0; b < L.nblk; ++b) {
+    const int t = h->b2t[at + b];
+    if (h->blk[t] > b || (t + 1 < L.first + L.count && h->blk[t + 1] <= b)) return false;
+  }
+  return true;
 }
 
 // Regions of the advance stages for update region [lo, hi).
@@ -1029,6 +1051,30 @@ int finalize_impl(amrx_hier* h) {
     B.count = (int)h->tasks.size() - B.first;
     B.nblk = nb;
   }
+  // block tables of every task list
+  h->tbl.assign(h->tasks.size() + 1, 0);
+  h->b2t.clear();
+  {
+    bool ok = true;
+    for (int l = 0; l < h->nlev; ++l) {
+      for (int s = 0; s < 2; ++s) {
+        for (int stg = 0; stg < NSTAGE; ++stg) ok = add_block_table(h, h->stage_b[l][s][stg]) && ok;
+        for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fa_b[l][s][t]) && ok;
+      }
+      ok = add_block_table(h, h->restr_b[l]) && ok;
+      ok = add_block_table(h, h->cfl_b[l]) && ok;
+    }
+    for (size_t id = 0; id < h->P.size(); ++id) {
+      for (int s = 0; s < 2; ++s) {
+        for (int stg = 0; stg < NSTAGE; ++stg) ok = add_block_table(h, h->stage_p[id][s][stg]) && ok;
+        for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fa_p[id][s][t]) && ok;
+      }
+      ok = add_block_table(h, h->restr_p[id]) && ok;
+    }
+    ok = add_block_table(h, h->cons_all) && ok;
+    if (!ok) return fail(h, AMRX_EINVAL, "internal error: inconsistent block table");
+    if (h->b2t.size() >= (size_t)INT_MAX) return fail(h, AMRX_ENOMEM, "block tables exceed 2^31 entries");
+  }
 
   // host-side bounds checks of everything the kernels index
   for (const Pro& pr : h->pros) {
@@ -1044,6 +1090,8 @@ int finalize_impl(amrx_hier* h) {
   h->off_pdev = o; o = align256(o + sizeof(PatchDev) * np);
   h->off_tasks = o; o = align256(o + sizeof(Task) * h->tasks.size());
   h->off_blk = o; o = align256(o + sizeof(int) * h->blk.size());
+  h->off_tbl = o; o = align256(o + sizeof(int) * h->tbl.size());
+  h->off_b2t = o; o = align256(o + sizeof(int) * h->b2t.size());
   h->off_runs = o; o = align256(o + sizeof(Run) * h->runs.size());
   h->off_runblk = o; o = align256(o + sizeof(int) * h->run_blk.size());
   h->off_pros = o; o = align256(o + sizeof(Pro) * h->pros.size());
@@ -1089,6 +1137,8 @@ DevCtx make_ctx(amrx_hier* h) {
   c.patches = (const PatchDev*)(s + h->off_pdev);
   c.tasks = (const Task*)(s + h->off_tasks);
   c.blk = (const int*)(s + h->off_blk);
+  c.tbl = (const int*)(s + h->off_tbl);
+  c.b2t = (const int*)(s + h->off_b2t);
   c.runs = (const Run*)(s + h->off_runs);
   c.run_blk = (const int*)(s + h->off_runblk);
   c.pros = (const Pro*)(s + h->off_pros);
@@ -1699,6 +1749,8 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
   put(h->off_pdev, h->pdev.data(), sizeof(PatchDev) * h->pdev.size());
   put(h->off_tasks, h->tasks.data(), sizeof(Task) * h->tasks.size());
   put(h->off_blk, h->blk.data(), sizeof(int) * h->blk.size());
+  put(h->off_tbl, h->tbl.data(), sizeof(int) * h->tbl.size());
+  put(h->off_b2t, h->b2t.data(), sizeof(int) * h->b2t.size());
   put(h->off_runs, h->runs.data(), sizeof(Run) * h->runs.size());
   put(h->off_runblk, h->run_blk.data(), sizeof(int) * h->run_blk.size());
   put(h->off_pros, h->pros.data(), sizeof(Pro) * h->pros.size());

@@ -347,13 +347,13 @@ __device__ __forceinline__ void split_index(unsigned n, unsigned d, double inv, 
   r = (int)rr;
 }
 
+// Task of block b (0 <= b < the list's block count) of the list starting at task `first`: one lookup
+// in the list's block table.
+__device__ __forceinline__ int task_of_block(const DevCtx& c, int first, int b) { return c.b2t[c.tbl[first] + b]; }
+
 __device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, int b, Where& w) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (c.blk[first + mid] <= b) lo = mid; else hi = mid - 1;
-  }
-  const int t = first + lo;
+  (void)n;
+  const int t = task_of_block(c, first, b);
   const Task& T = c.tasks[t];
   // a region lies inside one padded patch, whose volume the host keeps below 2^31 entries
   const unsigned ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
@@ -663,13 +663,10 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_fused_a(DevCtx c, int first, int
   R* sm = reinterpret_cast<R*>(smem_d);
   const int nthr = blockDim.x;
   const int vb = xcd_block(blockIdx.x, gridDim.x);
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (c.blk[first + mid] <= vb) lo = mid; else hi = mid - 1;
-  }
-  const Task& T = c.tasks[first + lo];
-  const int tile = vb - c.blk[first + lo];
+  (void)n;
+  const int t = task_of_block(c, first, vb);
+  const Task& T = c.tasks[t];
+  const int tile = vb - c.blk[t];
   const int ntx = (T.hi[0] - T.lo[0] + tx - 1) / tx, nty = (T.hi[1] - T.lo[1] + ty - 1) / ty;
   const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
   const int o[3] = {T.lo[0] + tix * tx, T.lo[1] + tiy * ty, T.lo[2] + tiz * tz};
@@ -1440,13 +1437,9 @@ __device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int f
                                       double* out = nullptr) {
   __shared__ double red[AMRX_BLOCK / 64];
   double s = 0.0;
+  (void)n;
   for (int b = b0; b < nblk; b += stride) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      const int mid = (lo + hi + 1) >> 1;
-      if (c.blk[first + mid] <= b) lo = mid; else hi = mid - 1;
-    }
-    const int t = first + lo;
+    const int t = task_of_block(c, first, b);
     const Task& T = c.tasks[t];
     const unsigned ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
     const unsigned local = (unsigned)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
