@@ -98,9 +98,8 @@ __device__ __forceinline__ R minmod2(R a, R b) {
 
 template <typename R>
 __device__ __forceinline__ R upwind(R flux, R minus_val, R plus_val) {
-  if (flux > R(0)) return minus_val;
-  if (flux < R(0)) return plus_val;
-  return R(0.5) * (minus_val + plus_val);
+  const R mean = R(0.5) * (minus_val + plus_val);
+  return flux > R(0) ? minus_val : (flux < R(0) ? plus_val : mean);
 }
 
 // gas pressure from conserved variables; MIX evaluates it in double
@@ -934,10 +933,11 @@ __device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R
   const R ea_bm = efa[q - sc], ea_b0 = efa[q];
   const R eb_am = efc[q - sa], eb_a0 = efc[q];
   const R r_mm = er[q - sa - sc], r_0m = er[q - sc], r_m0 = er[q - sa], r_00 = er[q];
-  const R d_b_upper = upwind(fa0[q], r_m0 - eb_am, r_00 - eb_a0);
-  const R d_b_lower = upwind(fa0[q - sc], eb_am - r_mm, eb_a0 - r_0m);
-  const R d_a_upper = upwind(fc0[q], r_0m - ea_bm, r_00 - ea_b0);
-  const R d_a_lower = upwind(fc0[q - sa], ea_bm - r_mm, ea_b0 - r_m0);
+  const R ma_hi = fa0[q], ma_lo = fa0[q - sc], mc_hi = fc0[q], mc_lo = fc0[q - sa];
+  const R d_b_upper = upwind(ma_hi, r_m0 - eb_am, r_00 - eb_a0);
+  const R d_b_lower = upwind(ma_lo, eb_am - r_mm, eb_a0 - r_0m);
+  const R d_a_upper = upwind(mc_hi, r_0m - ea_bm, r_00 - ea_b0);
+  const R d_a_lower = upwind(mc_lo, ea_bm - r_mm, ea_b0 - r_m0);
   const R emf = R(0.25) * (ea_bm + ea_b0 + eb_am + eb_a0) + R(0.25) * (d_b_lower - d_b_upper) +
                 R(0.25) * (d_a_lower - d_a_upper);
   X[(SCR_E + E) * v + q] = emf;
@@ -997,15 +997,6 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_edge(DevCtx c, int first, int n,
 // ---------------------------------------------------------------------------
 // stage 6: conservative cell update and Stokes face update into the next buffer
 // ---------------------------------------------------------------------------
-template <int D, typename R>
-__device__ __forceinline__ void face_update(const R* U, R* N, const R* EE, const Strides& S, long long q, R dt_dx) {
-  constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
-  const R* eC = EE + C * S.v;
-  const R* eA = EE + A * S.v;
-  const R curl = (eC[q + S.s[A]] - eC[q]) - (eA[q + S.s[C]] - eA[q]);
-  N[(5 + D) * S.v + q] = U[(5 + D) * S.v + q] - dt_dx * curl;
-}
-
 template <typename R, bool MIX>
 __device__ __forceinline__ void d_update(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level) {
   (void)nb;
@@ -1022,26 +1013,58 @@ __device__ __forceinline__ void d_update(const DevCtx& c, int vb, int nb, int fi
   const long long v = S.v;
   const R dt_dx = R(dt / p.dx);
   const bool ix = w.i < T.hi[0] - 1, iy = w.j < T.hi[1] - 1, iz = w.k < T.hi[2] - 1;
-  if (ix && iy && iz) {
-    R div[5] = {R(0), R(0), R(0), R(0), R(0)};
+  const bool cell = ix && iy && iz;
+  const bool face[3] = {iy && iz, ix && iz, ix && iy};
+  // every operand is loaded before the first store (the two buffers share one arena, so a
+  // load after a store could not be moved ahead of it)
+  R u[5], f0[3][4], f1[3][4], m0[3], m1[3];
+  if (cell) {
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
       const R* F4 = X + (SCR_F4 + 4 * d) * v;
       const R* F0 = X + (SCR_F0 + d) * v;
-      R f0[4], f1[4];
-      ld4(F4 + 4 * q, f0);
-      ld4(F4 + 4 * (q + S.s[d]), f1);
-      div[0] += F0[q + S.s[d]] - F0[q];
-#pragma unroll
-      for (int m = 0; m < 4; ++m) div[1 + m] += f1[m] - f0[m];
+      ld4(F4 + 4 * q, f0[d]);
+      ld4(F4 + 4 * (q + S.s[d]), f1[d]);
+      m0[d] = F0[q];
+      m1[d] = F0[q + S.s[d]];
     }
 #pragma unroll
-    for (int m = 0; m < 5; ++m) N[m * v + q] = U[m * v + q] - dt_dx * div[m];
+    for (int m = 0; m < 5; ++m) u[m] = U[m * v + q];
   }
+  // faces normal to D: Stokes update from the edge EMFs along C = D+2 and A = D+1
   const R* EE = X + SCR_E * v;
-  if (iy && iz) face_update<0>(U, N, EE, S, q, dt_dx);
-  if (ix && iz) face_update<1>(U, N, EE, S, q, dt_dx);
-  if (ix && iy) face_update<2>(U, N, EE, S, q, dt_dx);
+  R bo[3], ec_hi[3], ec_lo[3], ea_hi[3], ea_lo[3];
+#pragma unroll
+  for (int D = 0; D < 3; ++D) {
+    if (face[D]) {
+      const int A = (D + 1) % 3, C = (D + 2) % 3;
+      const R* eC = EE + C * v;
+      const R* eA = EE + A * v;
+      bo[D] = U[(5 + D) * v + q];
+      ec_hi[D] = eC[q + S.s[A]];
+      ec_lo[D] = eC[q];
+      ea_hi[D] = eA[q + S.s[C]];
+      ea_lo[D] = eA[q];
+    }
+  }
+  if (cell) {
+    R div[5] = {R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      div[0] += m1[d] - m0[d];
+#pragma unroll
+      for (int m = 0; m < 4; ++m) div[1 + m] += f1[d][m] - f0[d][m];
+    }
+#pragma unroll
+    for (int m = 0; m < 5; ++m) N[m * v + q] = u[m] - dt_dx * div[m];
+  }
+#pragma unroll
+  for (int D = 0; D < 3; ++D) {
+    if (face[D]) {
+      const R curl = (ec_hi[D] - ec_lo[D]) - (ea_hi[D] - ea_lo[D]);
+      N[(5 + D) * v + q] = bo[D] - dt_dx * curl;
+    }
+  }
 }
 
 template <typename R, bool MIX>
