@@ -83,7 +83,7 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=4, help="steps of the FP64 per-patch-launch comparison")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
-    ap.add_argument("--staged", action="store_true", help="run the first three advance stages as separate kernels")
+    ap.add_argument("--staged", action="store_true", help="run every advance stage as a separate kernel")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile of the fused kernel")
     ap.add_argument("--pair", action="store_true",
                     help="share launches between a level's advance and the finer level's first substep")
@@ -261,7 +261,7 @@ def main():
     import torch
 
     from paper_1112_1710_amd import BATCHED, CONCURRENT, FP32, FP32_MIXED, FP64, GRAPH, PERSISTENT, PLAIN, Hierarchy
-    from paper_1112_1710_amd.binding import TUNE_FUSED, TUNE_PAIR
+    from paper_1112_1710_amd.binding import TUNE_FUSED, TUNE_FUSED_EU, TUNE_PAIR
     prec = {"fp32": FP32, "fp32_mixed": FP32_MIXED, "fp64": FP64}[args.precision]
     mode = {"plain": PLAIN, "batched": BATCHED, "graph": GRAPH, "persistent": PERSISTENT,
             "concurrent": CONCURRENT}[args.mode]
@@ -281,11 +281,15 @@ def main():
     tiles = None
     if args.pair:
         h.tune_set(TUNE_PAIR, 1)
+    last = None
     if args.staged:
         h.tune_set(TUNE_FUSED, 0)
+        h.tune_set(TUNE_FUSED_EU, 0)
     elif not args.no_autotune:
         from paper_1112_1710_amd.autotune import autotune
-        tiles = {lvl: v[1] for lvl, v in autotune(h).items()}
+        chosen = autotune(h)
+        tiles = {str(k): v[1] for k, v in chosen.items() if isinstance(k, int)}
+        last = {str(k[1]): v[1] for k, v in chosen.items() if not isinstance(k, int)}
     sec, timing = timed_steps(h, mode, args.steps, args.warmup, torch, reset)
     value = zu / sec
     work = h.step_work()
@@ -354,6 +358,7 @@ def main():
                    "schedule": args.mode,
                    "steps_from": "t=0 state before every step" if steps_from_t0 else "consecutive steps",
                    "first_stages": "staged" if args.staged or tiles is None else tiles,
+                   "edge_update_stages": "staged" if args.staged or last is None else last,
                    "parallelism": "single GPU"},
         "roofline": roof,
         "kernel_ms_per_step": per_class,

@@ -190,6 +190,7 @@ enum {
   AMRX_K_COPY, AMRX_K_PROLONG, AMRX_K_RESTRICT, AMRX_K_FLUXCORR, AMRX_K_EMFCORR, AMRX_K_SYNC,
   AMRX_K_CFL, AMRX_K_CONS,
   AMRX_K_PRIMHALF,   /* stages prim, bhalf and pred fused into one LDS-tiled kernel */
+  AMRX_K_EDGEUPD,    /* stages edge EMF and update fused into one LDS-tiled kernel */
   AMRX_NKCLASS
 };
 
@@ -209,9 +210,11 @@ int hier_timing_read(amrx_hier* h, int n, double* total_ms, int* launches);
  * for AMRX_K_PROLONG; coarse nodes for AMRX_K_RESTRICT; list entries for
  * the corrections and synchronisation; interior cells for AMRX_K_CFL;
  * algorithmic words for AMRX_K_PRIMHALF: 8 read and 8 written per cell of the
- * primitive region, 14 written per cell of the half-step region), and
+ * primitive region, 14 written per cell of the half-step region; algorithmic
+ * words for AMRX_K_EDGEUPD: 23 read and 8 written per entry of the update
+ * region plus 3 read per edge of the edge region), and
  * launches[k] = kernel launches of that class in the batched schedule, for
- * the current tuning (the staged or the fused first three stages).  In the
+ * the current tuning (staged or fused first three and last two stages).  In the
  * batched schedule the flux and EMF corrections run inside the restriction's
  * launch (AMRX_K_FLUXCORR / AMRX_K_EMFCORR report entries but no launches) and
  * the CFL reductions of all levels share one launch. */
@@ -235,10 +238,16 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
  *     pre-advance buffer), two batched launches per grid; 0 (default) = one
  *     after the other.  Levels running the fused first stages are not paired;
  *     launches are not paired while launch timing is on.  Level ignored.
+ *   AMRX_TUNE_FUSED_EU: 0 (default) staged edge EMF and update kernels, 1 one
+ *     kernel over tiles of the update region that computes the tile's edge
+ *     EMFs (and a one-layer halo) into LDS and updates its cells and faces
+ *     from them; bit-identical results.  Levels running it are not paired.
+ *   AMRX_TUNE_TILE_EU: index into the tile table for AMRX_TUNE_FUSED_EU
  * level = -1 sets every level.  Pure host calls (captured graph-schedule steps
  * are discarded on a change).  EINVAL for a bad parameter, level or index, or
  * a tile whose LDS footprint exceeds the limit for the hierarchy's precision. */
-enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1, AMRX_TUNE_EXTEND_ALL = 2, AMRX_TUNE_PAIR = 3 };
+enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1, AMRX_TUNE_EXTEND_ALL = 2, AMRX_TUNE_PAIR = 3,
+       AMRX_TUNE_FUSED_EU = 4, AMRX_TUNE_TILE_EU = 5 };
 int hier_tune_set(amrx_hier* h, int level, int param, int value);
 int hier_tune_get(const amrx_hier* h, int level, int param, int* value);
 
@@ -254,6 +263,15 @@ int hier_tile_table(int precision, int* n_tiles, int* shapes, int* lds_bytes, in
  * repetition.  Writes only intermediate scratch, never the state (so it may
  * run between steps).  Synchronising.  Needs hier_bind. */
 int hier_tune_time(amrx_hier* h, int level, int substep, int tile, int reps, double* ms);
+
+/* Time the edge EMF and update stages of substep 0 of `level`: the fused
+ * kernel with tile `tile` (every table entry is allowed: its LDS footprint is
+ * 3 (tx+1)(ty+1)(tz+1) reals), or the two staged kernels for tile = -1;
+ * `reps` repetitions, *ms = mean device time per repetition.  Writes the
+ * level's next-state buffer and its EMF registers, which hold nothing needed
+ * between root steps: call it only between steps (hier_step), never inside a
+ * sequence of per-level calls.  Synchronising.  Needs hier_bind. */
+int hier_tune_time_eu(amrx_hier* h, int level, int tile, int reps, double* ms);
 
 /* Debug / test exports (pure host, after hier_finalize).  For every padded
  * cell (kind 0) or face normal to axis kind-1 (kind 1..3) of a patch, in

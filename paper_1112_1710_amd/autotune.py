@@ -1,13 +1,16 @@
-"""Autotuner for the first three advance stages (primitives, half-step face
-field, Hancock predictor).
+"""Autotuner for the two fusable groups of advance stages: the first three
+(primitives, half-step face field, Hancock predictor) and the last two (edge
+EMFs, update).
 
-For every level of a bound hierarchy the candidates are the three staged
-kernels and the fused LDS-tiled kernel with each tile shape of the library's
-table that fits the LDS limit at the hierarchy's precision.  Each is timed on
-the level's own patches (``hier_tune_time``: only these kernels, writing only
-intermediate scratch, so the state is untouched), summed over the level's
-substeps; the fastest is selected with ``hier_tune_set``.  All candidates give
-bit-identical results.
+For every level of a bound hierarchy and each group the candidates are the
+staged kernels and the fused LDS-tiled kernel with each tile shape of the
+library's table that fits the LDS limit at the hierarchy's precision.  Each is
+timed on the level's own patches (``hier_tune_time``: the first group, writing
+only intermediate scratch, summed over the level's substeps;
+``hier_tune_time_eu``: the last group on substep 0, writing only the level's
+next-state buffer and EMF registers, which hold nothing between root steps);
+the fastest is selected with ``hier_tune_set``.  All candidates give
+bit-identical results.  Call it between root steps.
 
 Choices are cached in a JSON file keyed by GPU architecture, precision and a
 size class of the level (patch count and the median side of the patches'
@@ -18,7 +21,7 @@ set, else ``~/.cache/amrx/tune.json``.
 import json
 import os
 
-from .binding import TUNE_FUSED, TUNE_TILE, tile_table
+from .binding import TUNE_FUSED, TUNE_FUSED_EU, TUNE_TILE, TUNE_TILE_EU, tile_table
 
 G = 4
 
@@ -78,50 +81,61 @@ def _store(path, data):
 STAGED = -1
 
 
-def _apply(h, level, choice):
+def _apply(h, level, choice, group="a"):
+    fused, tile = (TUNE_FUSED, TUNE_TILE) if group == "a" else (TUNE_FUSED_EU, TUNE_TILE_EU)
     if choice == STAGED:
-        h.tune_set(TUNE_FUSED, 0, level)
+        h.tune_set(fused, 0, level)
     else:
-        h.tune_set(TUNE_FUSED, 1, level)
-        h.tune_set(TUNE_TILE, choice, level)
+        h.tune_set(fused, 1, level)
+        h.tune_set(tile, choice, level)
 
 
 def _shape(table, choice):
     return "staged" if choice == STAGED else "x".join(str(x) for x in table[choice][:3])
 
 
-def autotune(h, reps=5, use_cache=True, path=None):
-    """Select staged or fused (and the tile) for every level of the bound hierarchy `h`.
+def autotune(h, reps=5, use_cache=True, path=None, groups=("a", "eu")):
+    """Select staged or fused (and the tile) for every level of the bound hierarchy `h` and each group.
 
-    Returns {level: (choice, shape, ms, source)}: choice -1 = staged, else the tile index; shape "staged" or
-    "TXxTYxTZ"; ms the summed time of the level's substeps; source "search" or "cache".
+    Returns {level: (choice, shape, ms, source)} for the first three stages, and, when "eu" is in `groups`,
+    the same for the edge/update stages under the key ("eu", level): choice -1 = staged, else the tile index;
+    shape "staged" or "TXxTYxTZ"; ms the measured time; source "search" or "cache".
     """
     path = path or cache_path()
     cache = _load(path) if use_cache else {}
     table = tile_table(h.precision)
-    candidates = [STAGED] + [t for t, (_, _, _, lds) in enumerate(table) if lds > 0]
+    candidates = {"a": [STAGED] + [t for t, (_, _, _, lds) in enumerate(table) if lds > 0],
+                  "eu": [STAGED] + list(range(len(table)))}
     arch = arch_name()
     levels = 1 + max(p[0] for p in h.spec.patches)
     out = {}
     changed = False
-    for level in range(levels):
-        key = f"{arch}|p{h.precision}|l{min(level, 1)}|{size_class(h.spec, level)}"
-        hit = cache.get(key)
-        if hit is not None and hit.get("choice") in candidates and hit.get("shape") == _shape(table, hit["choice"]):
-            _apply(h, level, hit["choice"])
-            out[level] = (hit["choice"], hit["shape"], hit.get("ms"), "cache")
-            continue
-        nsub = 1 if level == 0 else 2
-        times = {}
-        for t in candidates:
-            h.tune_time(level, 0, t, 1)  # warm-up
-            times[t] = sum(h.tune_time(level, s, t, reps) for s in range(nsub))
-        best = min(times, key=times.get)
-        _apply(h, level, best)
-        out[level] = (best, _shape(table, best), times[best], "search")
-        cache[key] = {"choice": best, "shape": _shape(table, best), "ms": times[best],
-                      "candidates": {_shape(table, t): times[t] for t in times}}
-        changed = True
+    for group in groups:
+        for level in range(levels):
+            tag = "" if group == "a" else "|eu"
+            key = f"{arch}|p{h.precision}|l{min(level, 1)}|{size_class(h.spec, level)}{tag}"
+            okey = level if group == "a" else ("eu", level)
+            cands = candidates[group]
+            hit = cache.get(key)
+            if hit is not None and hit.get("choice") in cands and hit.get("shape") == _shape(table, hit["choice"]):
+                _apply(h, level, hit["choice"], group)
+                out[okey] = (hit["choice"], hit["shape"], hit.get("ms"), "cache")
+                continue
+            times = {}
+            for t in cands:
+                if group == "a":
+                    nsub = 1 if level == 0 else 2
+                    h.tune_time(level, 0, t, 1)  # warm-up
+                    times[t] = sum(h.tune_time(level, s, t, reps) for s in range(nsub))
+                else:
+                    h.tune_time_eu(level, t, 1)  # warm-up
+                    times[t] = h.tune_time_eu(level, t, reps)
+            best = min(times, key=times.get)
+            _apply(h, level, best, group)
+            out[okey] = (best, _shape(table, best), times[best], "search")
+            cache[key] = {"choice": best, "shape": _shape(table, best), "ms": times[best],
+                          "candidates": {_shape(table, t): times[t] for t in times}}
+            changed = True
     if use_cache and changed:
         _store(path, cache)
     return out

@@ -14,8 +14,8 @@ PLAIN, BATCHED, GRAPH, PERSISTENT, CONCURRENT = 0, 1, 2, 3, 4
 G = 4
 
 KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
-                  "fluxcorr", "emfcorr", "sync", "cfl", "cons", "primhalf")
-TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL, TUNE_PAIR = 0, 1, 2, 3
+                  "fluxcorr", "emfcorr", "sync", "cfl", "cons", "primhalf", "edgeupd")
+TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL, TUNE_PAIR, TUNE_FUSED_EU, TUNE_TILE_EU = 0, 1, 2, 3, 4, 5
 
 _ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
 
@@ -61,6 +61,7 @@ EXPORTS = {
     "hier_tune_get": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int)], C.c_int),
     "hier_tile_table": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int], C.c_int),
     "hier_tune_time": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "hier_tune_time_eu": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
     "hier_debug_update_box": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
 }
 
@@ -293,6 +294,12 @@ class Hierarchy:
     def tune_time(self, level, substep, tile, reps=5):
         ms = C.c_double()
         self._check(self.lib.hier_tune_time(self.h, level, substep, tile, reps, C.byref(ms)))
+        return ms.value
+
+    def tune_time_eu(self, level, tile, reps=5):
+        """Mean ms of the edge EMF and update stages of substep 0 (tile -1: staged); between steps only."""
+        ms = C.c_double()
+        self._check(self.lib.hier_tune_time_eu(self.h, level, tile, reps, C.byref(ms)))
         return ms.value
 
     # ------------------------------------------------------------------ bookkeeping exports

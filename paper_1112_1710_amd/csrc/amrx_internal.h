@@ -183,7 +183,8 @@ enum { SLOT_PHYS = 0, SLOT_SYNC_F = 1, SLOT_SYNC_B = 2, SLOT_DT = 3, SLOT_SCHED 
 // ---------------------------------------------------------------------------
 enum { OP_CFL = 0, OP_DT, OP_COPY, OP_PROLONG, OP_PRIM, OP_BHALF, OP_PRED, OP_FLUX, OP_EDGE, OP_UPDATE, OP_RESTRICT,
        OP_FCORR, OP_ECORR, OP_SYNC,
-       OP_FUSEDA  /* fused first three stages (aux: tile index); host-launched schedules only */ };
+       OP_FUSEDA, /* fused first three stages (aux: tile index); host-launched schedules only */
+       OP_FUSEDB  /* fused edge EMF and update stages (aux: tile index); host-launched schedules only */ };
 
 struct Node {
   int op, level, substep, cur, aux;        // aux: parent parity (prolong), coarse parity (restrict, corrections)
@@ -217,6 +218,9 @@ hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int blk_first, 
 // fused stages 1-3 over tiles of tx x ty x tz cells of the primitive region (one block per tile)
 #define AMRX_FUSED_LDS_MAX 65536
 size_t fused_a_lds_bytes(int precision, int tx, int ty, int tz);
+size_t fused_b_lds_bytes(int precision, int tx, int ty, int tz);
+hipError_t launch_fused_b(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, int substep, int tx,
+                          int ty, int tz);
 int fused_a_threads(int tx, int ty, int tz);
 hipError_t launch_fused_a(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, int tx, int ty,
                           int tz);

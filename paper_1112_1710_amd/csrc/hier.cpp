@@ -106,6 +106,11 @@ struct amrx_hier {
   TaskList fa_b[AMRX_MAXLEV][2][NTILE];
   std::vector<std::array<std::array<TaskList, NTILE>, 2>> fa_p;
   bool fused[AMRX_MAXLEV] = {false};  // per level: fused (true) or staged first three stages
+  // fused edge EMF and update stages: tiles of the update region, one list per tile shape
+  TaskList fb_b[AMRX_MAXLEV][2][NTILE];
+  std::vector<std::array<std::array<TaskList, NTILE>, 2>> fb_p;
+  bool fused_b[AMRX_MAXLEV] = {false};  // per level: fused (true) or staged edge EMF and update stages
+  int tile_b[AMRX_MAXLEV] = {0};
   bool extend_all = false;            // extend every side of refined patches (set before finalize)
   bool pair_levels = false;           // share launches between a level's advance and the finer level's first substep
   int tile[AMRX_MAXLEV] = {0};
@@ -691,7 +696,8 @@ void sched_level(amrx_hier* h, SchedBuild& B, int l, int* cur, bool fixed_dt, bo
       B.emit(mk_node(OP_FUSEDA, l, s, c, t, T.first, T.count, 0, T.nblk, 0), l, acc);
       stg0 = STAGE_FLUX;
     }
-    for (int stg = stg0; stg < NSTAGE; ++stg) {
+    const int stg1 = (allow_fused && h->fused_b[l]) ? STAGE_EDGE : NSTAGE;
+    for (int stg = stg0; stg < stg1; ++stg) {
       const TaskList& T = h->stage_b[l][s][stg];
       std::vector<std::array<int, 3>> acc;
       switch (ops[stg]) {
@@ -707,6 +713,15 @@ void sched_level(amrx_hier* h, SchedBuild& B, int l, int* cur, bool fixed_dt, bo
       }
       if (!fixed_dt && ops[stg] != OP_PRIM) acc.push_back({dtk, 1, 0});
       B.emit(mk_node(ops[stg], l, s, c, 0, T.first, T.count, 0, T.nblk, 0), l, acc);
+    }
+    if (stg1 == STAGE_EDGE) {
+      const int t = h->tile_b[l];
+      const TaskList& T = h->fb_b[l][s][t];
+      std::vector<std::array<int, 3>> acc = {{ik, 1, 1}, {rk, 1, 1}, {ck, 1, 1}, {bi, 1, 0}, {bg, 1, 0},
+                                             {res_key(RES_BUFI, l, 1 - c), 0, 1}};
+      if (l > 0 && s == 0) acc.push_back({res_key(RES_BUFG, l, 1 - c), 0, 1});
+      if (!fixed_dt) acc.push_back({dtk, 1, 0});
+      B.emit(mk_node(OP_FUSEDB, l, s, c, t, T.first, T.count, 0, T.nblk, 0), l, acc);
     }
     cur[l] = 1 - c;
     if (l + 1 < h->nlev) {
@@ -822,6 +837,7 @@ int finalize_impl(amrx_hier* h) {
   h->src.assign(np, {});
   h->stage_p.assign(np, {});
   h->fa_p.assign(np, {});
+  h->fb_p.assign(np, {});
   h->copy_p.assign(np, {});
   h->pro_p.assign(np, {});
   h->restr_p.assign(np, {});
@@ -999,6 +1015,30 @@ int finalize_impl(amrx_hier* h) {
           T.count = 1;
         }
       }
+    // fused edge EMF and update stages: the update region in tiles, for every tile shape
+    for (int s = 0; s < nsub; ++s)
+      for (int t = 0; t < NTILE; ++t) {
+        TaskList& B = h->fb_b[l][s][t];
+        B.first = (int)h->tasks.size();
+        int nb = 0;
+        for (int id : h->lev[l]) {
+          int lo[3], hi[3], rlo[3], rhi[3];
+          update_box(h->P[id], s, lo, hi);
+          stage_regions(STAGE_UPDATE, 0, lo, hi, rlo, rhi);
+          nb += add_task_tiles(h, id, rlo, rhi, nb, t);
+        }
+        B.count = (int)h->tasks.size() - B.first;
+        B.nblk = nb;
+        for (int id : h->lev[l]) {
+          TaskList& T = h->fb_p[id][s][t];
+          T.first = (int)h->tasks.size();
+          int lo[3], hi[3], rlo[3], rhi[3];
+          update_box(h->P[id], s, lo, hi);
+          stage_regions(STAGE_UPDATE, 0, lo, hi, rlo, rhi);
+          T.nblk = add_task_tiles(h, id, rlo, rhi, 0, t);
+          T.count = 1;
+        }
+      }
     // restriction of level l onto l-1 (tasks per child: node box of its coarse box)
     if (l > 0) {
       TaskList& B = h->restr_b[l];
@@ -1060,6 +1100,7 @@ int finalize_impl(amrx_hier* h) {
       for (int s = 0; s < 2; ++s) {
         for (int stg = 0; stg < NSTAGE; ++stg) ok = add_block_table(h, h->stage_b[l][s][stg]) && ok;
         for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fa_b[l][s][t]) && ok;
+        for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fb_b[l][s][t]) && ok;
       }
       ok = add_block_table(h, h->restr_b[l]) && ok;
       ok = add_block_table(h, h->cfl_b[l]) && ok;
@@ -1068,6 +1109,7 @@ int finalize_impl(amrx_hier* h) {
       for (int s = 0; s < 2; ++s) {
         for (int stg = 0; stg < NSTAGE; ++stg) ok = add_block_table(h, h->stage_p[id][s][stg]) && ok;
         for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fa_p[id][s][t]) && ok;
+        for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fb_p[id][s][t]) && ok;
       }
       ok = add_block_table(h, h->restr_p[id]) && ok;
     }
@@ -1203,7 +1245,8 @@ int do_advance(amrx_hier* h, int level, double dt, int substep, bool plain) {
     }
     stg0 = STAGE_FLUX;
   }
-  for (int stg = stg0; stg < NSTAGE; ++stg) {
+  const int stg1 = h->fused_b[level] ? STAGE_EDGE : NSTAGE;
+  for (int stg = stg0; stg < stg1; ++stg) {
     if (plain) {
       for (int id : h->lev[level]) {
         const TaskList& T = h->stage_p[id][substep][stg];
@@ -1212,6 +1255,22 @@ int do_advance(amrx_hier* h, int level, double dt, int substep, bool plain) {
     } else {
       const TaskList& T = h->stage_b[level][substep][stg];
       HIPCHK(TIMED(AMRX_K_PRIM + stg, launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep)), "advance stage");
+    }
+  }
+  if (h->fused_b[level]) {
+    const int t = h->tile_b[level];
+    const int* ts = kTiles[t];
+    if (plain) {
+      for (int id : h->lev[level]) {
+        const TaskList& T = h->fb_p[id][substep][t];
+        HIPCHK(TIMED(AMRX_K_EDGEUPD, launch_fused_b(c, T.first, T.count, T.nblk, cur, level, substep, ts[0], ts[1],
+                                                    ts[2])),
+               "fused edge and update stages");
+      }
+    } else {
+      const TaskList& T = h->fb_b[level][substep][t];
+      HIPCHK(TIMED(AMRX_K_EDGEUPD, launch_fused_b(c, T.first, T.count, T.nblk, cur, level, substep, ts[0], ts[1], ts[2])),
+             "fused edge and update stages");
     }
   }
   h->cur[level] = 1 - cur;
@@ -1300,7 +1359,8 @@ int paired_advance(amrx_hier* h, int level, int s) {
 }
 
 bool can_pair(const amrx_hier* h, int level, bool plain) {
-  return h->pair_levels && !plain && !h->timing && level + 1 < h->nlev && !h->fused[level] && !h->fused[level + 1];
+  return h->pair_levels && !plain && !h->timing && level + 1 < h->nlev && !h->fused[level] && !h->fused[level + 1] &&
+         !h->fused_b[level] && !h->fused_b[level + 1];
 }
 
 // AMR(l) of Sec. 2.2 for one step of level `level`; with `first_done` the ghost fill and
@@ -1465,6 +1525,10 @@ hipError_t launch_node(amrx_hier* h, const Node& nd, hipStream_t s) {
     case OP_FUSEDA: {
       const int* ts = kTiles[nd.aux];
       return launch_fused_a(c, nd.first, nd.n, nd.nblk, nd.cur, nd.level, ts[0], ts[1], ts[2]);
+    }
+    case OP_FUSEDB: {
+      const int* ts = kTiles[nd.aux];
+      return launch_fused_b(c, nd.first, nd.n, nd.nblk, nd.cur, nd.level, nd.substep, ts[0], ts[1], ts[2]);
     }
     case OP_RESTRICT: return launch_restrict(c, nd.first, nd.n, 0, nd.nblk, nd.cur, nd.aux);
     case OP_FCORR: return launch_flux_corr(c, nd.first, nd.n, nd.aux);
@@ -1881,6 +1945,18 @@ int hier_tune_set(amrx_hier* h, int level, int param, int value) {
       changed = changed || h->tile[l] != value;
       h->tile[l] = value;
     }
+  } else if (param == AMRX_TUNE_FUSED_EU) {
+    if (value != 0 && value != 1) return fail(h, AMRX_EINVAL, "AMRX_TUNE_FUSED_EU takes 0 or 1");
+    for (int l = l0; l < l1; ++l) {
+      changed = changed || h->fused_b[l] != (value == 1);
+      h->fused_b[l] = value == 1;
+    }
+  } else if (param == AMRX_TUNE_TILE_EU) {
+    if (value < 0 || value >= NTILE) return fail(h, AMRX_EINVAL, "tile index out of range");
+    for (int l = l0; l < l1; ++l) {
+      changed = changed || h->tile_b[l] != value;
+      h->tile_b[l] = value;
+    }
   } else {
     return fail(h, AMRX_EINVAL, "unknown tuning parameter");
   }
@@ -1909,6 +1985,10 @@ int hier_tune_get(const amrx_hier* h, int level, int param, int* value) {
     *value = h->fused[level] ? 1 : 0;
   } else if (param == AMRX_TUNE_TILE) {
     *value = h->tile[level];
+  } else if (param == AMRX_TUNE_FUSED_EU) {
+    *value = h->fused_b[level] ? 1 : 0;
+  } else if (param == AMRX_TUNE_TILE_EU) {
+    *value = h->tile_b[level];
   } else {
     return AMRX_EINVAL;
   }
@@ -1974,6 +2054,41 @@ int hier_tune_time(amrx_hier* h, int level, int substep, int tile, int reps, dou
   return AMRX_OK;
 }
 
+int hier_tune_time_eu(amrx_hier* h, int level, int tile, int reps, double* ms) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (!ms || reps < 1 || level < 0 || level >= h->nlev) return fail(h, AMRX_EINVAL, "bad level, repetition count or output");
+  if (tile < -1 || tile >= NTILE) return fail(h, AMRX_EINVAL, "tile index out of range");
+  const TaskList& T = h->fb_b[level][0][tile < 0 ? 0 : tile];
+  const int* ts = kTiles[tile < 0 ? 0 : tile];
+  hipStream_t s = (hipStream_t)h->d.stream;
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a), "event create");
+  if (!hip_ok(h, hipEventCreate(&b), "event create")) {
+    (void)hipEventDestroy(a);
+    return AMRX_EHIP;
+  }
+  hipError_t e = hipEventRecord(a, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) {
+    if (tile >= 0) {
+      e = launch_fused_b(h->ctx, T.first, T.count, T.nblk, h->cur[level], level, 0, ts[0], ts[1], ts[2]);
+    } else {
+      for (int stg = STAGE_EDGE; stg <= STAGE_UPDATE && e == hipSuccess; ++stg) {
+        const TaskList& L = h->stage_b[level][0][stg];
+        e = launch_stage(h->ctx, stg, L.first, L.count, 0, L.nblk, h->cur[level], level, 0);
+      }
+    }
+  }
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t_ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t_ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  HIPCHK(e, "tile timing");
+  *ms = (double)t_ms / reps;
+  return AMRX_OK;
+}
+
 int hier_timing_enable(amrx_hier* h, int on) {
   if (!h) return AMRX_EINVAL;
   if (on) {
@@ -2020,9 +2135,14 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches) {
     const int nsub = l == 0 ? 1 : R;
     const double per_sub = l == 0 ? 1.0 : (double)(1 << (l - 1));  // executions of each substep
     for (int s = 0; s < nsub; ++s) {
-      for (int stg = h->fused[l] ? STAGE_FLUX : 0; stg < NSTAGE; ++stg) {
+      for (int stg = h->fused[l] ? STAGE_FLUX : 0; stg < (h->fused_b[l] ? STAGE_EDGE : NSTAGE); ++stg) {
         u[AMRX_K_PRIM + stg] += per_sub * task_units(h->stage_b[l][s][stg]);
         nl[AMRX_K_PRIM + stg] += (int)per_sub;
+      }
+      if (h->fused_b[l]) {
+        u[AMRX_K_EDGEUPD] += per_sub * (31.0 * task_units(h->stage_b[l][s][STAGE_UPDATE]) +
+                                        3.0 * task_units(h->stage_b[l][s][STAGE_EDGE]));
+        nl[AMRX_K_EDGEUPD] += (int)per_sub;
       }
       if (h->fused[l]) {
         u[AMRX_K_PRIMHALF] += per_sub * (16.0 * task_units(h->stage_b[l][s][STAGE_PRIM]) +

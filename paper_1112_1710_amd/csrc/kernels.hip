@@ -917,13 +917,11 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n,
 // ---------------------------------------------------------------------------
 // stage 5: upwinded CT-contact edge EMFs along E, boundary registers
 // ---------------------------------------------------------------------------
-template <int E, typename R, bool MIX>
-__device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R* X, int i, int j, int k, int level,
-                         int substep, double dt) {
-  using Q = typename RegOf<R, MIX>::T;
+// EMF along E at the edge of padded index q (low corner of the cell q in the two other axes)
+template <int E, typename R>
+__device__ __forceinline__ R edge_value(const Strides& S, const R* X, long long q) {
   constexpr int A = (E + 1) % 3, C = (E + 2) % 3;
   const long long v = S.v;
-  const long long q = i + j * S.s[1] + k * S.s[2];
   const long long sa = S.s[A], sc = S.s[C];
   const R* efa = X + (SCR_FE + 2 * A) * v;      // faces normal to A: EMF along (A+2)%3 = E
   const R* efc = X + (SCR_FE + 2 * C + 1) * v;  // faces normal to C: EMF along (C+1)%3 = E
@@ -938,11 +936,19 @@ __device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R
   const R d_b_lower = upwind(ma_lo, eb_am - r_mm, eb_a0 - r_0m);
   const R d_a_upper = upwind(mc_hi, r_0m - ea_bm, r_00 - ea_b0);
   const R d_a_lower = upwind(mc_lo, ea_bm - r_mm, ea_b0 - r_m0);
-  const R emf = R(0.25) * (ea_bm + ea_b0 + eb_am + eb_a0) + R(0.25) * (d_b_lower - d_b_upper) +
-                R(0.25) * (d_a_lower - d_a_upper);
-  X[(SCR_E + E) * v + q] = emf;
+  return R(0.25) * (ea_bm + ea_b0 + eb_am + eb_a0) + R(0.25) * (d_b_lower - d_b_upper) +
+         R(0.25) * (d_a_lower - d_a_upper);
+}
 
-  // registers on the patch's box surface --------------------------------------
+// EMF x dt of the edge (i, j, k) along E into the patch's edge registers (edges on its box surface)
+// and into a child's coarse edge registers (edges on a child's coarse box surface)
+template <int E, typename R, bool MIX>
+__device__ __forceinline__ void edge_registers(const DevCtx& c, const PatchDev& p, const Strides& S, int i, int j, int k,
+                                               R emf, int level, int substep, double dt) {
+  using Q = typename RegOf<R, MIX>::T;
+  constexpr int A = (E + 1) % 3, C = (E + 2) % 3;
+  const long long q = i + j * S.s[1] + k * S.s[2];
+  const long long sa = S.s[A], sc = S.s[C];
   Q* regs = (Q*)c.reg;
   const int r[3] = {i - AMRX_G, j - AMRX_G, k - AMRX_G};
   const Q val = (Q)emf * (Q)dt;
@@ -973,6 +979,15 @@ __device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R
   }
 }
 
+template <int E, typename R, bool MIX>
+__device__ void edge_emf(const DevCtx& c, const PatchDev& p, const Strides& S, R* X, int i, int j, int k, int level,
+                         int substep, double dt) {
+  const long long q = i + j * S.s[1] + k * S.s[2];
+  const R emf = edge_value<E>(S, X, q);
+  X[(SCR_E + E) * S.v + q] = emf;
+  edge_registers<E, R, MIX>(c, p, S, i, j, k, emf, level, substep, dt);
+}
+
 template <typename R, bool MIX>
 __device__ __forceinline__ void d_edge(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level, int substep) {
   (void)nb;
@@ -997,26 +1012,17 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_edge(DevCtx c, int first, int n,
 // ---------------------------------------------------------------------------
 // stage 6: conservative cell update and Stokes face update into the next buffer
 // ---------------------------------------------------------------------------
-template <typename R, bool MIX>
-__device__ __forceinline__ void d_update(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level) {
-  (void)nb;
-  const double dt = level_dt(c, level);
-  Where w;
-  if (!locate(c, first, n, vb, w)) return;
-  const Task& T = c.tasks[w.task];
-  const PatchDev& p = c.patches[T.patch];
-  const Strides S = strides(p);
-  const R* U = (const R*)c.state + p.st[cur];
-  R* N = (R*)c.state + p.st[1 - cur];
-  const R* X = (const R*)c.rscr + p.scr;
-  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+// Cell update (conservative flux differences) and Stokes update of the low faces of padded entry q
+// (cell if ix && iy && iz; face normal to D if the two other flags hold).  Edge EMF along E at entry
+// index eq + offsets is ee[E][...] with strides es (global arrays or an LDS tile).  Every operand is
+// loaded before the first store: both state buffers share one arena, so a load after a store could
+// not be moved ahead of it.
+template <typename R, typename I>
+__device__ __forceinline__ void update_entry(const R* U, R* N, const R* X, const Strides& S, long long q, bool ix,
+                                             bool iy, bool iz, R dt_dx, const R* const ee[3], const I es[3], I eq) {
   const long long v = S.v;
-  const R dt_dx = R(dt / p.dx);
-  const bool ix = w.i < T.hi[0] - 1, iy = w.j < T.hi[1] - 1, iz = w.k < T.hi[2] - 1;
   const bool cell = ix && iy && iz;
   const bool face[3] = {iy && iz, ix && iz, ix && iy};
-  // every operand is loaded before the first store (the two buffers share one arena, so a
-  // load after a store could not be moved ahead of it)
   R u[5], f0[3][4], f1[3][4], m0[3], m1[3];
   if (cell) {
 #pragma unroll
@@ -1031,20 +1037,17 @@ __device__ __forceinline__ void d_update(const DevCtx& c, int vb, int nb, int fi
 #pragma unroll
     for (int m = 0; m < 5; ++m) u[m] = U[m * v + q];
   }
-  // faces normal to D: Stokes update from the edge EMFs along C = D+2 and A = D+1
-  const R* EE = X + SCR_E * v;
+  // faces normal to D: curl of the edge EMFs along C = D+2 and A = D+1
   R bo[3], ec_hi[3], ec_lo[3], ea_hi[3], ea_lo[3];
 #pragma unroll
   for (int D = 0; D < 3; ++D) {
     if (face[D]) {
       const int A = (D + 1) % 3, C = (D + 2) % 3;
-      const R* eC = EE + C * v;
-      const R* eA = EE + A * v;
       bo[D] = U[(5 + D) * v + q];
-      ec_hi[D] = eC[q + S.s[A]];
-      ec_lo[D] = eC[q];
-      ea_hi[D] = eA[q + S.s[C]];
-      ea_lo[D] = eA[q];
+      ec_hi[D] = ee[C][eq + es[A]];
+      ec_lo[D] = ee[C][eq];
+      ea_hi[D] = ee[A][eq + es[C]];
+      ea_lo[D] = ee[A][eq];
     }
   }
   if (cell) {
@@ -1068,8 +1071,104 @@ __device__ __forceinline__ void d_update(const DevCtx& c, int vb, int nb, int fi
 }
 
 template <typename R, bool MIX>
+__device__ __forceinline__ void d_update(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level) {
+  (void)nb;
+  const double dt = level_dt(c, level);
+  Where w;
+  if (!locate(c, first, n, vb, w)) return;
+  const Task& T = c.tasks[w.task];
+  const PatchDev& p = c.patches[T.patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  R* N = (R*)c.state + p.st[1 - cur];
+  const R* X = (const R*)c.rscr + p.scr;
+  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+  const R dt_dx = R(dt / p.dx);
+  const bool ix = w.i < T.hi[0] - 1, iy = w.j < T.hi[1] - 1, iz = w.k < T.hi[2] - 1;
+  const R* EE = X + SCR_E * S.v;
+  const R* const ee[3] = {EE, EE + S.v, EE + 2 * S.v};
+  update_entry<R, long long>(U, N, X, S, q, ix, iy, iz, dt_dx, ee, S.s, q);
+}
+
+template <typename R, bool MIX>
 __global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int n, int cur, int level) {
   d_update<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level);
+}
+
+// ---------------------------------------------------------------------------
+// stages 5-6 fused: one workgroup per tile of the update region.  The edge
+// EMFs the tile's faces need (its own edges and one more layer on the high side
+// of the two axes normal to each edge) are computed into LDS, then the cells
+// and faces of the tile are updated from them.  Edges of the halo layer are
+// computed again by the neighbouring tile with the same arithmetic, and only a
+// tile's own edges write registers, so the results are bit-identical to the
+// staged edge and update kernels; the edge EMFs never reach HBM.
+// ---------------------------------------------------------------------------
+template <int E, typename R, bool MIX>
+__device__ __forceinline__ void fused_b_edges(const DevCtx& c, const PatchDev& p, const Strides& S, const R* X,
+                                              const Task& T, const int o[3], const int e[3], R* sE, int NE,
+                                              const int ls[3], int level, int substep, double dt) {
+  // box of the tile's edges along E: the tile along E, the tile + 1 along the other axes
+  const int b0 = e[0] + (E != 0 ? 1 : 0), b1 = e[1] + (E != 1 ? 1 : 0), b2 = e[2] + (E != 2 ? 1 : 0);
+  const int nbox = b0 * b1 * b2;
+  const int nthr = blockDim.x;
+  Walk3 w(threadIdx.x, nthr, b0, b1);
+  for (int t = threadIdx.x; t < nbox; t += nthr, w.next()) {
+    const int x = w.x, y = w.y, z = w.z;
+    const int g[3] = {o[0] + x, o[1] + y, o[2] + z};
+    // the staged edge region: along E the cells of the update region, along the others its nodes
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) in = in && g[a] < T.hi[a] - (a == E ? 1 : 0);
+    if (!in) continue;
+    const long long q = g[0] + g[1] * S.s[1] + g[2] * S.s[2];
+    const R emf = edge_value<E>(S, X, q);
+    sE[E * NE + x * ls[0] + y * ls[1] + z * ls[2]] = emf;
+    if (x < e[0] && y < e[1] && z < e[2]) edge_registers<E, R, MIX>(c, p, S, g[0], g[1], g[2], emf, level, substep, dt);
+  }
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_fused_b(DevCtx c, int first, int n, int cur, int level, int substep,
+                                                         int tx, int ty, int tz) {
+  extern __shared__ double smem_d[];
+  R* sE = reinterpret_cast<R*>(smem_d);
+  const int nthr = blockDim.x;
+  const int vb = xcd_block(blockIdx.x, gridDim.x);
+  (void)n;
+  const int t = task_of_block(c, first, vb);
+  const Task& T = c.tasks[t];
+  const int tile = vb - c.blk[t];
+  const int ntx = (T.hi[0] - T.lo[0] + tx - 1) / tx, nty = (T.hi[1] - T.lo[1] + ty - 1) / ty;
+  const int tix = tile % ntx, tiy = (tile / ntx) % nty, tiz = tile / (ntx * nty);
+  const int o[3] = {T.lo[0] + tix * tx, T.lo[1] + tiy * ty, T.lo[2] + tiz * tz};
+  const int e[3] = {min(tx, T.hi[0] - o[0]), min(ty, T.hi[1] - o[1]), min(tz, T.hi[2] - o[2])};
+  const PatchDev& p = c.patches[T.patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  R* N = (R*)c.state + p.st[1 - cur];
+  const R* X = (const R*)c.rscr + p.scr;
+  const double dt = level_dt(c, level);
+  const R dt_dx = R(dt / p.dx);
+  const int ls[3] = {1, tx + 1, (tx + 1) * (ty + 1)};
+  const int NE = ls[2] * (tz + 1);
+
+  // 1. edge EMFs of the tile and its high-side layer
+  fused_b_edges<0, R, MIX>(c, p, S, X, T, o, e, sE, NE, ls, level, substep, dt);
+  fused_b_edges<1, R, MIX>(c, p, S, X, T, o, e, sE, NE, ls, level, substep, dt);
+  fused_b_edges<2, R, MIX>(c, p, S, X, T, o, e, sE, NE, ls, level, substep, dt);
+  __syncthreads();
+
+  // 2. cells and low faces of the tile's entries
+  const R* const ee[3] = {sE, sE + NE, sE + 2 * NE};
+  const int CV = e[0] * e[1] * e[2];
+  Walk3 w(threadIdx.x, nthr, e[0], e[1]);
+  for (int k = threadIdx.x; k < CV; k += nthr, w.next()) {
+    const int g[3] = {o[0] + w.x, o[1] + w.y, o[2] + w.z};
+    const long long q = g[0] + g[1] * S.s[1] + g[2] * S.s[2];
+    const bool ix = g[0] < T.hi[0] - 1, iy = g[1] < T.hi[1] - 1, iz = g[2] < T.hi[2] - 1;
+    update_entry<R, int>(U, N, X, S, q, ix, iy, iz, dt_dx, ee, ls, w.x * ls[0] + w.y * ls[1] + w.z * ls[2]);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1870,6 +1969,26 @@ hipError_t launch_fused_a(const DevCtx& c, int task_first, int ntask, int nblk, 
     k_fused_a<float, false><<<g, nthr, lds, c.stream>>>(c, task_first, ntask, cur, level, tx, ty, tz);
   else
     k_fused_a<float, true><<<g, nthr, lds, c.stream>>>(c, task_first, ntask, cur, level, tx, ty, tz);
+  return hipGetLastError();
+}
+
+size_t fused_b_lds_bytes(int precision, int tx, int ty, int tz) {
+  return (size_t)3 * (tx + 1) * (ty + 1) * (tz + 1) * (precision == 0 ? sizeof(double) : sizeof(float));
+}
+
+hipError_t launch_fused_b(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, int substep, int tx,
+                          int ty, int tz) {
+  if (ntask == 0 || nblk == 0) return hipSuccess;
+  const size_t lds = fused_b_lds_bytes(c.precision, tx, ty, tz);
+  if (lds > AMRX_FUSED_LDS_MAX) return hipErrorInvalidValue;
+  const int nthr = fused_a_threads(tx, ty, tz);
+  const dim3 g(nblk);
+  if (c.precision == 0)
+    k_fused_b<double, false><<<g, nthr, lds, c.stream>>>(c, task_first, ntask, cur, level, substep, tx, ty, tz);
+  else if (c.precision == 1)
+    k_fused_b<float, false><<<g, nthr, lds, c.stream>>>(c, task_first, ntask, cur, level, substep, tx, ty, tz);
+  else
+    k_fused_b<float, true><<<g, nthr, lds, c.stream>>>(c, task_first, ntask, cur, level, substep, tx, ty, tz);
   return hipGetLastError();
 }
 

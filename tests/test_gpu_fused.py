@@ -1,11 +1,13 @@
-"""The LDS-tiled kernel that fuses the first three advance stages, and its autotuner.
+"""The LDS-tiled kernels that fuse the first three advance stages and the
+last two (edge EMFs and update), and their autotuner.
 
-The fused kernel performs the staged kernels' operations in the same order,
+The fused kernels perform the staged kernels' operations in the same order,
 so whole root steps must agree with the staged schedule bit for bit, for
-every tile shape (ragged tiles included: the primitive regions of these
-hierarchies are not multiples of any tile) and every precision.  Parity of
-the fused path with the oracle is covered by the parity tests, which run the
-default (fused) configuration.
+every tile shape (ragged tiles included: the regions of these hierarchies are
+not multiples of any tile) and every precision; the EMF registers the fused
+edge/update kernel writes feed the restriction's corrections, so root steps
+of multi-level hierarchies check them too.  Parity with the oracle is
+checked with both fusions on.
 """
 import numpy as np
 import pytest
@@ -50,6 +52,38 @@ def _cases():
 CASES = _cases()
 
 
+def _cases_eu():
+    try:
+        n = len(binding.tile_table(FP64))
+    except ImportError:
+        return []
+    return [(prec, t) for prec in (FP64, FP32, FP32_MIXED) for t in range(n)]
+
+
+CASES_EU = _cases_eu()
+
+
+@pytest.mark.parametrize("prec,tile", CASES_EU)
+def test_fused_edge_update_matches_staged_bit_for_bit(prec, tile):
+    spec = H.small_three_level()
+    _say("fused edge/update vs staged", prec, tile, binding.tile_table(prec)[tile][:3])
+    field = SmoothField(29)
+    a = Hierarchy(spec, prec)
+    b = Hierarchy(spec, prec)
+    a.tune_set(binding.TUNE_FUSED, 0)
+    b.tune_set(binding.TUNE_FUSED, 0)
+    b.tune_set(binding.TUNE_FUSED_EU, 1)
+    b.tune_set(binding.TUNE_TILE_EU, tile)
+    a.set_field(field)
+    b.set_field(field)
+    for _ in range(2):
+        dt = a.step(BATCHED)
+        assert b.step(BATCHED) == dt
+    _same_interiors(spec, a, b)
+    d = b.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+
+
 @pytest.mark.parametrize("prec,tile", CASES)
 def test_fused_matches_staged_bit_for_bit(prec, tile):
     spec = H.small_three_level()
@@ -71,7 +105,7 @@ def test_fused_matches_staged_bit_for_bit(prec, tile):
     assert b.diag()["phys_flag"] == 0
 
 
-@pytest.mark.parametrize("name", ["root_tiled", "single32"])
+@pytest.mark.parametrize("name", ["root_tiled", "single32", "small_three_level"])
 def test_fused_plain_and_graph_schedules(name):
     spec = H.single_patch(32) if name == "single32" else getattr(H, name)()
     _say("fused plain/graph", name)
@@ -83,6 +117,8 @@ def test_fused_plain_and_graph_schedules(name):
     for h in (pl, gr):
         h.tune_set(binding.TUNE_FUSED, 1)
         h.tune_set(binding.TUNE_TILE, 7)  # 24x8x2: ragged in x on these patches
+        h.tune_set(binding.TUNE_FUSED_EU, 1)
+        h.tune_set(binding.TUNE_TILE_EU, 3)  # 32x4x2
     for h in (ref, pl, gr):
         h.set_field(field)
     for _ in range(3):
@@ -106,12 +142,20 @@ def test_autotune_selects_allowed_tiles_and_keeps_results(tmp_path):
     cache = str(tmp_path / "tune.json")
     chosen = autotune(b, reps=2, path=cache)
     allowed = _allowed(FP32)
-    assert sorted(chosen) == list(range(spec.levels()))
-    for lvl, (t, shape, ms, src) in chosen.items():
-        assert (t == -1 or t in allowed) and src == "search" and ms > 0
-        assert b.tune_get(binding.TUNE_FUSED, level=lvl) == (0 if t == -1 else 1)
-        if t >= 0:
-            assert b.tune_get(binding.TUNE_TILE, level=lvl) == t
+    levels = list(range(spec.levels()))
+    assert sorted(k for k in chosen if isinstance(k, int)) == levels
+    assert sorted(k[1] for k in chosen if not isinstance(k, int)) == levels
+    for key, (t, shape, ms, src) in chosen.items():
+        assert src == "search" and ms > 0
+        if isinstance(key, int):
+            assert t == -1 or t in allowed
+            assert b.tune_get(binding.TUNE_FUSED, level=key) == (0 if t == -1 else 1)
+            if t >= 0:
+                assert b.tune_get(binding.TUNE_TILE, level=key) == t
+        else:
+            assert b.tune_get(binding.TUNE_FUSED_EU, level=key[1]) == (0 if t == -1 else 1)
+            if t >= 0:
+                assert b.tune_get(binding.TUNE_TILE_EU, level=key[1]) == t
     again = autotune(b, reps=2, path=cache)
     assert all(v[3] == "cache" and v[0] == chosen[k][0] for k, v in again.items())
     # timing runs touch only intermediates: the state still gives the staged result
@@ -122,13 +166,15 @@ def test_autotune_selects_allowed_tiles_and_keeps_results(tmp_path):
 
 @pytest.mark.parametrize("prec", [FP64, FP32])
 def test_fused_path_matches_oracle(prec):
-    """One root step with every level fused against the oracle (per-field relative L1, as the parity tests)."""
+    """One root step with every level running both fused kernels against the oracle (per-field relative L1,
+    as the parity tests)."""
     from ._common import FIELDS, oracle_from, rel_l1, upload_oracle_state
     spec = H.small_three_level()
     _say("fused vs oracle", prec)
     o = oracle_from(spec, SmoothField(24), round32=prec != FP64)
     h = Hierarchy(spec, prec)
     h.tune_set(binding.TUNE_FUSED, 1)
+    h.tune_set(binding.TUNE_FUSED_EU, 1)
     upload_oracle_state(h, o)
     dt = o.cfl_dt()
     o.root_step(dt)

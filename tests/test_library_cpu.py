@@ -221,6 +221,24 @@ def test_tile_table_and_tuning_switches(prec):
         h.tune_set(7, 0)
     with pytest.raises(binding.AmrxError):
         h.tune_set(binding.TUNE_TILE, 0, level=16)
+    # fused edge EMF + update stages: every tile allowed (LDS 3 (tx+1)(ty+1)(tz+1) reals)
+    h.tune_set(binding.TUNE_FUSED, 0)
+    assert all(h.tune_get(binding.TUNE_FUSED_EU, level=lv) == 0 for lv in range(3))
+    assert staged["edgeupd"] == (0.0, 0)
+    h.tune_set(binding.TUNE_FUSED_EU, 1)
+    feu = h.step_work()
+    assert feu["edge"] == (0.0, 0) and feu["update"] == (0.0, 0)
+    assert feu["edgeupd"][0] == 31 * staged["update"][0] + 3 * staged["edge"][0]
+    assert feu["edgeupd"][1] == staged["update"][1]
+    for k in ("prim", "bhalf", "pred", "flux", "copy"):
+        assert feu[k] == staged[k]
+    for t in range(len(table)):
+        h.tune_set(binding.TUNE_TILE_EU, t, level=1)
+        assert h.tune_get(binding.TUNE_TILE_EU, level=1) == t
+    with pytest.raises(binding.AmrxError):
+        h.tune_set(binding.TUNE_TILE_EU, len(table))
+    with pytest.raises(binding.AmrxError):
+        h.tune_set(binding.TUNE_FUSED_EU, 2)
 
 
 def test_autotune_size_classes():
@@ -290,6 +308,9 @@ class _FakeTuned:
     def tune_time(self, level, substep, tile, reps=5):
         return self.times[(level, tile)]
 
+    def tune_time_eu(self, level, tile, reps=5):
+        return self.times[("eu", level, tile)]
+
 
 def test_autotune_search_and_cache(tmp_path, monkeypatch):
     """The autotuner keeps the fastest candidate per level (staged = -1 or a tile), caches it, and a
@@ -303,6 +324,11 @@ def test_autotune_search_and_cache(tmp_path, monkeypatch):
     times = {(lv, t): 1.0 + 0.01 * (t + 1) for lv in range(2) for t in [-1] + allowed}
     times[(0, -1)] = 0.5           # level 0: staged fastest
     times[(1, allowed[2])] = 0.1   # level 1: one tile fastest
+    for lv in range(2):
+        for t in [-1] + list(range(len(table))):
+            times[("eu", lv, t)] = 1.0 + 0.01 * (t + 1)
+    times[("eu", 0, len(table) - 1)] = 0.2  # edge/update: a tile on level 0, staged on level 1
+    times[("eu", 1, -1)] = 0.3
     fake = _FakeTuned(spec, 1, times)
     path = str(tmp_path / "tune.json")
     out = at.autotune(fake, reps=1, path=path)
@@ -310,11 +336,15 @@ def test_autotune_search_and_cache(tmp_path, monkeypatch):
     assert out[1][0] == allowed[2] and out[1][3] == "search"
     assert (binding.TUNE_FUSED, 0, 0) in fake.calls
     assert (binding.TUNE_FUSED, 1, 1) in fake.calls and (binding.TUNE_TILE, allowed[2], 1) in fake.calls
+    assert out[("eu", 0)][0] == len(table) - 1 and out[("eu", 1)][1] == "staged"
+    assert (binding.TUNE_FUSED_EU, 1, 0) in fake.calls and (binding.TUNE_TILE_EU, len(table) - 1, 0) in fake.calls
+    assert (binding.TUNE_FUSED_EU, 0, 1) in fake.calls
 
     def no_timing(*a, **k):
         raise AssertionError("timed although cached")
     fake2 = _FakeTuned(spec, 1, times)
     fake2.tune_time = no_timing
+    fake2.tune_time_eu = no_timing
     out2 = at.autotune(fake2, reps=1, path=path)
     assert all(v[3] == "cache" for v in out2.values())
     assert [v[0] for v in out2.values()] == [v[0] for v in out.values()]
