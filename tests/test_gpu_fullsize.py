@@ -27,13 +27,27 @@ def _rel_l1(a, b):
     return float(np.sum(np.abs(a - b)) / max(np.sum(np.abs(b)), 1e-300))
 
 
+def _fused_config(h):
+    """Both fused kernels on every level, with the tiles the autotuner keeps for the benchmarked
+    two-level workload's refined level (8x8x4 first stages, 32x4x4 edge/update)."""
+    from paper_1112_1710_amd import binding
+    shapes = [row[:3] for row in binding.tile_table(h.precision)]
+    h.tune_set(binding.TUNE_FUSED, 1)
+    h.tune_set(binding.TUNE_TILE, shapes.index((8, 8, 4)))
+    h.tune_set(binding.TUNE_FUSED_EU, 1)
+    h.tune_set(binding.TUNE_TILE_EU, shapes.index((32, 4, 4)))
+
+
+@pytest.mark.parametrize("config", ["staged", "fused"])
 @pytest.mark.parametrize("precision", [FP32, FP64])
-def test_two_level_sampled_patches(precision):
+def test_two_level_sampled_patches(precision, config):
     """Ghost fill + prolongation and the extended substep-0 advance of sampled level-1 patches."""
     spec = H.two_level()
-    _say("two-level full size, sampled patches", precision)
+    _say("two-level full size, sampled patches", precision, config)
     field = SmoothField(1112)
     h = Hierarchy(spec, precision)
+    if config == "fused":
+        _fused_config(h)
     h.set_field(field)
     o = amr.Hierarchy(spec.root_n)
     for lv, lo, hi in spec.patches:
@@ -102,11 +116,14 @@ def test_two_level_sampled_patches(precision):
 
 
 def test_two_level_full_root_steps_properties():
-    """Two graph-replayed FP32 root steps of the full workload: conservation, div B, bit-zero sync."""
+    """Two graph-replayed FP32 root steps of the full workload, autotuned as the benchmark runs it:
+    conservation, div B, bit-zero sync."""
+    from paper_1112_1710_amd.autotune import autotune
     spec = H.two_level()
     _say("two-level full size, properties")
     h = Hierarchy(spec, FP32)
     h.set_field(SmoothField(1112))
+    autotune(h, reps=2, use_cache=False)
     s0, c0 = h.conservation()
     for _ in range(2):
         h.step(GRAPH)
