@@ -1104,27 +1104,46 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int 
 // tile's own edges write registers, so the results are bit-identical to the
 // staged edge and update kernels; the edge EMFs never reach HBM.
 // ---------------------------------------------------------------------------
-template <int E, typename R, bool MIX>
+// The tile's edges: at each entry of the tile grown by one node on the high side of every axis,
+// the edges along x, y and z that the staged edge region holds there (along E the cells of the
+// update region, along the other axes its nodes; along E within the tile, along the others up to
+// one past it).  The three EMFs of an entry are computed together so their loads are in flight at
+// once (every such entry lies inside the padded arrays; values outside the region are discarded).
+template <typename R, bool MIX>
 __device__ __forceinline__ void fused_b_edges(const DevCtx& c, const PatchDev& p, const Strides& S, const R* X,
                                               const Task& T, const int o[3], const int e[3], R* sE, int NE,
                                               const int ls[3], int level, int substep, double dt) {
-  // box of the tile's edges along E: the tile along E, the tile + 1 along the other axes
-  const int b0 = e[0] + (E != 0 ? 1 : 0), b1 = e[1] + (E != 1 ? 1 : 0), b2 = e[2] + (E != 2 ? 1 : 0);
+  const int b0 = e[0] + 1, b1 = e[1] + 1, b2 = e[2] + 1;
   const int nbox = b0 * b1 * b2;
   const int nthr = blockDim.x;
   Walk3 w(threadIdx.x, nthr, b0, b1);
   for (int t = threadIdx.x; t < nbox; t += nthr, w.next()) {
-    const int x = w.x, y = w.y, z = w.z;
-    const int g[3] = {o[0] + x, o[1] + y, o[2] + z};
-    // the staged edge region: along E the cells of the update region, along the others its nodes
-    bool in = true;
+    const int l[3] = {w.x, w.y, w.z};
+    const int g[3] = {o[0] + w.x, o[1] + w.y, o[2] + w.z};
+    bool node[3], cell[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) in = in && g[a] < T.hi[a] - (a == E ? 1 : 0);
-    if (!in) continue;
+    for (int a = 0; a < 3; ++a) {
+      node[a] = g[a] < T.hi[a];
+      cell[a] = l[a] < e[a] && g[a] < T.hi[a] - 1;
+    }
+    const bool own = l[0] < e[0] && l[1] < e[1] && l[2] < e[2];
     const long long q = g[0] + g[1] * S.s[1] + g[2] * S.s[2];
-    const R emf = edge_value<E>(S, X, q);
-    sE[E * NE + x * ls[0] + y * ls[1] + z * ls[2]] = emf;
-    if (x < e[0] && y < e[1] && z < e[2]) edge_registers<E, R, MIX>(c, p, S, g[0], g[1], g[2], emf, level, substep, dt);
+    const int lq = l[0] * ls[0] + l[1] * ls[1] + l[2] * ls[2];
+    const R v0 = edge_value<0>(S, X, q);
+    const R v1 = edge_value<1>(S, X, q);
+    const R v2 = edge_value<2>(S, X, q);
+    if (cell[0] && node[1] && node[2]) {
+      sE[lq] = v0;
+      if (own) edge_registers<0, R, MIX>(c, p, S, g[0], g[1], g[2], v0, level, substep, dt);
+    }
+    if (node[0] && cell[1] && node[2]) {
+      sE[NE + lq] = v1;
+      if (own) edge_registers<1, R, MIX>(c, p, S, g[0], g[1], g[2], v1, level, substep, dt);
+    }
+    if (node[0] && node[1] && cell[2]) {
+      sE[2 * NE + lq] = v2;
+      if (own) edge_registers<2, R, MIX>(c, p, S, g[0], g[1], g[2], v2, level, substep, dt);
+    }
   }
 }
 
@@ -1154,9 +1173,7 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_fused_b(DevCtx c, int first, int
   const int NE = ls[2] * (tz + 1);
 
   // 1. edge EMFs of the tile and its high-side layer
-  fused_b_edges<0, R, MIX>(c, p, S, X, T, o, e, sE, NE, ls, level, substep, dt);
-  fused_b_edges<1, R, MIX>(c, p, S, X, T, o, e, sE, NE, ls, level, substep, dt);
-  fused_b_edges<2, R, MIX>(c, p, S, X, T, o, e, sE, NE, ls, level, substep, dt);
+  fused_b_edges<R, MIX>(c, p, S, X, T, o, e, sE, NE, ls, level, substep, dt);
   __syncthreads();
 
   // 2. cells and low faces of the tile's entries
