@@ -254,12 +254,14 @@ def _pressure_rel_l1(h, o, gamma=5.0 / 3.0):
         m = o._interior_mask(p)
 
         def pres(c, f):
-            bc = [0.5 * (f[d] + np.roll(f[d], -1, axis=2 - d)) for d in range(3)]
-            kin = 0.5 * (c[1] ** 2 + c[2] ** 2 + c[3] ** 2) / c[0]
-            return (gamma - 1) * (c[4] - kin - 0.5 * (bc[0] ** 2 + bc[1] ** 2 + bc[2] ** 2))
+            # cell-centred field from the two faces of each cell; evaluated on interior cells only
+            # (the padding beyond the ghost layers holds no state)
+            bc = [0.5 * (f[d] + np.roll(f[d], -1, axis=2 - d))[m] for d in range(3)]
+            kin = 0.5 * (c[1][m] ** 2 + c[2][m] ** 2 + c[3][m] ** 2) / c[0][m]
+            return (gamma - 1) * (c[4][m] - kin - 0.5 * (bc[0] ** 2 + bc[1] ** 2 + bc[2] ** 2))
 
-        pg = pres(cells, faces)[m]
-        pr = pres(p.cells, p.faces)[m]
+        pg = pres(cells, faces)
+        pr = pres(p.cells, p.faces)
         num += float(np.sum(np.abs(pg - pr)))
         den += float(np.sum(np.abs(pr)))
     return num / den
