@@ -15,7 +15,10 @@ Paper passages followed here
     used here.
   * Sec. 2.3 (isolated grids): extended ghost cells R * n_ghost wide let a
     refined grid take its R substeps without new ghost data from the parent,
-    updating a region that shrinks by n_ghost per substep.
+    updating a region that shrinks by n_ghost per substep.  The same section
+    names the other solution: advance the parent first and update the ghost
+    cells of later substeps with the coarse grid's time derivative
+    (``ghosts="time"`` here; readings below).
   * Sec. 4: the serial level visit order 0, 1, 2, 2, 1, 2, 2 for three levels.
 
 Readings where the paper is silent (the solver is not described at all):
@@ -50,6 +53,16 @@ Readings where the paper is silent (the solver is not described at all):
     (the comparison is expected to find exact equality);
   * time step: dt_l,max = C / max (sum_d (|v_d| + c_f,d) / dx_l) over the
     level's interior cells, dt_0 = min_l R^l dt_l,max, dt_l = dt_0 / R^l.
+  * coarse-time-derivative ghosts (``ghosts="time"``): refined patches update
+    only their interiors at every substep; at substep s >= 1 the ghost data
+    without a same-level source is prolongated (as above) from the parent
+    state advanced by s dt_{l+1} along the coarse time derivative,
+    U^n + (s / R) (U^{n+1} - U^n), taken from the parent's pre-advance and
+    advanced arrays before restriction; the parent level's ghost layers of
+    depth n_g are first refreshed from their same-level sources at the new
+    time.  Every parent entry this prolongation reads must then be valid:
+    interior (closure, for faces) or a ghost entry within n_g layers that has
+    a same-level source; the hierarchy is rejected otherwise.
 """
 from __future__ import annotations
 
@@ -86,14 +99,15 @@ class _LazyMaps:
         return m[0] if self.kind == 0 else m[1]
 
 
-def update_box(lo, hi, level, substep, ratio=R, n_g=mhd.N_G):
+def update_box(lo, hi, level, substep, ratio=R, n_g=mhd.N_G, ghosts="extended"):
     """Cell box a patch updates at a substep (Sec. 2.3 extended ghost cells).
 
     Level 0 updates its interior; a refined patch at substep s in 0..R-1
     updates its interior grown by (R - 1 - s) * n_g cells, so an isolated grid
-    whose ghost region is R * n_g wide can take all R substeps.
+    whose ghost region is R * n_g wide can take all R substeps.  With
+    coarse-time-derivative ghosts every patch updates its interior.
     """
-    g = 0 if level == 0 else (ratio - 1 - substep) * n_g
+    g = 0 if (level == 0 or ghosts == "time") else (ratio - 1 - substep) * n_g
     return tuple(x - g for x in lo), tuple(x + g for x in hi)
 
 
@@ -129,7 +143,10 @@ class Patch:
 
 
 class Hierarchy:
-    def __init__(self, root_n, gamma=5.0 / 3.0, cfl=0.4):
+    def __init__(self, root_n, gamma=5.0 / 3.0, cfl=0.4, ghosts="extended"):
+        if ghosts not in ("extended", "time"):
+            raise ValueError("ghosts must be 'extended' or 'time'")
+        self.ghosts = ghosts
         self.root_n = np.asarray(root_n, dtype=np.int64)
         self.gamma = gamma
         self.cfl = cfl
@@ -192,6 +209,66 @@ class Hierarchy:
             raise NestingError("level-0 patches must tile the root grid")
         self.frozen = True
         self._build_maps()
+        if self.ghosts == "time":
+            self._check_time_ghosts()
+
+    def _check_time_ghosts(self):
+        """Every parent entry a substep >= 1 prolongation reads must be valid at the parent's new time."""
+        ng = mhd.N_G
+        for m in self.patches:
+            if not m.children:
+                continue
+            nb = m.n + 2 * G
+            gidx = [np.arange(int(nb[a]) + 1) for a in range(3)]
+            # ghost depth of each padded entry along each axis (0 inside the interior / closure)
+
+            def depth(a, closure):
+                i = gidx[a]
+                hi = G + int(m.n[a]) + (1 if closure else 0)
+                return np.maximum(np.maximum(G - i, i - (hi - 1)), 0)
+            csrc = self.cell_src[m.id]
+            dz, dy, dx_ = (depth(2, False)[:, None, None], depth(1, False)[None, :, None], depth(0, False)[None, None, :])
+            cdep = np.maximum(np.maximum(dz, dy), dx_)
+            cell_ok = (cdep == 0) | ((cdep <= ng) & (csrc >= 0))
+            face_ok = []
+            for d in range(3):
+                dd = [depth(a, a == d) for a in range(3)]
+                fdep = np.maximum(np.maximum(dd[2][:, None, None], dd[1][None, :, None]), dd[0][None, None, :])
+                face_ok.append((fdep == 0) | ((fdep <= ng) & (self.face_src[m.id][d] >= 0)))
+            mo = m.origin()
+            for p in m.children:
+                csrc_p = self.cell_src[p.id]
+                clo = (p.lo - G) // R
+                ncell = (p.n + 2 * G) // R
+                for cz in range(ncell[2]):
+                    for cy in range(ncell[1]):
+                        for cx in range(ncell[0]):
+                            if csrc_p[R * cz, R * cy, R * cx] >= 0:
+                                continue
+                            ci = clo + np.array([cx, cy, cz]) - mo
+                            X, Y, Z = (int(v) for v in ci)
+                            reads = [(Z, Y, X)]
+                            for d in range(3):
+                                e = [0, 0, 0]
+                                e[d] = 1
+                                reads += [(Z + e[2], Y + e[1], X + e[0]), (Z - e[2], Y - e[1], X - e[0])]
+                            if not all(cell_ok[r] for r in reads):
+                                raise NestingError("time-derivative ghosts: patch %d reads parent cells "
+                                                   "without new-time data" % p.id)
+                            for d in range(3):
+                                a1, a2 = [a for a in range(3) if a != d]
+                                for side in (0, 1):
+                                    f = [X, Y, Z]
+                                    f[d] += side
+                                    fr = [tuple(f)]
+                                    for a in (a1, a2):
+                                        for sgn in (1, -1):
+                                            g = list(f)
+                                            g[a] += sgn
+                                            fr.append(tuple(g))
+                                    if not all(face_ok[d][z, y, x] for (x, y, z) in fr):
+                                        raise NestingError("time-derivative ghosts: patch %d reads parent faces "
+                                                           "without new-time data" % p.id)
 
     # ------------------------------------------------------------------ ghost maps (brute force)
     def _images(self, p, q):
@@ -332,6 +409,13 @@ class Hierarchy:
         if level > 0 and substep == 0:
             for p in self.level_patches(level):
                 self._prolong(p)
+        elif level > 0 and self.ghosts == "time":
+            # the parent level has advanced: refresh its ghost layers at the new time, then
+            # prolongate from the parent state moved along the coarse time derivative
+            for q in self.level_patches(level - 1):
+                self._copy_from_sources(q)
+            for p in self.level_patches(level):
+                self._prolong(p, substep / R)
 
     # ------------------------------------------------------------------ prolongation
     @staticmethod
@@ -402,11 +486,16 @@ class Hierarchy:
         cls._interior_map = (M, outer_idx, inner_idx)
         return cls._interior_map
 
-    def _prolong(self, p):
-        """Fill p's ghost cells/faces that have no same-level source from the parent's pre-advance data."""
+    def _prolong(self, p, w=0.0):
+        """Fill p's ghost cells/faces that have no same-level source from the parent's pre-advance data,
+        or (w > 0) from the parent state U^n + w (U^{n+1} - U^n)."""
         m = p.parent
-        uc = m.old_cells
-        bc = m.old_faces
+        if w == 0.0:
+            uc = m.old_cells
+            bc = m.old_faces
+        else:
+            uc = m.old_cells + w * (m.cells - m.old_cells)
+            bc = [o + w * (f - o) for o, f in zip(m.old_faces, m.faces)]
         csrc = self.cell_src[p.id]
         fsrc = self.face_src[p.id]
         M, outer_idx, inner_idx = self.interior_face_map()
@@ -484,7 +573,7 @@ class Hierarchy:
     # ------------------------------------------------------------------ advance
     def region(self, p, substep):
         lo, hi = p.interior_box()
-        return update_box(lo, hi, p.level, substep)
+        return update_box(lo, hi, p.level, substep, ghosts=self.ghosts)
 
     def advance_level(self, level, dt, substep):
         self.log.append(level)
@@ -721,9 +810,9 @@ class Hierarchy:
         return out
 
 
-def build(spec, field=None, gamma=5.0 / 3.0, cfl=0.4):
+def build(spec, field=None, gamma=5.0 / 3.0, cfl=0.4, ghosts="extended"):
     """Hierarchy from a workloads HierarchySpec (and optional initial field)."""
-    h = Hierarchy(spec.root_n, gamma=gamma, cfl=cfl)
+    h = Hierarchy(spec.root_n, gamma=gamma, cfl=cfl, ghosts=ghosts)
     for lv, lo, hi in spec.patches:
         h.add(lv, lo, hi)
     h.freeze()

@@ -288,3 +288,118 @@ def test_cfl_brute_force():
                         smax = max(smax, s)
         best = min(best, 2 ** lv * 0.4 / smax)
     assert abs(dt - best) <= 1e-13 * best
+
+
+# ---------------------------------------------------------------------------------------------
+# coarse-time-derivative ghosts (the other solution for isolated grids named in Sec. 2.3)
+# ---------------------------------------------------------------------------------------------
+def test_time_ghosts_update_only_interiors():
+    """With time-derivative ghosts no patch updates ghost cells, at any substep."""
+    for s in range(2):
+        assert amr.update_box((4, 4, 4), (12, 10, 8), 1, s, ghosts="time") == ((4, 4, 4), (12, 10, 8))
+    assert amr.update_box((4, 4, 4), (12, 10, 8), 1, 0) == ((2, 2, 2), (14, 12, 10))
+
+
+def test_time_ghosts_nesting_rule():
+    """A grandchild whose prolongation would read parent ghost cells that nothing refreshes at the
+    parent's new time is rejected; one whose reads stay inside the parent or in ghost cells a
+    sibling of the parent holds is accepted; extended ghosts accept both."""
+    with pytest.raises(amr.NestingError):
+        amr.build(H.small_three_level(), ghosts="time")
+    amr.build(H.small_three_level(), ghosts="extended")
+    amr.build(H.small_three_level_td(), ghosts="time")
+
+
+def test_time_ghosts_free_stream():
+    fld = Uniform(1.3, (0.3, -0.2, 0.1), 0.9, (0.5, 0.7, -0.4))
+    h = amr.build(H.small_three_level_td(), fld, ghosts="time")
+    ref = h.copy_state()
+    h.root_step(0.003)
+    for p, (c, f) in zip(h.patches, ref):
+        i = h._interior_mask(p)
+        assert np.max(np.abs(p.cells[:, i] - c[:, i])) < 1e-14
+        for d in range(3):
+            m = h._closure_mask(p, d)
+            assert np.max(np.abs(p.faces[d][m] - f[d][m])) < 1e-14
+
+
+def test_time_ghosts_conservation_divergence_and_sync():
+    h = amr.build(H.small_three_level_td(), SmoothField(12), ghosts="time")
+    s0 = h.conservation()
+    scale = max(abs(s0[0]), abs(s0[4]))
+    for _ in range(2):
+        h.root_step()
+    s1 = h.conservation()
+    for q in range(5):
+        assert abs(s1[q] - s0[q]) <= 1e-13 * scale, q
+    assert h.max_divergence() < 1e-11
+    assert h.diag["sync_flux_max"] == 0.0 and h.diag["sync_face_max"] == 0.0
+
+
+def test_time_ghosts_stale_data_never_reach_the_interior():
+    """Poisoning every value outside each substep's update region (the parent's advanced ghost layers
+    included) leaves time-derivative-ghost results bit-identical."""
+    spec = H.small_three_level_td()
+    a = amr.build(spec, SmoothField(13), ghosts="time")
+    b = amr.build(spec, SmoothField(13), ghosts="time")
+    b.poison = True
+    for _ in range(2):
+        dt = a.root_step()
+        b.root_step(dt)
+    for p, q in zip(a.patches, b.patches):
+        i = a._interior_mask(p)
+        assert np.array_equal(p.cells[:, i], q.cells[:, i])
+        for d in range(3):
+            m = a._closure_mask(p, d)
+            assert np.array_equal(p.faces[d][m], q.faces[d][m])
+
+
+def test_time_ghosts_differ_from_extended_ghosts_at_truncation_level():
+    """Both ghost treatments are consistent discretisations: one root step of a smooth flow differs
+    between them, by far less than the flow's own change."""
+    spec = H.small_two_level()
+    a = amr.build(spec, SmoothField(14))
+    b = amr.build(spec, SmoothField(14), ghosts="time")
+    ref = a.copy_state()
+    dt = a.root_step()
+    b.root_step(dt)
+    for c in range(5):
+        diff = change = 0.0
+        for p, q, (c0, _) in zip(a.patches, b.patches, ref):
+            i = a._interior_mask(p)
+            diff += float(np.sum(np.abs(p.cells[c][i] - q.cells[c][i])))
+            change += float(np.sum(np.abs(p.cells[c][i] - c0[c][i])))
+        assert 0.0 < diff < 0.1 * change, (c, diff, change)
+
+
+def test_time_ghost_prolongation_is_linear_in_time():
+    """For parent states linear in space at both ends of the step, the substep-1 ghosts equal the
+    linear field of the time-interpolated parent state (the prolongation is exact on linear data)."""
+    h, m, p, truth = _prolong_setup(_Linear())
+    old_c, old_f = m.cells.copy(), [f.copy() for f in m.faces]
+    # a second linear state: cells and the divergence-free field scaled, cells shifted
+    new_c = 1.5 * old_c + 0.25
+    new_f = [1.5 * f for f in old_f]
+    m.old_cells, m.old_faces = old_c, old_f
+    m.cells, m.faces = new_c, new_f
+    want_c = 0.5 * (truth[0] + (1.5 * truth[0] + 0.25))
+    want_f = [0.5 * (f + 1.5 * f) for f in truth[1]]
+    # the fine patch's own faces (read where they bound a prolongated coarse cell) at the same time
+    for d in range(3):
+        own = h._closure_mask(p, d)
+        p.faces[d][own] = want_f[d][own]
+    h._prolong(p, 0.5)
+    # compare where the prolongation writes: ghost entries without a same-level source (the
+    # padding layer beyond the last cell excluded)
+    v = (slice(0, -1),) * 3
+    cm = np.zeros(p.shape, dtype=bool)
+    cm[v] = h.cell_src[p.id][v] < 0
+    assert cm.sum() > 0
+    assert np.max(np.abs(p.cells[:, cm] - want_c[:, cm])) < 1e-12
+    fv = [(slice(0, -1), slice(0, -1), slice(None)), (slice(0, -1), slice(None), slice(0, -1)),
+          (slice(None), slice(0, -1), slice(0, -1))]
+    for d in range(3):
+        fm = np.zeros(p.shape, dtype=bool)
+        fm[fv[d]] = h.face_src[p.id][d][fv[d]] < 0
+        assert fm.sum() > 0
+        assert np.max(np.abs(p.faces[d][fm] - want_f[d][fm])) < 1e-12, d

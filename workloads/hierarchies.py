@@ -197,6 +197,20 @@ def small_three_level(root=16):
     return spec
 
 
+def small_three_level_td(root=16):
+    """Tiny three-level hierarchy whose level-2 patches keep their prolongation stencils inside
+    data that is valid at the parent's new time (the parent's interior, or parent ghost cells a
+    sibling of the parent holds): two adjacent level-1 patches, one grandchild deep inside the
+    first and one next to their shared side."""
+    spec = HierarchySpec(root_n=(root,) * 3, name=f"small three-level {root}^3 (time-derivative ghosts)")
+    spec.patches.append((0, (0, 0, 0), (root,) * 3))
+    spec.patches.append((1, (4, 4, 4), (16, 16, 16)))
+    spec.patches.append((1, (16, 4, 4), (28, 16, 16)))
+    spec.patches.append((2, (14, 14, 14), (26, 26, 26)))
+    spec.patches.append((2, (34, 14, 14), (42, 22, 22)))
+    return spec
+
+
 def root_tiled(root=16, split=2):
     """Root level made of split^3 patches (exercises same-level periodic ghost exchange)."""
     spec = HierarchySpec(root_n=(root,) * 3, name=f"root {root}^3 tiled {split}^3")
