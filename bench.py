@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--staged", action="store_true", help="run every advance stage as a separate kernel")
+    ap.add_argument("--ghosts", default="extended", choices=["extended", "time"],
+                    help="later-substep ghost data of refined patches: extended ghost regions (default) or the "
+                         "coarse time derivative")
     ap.add_argument("--no-autotune", action="store_true", help="keep the default tile of the fused kernel")
     ap.add_argument("--pair", action="store_true",
                     help="share launches between a level's advance and the finer level's first substep")
@@ -268,7 +271,7 @@ def main():
     spec, field, desc = workload(args.workload)
     zu = spec.zone_updates_per_root_step()
 
-    h = Hierarchy(spec, prec)
+    h = Hierarchy(spec, prec, ghosts=args.ghosts)
     reset = None
     steps_from_t0 = args.workload == "deep"
     if steps_from_t0:
@@ -308,7 +311,7 @@ def main():
         bytes_per_launch = units_per_step * WORDS_PER_UNIT[dom] * word / max(launches_per_step, 1)
         avg_ms = ms_total / nlaunch
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        meas = MEASURED_TRAFFIC.get((args.workload, args.precision, dom))
+        meas = MEASURED_TRAFFIC.get((args.workload, args.precision, dom)) if args.ghosts == "extended" else None
         traffic = None
         if meas is not None and meas["sources"] == sources_hash():
             traffic = round(meas["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
@@ -319,7 +322,7 @@ def main():
         if dom in ALU_BOUND:
             flops_per_launch = units_per_step * ALU_BOUND[dom] / max(launches_per_step, 1)
             tf = flops_per_launch / (avg_ms * 1e-3) / 1e12
-            issue = MEASURED_VALU_ISSUE.get((args.workload, args.precision, dom))
+            issue = MEASURED_VALU_ISSUE.get((args.workload, args.precision, dom)) if args.ghosts == "extended" else None
             issue = issue["frac"] if issue is not None and issue["sources"] == sources_hash() else None
             roof = {"bound": "alu", "achieved": round(tf, 2), "peak": VALU_PEAK_TFLOPS, "unit": "TFLOP/s",
                     "frac": round(tf / VALU_PEAK_TFLOPS, 4), "traffic": traffic, "kernel": dom,
@@ -355,7 +358,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "patches": len(spec.patches), "levels": spec.levels(),
                    "cells": spec.cells(), "zone_updates_per_step": zu, "precision": args.precision,
-                   "schedule": args.mode,
+                   "schedule": args.mode, "ghosts": args.ghosts,
                    "steps_from": "t=0 state before every step" if steps_from_t0 else "consecutive steps",
                    "first_stages": "staged" if args.staged or tiles is None else tiles,
                    "edge_update_stages": "staged" if args.staged or last is None else last,
@@ -365,7 +368,7 @@ def main():
     }
 
     if not args.skip_plain:
-        hp = Hierarchy(spec, FP64)
+        hp = Hierarchy(spec, FP64, ghosts=args.ghosts)
         preset = None
         if steps_from_t0:
             preset = state_reset(hp, spec, field, FP64)

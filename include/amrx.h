@@ -243,11 +243,24 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
  *     EMFs (and a one-layer halo) into LDS and updates its cells and faces
  *     from them; bit-identical results.  Levels running it are not paired.
  *   AMRX_TUNE_TILE_EU: index into the tile table for AMRX_TUNE_FUSED_EU
+ *   AMRX_TUNE_GHOSTS: how refined patches get ghost data for their later
+ *     substeps (Sec. 2.3 names both solutions for isolated grids).  0 (default)
+ *     extended ghost regions: substep 0 also updates up to (R-1) n_g ghost
+ *     layers (on the sides AMRX_TUNE_EXTEND_ALL selects).  1 coarse time
+ *     derivative: every substep updates the interior only; before substep s >= 1
+ *     the parent level's n_g ghost layers are refreshed from their same-level
+ *     sources at its advanced time and the ghost data without a same-level
+ *     source is prolongated from old + (s / R) (new - old) of the parent (its
+ *     pre-advance and advanced buffers).  hier_finalize then returns ENEST if
+ *     such a prolongation would read a parent entry that is neither interior
+ *     (closure, for faces) nor a same-level-sourced ghost entry within n_g
+ *     layers.  Only before hier_finalize (ESTATE after); level ignored; the
+ *     persistent and concurrent schedules refuse it (EINVAL).
  * level = -1 sets every level.  Pure host calls (captured graph-schedule steps
  * are discarded on a change).  EINVAL for a bad parameter, level or index, or
  * a tile whose LDS footprint exceeds the limit for the hierarchy's precision. */
 enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1, AMRX_TUNE_EXTEND_ALL = 2, AMRX_TUNE_PAIR = 3,
-       AMRX_TUNE_FUSED_EU = 4, AMRX_TUNE_TILE_EU = 5 };
+       AMRX_TUNE_FUSED_EU = 4, AMRX_TUNE_TILE_EU = 5, AMRX_TUNE_GHOSTS = 6 };
 int hier_tune_set(amrx_hier* h, int level, int param, int value);
 int hier_tune_get(const amrx_hier* h, int level, int param, int* value);
 

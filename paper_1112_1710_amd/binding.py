@@ -15,7 +15,7 @@ G = 4
 
 KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
                   "fluxcorr", "emfcorr", "sync", "cfl", "cons", "primhalf", "edgeupd")
-TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL, TUNE_PAIR, TUNE_FUSED_EU, TUNE_TILE_EU = 0, 1, 2, 3, 4, 5
+TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL, TUNE_PAIR, TUNE_FUSED_EU, TUNE_TILE_EU, TUNE_GHOSTS = 0, 1, 2, 3, 4, 5, 6
 
 _ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
 
@@ -105,10 +105,13 @@ class Hierarchy:
     With ``device=None`` only the host bookkeeping is built (no HIP call is made).
     ``extend_all=True`` extends the substep-0 update region of refined patches over every side
     (each grid treated as isolated) instead of only over sides lacking same-level cover.
+    ``ghosts="time"`` selects coarse-time-derivative ghosts (interior-only updates; later-substep
+    ghosts prolongated from the parent moved along its time derivative) instead of extended
+    ghost regions.
     """
 
     def __init__(self, spec, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, device="cuda:0", stream=None,
-                 extend_all=False):
+                 extend_all=False, ghosts="extended"):
         self.lib = load_library()
         self.precision = precision
         self.spec = spec
@@ -140,6 +143,11 @@ class Hierarchy:
             self.ids.append(pid.value)
         if extend_all:
             self._check(self.lib.hier_tune_set(self.h, 0, TUNE_EXTEND_ALL, 1))
+        if ghosts not in ("extended", "time"):
+            raise ValueError("ghosts must be 'extended' or 'time'")
+        self.ghosts = ghosts
+        if ghosts == "time":
+            self._check(self.lib.hier_tune_set(self.h, 0, TUNE_GHOSTS, 1))
         sb, cb = C.c_size_t(), C.c_size_t()
         self._check(self.lib.hier_finalize(self.h, C.byref(sb), C.byref(cb)))
         self.state_bytes, self.scratch_bytes = sb.value, cb.value

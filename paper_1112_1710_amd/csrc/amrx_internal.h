@@ -224,7 +224,9 @@ hipError_t launch_fused_b(const DevCtx& c, int task_first, int ntask, int nblk, 
 int fused_a_threads(int tx, int ty, int tz);
 hipError_t launch_fused_a(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, int tx, int ty,
                           int tz);
-hipError_t launch_prolong(const DevCtx& c, int first, int n, int cur_fine, int old_parent);
+// Prolongation from the parent's buffer old_parent, or for w > 0 from old + w (new - old) with the
+// advanced buffer new_parent.
+hipError_t launch_prolong(const DevCtx& c, int first, int n, int cur_fine, int old_parent, int new_parent, double w);
 hipError_t launch_restrict(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk, int cur_fine,
                            int cur_coarse);
 hipError_t launch_flux_corr(const DevCtx& c, int first, int n, int cur_coarse);

@@ -112,6 +112,7 @@ struct amrx_hier {
   bool fused_b[AMRX_MAXLEV] = {false};  // per level: fused (true) or staged edge EMF and update stages
   int tile_b[AMRX_MAXLEV] = {0};
   bool extend_all = false;            // extend every side of refined patches (set before finalize)
+  bool time_ghosts = false;           // coarse-time-derivative ghosts instead of extended ghost regions
   bool pair_levels = false;           // share launches between a level's advance and the finer level's first substep
   int tile[AMRX_MAXLEV] = {0};
   // ghost-copy lists per depth class (0: 4 ghost layers, 1: 2 ghost layers)
@@ -237,6 +238,62 @@ void update_box(const HPatch& p, int substep, int lo[3], int hi[3]) {
     lo[a] = G - (p.ext[2 * a] ? g : 0);
     hi[a] = G + p.n[a] + (p.ext[2 * a + 1] ? g : 0);
   }
+}
+
+// With coarse-time-derivative ghosts a substep >= 1 prolongation of patch pid reads its parent's
+// advanced state: every parent cell and face it reads must lie in the parent's interior (closure,
+// for faces) or in a ghost layer within n_g of it that has a same-level source (refreshed by the
+// parent level's ghost copy at the new time).
+bool time_ghost_reads_valid(const amrx_hier* h, int pid) {
+  const HPatch& p = h->P[pid];
+  const HPatch& m = h->P[p.parent];
+  const auto& S = h->src[p.parent];
+  auto depth = [&](int a, int i, bool closure) {
+    const int hi = G + m.n[a] + (closure ? 1 : 0);
+    return std::max(std::max(G - i, i - (hi - 1)), 0);
+  };
+  auto ok = [&](int kind, int x, int y, int z) {
+    const int c[3] = {x, y, z};
+    int dep = 0;
+    for (int a = 0; a < 3; ++a) {
+      if (c[a] < 0 || c[a] >= m.dim[a]) return false;
+      dep = std::max(dep, depth(a, c[a], kind >= 1 && a == kind - 1));
+    }
+    if (dep == 0) return true;
+    return dep <= NG && S[kind][lin_of(m, c[0], c[1], c[2])] >= 0;
+  };
+  const auto& P = h->src[pid];
+  const int nc[3] = {(p.n[0] + 2 * G) / 2, (p.n[1] + 2 * G) / 2, (p.n[2] + 2 * G) / 2};
+  for (int cz = 0; cz < nc[2]; ++cz)
+    for (int cy = 0; cy < nc[1]; ++cy)
+      for (int cx = 0; cx < nc[0]; ++cx) {
+        if (P[0][lin_of(p, 2 * cx, 2 * cy, 2 * cz)] >= 0) continue;  // same-level data: not prolongated
+        const int ci[3] = {(p.lo[0] - G) / 2 + cx - (m.lo[0] - G), (p.lo[1] - G) / 2 + cy - (m.lo[1] - G),
+                           (p.lo[2] - G) / 2 + cz - (m.lo[2] - G)};
+        if (!ok(0, ci[0], ci[1], ci[2])) return false;
+        for (int d = 0; d < 3; ++d)
+          for (int sgn = -1; sgn <= 1; sgn += 2) {
+            int e[3] = {ci[0], ci[1], ci[2]};
+            e[d] += sgn;
+            if (!ok(0, e[0], e[1], e[2])) return false;
+          }
+        for (int d = 0; d < 3; ++d) {
+          int a1, a2;
+          other_axes(d, a1, a2);
+          for (int side = 0; side < 2; ++side) {
+            int f[3] = {ci[0], ci[1], ci[2]};
+            f[d] += side;
+            if (!ok(1 + d, f[0], f[1], f[2])) return false;
+            for (int a : {a1, a2})
+              for (int sgn = -1; sgn <= 1; sgn += 2) {
+                int g[3] = {f[0], f[1], f[2]};
+                g[a] += sgn;
+                if (!ok(1 + d, g[0], g[1], g[2])) return false;
+              }
+          }
+        }
+      }
+  return true;
 }
 
 // Sides of a refined patch whose extended ghost layers (every entry the later substeps'
@@ -845,8 +902,18 @@ int finalize_impl(amrx_hier* h) {
   h->ecorr_p.assign(np, {});
   h->sync_p.assign(np, {});
   for (int id = 0; id < np; ++id) build_sources(h, id);
-  for (int id = 0; id < np; ++id)
-    if (h->P[id].level > 0 && !h->extend_all) mark_sides(h, id);
+  for (int id = 0; id < np; ++id) {
+    if (h->P[id].level == 0) continue;
+    if (h->time_ghosts) {
+      for (int side = 0; side < 6; ++side) h->P[id].ext[side] = false;  // interiors only
+    } else if (!h->extend_all) {
+      mark_sides(h, id);
+    }
+  }
+  if (h->time_ghosts)
+    for (int id = 0; id < np; ++id)
+      if (h->P[id].level > 0 && !time_ghost_reads_valid(h, id))
+        return fail(h, AMRX_ENEST, "time-derivative ghosts: a prolongation reads parent entries without new-time data");
 
   // state and register layout
   h->pdev.assign(np, PatchDev{});
@@ -1212,13 +1279,35 @@ int do_ghost_fill(amrx_hier* h, int level, int substep, bool plain) {
     const CopyList& L = h->copy_b[level][cls];
     HIPCHK(TIMED(AMRX_K_COPY, launch_copy(c, L.first_run, L.nrun, L.first_blk, L.nblk, L.nelem, cur)), "ghost copy");
   }
-  if (level > 0 && substep == 0) {
+  if (level > 0 && (substep == 0 || h->time_ghosts)) {
+    // substep 0: the parent's pre-advance data; later substeps (coarse-time-derivative ghosts):
+    // the parent moved along its time derivative, old + (s / R) (new - old), after its level's
+    // ghost layers are refreshed at the new time
     const int old_parent = 1 - h->cur[level - 1];
+    const int new_parent = h->cur[level - 1];
+    const double w = (double)substep / R;
+    if (substep > 0) {
+      if (plain) {
+        for (int id : h->lev[level - 1]) {
+          const CopyList& L = h->copy_p[id][1];
+          HIPCHK(TIMED(AMRX_K_COPY, launch_copy(c, L.first_run, L.nrun, L.first_blk, L.nblk, L.nelem, new_parent)),
+                 "parent ghost copy");
+        }
+      } else {
+        const CopyList& L = h->copy_b[level - 1][1];
+        HIPCHK(TIMED(AMRX_K_COPY, launch_copy(c, L.first_run, L.nrun, L.first_blk, L.nblk, L.nelem, new_parent)),
+               "parent ghost copy");
+      }
+    }
     if (plain) {
       for (int id : h->lev[level])
-        HIPCHK(TIMED(AMRX_K_PROLONG, launch_prolong(c, h->pro_p[id].first, h->pro_p[id].count, cur, old_parent)), "prolongation");
+        HIPCHK(TIMED(AMRX_K_PROLONG, launch_prolong(c, h->pro_p[id].first, h->pro_p[id].count, cur, old_parent,
+                                                    new_parent, w)),
+               "prolongation");
     } else {
-      HIPCHK(TIMED(AMRX_K_PROLONG, launch_prolong(c, h->pro_b[level].first, h->pro_b[level].count, cur, old_parent)), "prolongation");
+      HIPCHK(TIMED(AMRX_K_PROLONG, launch_prolong(c, h->pro_b[level].first, h->pro_b[level].count, cur, old_parent,
+                                                  new_parent, w)),
+             "prolongation");
     }
   }
   return AMRX_OK;
@@ -1514,7 +1603,7 @@ hipError_t launch_node(amrx_hier* h, const Node& nd, hipStream_t s) {
     case OP_CFL: return launch_cfl(c, nd.first, nd.n, 0, nd.nblk, nd.cur, nd.level);
     case OP_DT: return launch_dt_from_cfl(c, h->nlev, h->d.cfl);
     case OP_COPY: return launch_copy(c, nd.first, nd.n, nd.blk_first, nd.nblk, nd.nelem, nd.cur);
-    case OP_PROLONG: return launch_prolong(c, nd.first, nd.n, nd.cur, nd.aux);
+    case OP_PROLONG: return launch_prolong(c, nd.first, nd.n, nd.cur, nd.aux, nd.aux, 0.0);
     case OP_PRIM:
     case OP_BHALF:
     case OP_PRED:
@@ -1876,6 +1965,8 @@ int hier_step(amrx_hier* h, int mode, double* dt0) {
   if (!dt0 || mode < AMRX_PLAIN || mode > AMRX_CONCURRENT) return AMRX_EINVAL;
   if (!(*dt0 > 0.0)) *dt0 = 0.0;
   if (mode == AMRX_GRAPH) return graph_step(h, dt0);
+  if ((mode == AMRX_CONCURRENT || mode == AMRX_PERSISTENT) && h->time_ghosts)
+    return fail(h, AMRX_EINVAL, "device-scheduled steps do not support time-derivative ghosts");
   if (mode == AMRX_CONCURRENT)
     // Switched off: its first capture ended the calling process with a segmentation fault on the
     // MI355X and no cause in this library has been shown; the code stays for a later check.
@@ -1939,6 +2030,11 @@ int hier_tune_set(amrx_hier* h, int level, int param, int value) {
     if (h->frozen) return fail(h, AMRX_ESTATE, "AMRX_TUNE_EXTEND_ALL must be set before hier_finalize");
     h->extend_all = value == 1;
     return AMRX_OK;
+  } else if (param == AMRX_TUNE_GHOSTS) {
+    if (value != 0 && value != 1) return fail(h, AMRX_EINVAL, "AMRX_TUNE_GHOSTS takes 0 or 1");
+    if (h->frozen) return fail(h, AMRX_ESTATE, "AMRX_TUNE_GHOSTS must be set before hier_finalize");
+    h->time_ghosts = value == 1;
+    return AMRX_OK;
   } else if (param == AMRX_TUNE_TILE) {
     if (!tile_allowed(h->d.precision, value)) return fail(h, AMRX_EINVAL, "tile index out of range or too large");
     for (int l = l0; l < l1; ++l) {
@@ -1974,6 +2070,10 @@ int hier_tune_get(const amrx_hier* h, int level, int param, int* value) {
   if (!h || !value) return AMRX_EINVAL;
   if (param == AMRX_TUNE_EXTEND_ALL) {
     *value = h->extend_all ? 1 : 0;
+    return AMRX_OK;
+  }
+  if (param == AMRX_TUNE_GHOSTS) {
+    *value = h->time_ghosts ? 1 : 0;
     return AMRX_OK;
   }
   if (param == AMRX_TUNE_PAIR) {
@@ -2152,9 +2252,13 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches) {
       const int cls = (l > 0 && s == 0) ? 0 : 1;
       u[AMRX_K_COPY] += per_sub * h->copy_b[l][cls].comps;
       nl[AMRX_K_COPY] += (int)per_sub;
-      if (l > 0 && s == 0) {
+      if (l > 0 && (s == 0 || h->time_ghosts)) {
         u[AMRX_K_PROLONG] += per_sub * h->pro_b[l].count;
         nl[AMRX_K_PROLONG] += (int)per_sub;
+      }
+      if (l > 0 && s > 0 && h->time_ghosts) {  // the parent level's ghost refresh at its new time
+        u[AMRX_K_COPY] += per_sub * h->copy_b[l - 1][1].comps;
+        nl[AMRX_K_COPY] += (int)per_sub;
       }
       if (l + 1 < h->nlev) {
         u[AMRX_K_RESTRICT] += per_sub * task_units(h->restr_b[l + 1]);
@@ -2179,6 +2283,7 @@ int hier_debug_schedule(amrx_hier* h, int fixed_dt, int nworkgroups, int* sizes,
                         int* queues) {
   if (!h || !sizes) return AMRX_EINVAL;
   if (!h->frozen) return AMRX_ESTATE;
+  if (h->time_ghosts) return AMRX_EINVAL;  // the device schedules know extended ghosts only
   SchedImage img = build_sched(h, fixed_dt != 0, nworkgroups > 0 ? nworkgroups : 1);
   sizes[0] = (int)img.nodes.size();
   sizes[1] = (int)img.preds.size();

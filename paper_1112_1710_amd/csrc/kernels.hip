@@ -1233,7 +1233,8 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_copy(DevCtx c, int first, int n,
 // prolongation of one parent cell into a fine ghost region
 // ---------------------------------------------------------------------------
 template <typename R>
-__device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int first, int n, int cur_fine, int old_parent) {
+__device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int first, int n, int cur_fine, int old_parent,
+                                          int new_parent = 0, double w = 0.0) {
   (void)nb;
   const int id = vb * AMRX_BLOCK + threadIdx.x;
   if (id >= n) return;
@@ -1242,16 +1243,23 @@ __device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int f
   const PatchDev& mp = c.patches[fp.parent];
   const Strides FS = strides(fp), MS = strides(mp);
   const R* M = (const R*)c.state + mp.st[old_parent];
+  const R* Mn = (const R*)c.state + mp.st[new_parent];
   R* F = (R*)c.state + fp.st[cur_fine];
+  // parent value at offset o: the old buffer, or old + w (new - old) along the coarse time derivative
+  const R wr = R(w);
+  auto pv = [&](long long o) -> R {
+    const R a = M[o];
+    return w == 0.0 ? a : a + wr * (Mn[o] - a);
+  };
   const long long P0 = pr.pidx;
   const long long f0 = 2LL * pr.c[0] + 2LL * pr.c[1] * FS.s[1] + 2LL * pr.c[2] * FS.s[2];
   // cells: conservative minmod-limited linear
   for (int m = 0; m < 5; ++m) {
-    const R* u = M + m * MS.v;
-    const R u0 = u[P0];
-    const R sx = minmod2(u[P0 + MS.s[0]] - u0, u0 - u[P0 - MS.s[0]]);
-    const R sy = minmod2(u[P0 + MS.s[1]] - u0, u0 - u[P0 - MS.s[1]]);
-    const R sz = minmod2(u[P0 + MS.s[2]] - u0, u0 - u[P0 - MS.s[2]]);
+    const long long u = m * MS.v;
+    const R u0 = pv(u + P0);
+    const R sx = minmod2(pv(u + P0 + MS.s[0]) - u0, u0 - pv(u + P0 - MS.s[0]));
+    const R sy = minmod2(pv(u + P0 + MS.s[1]) - u0, u0 - pv(u + P0 - MS.s[1]));
+    const R sz = minmod2(pv(u + P0 + MS.s[2]) - u0, u0 - pv(u + P0 - MS.s[2]));
     for (int oz = 0; oz < 2; ++oz)
       for (int oy = 0; oy < 2; ++oy)
         for (int ox = 0; ox < 2; ++ox)
@@ -1263,7 +1271,7 @@ __device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int f
   for (int d = 0; d < 3; ++d) {
     int a1, a2;
     other_axes(d, a1, a2);
-    const R* b = M + (5 + d) * MS.v;
+    const long long b = (5 + d) * MS.v;
     R* fb = F + (5 + d) * FS.v;
     for (int s = 0; s < 2; ++s) {
       const long long fbase = f0 + 2LL * s * FS.s[d];
@@ -1272,9 +1280,9 @@ __device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int f
           for (int t1 = 0; t1 < 2; ++t1) outer[d][s][t2][t1] = fb[fbase + t1 * FS.s[a1] + t2 * FS.s[a2]];
       } else {
         const long long pf = P0 + s * MS.s[d];
-        const R bc = b[pf];
-        const R s1 = minmod2(b[pf + MS.s[a1]] - bc, bc - b[pf - MS.s[a1]]);
-        const R s2 = minmod2(b[pf + MS.s[a2]] - bc, bc - b[pf - MS.s[a2]]);
+        const R bc = pv(b + pf);
+        const R s1 = minmod2(pv(b + pf + MS.s[a1]) - bc, bc - pv(b + pf - MS.s[a1]));
+        const R s2 = minmod2(pv(b + pf + MS.s[a2]) - bc, bc - pv(b + pf - MS.s[a2]));
         for (int t2 = 0; t2 < 2; ++t2)
           for (int t1 = 0; t1 < 2; ++t1) {
             const R val = bc + R(0.25) * (R(2 * t1 - 1) * s1 + R(2 * t2 - 1) * s2);
@@ -1331,8 +1339,9 @@ __device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int f
 }
 
 template <typename R>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_prolong(DevCtx c, int first, int n, int cur_fine, int old_parent) {
-  d_prolong<R>(c, blockIdx.x, gridDim.x, first, n, cur_fine, old_parent);
+__global__ __launch_bounds__(AMRX_BLOCK) void k_prolong(DevCtx c, int first, int n, int cur_fine, int old_parent,
+                                                         int new_parent, double w) {
+  d_prolong<R>(c, blockIdx.x, gridDim.x, first, n, cur_fine, old_parent, new_parent, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -2015,9 +2024,9 @@ hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int blk_first, 
   return hipGetLastError();
 }
 
-hipError_t launch_prolong(const DevCtx& c, int first, int n, int cur_fine, int old_parent) {
+hipError_t launch_prolong(const DevCtx& c, int first, int n, int cur_fine, int old_parent, int new_parent, double w) {
   if (n == 0) return hipSuccess;
-  DISPATCH_R(k_prolong, dim3(grid_of(n, AMRX_BLOCK)), c, first, n, cur_fine, old_parent);
+  DISPATCH_R(k_prolong, dim3(grid_of(n, AMRX_BLOCK)), c, first, n, cur_fine, old_parent, new_parent, w);
   return hipGetLastError();
 }
 

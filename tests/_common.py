@@ -7,8 +7,8 @@ from workloads.fields import G
 FIELDS = ("rho", "mx", "my", "mz", "E", "bx", "by", "bz")
 
 
-def oracle_from(spec, field, round32=False, gamma=5.0 / 3.0):
-    o = amr.build(spec, field, gamma=gamma)
+def oracle_from(spec, field, round32=False, gamma=5.0 / 3.0, ghosts="extended"):
+    o = amr.build(spec, field, gamma=gamma, ghosts=ghosts)
     if round32:
         for p in o.patches:
             p.cells = p.cells.astype(np.float32).astype(np.float64)

@@ -348,3 +348,50 @@ def test_autotune_search_and_cache(tmp_path, monkeypatch):
     out2 = at.autotune(fake2, reps=1, path=path)
     assert all(v[3] == "cache" for v in out2.values())
     assert [v[0] for v in out2.values()] == [v[0] for v in out.values()]
+
+
+@pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "small_three_level_td", "root_tiled",
+                                  "block_two_level", "two_level"])
+def test_time_ghost_nesting_rule_matches_oracle(name):
+    """Coarse-time-derivative ghosts: the library accepts exactly the hierarchies the oracle accepts, and
+    refined patches then update their interiors only, at both substeps."""
+    _lib()
+    spec = getattr(H, name)()
+    try:
+        amr.build(spec, ghosts="time")
+        want = True
+    except amr.NestingError:
+        want = False
+    if not want:
+        with pytest.raises(binding.AmrxError) as ei:
+            binding.Hierarchy(spec, device=None, ghosts="time")
+        assert ei.value.code == -2  # ENEST
+        return
+    h = binding.Hierarchy(spec, device=None, ghosts="time")
+    assert h.tune_get(binding.TUNE_GHOSTS) == 1
+    for pid, (lv, lo, hi) in enumerate(spec.patches):
+        n = tuple(hi[a] - lo[a] for a in range(3))
+        for s in (0, 1):
+            if lv == 0 and s == 1:
+                continue
+            assert h.update_box(pid, s) == ((4, 4, 4), tuple(4 + x for x in n)), (pid, s)
+
+
+def test_time_ghost_switch_and_step_work():
+    _lib()
+    spec = H.small_three_level_td()
+    ext = binding.Hierarchy(spec, device=None)
+    td = binding.Hierarchy(spec, device=None, ghosts="time")
+    assert ext.tune_get(binding.TUNE_GHOSTS) == 0
+    with pytest.raises(binding.AmrxError) as ei:
+        td.tune_set(binding.TUNE_GHOSTS, 0)  # only before finalize
+    assert ei.value.code == -6
+    we, wt = ext.step_work(), td.step_work()
+    # interior-only updates: less work in every advance stage
+    for k in ("prim", "bhalf", "pred", "flux", "edge", "update"):
+        assert wt[k][0] < we[k][0] and wt[k][1] == we[k][1], k
+    # substep 1 of each refined level adds a prolongation and a ghost copy of its parent level
+    # (level 1: once per root step, level 2: twice)
+    assert wt["prolong"][1] == we["prolong"][1] + 3
+    assert wt["copy"][1] == we["copy"][1] + 3
+    assert wt["prolong"][0] == 2 * we["prolong"][0]
