@@ -77,7 +77,8 @@ def parse():
                     help="root steps of the low-beta precision report (workload lowbeta)")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp32_mixed", "fp64"],
                     help="default fp32 (fp32_mixed for the low-beta workload)")
-    ap.add_argument("--mode", default="graph", choices=["plain", "batched", "graph", "persistent", "concurrent"])
+    ap.add_argument("--mode", default="graph", choices=["plain", "batched", "graph", "persistent", "concurrent",
+                                                         "layered"])
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="after the timed steps, copy a 512 MiB buffer once (reference dispatch for HBM counters)")
     ap.add_argument("--plain-steps", type=int, default=4, help="steps of the FP64 per-patch-launch comparison")
@@ -255,6 +256,8 @@ def cpu_baseline():
 
 def main():
     args = parse()
+    if args.mode == "layered":
+        args.staged = True  # the layered schedule runs the staged kernels (device-side nodes)
     if args.precision is None:
         args.precision = "fp32_mixed" if args.workload == "lowbeta" else "fp32"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -263,11 +266,12 @@ def main():
         sys.exit(2)
     import torch
 
-    from paper_1112_1710_amd import BATCHED, CONCURRENT, FP32, FP32_MIXED, FP64, GRAPH, PERSISTENT, PLAIN, Hierarchy
+    from paper_1112_1710_amd import (BATCHED, CONCURRENT, FP32, FP32_MIXED, FP64, GRAPH, LAYERED, PERSISTENT, PLAIN,
+                                     Hierarchy)
     from paper_1112_1710_amd.binding import TUNE_FUSED, TUNE_FUSED_EU, TUNE_PAIR
     prec = {"fp32": FP32, "fp32_mixed": FP32_MIXED, "fp64": FP64}[args.precision]
     mode = {"plain": PLAIN, "batched": BATCHED, "graph": GRAPH, "persistent": PERSISTENT,
-            "concurrent": CONCURRENT}[args.mode]
+            "concurrent": CONCURRENT, "layered": LAYERED}[args.mode]
     spec, field, desc = workload(args.workload)
     zu = spec.zone_updates_per_root_step()
 
@@ -296,7 +300,7 @@ def main():
     sec, timing = timed_steps(h, mode, args.steps, args.warmup, torch, reset)
     value = zu / sec
     work = h.step_work()
-    if mode in (GRAPH, PERSISTENT, CONCURRENT):
+    if mode in (GRAPH, PERSISTENT, CONCURRENT, LAYERED):
         # kernels inside a replayed graph or the persistent kernel are not bracketed by events: take the per-kernel
         # launch times from an instrumented batched pass of the same steps
         _, timing = timed_steps(h, BATCHED, args.steps, 1, torch, reset)

@@ -77,12 +77,19 @@ enum {
   AMRX_PERSISTENT = 3,/* one launch of a persistent work-queue kernel per root step: every
                          batched launch becomes a node of a dependency graph, levels run
                          concurrently and ready work of finer levels is taken first (Sec. 4) */
-  AMRX_CONCURRENT = 4 /* the same dependency graph of batched launches captured into a HIP graph
+  AMRX_CONCURRENT = 4,/* the same dependency graph of batched launches captured into a HIP graph
                          with one branch per level: launches of different levels that touch
                          disjoint data run concurrently (Sec. 4: coarser levels fill the gaps
                          left by finer ones); replayed like AMRX_GRAPH.
                          AMRX_PERSISTENT and AMRX_CONCURRENT are disabled in this build
                          (hier_step returns EINVAL for them). */
+  AMRX_LAYERED = 5    /* the AMRX_PERSISTENT dependency graph cut into layers of mutually
+                         independent batched launches (a node's layer is one past its latest
+                         predecessor's); one launch per layer of a persistent grid whose
+                         workgroups claim the layer's block ranges, finer levels' first, from
+                         an atomic counter and never wait for each other.  Staged stages only
+                         (the fused-kernel tunings do not apply); synchronising like
+                         AMRX_BATCHED's dt readback; bit-identical results. */
 };
 
 typedef struct amrx_hier amrx_hier;
@@ -292,6 +299,12 @@ int hier_tune_time_eu(amrx_hier* h, int level, int tile, int reps, double* ms);
  * src_patch * 2^32 + linear padded index, the patch's own interior (closure)
  * entries included, or -1 where none exists.  `out` holds V entries. */
 int hier_debug_sources(const amrx_hier* h, int patch_id, int kind, long long* out);
+
+/* The layered schedule (AMRX_LAYERED) of one root step for the current buffer
+ * parities: sizes = (layers, items); first (layers + 1 ints) the first item of
+ * each layer; items (4 ints each: node, first block, end block, 0) in launch
+ * order, nodes numbered as hier_debug_schedule reports them.  Pure host call. */
+int hier_debug_layers(amrx_hier* h, int fixed_dt, int* sizes, int* first, int* items);
 
 /* The persistent schedule of one root step as built for the current buffer
  * parities (fixed_dt: dt0 preset instead of computed), for `nworkgroups`

@@ -10,7 +10,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libamrx.so")
 
 FP64, FP32, FP32_MIXED = 0, 1, 2
-PLAIN, BATCHED, GRAPH, PERSISTENT, CONCURRENT = 0, 1, 2, 3, 4
+PLAIN, BATCHED, GRAPH, PERSISTENT, CONCURRENT, LAYERED = 0, 1, 2, 3, 4, 5
 G = 4
 
 KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
@@ -53,6 +53,7 @@ EXPORTS = {
     "hier_timing_enable": ([C.c_void_p, C.c_int], C.c_int),
     "hier_timing_read": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
     "hier_step_work": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
+    "hier_debug_layers": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hier_debug_schedule": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hier_debug_sources": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_longlong)], C.c_int),
@@ -337,6 +338,17 @@ class Hierarchy:
         a = np.ctypeslib.as_array
         return (a(nodes)[:12 * nn].reshape(nn, 12).copy(), a(preds)[:npr].copy(),
                 a(items)[:4 * ni].reshape(ni, 4).copy(), a(queues)[:2 * nq].reshape(nq, 2).copy())
+
+    def debug_layers(self, fixed_dt=False):
+        """Layered schedule: the first item of each layer (layers + 1) and the items (M, 4) in launch order."""
+        sizes = (C.c_int * 2)()
+        self._check(self.lib.hier_debug_layers(self.h, int(fixed_dt), sizes, None, None))
+        nl, ni = sizes[0], sizes[1]
+        first = (C.c_int * (nl + 1))()
+        items = (C.c_int * max(1, 4 * ni))()
+        self._check(self.lib.hier_debug_layers(self.h, int(fixed_dt), sizes, first, items))
+        a = np.ctypeslib.as_array
+        return a(first)[:nl + 1].copy(), a(items)[:4 * ni].reshape(ni, 4).copy()
 
     def debug_prolong_cells(self, pid):
         cnt = C.c_int()

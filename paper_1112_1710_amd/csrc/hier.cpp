@@ -53,6 +53,9 @@ struct SchedVariant {
   unsigned long long used = 0;
   int nnodes = 0, nq = 0;
   size_t off_nodes = 0, off_preds = 0, off_items = 0, off_queues = 0, off_heads = 0, off_done = 0;
+  // layered schedule: items of layer L are [layer_first[L], layer_first[L + 1]), spanning layer_blocks[L] blocks
+  std::vector<int> layer_first, layer_blocks, layer_op;
+  size_t off_counters = 0;
   int cur_after[AMRX_MAXLEV] = {0};
 };
 
@@ -151,6 +154,8 @@ struct amrx_hier {
   size_t off_sched = 0, sched_slot_bytes = 0;
   unsigned long long sched_clock = 0;
   int nworkgroups = 0;
+  int layer_wg = 0;     // persistent grid of a mixed layer launch (the generic kernel's residency)
+  int layer_op_wg = 0;  // persistent grid of a one-operation layer launch
   bool persistent_enabled = false;
 
   // concurrent schedule: branch streams and the events of one capture
@@ -1698,6 +1703,112 @@ int concurrent_step(amrx_hier* h, double* dt0) {
   return finish_step(h, dt0);
 }
 
+// Layered schedule: the root step's dependency graph (the persistent schedule's nodes and
+// reduced predecessor lists) cut into layers by longest path from the sources, so that no two
+// nodes of a layer depend on each other; inside a layer the items of finer levels come first.
+struct LayerPlan {
+  std::vector<Node> nodes;
+  std::vector<Item> items;
+  std::vector<int> first, blocks, op;  // per layer; op: the one operation of all its nodes, else -1
+  int cur_after[AMRX_MAXLEV];
+};
+
+LayerPlan build_layers(amrx_hier* h, bool fixed_dt) {
+  const SchedImage img = build_sched(h, fixed_dt, h->layer_wg > 0 ? h->layer_wg : 1);
+  const int nn = (int)img.nodes.size();
+  std::vector<int> layer(nn, 0);
+  int nl = 0;
+  for (int v = 0; v < nn; ++v) {
+    const Node& nd = img.nodes[v];
+    for (int k = nd.pred_first; k < nd.pred_first + nd.npred; ++k) layer[v] = std::max(layer[v], layer[img.preds[k]] + 1);
+    nl = std::max(nl, layer[v] + 1);
+  }
+  LayerPlan P;
+  P.nodes = img.nodes;
+  for (int L = 0; L < nl; ++L) {
+    P.first.push_back((int)P.items.size());
+    int nb = 0;
+    for (int q = (int)img.queues.size() - 1; q >= 0; --q) {  // finest level's queue first
+      const Queue& Q = img.queues[q];
+      for (int i = Q.first; i < Q.first + Q.len; ++i) {
+        const Item& it = img.items[i];
+        if (layer[it.node] != L) continue;
+        P.items.push_back(it);
+        nb += it.b1 - it.b0;
+      }
+    }
+    P.blocks.push_back(nb);
+    int op = -2;
+    for (int i = P.first.back(); i < (int)P.items.size(); ++i) {
+      const int o = P.nodes[P.items[i].node].op;
+      op = (op == -2 || op == o) ? o : -1;
+    }
+    P.op.push_back(op < 0 ? -1 : op);
+  }
+  P.first.push_back((int)P.items.size());
+  std::memcpy(P.cur_after, img.cur_after, sizeof P.cur_after);
+  return P;
+}
+
+int layered_step(amrx_hier* h, double* dt0) {
+  const bool fixed = *dt0 > 0.0;
+  const unsigned key = (1u << 21) | (parity_key(h) * 2u + (fixed ? 1u : 0u));
+  int slot = -1;
+  for (int i = 0; i < 4; ++i)
+    if (h->sv[i].valid && h->sv[i].key == key) slot = i;
+  if (slot < 0) {
+    slot = 0;
+    for (int i = 1; i < 4; ++i)
+      if (!h->sv[i].valid || (h->sv[slot].valid && h->sv[i].used < h->sv[slot].used)) slot = i;
+    const LayerPlan P = build_layers(h, fixed);
+    const int nl = (int)P.blocks.size();
+    const size_t bytes = align256(sizeof(Node) * P.nodes.size()) + align256(sizeof(Item) * P.items.size()) +
+                         align256(sizeof(int) * nl);
+    if (bytes > h->sched_slot_bytes) return fail(h, AMRX_ENOMEM, "layered schedule larger than its reserved slot");
+    std::vector<char> buf(bytes, 0);
+    SchedVariant& v = h->sv[slot];
+    v.off_nodes = 0;
+    if (!P.nodes.empty()) std::memcpy(buf.data(), P.nodes.data(), sizeof(Node) * P.nodes.size());
+    v.off_items = align256(sizeof(Node) * P.nodes.size());
+    if (!P.items.empty()) std::memcpy(buf.data() + v.off_items, P.items.data(), sizeof(Item) * P.items.size());
+    v.off_counters = v.off_items + align256(sizeof(Item) * P.items.size());
+    char* base = h->scratch + h->off_sched + (size_t)slot * h->sched_slot_bytes;
+    HIPCHK(hipMemcpyAsync(base, buf.data(), buf.size(), hipMemcpyHostToDevice, (hipStream_t)h->d.stream),
+           "upload layered schedule");
+    HIPCHK(hipStreamSynchronize((hipStream_t)h->d.stream), "stream synchronize");
+    v.key = key;
+    v.valid = true;
+    v.nnodes = (int)P.nodes.size();
+    v.layer_first = P.first;
+    v.layer_blocks = P.blocks;
+    v.layer_op = P.op;
+    std::memcpy(v.cur_after, P.cur_after, sizeof v.cur_after);
+  }
+  SchedVariant& v = h->sv[slot];
+  v.used = ++h->sched_clock;
+  char* base = h->scratch + h->off_sched + (size_t)slot * h->sched_slot_bytes;
+  const Node* nodes = (const Node*)(base + v.off_nodes);
+  const Item* items = (const Item*)(base + v.off_items);
+  int* counters = (int*)(base + v.off_counters);
+  const int nl = (int)v.layer_blocks.size();
+  HIPCHK(launch_clear_slots(h->ctx), "clear slots");
+  if (fixed) HIPCHK(launch_set_dt(h->ctx, *dt0), "set dt");
+  HIPCHK(launch_clear_ints(h->ctx, counters, nl), "clear layer counters");
+  for (int L = 0; L < nl; ++L) {
+    const int n = v.layer_first[L + 1] - v.layer_first[L];
+    const int g = std::max(1, std::min(v.layer_op[L] >= 0 ? h->layer_op_wg : h->layer_wg, v.layer_blocks[L]));
+    HIPCHK(launch_layer(h->ctx, nodes, items, v.layer_first[L], n, counters + L, g, h->nlev, h->d.cfl, v.layer_op[L]),
+           "layer launch");
+  }
+  std::memcpy(h->cur, v.cur_after, sizeof h->cur);
+  unsigned long long sl[NSLOT];
+  const int rc = read_slots(h, sl);
+  if (rc) return rc;
+  *dt0 = bits_to_double(sl[SLOT_DT]);
+  if (sl[SLOT_PHYS]) return fail(h, AMRX_EPHYS, "unphysical state (rho<=0, p<=0 or non-finite)");
+  return AMRX_OK;
+}
+
 // Persistent schedule: one launch of the fine-first work-queue kernel per root step.
 int persistent_step(amrx_hier* h, double* dt0) {
   const bool fixed = *dt0 > 0.0;
@@ -1922,6 +2033,8 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
     // at most 4 workgroups (16 waves) per CU: enough to hide latency, few enough idle pollers
     h->nworkgroups = std::max(1, ncu) * std::min(4, persistent_blocks_per_cu(h->d.precision));
+    h->layer_wg = std::max(1, ncu) * layer_blocks_per_cu(h->d.precision);
+    h->layer_op_wg = std::max(1, ncu) * 8;  // one-operation layers: up to 8 workgroups (32 waves) per CU
   }
   for (int l = 0; l < AMRX_MAXLEV; ++l) h->cur[l] = 0;
   h->bound = true;
@@ -1962,11 +2075,12 @@ int cfl_dt(amrx_hier* h, double* dt0) {
 
 int hier_step(amrx_hier* h, int mode, double* dt0) {
   if (!ready(h)) return AMRX_ESTATE;
-  if (!dt0 || mode < AMRX_PLAIN || mode > AMRX_CONCURRENT) return AMRX_EINVAL;
+  if (!dt0 || mode < AMRX_PLAIN || mode > AMRX_LAYERED) return AMRX_EINVAL;
   if (!(*dt0 > 0.0)) *dt0 = 0.0;
   if (mode == AMRX_GRAPH) return graph_step(h, dt0);
-  if ((mode == AMRX_CONCURRENT || mode == AMRX_PERSISTENT) && h->time_ghosts)
+  if ((mode == AMRX_CONCURRENT || mode == AMRX_PERSISTENT || mode == AMRX_LAYERED) && h->time_ghosts)
     return fail(h, AMRX_EINVAL, "device-scheduled steps do not support time-derivative ghosts");
+  if (mode == AMRX_LAYERED) return layered_step(h, dt0);
   if (mode == AMRX_CONCURRENT)
     // Switched off: its first capture ended the calling process with a segmentation fault on the
     // MI355X and no cause in this library has been shown; the code stays for a later check.
@@ -2276,6 +2390,18 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches) {
     units[i] = u[i];
     launches[i] = nl[i];
   }
+  return AMRX_OK;
+}
+
+int hier_debug_layers(amrx_hier* h, int fixed_dt, int* sizes, int* first, int* items) {
+  if (!h || !sizes) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  if (h->time_ghosts) return AMRX_EINVAL;
+  const LayerPlan P = build_layers(h, fixed_dt != 0);
+  sizes[0] = (int)P.blocks.size();
+  sizes[1] = (int)P.items.size();
+  if (first) std::memcpy(first, P.first.data(), sizeof(int) * P.first.size());
+  if (items) std::memcpy(items, P.items.data(), sizeof(Item) * P.items.size());
   return AMRX_OK;
 }
 

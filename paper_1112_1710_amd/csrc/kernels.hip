@@ -1892,6 +1892,37 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_persistent(DevCtx c, Sched sc, i
 }
 
 // ---------------------------------------------------------------------------
+// layered fine-first schedule: the dependency graph of one root step cut into
+// layers of mutually independent batched launches (a node's layer is one more
+// than its latest predecessor's).  One launch per layer with a persistent grid;
+// workgroups claim the layer's items (block ranges of its nodes, finer levels'
+// items first) from an atomic counter and leave once it passes the end: no
+// workgroup ever waits for another, so every launch drains.
+// ---------------------------------------------------------------------------
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_layer(DevCtx c, const Node* nodes, const Item* items, int first, int n,
+                                                       int* counter, int nlev, double cfl) {
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n) return;
+    const Item I = items[first + it];
+    const Node nd = nodes[I.node];
+    for (int b = I.b0; b < I.b1; ++b) {
+      run_node<R, MIX>(c, nd, b, nlev, cfl);
+      __syncthreads();
+    }
+  }
+}
+
+__global__ void k_clear_ints(int* p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
+// ---------------------------------------------------------------------------
 // paired launches: two independent batched launches (one level's advance stage
 // and the next finer level's ghost fill or advance stage of its first substep,
 // which reads only the coarse level's pre-advance buffer) in one grid, so that
@@ -1931,6 +1962,37 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_pair(DevCtx c, Node a, Node b, i
     const int vb = pair_block<OB>((int)((g - ka) * 8 + lane), pb);
     if (vb < b.nblk) run_op<OB, R, MIX>(c, b, vb);
   }
+}
+
+// A layer whose launches all run one stage or ghost-fill operation: the same claim loop with only
+// that operation's code (the register footprint of the generic kernel covers every operation).
+template <int OP, typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_layer_op(DevCtx c, const Node* nodes, const Item* items, int first,
+                                                          int n, int* counter) {
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = s_item;
+    __syncthreads();
+    if (it >= n) return;
+    const Item I = items[first + it];
+    const Node nd = nodes[I.node];
+    for (int b = I.b0; b < I.b1; ++b) {
+      run_op<OP, R, MIX>(c, nd, b);
+      // only the ghost copy shares LDS between the threads of a block
+      if (OP == OP_COPY) __syncthreads();
+    }
+  }
+}
+
+template <int OP>
+hipError_t launch_layer_op_t(const DevCtx& c, const Node* nodes, const Item* items, int first, int n, int* counter,
+                             int g) {
+  if (c.precision == 0) k_layer_op<OP, double, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter);
+  else if (c.precision == 1) k_layer_op<OP, float, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter);
+  else k_layer_op<OP, float, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter);
+  return hipGetLastError();
 }
 
 __global__ void k_clear_sched(Sched sc, int nnodes) {
@@ -2139,6 +2201,43 @@ hipError_t launch_persistent(const DevCtx& c, const Sched& sc, int nnodes, int n
   else if (c.precision == 1) k_persistent<float, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, sc, nlev, cfl);
   else k_persistent<float, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, sc, nlev, cfl);
   return hipGetLastError();
+}
+
+hipError_t launch_layer(const DevCtx& c, const Node* nodes, const Item* items, int first, int n, int* counter,
+                        int nworkgroups, int nlev, double cfl, int op) {
+  if (n <= 0) return hipSuccess;
+  const int gi = nworkgroups;
+  switch (op) {
+    case OP_COPY: return launch_layer_op_t<OP_COPY>(c, nodes, items, first, n, counter, gi);
+    case OP_PROLONG: return launch_layer_op_t<OP_PROLONG>(c, nodes, items, first, n, counter, gi);
+    case OP_PRIM: return launch_layer_op_t<OP_PRIM>(c, nodes, items, first, n, counter, gi);
+    case OP_BHALF: return launch_layer_op_t<OP_BHALF>(c, nodes, items, first, n, counter, gi);
+    case OP_PRED: return launch_layer_op_t<OP_PRED>(c, nodes, items, first, n, counter, gi);
+    case OP_FLUX: return launch_layer_op_t<OP_FLUX>(c, nodes, items, first, n, counter, gi);
+    case OP_EDGE: return launch_layer_op_t<OP_EDGE>(c, nodes, items, first, n, counter, gi);
+    case OP_UPDATE: return launch_layer_op_t<OP_UPDATE>(c, nodes, items, first, n, counter, gi);
+    default: break;
+  }
+  const dim3 g(nworkgroups);
+  if (c.precision == 0) k_layer<double, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter, nlev, cfl);
+  else if (c.precision == 1) k_layer<float, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter, nlev, cfl);
+  else k_layer<float, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter, nlev, cfl);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_ints(const DevCtx& c, int* p, int n) {
+  if (n <= 0) return hipSuccess;
+  k_clear_ints<<<grid_of(n, AMRX_BLOCK) < 64 ? grid_of(n, AMRX_BLOCK) : 64, AMRX_BLOCK, 0, c.stream>>>(p, n);
+  return hipGetLastError();
+}
+
+int layer_blocks_per_cu(int precision) {
+  int nb = 0;
+  hipError_t e;
+  if (precision == 0) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_layer<double, false>, AMRX_BLOCK, 0);
+  else if (precision == 1) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_layer<float, false>, AMRX_BLOCK, 0);
+  else e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_layer<float, true>, AMRX_BLOCK, 0);
+  return e == hipSuccess && nb > 0 ? nb : 1;
 }
 
 int persistent_blocks_per_cu(int precision) {

@@ -332,6 +332,38 @@ def test_persistent_schedule_is_bit_identical_to_batched(name):
     assert b.diag()["phys_flag"] == 0.0
 
 
+@pytest.mark.parametrize("name,prec", [("small_three_level", FP64), ("root_tiled", FP64), ("two_level", FP32),
+                                       ("block_two_level", FP32_MIXED)])
+def test_layered_schedule_is_bit_identical_to_batched(name, prec):
+    """The layered fine-first schedule (one persistent-grid launch per layer of independent launches,
+    no waiting between workgroups) gives the batched schedule's results bit for bit, with the CFL
+    time step computed on the device and with a preset one."""
+    from paper_1112_1710_amd import LAYERED
+    spec = getattr(H, name)()
+    field = SmoothField(15)
+    a = Hierarchy(spec, prec)
+    b = Hierarchy(spec, prec)
+    a.set_field(field)
+    b.set_field(field)
+    for k in range(3):
+        fixed = 1e-3 if k == 1 else 0.0
+        _say("layered schedule", name, prec, "step", k)
+        dt = a.step(BATCHED, fixed)
+        assert b.step(LAYERED, fixed) == dt
+    _assert_same_interiors(spec, a, b)
+    d = b.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+
+
+def test_layered_schedule_refuses_time_ghosts():
+    from paper_1112_1710_amd import LAYERED
+    h = Hierarchy(H.small_two_level(), FP64, ghosts="time")
+    h.set_field(SmoothField(16))
+    with pytest.raises(AmrxError) as ei:
+        h.step(LAYERED)
+    assert ei.value.code == -1
+
+
 def _grouped_rel_l1(h, o):
     """Relative L1 per field, with a component whose exact value is zero (here b_z and m_z, which
     round-off alone makes nonzero) measured against its vector's total magnitude instead."""

@@ -162,6 +162,45 @@ def test_persistent_schedule_claims_complete(name, fixed_dt):
     assert np.array_equal(done, nblk)
 
 
+@pytest.mark.parametrize("name", ["small_three_level", "root_tiled", "two_level"])
+@pytest.mark.parametrize("fixed_dt", [False, True])
+def test_layered_schedule_plan(name, fixed_dt):
+    """The layered schedule covers every block of every node of the dependency graph exactly once,
+    puts every node after all its predecessors' layers (so a layer's launches are independent),
+    and orders a layer's items finest level first, program order within a level."""
+    _lib()
+    spec = getattr(H, name)()
+    h = binding.Hierarchy(spec, device=None)
+    nodes, preds, _, _ = h.debug_schedule(fixed_dt, 1)
+    first, items = h.debug_layers(fixed_dt)
+    nn = len(nodes)
+    layer_of_item = np.repeat(np.arange(len(first) - 1), np.diff(first))
+    node_layer = np.full(nn, -1)
+    covered = [[] for _ in range(nn)]
+    for it, L in zip(items, layer_of_item):
+        v = it[0]
+        assert node_layer[v] in (-1, L)
+        node_layer[v] = L
+        covered[v].append((it[1], it[2]))
+    for v in range(nn):
+        spans = sorted(covered[v])
+        want = nodes[v, 8]
+        if want == 0:
+            continue
+        assert spans[0][0] == 0 and spans[-1][1] == want, v
+        assert all(a[1] == b[0] for a, b in zip(spans, spans[1:])), v
+        pf, npr = nodes[v, 10], nodes[v, 11]
+        for p in preds[pf:pf + npr]:
+            if nodes[p, 8] > 0:
+                assert node_layer[p] < node_layer[v], (p, v)
+    for L in range(len(first) - 1):
+        lv = [nodes[items[i, 0], 1] for i in range(first[L], first[L + 1])]
+        assert lv == sorted(lv, reverse=True), L
+    assert len(first) - 1 <= nn
+    if spec.levels() > 1:
+        assert len(first) - 1 < nn  # launches of different levels share layers
+
+
 def test_padded_volume_limit():
     """Patches whose ghost-padded volume reaches 2^31 entries are rejected (kernels index them with 32 bits)."""
     lib = _lib()
