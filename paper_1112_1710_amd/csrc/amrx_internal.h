@@ -253,7 +253,9 @@ hipError_t launch_persistent(const DevCtx& c, const Sched& sc, int nnodes, int n
 // two independent batched launches in one grid (supported combinations only)
 bool pair_supported(int op_a, int op_b);
 hipError_t launch_pair(const DevCtx& c, const Node& a, const Node& b);
-// op: the single operation of every node of the layer (a specialised kernel), or -1 for mixed layers
+// op: the single operation of every node of the layer, 64 * (a + 1) + b for a layer of the two
+// operations a < b with a specialised kernel (layer2_supported), or -1 for other layers
+bool layer2_supported(int oa, int ob);
 hipError_t launch_layer(const DevCtx& c, const Node* nodes, const Item* items, int first, int n, int* counter,
                         int nworkgroups, int nlev, double cfl, int op);
 hipError_t launch_clear_ints(const DevCtx& c, int* p, int n);

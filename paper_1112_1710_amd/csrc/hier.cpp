@@ -1738,12 +1738,21 @@ LayerPlan build_layers(amrx_hier* h, bool fixed_dt) {
       }
     }
     P.blocks.push_back(nb);
-    int op = -2;
+    int oa = -1, ob = -1;
+    bool more = false;
     for (int i = P.first.back(); i < (int)P.items.size(); ++i) {
       const int o = P.nodes[P.items[i].node].op;
-      op = (op == -2 || op == o) ? o : -1;
+      if (oa < 0 || oa == o) oa = o;
+      else if (ob < 0 || ob == o) ob = o;
+      else more = true;
     }
-    P.op.push_back(op < 0 ? -1 : op);
+    int op = -1;
+    if (!more && oa >= 0 && ob < 0 && oa >= OP_COPY && oa <= OP_UPDATE) op = oa;
+    if (!more && oa >= 0 && ob >= 0) {
+      const int lo = std::min(oa, ob), hi = std::max(oa, ob);
+      if (layer2_supported(lo, hi)) op = 64 * (lo + 1) + hi;
+    }
+    P.op.push_back(op);
   }
   P.first.push_back((int)P.items.size());
   std::memcpy(P.cur_after, img.cur_after, sizeof P.cur_after);

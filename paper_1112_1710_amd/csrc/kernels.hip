@@ -1906,7 +1906,9 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_layer(DevCtx c, const Node* node
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = s_item;
+    // the claimed index is the same in every lane: keep it (and all node parameters derived from it)
+    // in scalar registers
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= n) return;
     const Item I = items[first + it];
@@ -1973,7 +1975,7 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_layer_op(DevCtx c, const Node* n
   for (;;) {
     if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
     __syncthreads();
-    const int it = s_item;
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
     __syncthreads();
     if (it >= n) return;
     const Item I = items[first + it];
@@ -1985,6 +1987,41 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_layer_op(DevCtx c, const Node* n
     }
   }
 }
+
+// A layer whose launches run two stage or ghost-fill operations (typically a coarse level's stage
+// beside a finer level's next one): the claim loop with only those two operations' code.
+template <int OA, int OB, typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_layer2(DevCtx c, const Node* nodes, const Item* items, int first, int n,
+                                                        int* counter) {
+  __shared__ int s_item;
+  for (;;) {
+    if (threadIdx.x == 0) s_item = atomicAdd(counter, 1);
+    __syncthreads();
+    const int it = __builtin_amdgcn_readfirstlane(s_item);
+    __syncthreads();
+    if (it >= n) return;
+    const Item I = items[first + it];
+    const Node nd = nodes[I.node];
+    for (int b = I.b0; b < I.b1; ++b) {
+      if (nd.op == OA) run_op<OA, R, MIX>(c, nd, b);
+      else run_op<OB, R, MIX>(c, nd, b);
+      if (OA == OP_COPY || OB == OP_COPY) __syncthreads();
+    }
+  }
+}
+
+template <int OA, int OB>
+hipError_t launch_layer2_t(const DevCtx& c, const Node* nodes, const Item* items, int first, int n, int* counter, int g) {
+  if (c.precision == 0) k_layer2<OA, OB, double, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter);
+  else if (c.precision == 1) k_layer2<OA, OB, float, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter);
+  else k_layer2<OA, OB, float, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter);
+  return hipGetLastError();
+}
+
+// operation pairs with a specialised layer kernel, as (lower op, higher op)
+#define LAYER2_CASES(X)                                                                               \
+  X(OP_PRIM, OP_BHALF) X(OP_BHALF, OP_PRED) X(OP_PRED, OP_FLUX) X(OP_FLUX, OP_EDGE) X(OP_EDGE, OP_UPDATE) \
+  X(OP_COPY, OP_PROLONG) X(OP_COPY, OP_PRIM) X(OP_PROLONG, OP_PRIM)
 
 template <int OP>
 hipError_t launch_layer_op_t(const DevCtx& c, const Node* nodes, const Item* items, int first, int n, int* counter,
@@ -2203,6 +2240,13 @@ hipError_t launch_persistent(const DevCtx& c, const Sched& sc, int nnodes, int n
   return hipGetLastError();
 }
 
+bool layer2_supported(int oa, int ob) {
+#define X(A, B) if (oa == A && ob == B) return true;
+  LAYER2_CASES(X)
+#undef X
+  return false;
+}
+
 hipError_t launch_layer(const DevCtx& c, const Node* nodes, const Item* items, int first, int n, int* counter,
                         int nworkgroups, int nlev, double cfl, int op) {
   if (n <= 0) return hipSuccess;
@@ -2217,6 +2261,13 @@ hipError_t launch_layer(const DevCtx& c, const Node* nodes, const Item* items, i
     case OP_EDGE: return launch_layer_op_t<OP_EDGE>(c, nodes, items, first, n, counter, gi);
     case OP_UPDATE: return launch_layer_op_t<OP_UPDATE>(c, nodes, items, first, n, counter, gi);
     default: break;
+  }
+  if (op >= 64) {  // a pair: 64 * (lower op + 1) + higher op
+    const int oa = op / 64 - 1, ob = op % 64;
+#define X(A, B) if (oa == A && ob == B) return launch_layer2_t<A, B>(c, nodes, items, first, n, counter, gi);
+    LAYER2_CASES(X)
+#undef X
+    return hipErrorInvalidValue;
   }
   const dim3 g(nworkgroups);
   if (c.precision == 0) k_layer<double, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, nodes, items, first, n, counter, nlev, cfl);
