@@ -47,13 +47,13 @@ WORDS_PER_UNIT = {
 # 512 MiB copy's readings), keyed by (workload, precision, kernel class); valid only for the kernel sources whose
 # hash is stored beside it, null otherwise.
 MEASURED_TRAFFIC = {
-    ("two_level", "fp32", "flux"): {"bytes_per_launch": 644.8e6, "sources": "875e099af864c4d2:932ae6b69edeb2e7"},
+    ("two_level", "fp32", "flux"): {"bytes_per_launch": 645.1e6, "sources": "1158551f15f51c73:36f623ae7c4c441c"},
 }
 
 # Fraction of the dominant kernel's vector-ALU issue slots used (SQ_INSTS_VALU against 256 CUs x one
 # wave-instruction per cycle x 2.4 GHz over its mean duration), from rocprofv3 counters, same validity rule.
 MEASURED_VALU_ISSUE = {
-    ("two_level", "fp32", "flux"): {"frac": 0.67, "sources": "875e099af864c4d2:932ae6b69edeb2e7"},
+    ("two_level", "fp32", "flux"): {"frac": 0.66, "sources": "1158551f15f51c73:36f623ae7c4c441c"},
 }
 
 
