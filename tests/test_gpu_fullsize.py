@@ -138,6 +138,26 @@ def test_two_level_full_root_steps_properties():
         assert abs(tot1[q] - tot0[q]) <= 1e-5 * scale, (q, tot0[q], tot1[q])
 
 
+def test_two_level_time_ghosts_root_steps_properties():
+    """The full two-level workload with coarse-time-derivative ghosts (as `bench.py --ghosts time` runs it):
+    two graph-replayed FP32 root steps keep mass and energy to float32 round-off of the totals, the
+    shared-face synchronisation exact and the state physical."""
+    spec = H.two_level()
+    _say("two-level full size, time-derivative ghosts")
+    h = Hierarchy(spec, FP32, ghosts="time")
+    h.set_field(SmoothField(1112))
+    s0, c0 = h.conservation()
+    for _ in range(2):
+        h.step(GRAPH)
+    s1, c1 = h.conservation()
+    d = h.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+    tot0, tot1 = s0 + c0, s1 + c1
+    for q in range(5):
+        scale = max(abs(tot0[q]), 0.05)
+        assert abs(tot1[q] - tot0[q]) <= 1e-5 * scale, (q, tot0[q], tot1[q])
+
+
 def test_uniform_256_sampled_windows():
     """Windows of the 256^3 FP32 advance recomputed by the oracle from the GPU's ghost-filled input."""
     n = 256
