@@ -14,4 +14,6 @@ Modules
          prolongation, restriction, flux/EMF registers and corrections,
          same-level synchronisation, the recursive level driver, CFL time
          step and conservation sums
+  regrid refinement flags, clustering of flagged cells into new patches,
+         and the initialisation of new patches from old ones and the parent
 """
