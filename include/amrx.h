@@ -293,6 +293,45 @@ int hier_tune_time(amrx_hier* h, int level, int substep, int tile, int reps, dou
  * sequence of per-level calls.  Synchronising.  Needs hier_bind. */
 int hier_tune_time_eu(amrx_hier* h, int level, int tile, int reps, double* ms);
 
+/* Regridding of the finest level (Sec. 2.2: a level's grids decide which cells
+ * to refine and lay down child grids over them; new grids take the data of the
+ * preceding grids of their level where those overlap them and are prolongated
+ * from the parent elsewhere).
+ *
+ * hier_flag_bytes: bytes of a flag array = padded cells of all patches.
+ * hier_flag: device flags (one byte per padded cell; patch p's cell at padded
+ *   index q is byte first_state_offset(p) / 16 + q, see patch_layout) of the
+ *   interior cells of `level`: 1 where the density jump to a face neighbour
+ *   inside the same patch exceeds eps times the smaller density, evaluated in
+ *   the state's precision.  Asynchronous on desc.stream.
+ * amrx_cluster: Berger-Rigoutsos clustering (pure host) of a flag array
+ *   f[(z ny + y) nx + x]: boxes (lo x, y, z, hi x, y, z; cap of them) covering
+ *   every flag, each shrunk to its flags and kept once flagged / volume >=
+ *   efficiency or no side can be cut into two of >= min_side; cuts at the
+ *   flag-free plane nearest the middle, else at the strongest sign change of
+ *   the signature's second difference, else in the middle of the longest
+ *   axis.  ENOMEM (with *nboxes set) if more than cap boxes result.
+ * hier_regrid_boxes: level-(level+1) boxes (pure host) from a downloaded flag
+ *   array: per level-`level` patch in id order its interior flags grown by one
+ *   cell in all 26 directions, cleared within one cell of the interior
+ *   boundary (the nesting rule), clustered, scaled by R.
+ * hier_init_from_bytes / hier_init_from: fill a new hierarchy `dst` whose
+ *   finest level `level` replaces that of `src` (the levels below must be the
+ *   same patches in both; same precision): lower levels copy src's current
+ *   buffers, level-`level` interiors (closures, for faces) copy src's
+ *   level-`level` patches where they overlap, and the remaining parent cells
+ *   under them are prolongated (the ghost-fill operator) from dst's parent
+ *   level.  work: device workspace of at least the queried bytes, 256-byte
+ *   aligned.  Synchronising; ghost data is filled by the next step. */
+int hier_flag_bytes(const amrx_hier* h, size_t* bytes);
+int hier_flag(amrx_hier* h, int level, double eps, unsigned char* flags);
+int amrx_cluster(const unsigned char* flags, int nx, int ny, int nz, int min_side, double efficiency, int* boxes,
+                 int cap, int* nboxes);
+int hier_regrid_boxes(const amrx_hier* h, int level, const unsigned char* flags, int min_side, double efficiency,
+                      int* boxes, int cap, int* nboxes);
+int hier_init_from_bytes(const amrx_hier* dst, const amrx_hier* src, int level, size_t* bytes);
+int hier_init_from(amrx_hier* dst, const amrx_hier* src, int level, void* work, size_t work_bytes);
+
 /* Debug / test exports (pure host, after hier_finalize).  For every padded
  * cell (kind 0) or face normal to axis kind-1 (kind 1..3) of a patch, in
  * node-padded [z][y][x] order: the same-level source as

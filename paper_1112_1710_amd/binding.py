@@ -53,6 +53,14 @@ EXPORTS = {
     "hier_timing_enable": ([C.c_void_p, C.c_int], C.c_int),
     "hier_timing_read": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
     "hier_step_work": ([C.c_void_p, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int)], C.c_int),
+    "hier_flag_bytes": ([C.c_void_p, C.POINTER(C.c_size_t)], C.c_int),
+    "hier_flag": ([C.c_void_p, C.c_int, C.c_double, C.c_void_p], C.c_int),
+    "amrx_cluster": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_int), C.c_int,
+                      C.POINTER(C.c_int)], C.c_int),
+    "hier_regrid_boxes": ([C.c_void_p, C.c_int, C.c_void_p, C.c_int, C.c_double, C.POINTER(C.c_int), C.c_int,
+                           C.POINTER(C.c_int)], C.c_int),
+    "hier_init_from_bytes": ([C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+    "hier_init_from": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t], C.c_int),
     "hier_debug_layers": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hier_debug_schedule": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
@@ -339,6 +347,58 @@ class Hierarchy:
         return (a(nodes)[:12 * nn].reshape(nn, 12).copy(), a(preds)[:npr].copy(),
                 a(items)[:4 * ni].reshape(ni, 4).copy(), a(queues)[:2 * nq].reshape(nq, 2).copy())
 
+    # ------------------------------------------------------------------ regridding
+    def flag_array(self, level, eps):
+        """Refinement flags of `level` (one byte per padded cell of every patch, see hier_flag) on the host."""
+        torch = self._torch
+        nb = C.c_size_t()
+        self._check(self.lib.hier_flag_bytes(self.h, C.byref(nb)))
+        with torch.cuda.stream(self.stream):
+            buf = torch.zeros(max(1, nb.value), dtype=torch.uint8, device=self.device)
+        self._check(self.lib.hier_flag(self.h, int(level), float(eps), C.c_void_p(buf.data_ptr())))
+        self.synchronize()
+        return buf.cpu().numpy()
+
+    def flags(self, level, eps):
+        """{patch id: interior flags [z, y, x] (uint8)} of the patches of `level`."""
+        arr = self.flag_array(level, eps)
+        esize = 8 if self.precision == FP64 else 4
+        out = {}
+        for pid, (lv, lo, hi) in enumerate(self.spec.patches):
+            if lv != level:
+                continue
+            offs, shape = self.layout(pid, 0)
+            base = offs[0] // esize // 16
+            vol = shape[0] * shape[1] * shape[2]
+            full = arr[base:base + vol].reshape(shape)
+            n = [hi[a] - lo[a] for a in range(3)]
+            out[pid] = full[G:G + n[2], G:G + n[1], G:G + n[0]].copy()
+        return out
+
+    def regrid_boxes(self, level, eps, min_side=4, efficiency=0.7):
+        """Level-(level+1) boxes [((lo), (hi))] laid over the flagged cells of `level` (flags on the GPU,
+        buffer, nesting and clustering on the host)."""
+        arr = np.ascontiguousarray(self.flag_array(level, eps))
+        cap = 1 << 16
+        boxes = (C.c_int * (6 * cap))()
+        n = C.c_int()
+        self._check(self.lib.hier_regrid_boxes(self.h, int(level), arr.ctypes.data_as(C.c_void_p), int(min_side),
+                                               float(efficiency), boxes, cap, C.byref(n)))
+        b = np.ctypeslib.as_array(boxes)[:6 * n.value].reshape(n.value, 6)
+        return [(tuple(int(x) for x in r[:3]), tuple(int(x) for x in r[3:])) for r in b]
+
+    def init_from(self, src, level):
+        """Fill this hierarchy (whose finest level `level` replaces src's) from src (hier_init_from)."""
+        torch = self._torch
+        nb = C.c_size_t()
+        self._check(self.lib.hier_init_from_bytes(self.h, src.h, int(level), C.byref(nb)))
+        with torch.cuda.stream(self.stream):
+            work = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+        addr = (work.data_ptr() + 255) & ~255
+        src.synchronize()
+        self._check(self.lib.hier_init_from(self.h, src.h, int(level), C.c_void_p(addr), nb.value))
+        del work
+
     def debug_layers(self, fixed_dt=False):
         """Layered schedule: the first item of each layer (layers + 1) and the items (M, 4) in launch order."""
         sizes = (C.c_int * 2)()
@@ -357,3 +417,19 @@ class Hierarchy:
         buf = (C.c_int * max(1, 3 * n))()
         self._check(self.lib.hier_debug_prolong_cells(self.h, pid, C.byref(cnt), buf, n))
         return np.ctypeslib.as_array(buf)[:3 * n].reshape(n, 3).copy()
+
+
+def cluster_flags(flags, min_side=4, efficiency=0.7):
+    """Berger-Rigoutsos boxes [((lo x, y, z), (hi x, y, z))] of a flag array f[z, y, x] (amrx_cluster)."""
+    lib = load_library()
+    f = np.ascontiguousarray(flags, dtype=np.uint8)
+    nz, ny, nx = f.shape
+    cap = max(16, f.size)
+    boxes = (C.c_int * (6 * cap))()
+    n = C.c_int()
+    rc = lib.amrx_cluster(f.ctypes.data_as(C.c_void_p), nx, ny, nz, int(min_side), float(efficiency), boxes, cap,
+                          C.byref(n))
+    if rc != 0:
+        raise AmrxError(rc, "amrx_cluster")
+    b = np.ctypeslib.as_array(boxes)[:6 * n.value].reshape(n.value, 6)
+    return [(tuple(int(x) for x in r[:3]), tuple(int(x) for x in r[3:])) for r in b]

@@ -74,6 +74,12 @@ struct Pro {
   int flags;   // bit 2*d+s: the coarse face (axis d, side s) already holds same-level fine data
 };
 
+// A run of consecutive state entries copied from one hierarchy's arena to another's (regridding).
+struct XRun {
+  long long src, dst;  // offsets in reals of the two arenas
+  long long off;       // first element of the run within its list (prefix sum of lengths)
+};
+
 // An entry of the correction lists of a parent patch.
 struct Corr {
   int patch;   // parent
@@ -259,5 +265,8 @@ bool layer2_supported(int oa, int ob);
 hipError_t launch_layer(const DevCtx& c, const Node* nodes, const Item* items, int first, int n, int* counter,
                         int nworkgroups, int nlev, double cfl, int op);
 hipError_t launch_clear_ints(const DevCtx& c, int* p, int n);
+hipError_t launch_flag(const DevCtx& c, int first, int n, int nblk, int cur, double eps, unsigned char* flags);
+hipError_t launch_xcopy(int precision, hipStream_t s, const void* src, void* dst, const XRun* runs, int nrun,
+                        long long nelem);
 int layer_blocks_per_cu(int precision);
 int persistent_blocks_per_cu(int precision);

@@ -2402,6 +2402,375 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches) {
   return AMRX_OK;
 }
 
+// ---------------------------------------------------------------------------------------------
+// regridding of the finest level (Sec. 2.2: refinement flags, new child grids, their
+// initialisation from the preceding grids of the level and from the parent)
+// ---------------------------------------------------------------------------------------------
+int hier_flag_bytes(const amrx_hier* h, size_t* bytes) {
+  if (!h || !bytes) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  size_t v = 0;
+  for (const HPatch& p : h->P) v += (size_t)p.vol;
+  *bytes = v;
+  return AMRX_OK;
+}
+
+int hier_flag(amrx_hier* h, int level, double eps, unsigned char* flags) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (!flags || level < 0 || level >= h->nlev || !(eps >= 0.0)) return fail(h, AMRX_EINVAL, "bad level, eps or buffer");
+  const TaskList& T = h->cfl_b[level];
+  HIPCHK(launch_flag(h->ctx, T.first, T.count, T.nblk, h->cur[level], eps, flags), "flag launch");
+  return AMRX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+// Berger-Rigoutsos clustering of a flag array f[(z * ny + y) * nx + x]
+struct CBox {
+  int lo[3], hi[3];
+};
+
+struct Flags3 {
+  const unsigned char* f;
+  int n[3];
+  bool at(int x, int y, int z) const { return f[((size_t)z * n[1] + y) * n[0] + x] != 0; }
+};
+
+// signature along axis a: flags in each plane normal to a, inside the box
+std::vector<long long> box_signature(const Flags3& F, const CBox& b, int a) {
+  std::vector<long long> s(b.hi[a] - b.lo[a], 0);
+  for (int z = b.lo[2]; z < b.hi[2]; ++z)
+    for (int y = b.lo[1]; y < b.hi[1]; ++y)
+      for (int x = b.lo[0]; x < b.hi[0]; ++x)
+        if (F.at(x, y, z)) {
+          const int c[3] = {x, y, z};
+          ++s[c[a] - b.lo[a]];
+        }
+  return s;
+}
+
+bool shrink_to_flags(const Flags3& F, CBox& b) {
+  CBox out;
+  for (int a = 0; a < 3; ++a) {
+    const std::vector<long long> s = box_signature(F, b, a);
+    int first = -1, last = -1;
+    for (int i = 0; i < (int)s.size(); ++i)
+      if (s[i] > 0) {
+        if (first < 0) first = i;
+        last = i;
+      }
+    if (first < 0) return false;
+    out.lo[a] = b.lo[a] + first;
+    out.hi[a] = b.lo[a] + last + 1;
+  }
+  b = out;
+  return true;
+}
+
+// (axis, absolute cut) or axis -1
+void choose_cut(const Flags3& F, const CBox& b, int min_side, int& axis, int& cut) {
+  int n[3];
+  for (int a = 0; a < 3; ++a) n[a] = b.hi[a] - b.lo[a];
+  axis = -1;
+  // a plane without flags nearest the middle (ties: lower axis, then lower position)
+  long long best_d = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 2 * min_side) continue;
+    const std::vector<long long> s = box_signature(F, b, a);
+    for (int i = min_side; i <= n[a] - min_side; ++i) {
+      if (i >= n[a] || s[i] != 0) continue;
+      const long long d = std::llabs(2LL * i - n[a]);
+      if (axis < 0 || d < best_d) {
+        axis = a;
+        cut = b.lo[a] + i;
+        best_d = d;
+      }
+    }
+  }
+  if (axis >= 0) return;
+  // the strongest sign change of the signature's second difference
+  long long best_str = 0;
+  for (int a = 0; a < 3; ++a) {
+    if (n[a] < 2 * min_side) continue;
+    const std::vector<long long> s = box_signature(F, b, a);
+    std::vector<long long> lap(n[a], 0);
+    for (int i = 1; i + 1 < n[a]; ++i) lap[i] = s[i + 1] - 2 * s[i] + s[i - 1];
+    for (int i = 1; i + 2 < n[a]; ++i) {
+      const int c = i + 1;
+      if (c < min_side || n[a] - c < min_side) continue;
+      if (!((lap[i] < 0 && lap[i + 1] > 0) || (lap[i] > 0 && lap[i + 1] < 0))) continue;
+      const long long str = std::llabs(lap[i + 1] - lap[i]);
+      const long long d = std::llabs(2LL * c - n[a]);
+      if (axis < 0 || str > best_str || (str == best_str && d < best_d)) {
+        axis = a;
+        cut = b.lo[a] + c;
+        best_str = str;
+        best_d = d;
+      }
+    }
+  }
+  if (axis >= 0) return;
+  // the middle of the longest axis that can be cut (lower axis on ties)
+  for (int a = 0; a < 3; ++a)
+    if (n[a] >= 2 * min_side && (axis < 0 || n[a] > n[axis])) axis = a;
+  if (axis >= 0) cut = b.lo[axis] + n[axis] / 2;
+}
+
+std::vector<CBox> cluster_flags(const Flags3& F, int min_side, double efficiency) {
+  std::vector<CBox> out, stack;
+  CBox all;
+  for (int a = 0; a < 3; ++a) {
+    all.lo[a] = 0;
+    all.hi[a] = F.n[a];
+  }
+  stack.push_back(all);
+  while (!stack.empty()) {
+    CBox b = stack.back();
+    stack.pop_back();
+    if (!shrink_to_flags(F, b)) continue;
+    long long vol = 1, nf = 0;
+    for (int a = 0; a < 3; ++a) vol *= b.hi[a] - b.lo[a];
+    for (int z = b.lo[2]; z < b.hi[2]; ++z)
+      for (int y = b.lo[1]; y < b.hi[1]; ++y)
+        for (int x = b.lo[0]; x < b.hi[0]; ++x) nf += F.at(x, y, z) ? 1 : 0;
+    if ((double)nf >= efficiency * (double)vol) {
+      out.push_back(b);
+      continue;
+    }
+    int axis, cut;
+    choose_cut(F, b, min_side, axis, cut);
+    if (axis < 0) {
+      out.push_back(b);
+      continue;
+    }
+    CBox left = b, right = b;
+    left.hi[axis] = cut;
+    right.lo[axis] = cut;
+    stack.push_back(right);  // the low part is taken first
+    stack.push_back(left);
+  }
+  return out;
+}
+}  // namespace
+
+extern "C" {
+
+int amrx_cluster(const unsigned char* flags, int nx, int ny, int nz, int min_side, double efficiency, int* boxes,
+                 int cap, int* nboxes) {
+  if (!flags || !nboxes || nx <= 0 || ny <= 0 || nz <= 0 || min_side < 1 || cap < 0) return AMRX_EINVAL;
+  const Flags3 F{flags, {nx, ny, nz}};
+  const std::vector<CBox> out = cluster_flags(F, min_side, efficiency);
+  *nboxes = (int)out.size();
+  if ((int)out.size() > cap) return AMRX_ENOMEM;
+  for (size_t i = 0; i < out.size(); ++i)
+    for (int a = 0; a < 3; ++a) {
+      boxes[6 * i + a] = out[i].lo[a];
+      boxes[6 * i + 3 + a] = out[i].hi[a];
+    }
+  return AMRX_OK;
+}
+
+int hier_regrid_boxes(const amrx_hier* h, int level, const unsigned char* flags, int min_side, double efficiency,
+                      int* boxes, int cap, int* nboxes) {
+  if (!h || !flags || !nboxes || cap < 0 || min_side < 1) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  if (level < 0 || level >= h->nlev) return AMRX_EINVAL;
+  std::vector<CBox> all;
+  for (int id : h->lev[level]) {
+    const HPatch& m = h->P[id];
+    const size_t base = (size_t)h->pdev[id].st[0] / 16;
+    const int n0 = m.n[0], n1 = m.n[1], n2 = m.n[2];
+    std::vector<unsigned char> f((size_t)n0 * n1 * n2, 0), g;
+    for (int z = 0; z < n2; ++z)
+      for (int y = 0; y < n1; ++y)
+        for (int x = 0; x < n0; ++x)
+          f[((size_t)z * n1 + y) * n0 + x] = flags[base + (size_t)lin_of(m, G + x, G + y, G + z)] ? 1 : 0;
+    // one-cell buffer in all 26 directions
+    g = f;
+    for (int z = 0; z < n2; ++z)
+      for (int y = 0; y < n1; ++y)
+        for (int x = 0; x < n0; ++x) {
+          if (!f[((size_t)z * n1 + y) * n0 + x]) continue;
+          for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+              for (int dx = -1; dx <= 1; ++dx) {
+                const int X = x + dx, Y = y + dy, Z = z + dz;
+                if (X >= 0 && X < n0 && Y >= 0 && Y < n1 && Z >= 0 && Z < n2) g[((size_t)Z * n1 + Y) * n0 + X] = 1;
+              }
+        }
+    // nesting: nothing within one parent cell of the interior boundary is refined
+    for (int z = 0; z < n2; ++z)
+      for (int y = 0; y < n1; ++y)
+        for (int x = 0; x < n0; ++x)
+          if (x == 0 || y == 0 || z == 0 || x == n0 - 1 || y == n1 - 1 || z == n2 - 1) g[((size_t)z * n1 + y) * n0 + x] = 0;
+    const Flags3 F{g.data(), {n0, n1, n2}};
+    for (CBox b : cluster_flags(F, min_side, efficiency)) {
+      for (int a = 0; a < 3; ++a) {
+        b.lo[a] = R * (m.lo[a] + b.lo[a]);
+        b.hi[a] = R * (m.lo[a] + b.hi[a]);
+      }
+      all.push_back(b);
+    }
+  }
+  *nboxes = (int)all.size();
+  if ((int)all.size() > cap) return AMRX_ENOMEM;
+  for (size_t i = 0; i < all.size(); ++i)
+    for (int a = 0; a < 3; ++a) {
+      boxes[6 * i + a] = all[i].lo[a];
+      boxes[6 * i + 3 + a] = all[i].hi[a];
+    }
+  return AMRX_OK;
+}
+
+}  // extern "C"
+
+namespace {
+struct InitPlan {
+  std::vector<XRun> runs;
+  long long nelem = 0;
+  std::vector<Pro> pros;
+  std::vector<std::array<int, 2>> same;  // (dst patch, src patch) pairs with identical boxes below `level`
+};
+
+int plan_init(const amrx_hier* dst, const amrx_hier* src, int level, InitPlan& P, std::string& err) {
+  if (dst->d.precision != src->d.precision || level < 1 || level >= dst->nlev ||
+      dst->nlev != level + 1) {
+    err = "regrid transfer: equal precisions and the new level as the destination's finest one required";
+    return AMRX_EINVAL;
+  }
+  for (const HPatch& p : dst->P) {
+    if (p.level >= level) continue;
+    int match = -1;
+    for (const HPatch& q : src->P)
+      if (q.level == p.level && q.lo[0] == p.lo[0] && q.lo[1] == p.lo[1] && q.lo[2] == p.lo[2] &&
+          q.hi[0] == p.hi[0] && q.hi[1] == p.hi[1] && q.hi[2] == p.hi[2])
+        match = q.id;
+    if (match < 0) {
+      err = "regrid transfer: the levels below the new one must be the same patches in both hierarchies";
+      return AMRX_EINVAL;
+    }
+    P.same.push_back({p.id, match});
+  }
+  for (int pid : dst->lev[level]) {
+    const HPatch& p = dst->P[pid];
+    const PatchDev& pd = dst->pdev[pid];
+    const long long pbase = pd.st[dst->cur[level]];
+    std::vector<char> covered((size_t)p.vol, 0);   // fine cells held by an old patch
+    std::vector<char> fcov[3];
+    for (int d = 0; d < 3; ++d) fcov[d].assign((size_t)p.vol, 0);
+    if (level < src->nlev)
+      for (int qid : src->lev[level]) {
+        const HPatch& q = src->P[qid];
+        const PatchDev& qd = src->pdev[qid];
+        const long long qbase = qd.st[src->cur[level]];
+        for (int kind = 0; kind < 4; ++kind) {
+          int lo[3], hi[3];
+          bool any = true;
+          for (int a = 0; a < 3; ++a) {
+            lo[a] = std::max(p.lo[a], q.lo[a]);
+            hi[a] = std::min(p.hi[a], q.hi[a]) + ((kind >= 1 && a == kind - 1) ? 1 : 0);
+            any = any && hi[a] > lo[a];
+          }
+          if (!any) continue;
+          const int nf = kind == 0 ? 5 : 1;
+          for (int m = 0; m < nf; ++m) {
+            const int field = kind == 0 ? m : 4 + kind;
+            for (int z = lo[2]; z < hi[2]; ++z)
+              for (int y = lo[1]; y < hi[1]; ++y) {
+                const long long pl = lin_of(p, lo[0] - p.lo[0] + G, y - p.lo[1] + G, z - p.lo[2] + G);
+                const long long ql = lin_of(q, lo[0] - q.lo[0] + G, y - q.lo[1] + G, z - q.lo[2] + G);
+                XRun r;
+                r.src = qbase + (long long)field * q.vol + ql;
+                r.dst = pbase + (long long)field * p.vol + pl;
+                r.off = P.nelem;
+                P.runs.push_back(r);
+                P.nelem += hi[0] - lo[0];
+                if (m == 0)
+                  for (int x = 0; x < hi[0] - lo[0]; ++x) (kind == 0 ? covered : fcov[kind - 1])[pl + x] = 1;
+              }
+          }
+        }
+      }
+    // parent cells under the interior that no old patch holds: prolongation
+    const HPatch& mp = dst->P[p.parent];
+    for (int cz = 0; cz < p.n[2] / 2; ++cz)
+      for (int cy = 0; cy < p.n[1] / 2; ++cy)
+        for (int cx = 0; cx < p.n[0] / 2; ++cx) {
+          const int fx = G + 2 * cx, fy = G + 2 * cy, fz = G + 2 * cz;
+          if (covered[lin_of(p, fx, fy, fz)]) continue;
+          Pro pr;
+          pr.patch = pid;
+          pr.c[0] = fx / 2;
+          pr.c[1] = fy / 2;
+          pr.c[2] = fz / 2;
+          const int gi[3] = {p.lo[0] / 2 + cx, p.lo[1] / 2 + cy, p.lo[2] / 2 + cz};
+          pr.pidx = (int)lin_of(mp, gi[0] - (mp.lo[0] - G), gi[1] - (mp.lo[1] - G), gi[2] - (mp.lo[2] - G));
+          int flags = 0;
+          for (int d = 0; d < 3; ++d)
+            for (int sd = 0; sd < 2; ++sd) {
+              int f[3] = {fx, fy, fz};
+              f[d] += 2 * sd;
+              if (fcov[d][lin_of(p, f[0], f[1], f[2])]) flags |= 1 << (2 * d + sd);
+            }
+          pr.flags = flags;
+          P.pros.push_back(pr);
+        }
+  }
+  return AMRX_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int hier_init_from_bytes(const amrx_hier* dst, const amrx_hier* src, int level, size_t* bytes) {
+  if (!dst || !src || !bytes) return AMRX_EINVAL;
+  if (!dst->frozen || !src->frozen) return AMRX_ESTATE;
+  InitPlan P;
+  std::string err;
+  const int rc = plan_init(dst, src, level, P, err);
+  if (rc) return rc;
+  *bytes = align256(sizeof(XRun) * P.runs.size()) + align256(sizeof(Pro) * P.pros.size()) + 256;
+  return AMRX_OK;
+}
+
+int hier_init_from(amrx_hier* dst, const amrx_hier* src, int level, void* work, size_t work_bytes) {
+  if (!ready(dst)) return AMRX_ESTATE;
+  amrx_hier* h = dst;  // error reporting of the checks below
+  if (!src || !src->bound) return fail(dst, AMRX_ESTATE, "source hierarchy not bound");
+  InitPlan P;
+  std::string err;
+  const int rc = plan_init(dst, src, level, P, err);
+  if (rc) return fail(dst, rc, err);
+  const size_t need = align256(sizeof(XRun) * P.runs.size()) + align256(sizeof(Pro) * P.pros.size()) + 256;
+  if (!work || work_bytes < need || ((uintptr_t)work & 255)) return fail(dst, AMRX_EINVAL, "workspace too small or unaligned");
+  hipStream_t s = (hipStream_t)dst->d.stream;
+  const size_t word = dst->d.precision == 0 ? sizeof(double) : sizeof(float);
+  // levels below: the same patches, whole current buffers
+  for (const auto& pr : P.same) {
+    const PatchDev& pd = dst->pdev[pr[0]];
+    const PatchDev& qd = src->pdev[pr[1]];
+    const int l = dst->P[pr[0]].level;
+    HIPCHK(hipMemcpyAsync(dst->state + pd.st[dst->cur[l]] * word, src->state + qd.st[src->cur[l]] * word,
+                          (size_t)8 * pd.vol * word, hipMemcpyDeviceToDevice, s),
+           "copy unchanged level");
+  }
+  char* w = (char*)work;
+  XRun* runs = (XRun*)w;
+  Pro* pros = (Pro*)(w + align256(sizeof(XRun) * P.runs.size()));
+  if (!P.runs.empty())
+    HIPCHK(hipMemcpyAsync(runs, P.runs.data(), sizeof(XRun) * P.runs.size(), hipMemcpyHostToDevice, s), "upload runs");
+  if (!P.pros.empty())
+    HIPCHK(hipMemcpyAsync(pros, P.pros.data(), sizeof(Pro) * P.pros.size(), hipMemcpyHostToDevice, s), "upload pros");
+  HIPCHK(launch_xcopy(dst->d.precision, s, src->state, dst->state, runs, (int)P.runs.size(), P.nelem), "overlap copy");
+  DevCtx c = dst->ctx;
+  c.pros = pros;
+  const int pc = dst->cur[level - 1];
+  HIPCHK(launch_prolong(c, 0, (int)P.pros.size(), dst->cur[level], pc, pc, 0.0), "prolongation of new cells");
+  HIPCHK(hipStreamSynchronize(s), "stream synchronize");
+  return AMRX_OK;
+}
+
 int hier_debug_layers(amrx_hier* h, int fixed_dt, int* sizes, int* first, int* items) {
   if (!h || !sizes) return AMRX_EINVAL;
   if (!h->frozen) return AMRX_ESTATE;

@@ -1892,6 +1892,56 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_persistent(DevCtx c, Sched sc, i
 }
 
 // ---------------------------------------------------------------------------
+// regridding: refinement flags of a level's interior cells, and element runs
+// copied between the state arenas of two hierarchies
+// ---------------------------------------------------------------------------
+// flag of an interior cell: the density jump to a face neighbour inside the patch exceeds
+// eps times the smaller density, evaluated in the state's precision; one byte per padded cell
+// at (first state offset of the patch) / 16 + padded index
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flag(DevCtx c, int first, int n, int cur, double eps,
+                                                      unsigned char* flags) {
+  Where w;
+  if (!locate(c, first, n, xcd_block(blockIdx.x, gridDim.x), w)) return;
+  const PatchDev& p = c.patches[c.tasks[w.task].patch];
+  const Strides S = strides(p);
+  const R* U = (const R*)c.state + p.st[cur];
+  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+  const R e = R(eps);
+  const R rc = U[q];
+  const int g[3] = {w.i, w.j, w.k};
+  bool f = false;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    if (g[d] > AMRX_G) {
+      const R rn = U[q - S.s[d]];
+      f = f || fabs(rn - rc) > e * fmin(rn, rc);
+    }
+    if (g[d] < AMRX_G + p.n[d] - 1) {
+      const R rn = U[q + S.s[d]];
+      f = f || fabs(rn - rc) > e * fmin(rn, rc);
+    }
+  }
+  flags[p.st[0] / 16 + q] = f ? 1 : 0;
+}
+
+// one thread per element of a list of runs (src offset, dst offset, length; offsets in reals
+// of the two arenas); off[r] = first element of run r (prefix), r found by binary search
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_xcopy(const R* src, R* dst, const XRun* runs, int nrun, long long nelem) {
+  const long long e = (long long)blockIdx.x * AMRX_BLOCK + threadIdx.x;
+  if (e >= nelem) return;
+  int lo = 0, hi = nrun - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (runs[mid].off <= e) lo = mid; else hi = mid - 1;
+  }
+  const XRun& r = runs[lo];
+  const long long k = e - r.off;
+  dst[r.dst + k] = src[r.src + k];
+}
+
+// ---------------------------------------------------------------------------
 // layered fine-first schedule: the dependency graph of one root step cut into
 // layers of mutually independent batched launches (a node's layer is one more
 // than its latest predecessor's).  One launch per layer with a persistent grid;
@@ -2237,6 +2287,22 @@ hipError_t launch_persistent(const DevCtx& c, const Sched& sc, int nnodes, int n
   if (c.precision == 0) k_persistent<double, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, sc, nlev, cfl);
   else if (c.precision == 1) k_persistent<float, false><<<g, AMRX_BLOCK, 0, c.stream>>>(c, sc, nlev, cfl);
   else k_persistent<float, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, sc, nlev, cfl);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag(const DevCtx& c, int first, int n, int nblk, int cur, double eps, unsigned char* flags) {
+  if (n == 0 || nblk == 0) return hipSuccess;
+  if (c.precision == 0) k_flag<double><<<nblk, AMRX_BLOCK, 0, c.stream>>>(c, first, n, cur, eps, flags);
+  else k_flag<float><<<nblk, AMRX_BLOCK, 0, c.stream>>>(c, first, n, cur, eps, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_xcopy(int precision, hipStream_t s, const void* src, void* dst, const XRun* runs, int nrun,
+                        long long nelem) {
+  if (nrun == 0 || nelem == 0) return hipSuccess;
+  const unsigned g = (unsigned)((nelem + AMRX_BLOCK - 1) / AMRX_BLOCK);
+  if (precision == 0) k_xcopy<double><<<g, AMRX_BLOCK, 0, s>>>((const double*)src, (double*)dst, runs, nrun, nelem);
+  else k_xcopy<float><<<g, AMRX_BLOCK, 0, s>>>((const float*)src, (float*)dst, runs, nrun, nelem);
   return hipGetLastError();
 }
 

@@ -1,0 +1,64 @@
+"""Regridding of the finest level of a bound hierarchy (Sec. 2.2: grids decide which cells to
+refine and lay down child grids over them; new grids take the data of the preceding grids of
+their level where those overlap them and are prolongated from the parent elsewhere).
+
+Flags are computed on the GPU (``hier_flag``), grown by a one-cell buffer, kept off the parent's
+boundary layer and clustered on the host (``hier_regrid_boxes``); the new hierarchy is built
+and filled on the GPU (``hier_init_from``).  The topology of a hierarchy is fixed once it is
+finalised, so a regrid returns a new hierarchy.
+"""
+from dataclasses import dataclass, field
+
+from .binding import Hierarchy
+
+
+@dataclass
+class Spec:
+    """Patch list of a hierarchy: root_n and [(level, lo, hi), ...] in level index space."""
+    root_n: tuple
+    patches: list = field(default_factory=list)
+    name: str = ""
+
+    def levels(self):
+        return 1 + max(p[0] for p in self.patches)
+
+    def cells(self, level=None):
+        tot = 0
+        for lv, lo, hi in self.patches:
+            if level is None or lv == level:
+                n = 1
+                for a in range(3):
+                    n *= hi[a] - lo[a]
+                tot += n
+        return tot
+
+    def zone_updates_per_root_step(self):
+        tot = 0
+        for lv, lo, hi in self.patches:
+            n = 1
+            for a in range(3):
+                n *= hi[a] - lo[a]
+            tot += n * 2 ** lv
+        return tot
+
+
+def new_spec(h, eps, min_side=4, efficiency=0.7):
+    """The patch list with the finest level of bound hierarchy h replaced by boxes over the
+    flagged cells of the level below."""
+    top = h.levels - 1
+    if top < 1:
+        raise ValueError("regridding needs a refined level")
+    boxes = h.regrid_boxes(top - 1, eps, min_side, efficiency)
+    if not boxes:
+        raise ValueError("no cell of the level below the finest one is flagged")
+    keep = [p for p in h.spec.patches if p[0] < top]
+    return Spec(root_n=tuple(h.spec.root_n), patches=keep + [(top, lo, hi) for lo, hi in boxes],
+                name=f"{getattr(h.spec, 'name', '')} (regridded)")
+
+
+def regrid(h, eps, min_side=4, efficiency=0.7, **kwargs):
+    """A new hierarchy whose finest level covers the flagged cells of the level below, filled from h."""
+    spec = new_spec(h, eps, min_side, efficiency)
+    h2 = Hierarchy(spec, h.precision, device=h.device, **kwargs)
+    h2.init_from(h, h.levels - 1)
+    return h2

@@ -434,3 +434,50 @@ def test_time_ghost_switch_and_step_work():
     assert wt["prolong"][1] == we["prolong"][1] + 3
     assert wt["copy"][1] == we["copy"][1] + 3
     assert wt["prolong"][0] == 2 * we["prolong"][0]
+
+
+@pytest.mark.parametrize("seed", range(8))
+def test_clustering_matches_oracle(seed):
+    """The library's Berger-Rigoutsos clustering returns the oracle's boxes, in the same order."""
+    _lib()
+    from oracle import regrid as oregrid
+    rng = np.random.default_rng(100 + seed)
+    shape = tuple(int(x) for x in rng.integers(6, 20, 3))
+    f = rng.random(shape) < rng.uniform(0.02, 0.2)
+    if seed % 2:
+        f = oregrid.buffer_flags(f) & (rng.random(shape) < 0.8)
+    for min_side, eff in ((2, 0.7), (3, 0.85), (4, 0.5)):
+        want = oregrid.cluster(f, min_side, eff)
+        got = binding.cluster_flags(f, min_side, eff)
+        assert got == want, (min_side, eff)
+
+
+def test_regrid_boxes_match_oracle():
+    """From the same raw flags the library's buffer, nesting layer and clustering per parent give the
+    oracle's level-1 boxes (host logic; the flags here come from the oracle's criterion)."""
+    _lib()
+    from oracle import regrid as oregrid
+    from workloads.fields import SmoothField
+    spec = H.root_tiled()
+    o = amr.build(spec, SmoothField(41))
+    h = binding.Hierarchy(spec, device=None)
+    nb = ctypes.c_size_t()
+    assert h.lib.hier_flag_bytes(h.h, ctypes.byref(nb)) == 0
+    arr = np.zeros(nb.value, dtype=np.uint8)
+    for pid, p in enumerate(o.patches):
+        n = p.n
+        rho = p.cells[0][4:4 + n[2], 4:4 + n[1], 4:4 + n[0]]
+        raw = oregrid.flag_cells(rho, 0.02)
+        offs, shape = h.layout(pid, 0)
+        base = offs[0] // 8 // 16
+        full = np.zeros(shape, dtype=np.uint8)
+        full[4:4 + n[2], 4:4 + n[1], 4:4 + n[0]] = raw
+        arr[base:base + full.size] = full.ravel()
+    cap = 4096
+    boxes = (ctypes.c_int * (6 * cap))()
+    cnt = ctypes.c_int()
+    assert h.lib.hier_regrid_boxes(h.h, 0, arr.ctypes.data_as(ctypes.c_void_p), 2, 0.7, boxes, cap,
+                                   ctypes.byref(cnt)) == 0
+    got = [(tuple(boxes[6 * i:6 * i + 3]), tuple(boxes[6 * i + 3:6 * i + 6])) for i in range(cnt.value)]
+    want = oregrid.child_boxes(o, 0, 0.02, min_side=2, efficiency=0.7)
+    assert cnt.value > 0 and got == want
