@@ -85,6 +85,8 @@ def parse():
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
     ap.add_argument("--staged", action="store_true", help="run every advance stage as a separate kernel")
+    ap.add_argument("--regrid-eps", type=float, default=None,
+                    help="after the timed steps, time one regrid of the finest level with this flag threshold")
     ap.add_argument("--ghosts", default="extended", choices=["extended", "time"],
                     help="later-substep ghost data of refined patches: extended ghost regions (default) or the "
                          "coarse time derivative")
@@ -220,6 +222,38 @@ def timed_steps(h, mode, steps, warmup, torch, reset=None):
     return total / steps, h.timing_read()
 
 
+def time_regrid(h, eps, torch, min_side=4, efficiency=0.7):
+    """Wall time of one regrid of the finest level: GPU flags, host buffer/nesting/clustering, the new
+    hierarchy's host bookkeeping (finalize) and arenas, and its GPU initialisation from the old one."""
+    import time
+    from paper_1112_1710_amd.binding import Hierarchy
+    from paper_1112_1710_amd.regrid import Spec
+    top = h.levels - 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    flags = h.flag_array(top - 1, eps)
+    t1 = time.perf_counter()
+    boxes = h.boxes_from_flags(top - 1, flags, min_side, efficiency)
+    t2 = time.perf_counter()
+    spec = Spec(root_n=tuple(h.spec.root_n),
+                patches=[p for p in h.spec.patches if p[0] < top] + [(top, lo, hi) for lo, hi in boxes])
+    h2 = Hierarchy(spec, h.precision, device=h.device)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
+    h2.init_from(h, top)
+    torch.cuda.synchronize()
+    t4 = time.perf_counter()
+    old = sum(1 for p in h.spec.patches if p[0] == top)
+    rep = {"eps": eps, "flagged_cells": int(flags.sum()), "patches_before": old, "patches_after": len(boxes),
+           "cells_after": spec.cells(top), "flag_ms": round((t1 - t0) * 1e3, 2),
+           "cluster_ms": round((t2 - t1) * 1e3, 2),
+           "build_ms": round((t3 - t2) * 1e3, 2), "init_ms": round((t4 - t3) * 1e3, 2),
+           "total_ms": round((t4 - t0) * 1e3, 2)}
+    del h2
+    torch.cuda.empty_cache()
+    return rep
+
+
 def state_reset(h, spec, field, precision):
     """A callable that re-uploads the initial state (generated once, kept on the host in the state's dtype)."""
     import numpy as np
@@ -336,6 +370,9 @@ def main():
         else:
             roof = hbm
     per_class = {k: round(v[0] / args.steps, 4) for k, v in timing.items() if v[1]}
+    regrid_report = None
+    if args.regrid_eps is not None and spec.levels() > 1:
+        regrid_report = time_regrid(h, args.regrid_eps, torch)
     reset = None  # the closure holds the hierarchy
     del h
     torch.cuda.empty_cache()
@@ -370,6 +407,8 @@ def main():
         "roofline": roof,
         "kernel_ms_per_step": per_class,
     }
+    if regrid_report is not None:
+        out["regrid"] = regrid_report
 
     if not args.skip_plain:
         hp = Hierarchy(spec, FP64, ghosts=args.ghosts)

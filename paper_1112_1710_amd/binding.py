@@ -378,7 +378,11 @@ class Hierarchy:
     def regrid_boxes(self, level, eps, min_side=4, efficiency=0.7):
         """Level-(level+1) boxes [((lo), (hi))] laid over the flagged cells of `level` (flags on the GPU,
         buffer, nesting and clustering on the host)."""
-        arr = np.ascontiguousarray(self.flag_array(level, eps))
+        return self.boxes_from_flags(level, self.flag_array(level, eps), min_side, efficiency)
+
+    def boxes_from_flags(self, level, flag_array, min_side=4, efficiency=0.7):
+        """Host part of regrid_boxes: buffer, nesting layer and clustering of a downloaded flag array."""
+        arr = np.ascontiguousarray(flag_array, dtype=np.uint8)
         cap = 1 << 16
         boxes = (C.c_int * (6 * cap))()
         n = C.c_int()
