@@ -488,10 +488,18 @@ void build_runs(amrx_hier* h, int pid, int depth, bool by_side, int& nelem, doub
       lo[a] = G - dlo;
       hi[a] = G + p.n[a] + dhi + ((kind >= 1 && a == kind - 1) ? 1 : 0);
     }
+    int own_hi[3];
+    for (int a = 0; a < 3; ++a) own_hi[a] = G + p.n[a] + ((kind >= 1 && a == kind - 1) ? 1 : 0);
     for (int k = lo[2]; k < hi[2]; ++k)
       for (int j = lo[1]; j < hi[1]; ++j) {
+        // rows through the patch's own entries skip them in one step
+        const bool inner_row = j >= G && j < own_hi[1] && k >= G && k < own_hi[2];
         int i = lo[0];
         while (i < hi[0]) {
+          if (inner_row && i == G) {
+            i = own_hi[0];
+            continue;
+          }
           const long long l = lin_of(p, i, j, k);
           if (arr[l] < 0 || is_own(p, kind, i, j, k)) {
             ++i;
@@ -524,6 +532,40 @@ void build_runs(amrx_hier* h, int pid, int depth, bool by_side, int& nelem, doub
   }
 }
 
+// Blocks of a copy list: the run holding the first element of every block.
+void copy_list_blocks(amrx_hier* h, CopyList& L) {
+  L.first_blk = (int)h->run_blk.size();
+  L.nblk = (L.nelem + AMRX_BLOCK - 1) / AMRX_BLOCK;
+  int r = 0;
+  for (int b = 0; b < L.nblk; ++b) {
+    const int e0 = b * AMRX_BLOCK;
+    while (r + 1 < L.nrun && h->runs[L.first_run + r + 1].off <= e0) ++r;
+    h->run_blk.push_back(r);
+  }
+}
+
+// The single-patch list of one patch from a batched list: the batched list is built patch by
+// patch, so that patch's runs are the contiguous range [r0, r1) of it; their element offsets
+// are rebased to start at zero.
+CopyList copy_list_of_patch(amrx_hier* h, int r0, int r1) {
+  CopyList L;
+  L.first_run = (int)h->runs.size();
+  int nelem = 0;
+  double comps = 0;
+  for (int r = r0; r < r1; ++r) {
+    Run x = h->runs[r];
+    x.off = nelem;
+    nelem += x.len;
+    comps += (double)x.len * (x.kind == 0 ? 5 : 1);
+    h->runs.push_back(x);
+  }
+  L.nrun = r1 - r0;
+  L.nelem = nelem;
+  L.comps = comps;
+  copy_list_blocks(h, L);
+  return L;
+}
+
 CopyList make_copy_list(amrx_hier* h, const std::vector<int>& pids, int depth, bool by_side) {
   CopyList L;
   L.first_run = (int)h->runs.size();
@@ -533,14 +575,7 @@ CopyList make_copy_list(amrx_hier* h, const std::vector<int>& pids, int depth, b
   L.nrun = (int)h->runs.size() - L.first_run;
   L.nelem = nelem;
   L.comps = comps;
-  L.first_blk = (int)h->run_blk.size();
-  L.nblk = (nelem + AMRX_BLOCK - 1) / AMRX_BLOCK;
-  int r = 0;
-  for (int b = 0; b < L.nblk; ++b) {
-    const int e0 = b * AMRX_BLOCK;
-    while (r + 1 < L.nrun && h->runs[L.first_run + r + 1].off <= e0) ++r;
-    h->run_blk.push_back(r);
-  }
+  copy_list_blocks(h, L);
   return L;
 }
 
@@ -627,6 +662,10 @@ void build_syncs(amrx_hier* h, int pid) {
         for (int sx = -1; sx <= 1; ++sx) {
           if (q == pid && sx == 0 && sy == 0 && sz == 0) continue;
           const int s[3] = {sx * nl_of(h, p.level, 0), sy * nl_of(h, p.level, 1), sz * nl_of(h, p.level, 2)};
+          // only boxes that touch or overlap can share a face
+          bool touch = true;
+          for (int a = 0; a < 3; ++a) touch = touch && Q.lo[a] + s[a] <= p.hi[a] && Q.hi[a] + s[a] >= p.lo[a];
+          if (!touch) continue;
           for (int d = 0; d < 3; ++d) {
             int a1, a2;
             other_axes(d, a1, a2);
@@ -994,7 +1033,14 @@ int finalize_impl(amrx_hier* h) {
       if (l == 0 && cls == 0) continue;
       const int depth = cls == 0 ? G : NG;
       h->copy_b[l][cls] = make_copy_list(h, h->lev[l], depth, cls == 0);
-      for (int id : h->lev[l]) h->copy_p[id][cls] = make_copy_list(h, std::vector<int>{id}, depth, cls == 0);
+      const CopyList B = h->copy_b[l][cls];
+      int r = B.first_run;
+      for (int id : h->lev[l]) {
+        const int r0 = r;
+        while (r < B.first_run + B.nrun && h->runs[r].dst_patch == id) ++r;
+        h->copy_p[id][cls] = copy_list_of_patch(h, r0, r);
+      }
+      if (r != B.first_run + B.nrun) return fail(h, AMRX_EINVAL, "copy runs out of patch order");
     }
     // prolongation
     h->pro_b[l].first = (int)h->pros.size();
