@@ -47,13 +47,13 @@ WORDS_PER_UNIT = {
 # 512 MiB copy's readings), keyed by (workload, precision, kernel class); valid only for the kernel sources whose
 # hash is stored beside it, null otherwise.
 MEASURED_TRAFFIC = {
-    ("two_level", "fp32", "flux"): {"bytes_per_launch": 645.1e6, "sources": "1158551f15f51c73:36f623ae7c4c441c"},
+    ("two_level", "fp32", "flux"): {"bytes_per_launch": 645.0e6, "sources": "36c943071a633992:ac4a7d69d709b97f"},
 }
 
 # Fraction of the dominant kernel's vector-ALU issue slots used (SQ_INSTS_VALU against 256 CUs x one
 # wave-instruction per cycle x 2.4 GHz over its mean duration), from rocprofv3 counters, same validity rule.
 MEASURED_VALU_ISSUE = {
-    ("two_level", "fp32", "flux"): {"frac": 0.66, "sources": "1158551f15f51c73:36f623ae7c4c441c"},
+    ("two_level", "fp32", "flux"): {"frac": 0.66, "sources": "36c943071a633992:ac4a7d69d709b97f"},
 }
 
 
