@@ -22,7 +22,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
 # vector ALU peaks: 256 CU x 4 SIMD x 16 lanes x 2 flops (FMA) x 2.4 GHz.  FP32 reaches 157.3 TFLOP/s only with
-# packed two-wide FP32 instructions, which this build does not emit; FP64 runs at the same 78.6.
+# packed two-wide FP32 instructions, which the kernels here do not use; FP64 runs at the same 78.6.
 VALU_PEAK_TFLOPS = 78.6
 
 # Kernel classes bound by vector arithmetic rather than HBM, with their algorithmic floating-point operations per
@@ -31,7 +31,7 @@ VALU_PEAK_TFLOPS = 78.6
 ALU_BOUND = {"flux": 570}
 
 # Algorithmic words moved per processed entry of each kernel class (reads + writes of
-# distinct values, neighbour re-reads not counted); see DESIGN.md "Kernels and rooflines".
+# distinct values, neighbour re-reads not counted).
 WORDS_PER_UNIT = {
     "prim": 8 + 11,      # U (5) + one face per axis (3) in; w (8) + cell EMF (3) out
     "bhalf": 6 + 3,      # 3 faces + 3 cell EMFs in; 3 half-step faces out
@@ -295,7 +295,7 @@ def main():
     if args.precision is None:
         args.precision = "fp32_mixed" if args.workload == "lowbeta" else "fp32"
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        sys.stderr.write("bench.py measures one GPU only: this build has no multi-GPU path "
+        sys.stderr.write("bench.py measures one GPU only: the library has no multi-GPU path "
                          "(run with --gpus 1).\n")
         sys.exit(2)
     import torch

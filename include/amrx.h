@@ -81,7 +81,7 @@ enum {
                          with one branch per level: launches of different levels that touch
                          disjoint data run concurrently (Sec. 4: coarser levels fill the gaps
                          left by finer ones); replayed like AMRX_GRAPH.
-                         AMRX_PERSISTENT and AMRX_CONCURRENT are disabled in this build
+                         AMRX_PERSISTENT and AMRX_CONCURRENT are disabled in this version of the library
                          (hier_step returns EINVAL for them). */
   AMRX_LAYERED = 5    /* the AMRX_PERSISTENT dependency graph cut into layers of mutually
                          independent batched launches (a node's layer is one past its latest

@@ -2140,12 +2140,12 @@ int hier_step(amrx_hier* h, int mode, double* dt0) {
     // Switched off: its first capture ended the calling process with a segmentation fault on the
     // MI355X and no cause in this library has been shown; the code stays for a later check.
     return h->concurrent_enabled ? concurrent_step(h, dt0)
-                                 : fail(h, AMRX_EINVAL, "the concurrent schedule is disabled in this build");
+                                 : fail(h, AMRX_EINVAL, "the concurrent schedule is disabled in this version of the library");
   if (mode == AMRX_PERSISTENT)
     // Switched off: its launches stalled on the MI355X (run killed after 180 s of silence,
     // twice) and the cause has not been shown yet; the schedule itself is checked on the host.
     return h->persistent_enabled ? persistent_step(h, dt0)
-                                 : fail(h, AMRX_EINVAL, "the persistent schedule is disabled in this build");
+                                 : fail(h, AMRX_EINVAL, "the persistent schedule is disabled in this version of the library");
   const int rc = enqueue_step(h, mode == AMRX_PLAIN, *dt0);
   if (rc) return rc;
   return finish_step(h, dt0);
