@@ -108,3 +108,83 @@ def test_regrid_matches_oracle(precision):
     assert np.all(err <= TOL[precision]), dict(zip(FIELDS, err))
     d = h2.diag()
     assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+
+
+def test_regrid_full_size_two_level_fp32():
+    """The benchmark's regrid (two-level 128^3 root + 512 patches, FP32, eps 0.02, default clustering) on a
+    seeded state with a density bump: flags of the whole root bit for bit and the same boxes as the oracle;
+    the root carried over bit for bit; the new level's data on a sample of new patches (no, partial and full
+    overlap with the old level) against the oracle's initialisation of those patches."""
+    from paper_1112_1710_amd.regrid import Spec
+    spec = H.two_level()
+    eps = 0.02
+    _say("regrid full size")
+    o = _bumped_oracle(spec, FP32, seed=61)
+    h = Hierarchy(spec, FP32)
+    upload_oracle_state(h, o)
+    root = o.patches[0]
+    n = root.n
+    want_flags = oregrid.flag_cells(root.cells[0][G:G + n[2], G:G + n[1], G:G + n[0]], eps, np.float32)
+    got_flags = h.flags(0, eps)[0].astype(bool)
+    assert np.array_equal(got_flags, want_flags) and want_flags.sum() > 0
+    want_boxes = oregrid.child_boxes(o, 0, eps, np.float32)
+    h2 = regrid(h, eps)
+    n0 = sum(1 for p in h2.spec.patches if p[0] == 0)
+    got_boxes = [(tuple(lo), tuple(hi)) for lv, lo, hi in h2.spec.patches if lv == 1]
+    assert got_boxes == [(tuple(lo), tuple(hi)) for lo, hi in want_boxes]
+    _say("  flags", int(want_flags.sum()), "boxes", len(got_boxes))
+    # the root is carried over unchanged
+    c0, f0 = h.download(0)
+    c1, f1 = h2.download(0)
+    assert np.array_equal(c0, c1) and all(np.array_equal(a, b) for a, b in zip(f0, f1))
+    # sample of new patches by overlap with the old level
+    old1 = [q for q in o.patches if q.level == 1]
+
+    def frac(b):
+        lo, hi = np.array(b[0]), np.array(b[1])
+        s = 0
+        for q in old1:
+            l, u = np.maximum(lo, q.lo), np.minimum(hi, q.hi)
+            if np.all(u > l):
+                s += int(np.prod(u - l))
+        return s / int(np.prod(hi - lo))
+
+    fr = [frac(b) for b in got_boxes]
+    none = [i for i, f in enumerate(fr) if f == 0.0]
+    part = [i for i, f in enumerate(fr) if 0.0 < f < 1.0]
+    full = [i for i, f in enumerate(fr) if f == 1.0]
+    assert none and part and full
+    pick = sorted({none[0], none[-1], part[0], part[len(part) // 2], part[-1], full[0]})
+    o2 = amr.Hierarchy(spec.root_n)
+    for lv, lo, hi in spec.patches:
+        if lv == 0:
+            o2.add(lv, lo, hi)
+    for i in pick:
+        o2.add(1, got_boxes[i][0], got_boxes[i][1])
+    o2.freeze()
+    o2.patches[0].cells = root.cells.copy()
+    o2.patches[0].faces = [f.copy() for f in root.faces]
+    oregrid.init_from(o2, o, 1)
+    num = np.zeros(8)
+    den = np.zeros(8)
+    for k, i in enumerate(pick):
+        p = o2.patches[n0 + k]
+        cells, faces = h2.download(n0 + i)
+        m = o2._interior_mask(p)
+        for c in range(5):
+            num[c] += np.sum(np.abs(cells[c][m] - p.cells[c][m]))
+            den[c] += np.sum(np.abs(p.cells[c][m]))
+        for d in range(3):
+            mk = o2._closure_mask(p, d)
+            num[5 + d] += np.sum(np.abs(faces[d][mk] - p.faces[d][mk]))
+            den[5 + d] += np.sum(np.abs(p.faces[d][mk]))
+        # cells under old patches arrive bit for bit
+        po = p.origin()
+        for q in old1:
+            lo, hi = np.maximum(p.lo, q.lo), np.minimum(p.hi, q.hi)
+            if np.any(hi <= lo):
+                continue
+            sl = tuple(slice(int(lo[a] - po[a]), int(hi[a] - po[a])) for a in (2, 1, 0))
+            assert np.array_equal(cells[(slice(None),) + sl], p.cells[(slice(None),) + sl]), (i, q.lo)
+    err = num / np.maximum(den, 1e-300)
+    assert np.all(err <= TOL[FP32]), dict(zip(FIELDS, err))
