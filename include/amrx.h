@@ -322,7 +322,18 @@ int hier_tune_time_eu(amrx_hier* h, int level, int tile, int reps, double* ms);
  *   level-`level` patches where they overlap, and the remaining parent cells
  *   under them are prolongated (the ghost-fill operator) from dst's parent
  *   level.  work: device workspace of at least the queried bytes, 256-byte
- *   aligned.  Synchronising; ghost data is filled by the next step. */
+ *   aligned.  Synchronising; ghost data is filled by the next step.
+ * hier_init_from_levels_bytes / hier_init_from_levels: the same with two
+ *   sources, for regridding several levels coarse to fine (Sec. 2.2: each new
+ *   level is laid over the flags of the new level below it and takes the data
+ *   of the old grids of its own level): the levels below `level` copy the
+ *   identical patches of `below` (a hierarchy already holding the new coarser
+ *   levels), level `level` copies the overlapping level-`level` patches of
+ *   `src` (the old hierarchy; none when src has no such level) and is
+ *   prolongated from dst's level - 1 elsewhere.  hier_init_from(dst, src, ...)
+ *   is hier_init_from_levels(dst, src, src, ...).  EINVAL when `below` lacks
+ *   a patch of dst's lower levels, when the precisions differ or when `level`
+ *   is not dst's finest level; ESTATE when a hierarchy is not bound. */
 int hier_flag_bytes(const amrx_hier* h, size_t* bytes);
 int hier_flag(amrx_hier* h, int level, double eps, unsigned char* flags);
 int amrx_cluster(const unsigned char* flags, int nx, int ny, int nz, int min_side, double efficiency, int* boxes,
@@ -331,6 +342,10 @@ int hier_regrid_boxes(const amrx_hier* h, int level, const unsigned char* flags,
                       int* boxes, int cap, int* nboxes);
 int hier_init_from_bytes(const amrx_hier* dst, const amrx_hier* src, int level, size_t* bytes);
 int hier_init_from(amrx_hier* dst, const amrx_hier* src, int level, void* work, size_t work_bytes);
+int hier_init_from_levels_bytes(const amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level,
+                                size_t* bytes);
+int hier_init_from_levels(amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level, void* work,
+                          size_t work_bytes);
 
 /* Debug / test exports (pure host, after hier_finalize).  For every padded
  * cell (kind 0) or face normal to axis kind-1 (kind 1..3) of a patch, in

@@ -1,5 +1,6 @@
-"""Regridding of the finest level: refinement flags, clustering into patches, and the
-initialisation of the new patches from the old ones and their parent.
+"""Regridding: refinement flags, clustering into patches, and the initialisation of the new
+patches from the old ones and their parent; of the finest level alone, or of every level from a
+given one upward, coarse to fine.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 
@@ -40,7 +41,11 @@ clustering method):
     interiors shrunk by one cell); the remaining
     parent cells under the new interior are prolongated as in ghost filling,
     from the parent's current state, with the outer fine faces that old
-    patches hold kept and the divergence-free interior closure applied.
+    patches hold kept and the divergence-free interior closure applied;
+  * several levels (Sec. 2.2 applied level after level): the new level l is
+    clustered over the flags of the new level l - 1 (already initialised), and
+    initialised from the old level l and the new level l - 1; a level without
+    flags ends the hierarchy there (the old finer levels are dropped).
 """
 from __future__ import annotations
 
@@ -312,3 +317,33 @@ def _prolong_interior(h, p, own_c, own_f):
                     fidx[a1] += t1
                     fidx[a2] += t2
                     p.faces[d][fidx[2], fidx[1], fidx[0]] = inner[k]
+
+
+def regrid_levels(old, eps, dtype=np.float64, min_side=4, efficiency=0.7, from_level=1):
+    """A new oracle hierarchy: the levels of `old` below `from_level` unchanged, every level from
+    `from_level` up to old's finest laid over the flags of the new level below it and initialised
+    from old's patches of its own level and from its new parents.  Stops at the first level whose
+    parents hold no flag (ValueError when that is `from_level` itself)."""
+    top = old.nlevels - 1
+    if not 1 <= from_level <= top:
+        raise ValueError("from_level must name a refined level")
+    cur = old
+    for level in range(from_level, top + 1):
+        boxes = child_boxes(cur, level - 1, eps, dtype, min_side, efficiency)
+        if not boxes:
+            if level == from_level:
+                raise ValueError("no cell below the first regridded level is flagged")
+            break
+        new = amr.Hierarchy(old.root_n, gamma=old.gamma, cfl=old.cfl, ghosts=old.ghosts)
+        keep = [p for p in cur.patches if p.level < level]
+        for p in keep:
+            new.add(p.level, tuple(int(v) for v in p.lo), tuple(int(v) for v in p.hi))
+        for lo, hi in boxes:
+            new.add(level, lo, hi)
+        new.freeze()
+        for q, p in zip(new.patches, keep):
+            q.cells = p.cells.copy()
+            q.faces = [f.copy() for f in p.faces]
+        init_from(new, old, level)
+        cur = new
+    return cur

@@ -61,6 +61,8 @@ EXPORTS = {
                            C.POINTER(C.c_int)], C.c_int),
     "hier_init_from_bytes": ([C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
     "hier_init_from": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t], C.c_int),
+    "hier_init_from_levels_bytes": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
+    "hier_init_from_levels": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t], C.c_int),
     "hier_debug_layers": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hier_debug_schedule": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
@@ -391,16 +393,26 @@ class Hierarchy:
         b = np.ctypeslib.as_array(boxes)[:6 * n.value].reshape(n.value, 6)
         return [(tuple(int(x) for x in r[:3]), tuple(int(x) for x in r[3:])) for r in b]
 
-    def init_from(self, src, level):
-        """Fill this hierarchy (whose finest level `level` replaces src's) from src (hier_init_from)."""
-        torch = self._torch
+    def init_from_bytes(self, src, level, below=None):
+        """Workspace bytes of init_from (pure host)."""
         nb = C.c_size_t()
-        self._check(self.lib.hier_init_from_bytes(self.h, src.h, int(level), C.byref(nb)))
+        b = src if below is None else below
+        self._check(self.lib.hier_init_from_levels_bytes(self.h, b.h, src.h, int(level), C.byref(nb)))
+        return nb.value
+
+    def init_from(self, src, level, below=None):
+        """Fill this hierarchy, whose finest level is `level`: the lower levels from the identical patches
+        of `below` (default: src), level `level` from src's overlapping patches of that level and by
+        prolongation elsewhere (hier_init_from_levels)."""
+        torch = self._torch
+        b = src if below is None else below
+        nb = self.init_from_bytes(src, level, below)
         with torch.cuda.stream(self.stream):
-            work = torch.empty(nb.value + 256, dtype=torch.uint8, device=self.device)
+            work = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
         addr = (work.data_ptr() + 255) & ~255
         src.synchronize()
-        self._check(self.lib.hier_init_from(self.h, src.h, int(level), C.c_void_p(addr), nb.value))
+        b.synchronize()
+        self._check(self.lib.hier_init_from_levels(self.h, b.h, src.h, int(level), C.c_void_p(addr), nb))
         del work
 
     def debug_layers(self, fixed_dt=False):

@@ -2679,21 +2679,25 @@ struct InitPlan {
   std::vector<std::array<int, 2>> same;  // (dst patch, src patch) pairs with identical boxes below `level`
 };
 
-int plan_init(const amrx_hier* dst, const amrx_hier* src, int level, InitPlan& P, std::string& err) {
-  if (dst->d.precision != src->d.precision || level < 1 || level >= dst->nlev ||
-      dst->nlev != level + 1) {
+// Transfer plan: dst's levels below `level` from the identical patches of `below`, dst's level
+// `level` (its finest) from src's patches of that level where they overlap and by prolongation
+// from dst's level - 1 elsewhere.
+int plan_init(const amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level, InitPlan& P,
+              std::string& err) {
+  if (dst->d.precision != src->d.precision || dst->d.precision != below->d.precision || level < 1 ||
+      level >= dst->nlev || dst->nlev != level + 1) {
     err = "regrid transfer: equal precisions and the new level as the destination's finest one required";
     return AMRX_EINVAL;
   }
   for (const HPatch& p : dst->P) {
     if (p.level >= level) continue;
     int match = -1;
-    for (const HPatch& q : src->P)
+    for (const HPatch& q : below->P)
       if (q.level == p.level && q.lo[0] == p.lo[0] && q.lo[1] == p.lo[1] && q.lo[2] == p.lo[2] &&
           q.hi[0] == p.hi[0] && q.hi[1] == p.hi[1] && q.hi[2] == p.hi[2])
         match = q.id;
     if (match < 0) {
-      err = "regrid transfer: the levels below the new one must be the same patches in both hierarchies";
+      err = "regrid transfer: the levels below the new one must be the same patches in the destination and the coarse-level source";
       return AMRX_EINVAL;
     }
     P.same.push_back({p.id, match});
@@ -2769,24 +2773,30 @@ int plan_init(const amrx_hier* dst, const amrx_hier* src, int level, InitPlan& P
 
 extern "C" {
 
-int hier_init_from_bytes(const amrx_hier* dst, const amrx_hier* src, int level, size_t* bytes) {
-  if (!dst || !src || !bytes) return AMRX_EINVAL;
-  if (!dst->frozen || !src->frozen) return AMRX_ESTATE;
+int hier_init_from_levels_bytes(const amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level,
+                                size_t* bytes) {
+  if (!dst || !below || !src || !bytes) return AMRX_EINVAL;
+  if (!dst->frozen || !below->frozen || !src->frozen) return AMRX_ESTATE;
   InitPlan P;
   std::string err;
-  const int rc = plan_init(dst, src, level, P, err);
+  const int rc = plan_init(dst, below, src, level, P, err);
   if (rc) return rc;
   *bytes = align256(sizeof(XRun) * P.runs.size()) + align256(sizeof(Pro) * P.pros.size()) + 256;
   return AMRX_OK;
 }
 
-int hier_init_from(amrx_hier* dst, const amrx_hier* src, int level, void* work, size_t work_bytes) {
+int hier_init_from_bytes(const amrx_hier* dst, const amrx_hier* src, int level, size_t* bytes) {
+  return hier_init_from_levels_bytes(dst, src, src, level, bytes);
+}
+
+int hier_init_from_levels(amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level, void* work,
+                          size_t work_bytes) {
   if (!ready(dst)) return AMRX_ESTATE;
   amrx_hier* h = dst;  // error reporting of the checks below
-  if (!src || !src->bound) return fail(dst, AMRX_ESTATE, "source hierarchy not bound");
+  if (!src || !src->bound || !below || !below->bound) return fail(dst, AMRX_ESTATE, "source hierarchy not bound");
   InitPlan P;
   std::string err;
-  const int rc = plan_init(dst, src, level, P, err);
+  const int rc = plan_init(dst, below, src, level, P, err);
   if (rc) return fail(dst, rc, err);
   const size_t need = align256(sizeof(XRun) * P.runs.size()) + align256(sizeof(Pro) * P.pros.size()) + 256;
   if (!work || work_bytes < need || ((uintptr_t)work & 255)) return fail(dst, AMRX_EINVAL, "workspace too small or unaligned");
@@ -2795,9 +2805,9 @@ int hier_init_from(amrx_hier* dst, const amrx_hier* src, int level, void* work, 
   // levels below: the same patches, whole current buffers
   for (const auto& pr : P.same) {
     const PatchDev& pd = dst->pdev[pr[0]];
-    const PatchDev& qd = src->pdev[pr[1]];
+    const PatchDev& qd = below->pdev[pr[1]];
     const int l = dst->P[pr[0]].level;
-    HIPCHK(hipMemcpyAsync(dst->state + pd.st[dst->cur[l]] * word, src->state + qd.st[src->cur[l]] * word,
+    HIPCHK(hipMemcpyAsync(dst->state + pd.st[dst->cur[l]] * word, below->state + qd.st[below->cur[l]] * word,
                           (size_t)8 * pd.vol * word, hipMemcpyDeviceToDevice, s),
            "copy unchanged level");
   }
@@ -2815,6 +2825,10 @@ int hier_init_from(amrx_hier* dst, const amrx_hier* src, int level, void* work, 
   HIPCHK(launch_prolong(c, 0, (int)P.pros.size(), dst->cur[level], pc, pc, 0.0), "prolongation of new cells");
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   return AMRX_OK;
+}
+
+int hier_init_from(amrx_hier* dst, const amrx_hier* src, int level, void* work, size_t work_bytes) {
+  return hier_init_from_levels(dst, src, src, level, work, work_bytes);
 }
 
 int hier_debug_layers(amrx_hier* h, int fixed_dt, int* sizes, int* first, int* items) {

@@ -1,6 +1,7 @@
-"""Regridding of the finest level of a bound hierarchy (Sec. 2.2: grids decide which cells to
-refine and lay down child grids over them; new grids take the data of the preceding grids of
-their level where those overlap them and are prolongated from the parent elsewhere).
+"""Regridding of a bound hierarchy, of its finest level or of every level from a given one
+upward (Sec. 2.2: grids decide which cells to refine and lay down child grids over them; new
+grids take the data of the preceding grids of their level where those overlap them and are
+prolongated from the parent elsewhere).
 
 Flags are computed on the GPU (``hier_flag``), grown by a one-cell buffer, kept off the parent's
 boundary layer and clustered on the host (``hier_regrid_boxes``); the new hierarchy is built
@@ -62,3 +63,27 @@ def regrid(h, eps, min_side=4, efficiency=0.7, **kwargs):
     h2 = Hierarchy(spec, h.precision, device=h.device, **kwargs)
     h2.init_from(h, h.levels - 1)
     return h2
+
+
+def regrid_levels(h, eps, min_side=4, efficiency=0.7, from_level=1, **kwargs):
+    """A new hierarchy with h's levels below `from_level` and every level from `from_level` up to h's
+    finest regridded coarse to fine: level l is laid over the flags of the new level l - 1 and filled
+    from h's level-l patches where they overlap and from the new level l - 1 elsewhere.  A level
+    whose parents hold no flag ends the hierarchy (ValueError when that is `from_level`)."""
+    top = h.levels - 1
+    if not 1 <= from_level <= top:
+        raise ValueError("from_level must name a refined level")
+    cur = h
+    for level in range(from_level, top + 1):
+        boxes = cur.regrid_boxes(level - 1, eps, min_side, efficiency)
+        if not boxes:
+            if level == from_level:
+                raise ValueError("no cell below the first regridded level is flagged")
+            break
+        keep = [p for p in cur.spec.patches if p[0] < level]
+        spec = Spec(root_n=tuple(h.spec.root_n), patches=keep + [(level, lo, hi) for lo, hi in boxes],
+                    name=f"{getattr(h.spec, 'name', '')} (regridded from level {from_level})")
+        nxt = Hierarchy(spec, h.precision, device=h.device, **kwargs)
+        nxt.init_from(h, level, below=cur)
+        cur = nxt
+    return cur

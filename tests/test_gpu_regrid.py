@@ -1,6 +1,7 @@
 """Regridding on the GPU against the oracle: refinement flags bit for bit, the boxes laid over
-them, the new finest level's initial data (copied overlaps bit for bit, prolongated cells to the
-parity tolerance) and a root step of the regridded hierarchy."""
+them, the new levels' initial data (copied overlaps bit for bit, prolongated cells to the parity
+tolerance) and a root step of the regridded hierarchy; the finest level alone and every level
+coarse to fine."""
 import numpy as np
 import pytest
 
@@ -9,7 +10,7 @@ pytestmark = pytest.mark.gpu
 
 from oracle import amr, regrid as oregrid  # noqa: E402
 from paper_1112_1710_amd import BATCHED, FP32, FP64, Hierarchy  # noqa: E402
-from paper_1112_1710_amd.regrid import new_spec, regrid  # noqa: E402
+from paper_1112_1710_amd.regrid import new_spec, regrid, regrid_levels  # noqa: E402
 from workloads import hierarchies as H  # noqa: E402
 from workloads.fields import G, SmoothField  # noqa: E402
 
@@ -188,3 +189,46 @@ def test_regrid_full_size_two_level_fp32():
             assert np.array_equal(cells[(slice(None),) + sl], p.cells[(slice(None),) + sl]), (i, q.lo)
     err = num / np.maximum(den, 1e-300)
     assert np.all(err <= TOL[FP32]), dict(zip(FIELDS, err))
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("eps,levels", [(0.2, 3), (0.25, 2)])
+def test_regrid_levels_matches_oracle(precision, eps, levels):
+    """Regrid levels 1 and 2 of a three-level hierarchy coarse to fine (level 2 over the flags of the new
+    level 1; at eps 0.25 the new level 1 holds no flag and the hierarchy ends there): the oracle's boxes
+    on every level, its new state, old same-level data bit for bit, and one root step afterwards."""
+    spec = H.small_three_level()
+    _say("regrid levels", precision, eps)
+    o = _bumped_oracle(spec, precision, centre=(0.28, 0.27, 0.25), width=0.06)
+    h = Hierarchy(spec, precision)
+    upload_oracle_state(h, o)
+    dtype = np.float64 if precision == FP64 else np.float32
+    want = oregrid.regrid_levels(o, eps, dtype, min_side=4)
+    h2 = regrid_levels(h, eps, min_side=4)
+    assert want.nlevels == levels and h2.levels == levels
+    got = [(lv, tuple(int(v) for v in lo), tuple(int(v) for v in hi)) for lv, lo, hi in h2.spec.patches]
+    exp = [(p.level, tuple(int(v) for v in p.lo), tuple(int(v) for v in p.hi)) for p in want.patches]
+    assert got == exp
+    err = rel_l1(h2, want)
+    assert np.all(err <= TOL[precision]), dict(zip(FIELDS, err))
+    copied = 0
+    for pid, p in enumerate(want.patches):
+        if p.level == 0:
+            continue
+        cells, _ = h2.download(pid)
+        po = p.origin()
+        for q in o.level_patches(p.level):
+            lo, hi = np.maximum(p.lo, q.lo), np.minimum(p.hi, q.hi)
+            if np.any(hi <= lo):
+                continue
+            sl = tuple(slice(int(lo[a] - po[a]), int(hi[a] - po[a])) for a in (2, 1, 0))
+            assert np.array_equal(cells[(slice(None),) + sl], p.cells[(slice(None),) + sl]), (pid, q.lo)
+            copied += 1
+    assert copied > 0
+    dt = want.cfl_dt()
+    want.root_step(dt)
+    h2.step(BATCHED, dt)
+    err = rel_l1(h2, want)
+    assert np.all(err <= TOL[precision]), dict(zip(FIELDS, err))
+    d = h2.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0

@@ -481,3 +481,27 @@ def test_regrid_boxes_match_oracle():
     got = [(tuple(boxes[6 * i:6 * i + 3]), tuple(boxes[6 * i + 3:6 * i + 6])) for i in range(cnt.value)]
     want = oregrid.child_boxes(o, 0, 0.02, min_side=2, efficiency=0.7)
     assert cnt.value > 0 and got == want
+
+
+def test_init_from_levels_checks_its_sources():
+    """The two-source transfer (coarser levels from one hierarchy, the new finest level from another) is
+    planned on the host: it needs the destination's lower levels in `below`, the new level as the
+    destination's finest one and one precision; the one-source form is its special case."""
+    _lib()
+    from paper_1112_1710_amd import FP32, FP64, AmrxError
+    old = binding.Hierarchy(H.small_three_level(), FP64, device=None)
+    b1 = [(1, (4, 4, 4), (20, 20, 20))]
+    b2 = [(2, (12, 12, 12), (24, 24, 24))]
+    root = [p for p in H.small_three_level().patches if p[0] == 0]
+    cur = binding.Hierarchy(H.HierarchySpec(root_n=(16, 16, 16), patches=root + b1), FP64, device=None)
+    dst = binding.Hierarchy(H.HierarchySpec(root_n=(16, 16, 16), patches=root + b1 + b2), FP64, device=None)
+    assert dst.init_from_bytes(old, 2, below=cur) > 0
+    assert cur.init_from_bytes(old, 1) > 0          # one source: the root is shared
+    for args in ((old, 2, old), (old, 1, cur)):
+        with pytest.raises(AmrxError) as ei:
+            dst.init_from_bytes(args[0], args[1], below=args[2])
+        assert ei.value.code == -1
+    cur32 = binding.Hierarchy(H.HierarchySpec(root_n=(16, 16, 16), patches=root + b1), FP32, device=None)
+    with pytest.raises(AmrxError) as ei:
+        dst.init_from_bytes(old, 2, below=cur32)
+    assert ei.value.code == -1

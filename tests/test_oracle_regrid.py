@@ -205,3 +205,108 @@ def test_uniform_state_stays_uniform():
     for d in range(3):
         m = new._closure_mask(p, d)
         assert np.max(np.abs(p.faces[d][m] - ref.faces[d][m])) < 1e-14
+
+
+# ---------------------------------------------------------------------------------------------
+# regridding every level from a given one, coarse to fine
+# ---------------------------------------------------------------------------------------------
+def _bumped_three_level(seed=51, centre=(0.28, 0.27, 0.25), width=0.06):
+    """The three-level test hierarchy with a density bump inside its old level-2 patches."""
+    o = amr.build(H.small_three_level(), SmoothField(seed))
+    for p in o.patches:
+        n = o.nl(p.level)
+        c = [(np.arange(p.lo[a] - G, p.hi[a] + G + 1) + 0.5) / n[a] for a in range(3)]
+        z, y, x = np.meshgrid(c[2], c[1], c[0], indexing="ij")
+        r2 = (x - centre[0]) ** 2 + (y - centre[1]) ** 2 + (z - centre[2]) ** 2
+        p.cells[0] *= 1.0 + 0.6 * np.exp(-r2 / width ** 2)
+    return o
+
+
+def _check_new_level(old, new, level, eps):
+    """Nesting, flag coverage, copied overlaps, conservative prolongation and div B of new level `level`."""
+    parents = new.level_patches(level - 1)
+    kids = new.level_patches(level)
+    for p in kids:
+        m = p.parent
+        assert m in parents
+        # inside the parent's interior shrunk by one parent cell
+        assert np.all(p.lo >= 2 * (m.lo + 1)) and np.all(p.hi <= 2 * (m.hi - 1))
+    # every buffered flag of a parent (off its boundary layer) lies under a child
+    for m in parents:
+        n = m.n
+        f = regrid.buffer_flags(regrid.flag_cells(m.cells[0][G:G + n[2], G:G + n[1], G:G + n[0]], eps))
+        f[:1] = f[-1:] = False
+        f[:, :1] = f[:, -1:] = False
+        f[:, :, :1] = f[:, :, -1:] = False
+        cov = np.zeros(f.shape, dtype=bool)
+        for p in kids:
+            if p.parent is m:
+                lo, hi = p.lo // 2 - m.lo, p.hi // 2 - m.lo
+                cov[lo[2]:hi[2], lo[1]:hi[1], lo[0]:hi[0]] = True
+        assert np.all(cov[f])
+    copied = prolonged = 0
+    for p in kids:
+        po = p.origin()
+        under = np.zeros(p.shape, dtype=bool)
+        for q in old.level_patches(level):
+            lo, hi = np.maximum(p.lo, q.lo), np.minimum(p.hi, q.hi)
+            if np.any(hi <= lo):
+                continue
+            qo = q.origin()
+            ps = tuple(slice(int(lo[a] - po[a]), int(hi[a] - po[a])) for a in (2, 1, 0))
+            qs = tuple(slice(int(lo[a] - qo[a]), int(hi[a] - qo[a])) for a in (2, 1, 0))
+            assert np.array_equal(p.cells[(slice(None),) + ps], q.cells[(slice(None),) + qs])
+            under[ps] = True
+            copied += int(np.prod(hi - lo))
+        # prolongated parent cells restrict back to the (new) parent
+        m = p.parent
+        mo = m.origin()
+        for cz in range(p.n[2] // 2):
+            for cy in range(p.n[1] // 2):
+                for cx in range(p.n[0] // 2):
+                    fz, fy, fx = G + 2 * cz, G + 2 * cy, G + 2 * cx
+                    if under[fz, fy, fx]:
+                        continue
+                    g = p.lo // 2 + np.array([cx, cy, cz]) - mo
+                    mean = p.cells[:, fz:fz + 2, fy:fy + 2, fx:fx + 2].mean(axis=(1, 2, 3))
+                    ref = m.cells[:, g[2], g[1], g[0]]
+                    assert np.max(np.abs(mean - ref)) <= 1e-14 * np.max(np.abs(ref))
+                    prolonged += 8
+        i = new._interior_mask(p)
+        div = amr.mhd.divergence(p.faces, new.dxv(level))
+        assert np.max(np.abs(div[i])) * new.dx(level) < 1e-13
+    return copied, prolonged
+
+
+def test_regrid_levels_lays_every_level_over_the_new_flags():
+    old = _bumped_three_level()
+    new = regrid.regrid_levels(old, 0.2, min_side=4)
+    assert new.nlevels == 3
+    # the root is untouched
+    assert np.array_equal(new.patches[0].cells, old.patches[0].cells)
+    assert all(np.array_equal(a, b) for a, b in zip(new.patches[0].faces, old.patches[0].faces))
+    for level in (1, 2):
+        copied, prolonged = _check_new_level(old, new, level, 0.2)
+        assert copied > 0 and prolonged > 0, (level, copied, prolonged)
+
+
+def test_regrid_levels_from_the_finest_keeps_the_coarser_levels():
+    old = _bumped_three_level()
+    new = regrid.regrid_levels(old, 0.2, min_side=4, from_level=2)
+    for p, q in zip(new.patches, old.patches):
+        if q.level == 2 or p.level == 2:
+            break
+        assert p.level == q.level and np.array_equal(p.lo, q.lo) and np.array_equal(p.hi, q.hi)
+        assert np.array_equal(p.cells, q.cells)
+    assert len(new.level_patches(1)) == len(old.level_patches(1))
+    _check_new_level(old, new, 2, 0.2)
+
+
+def test_regrid_levels_ends_at_a_level_without_flags():
+    old = _bumped_three_level()
+    new = regrid.regrid_levels(old, 0.25, min_side=4)
+    assert new.nlevels == 2
+    _check_new_level(old, new, 1, 0.25)
+    flat = amr.build(H.small_three_level(), Uniform(1.0, (0.1, 0.0, 0.0), 1.0, (0.3, 0.2, 0.1)))
+    with pytest.raises(ValueError):
+        regrid.regrid_levels(flat, 0.01)
