@@ -87,6 +87,9 @@ def parse():
     ap.add_argument("--staged", action="store_true", help="run every advance stage as a separate kernel")
     ap.add_argument("--regrid-eps", type=float, default=None,
                     help="after the timed steps, time one regrid of the finest level with this flag threshold")
+    ap.add_argument("--regrid-from", type=int, default=None,
+                    help="with --regrid-eps: regrid every level from this one up, coarse to fine, instead of the "
+                         "finest level alone")
     ap.add_argument("--ghosts", default="extended", choices=["extended", "time"],
                     help="later-substep ghost data of refined patches: extended ghost regions (default) or the "
                          "coarse time derivative")
@@ -254,6 +257,32 @@ def time_regrid(h, eps, torch, min_side=4, efficiency=0.7):
     return rep
 
 
+def time_regrid_levels(h, eps, from_level, torch, min_side=4, efficiency=0.7):
+    """Wall time of one regrid of every level from `from_level` up, coarse to fine (per level: GPU
+    flags of the new level below, host clustering, the level's hierarchy built and filled)."""
+    import time
+    from paper_1112_1710_amd.regrid import regrid_levels
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    try:
+        h2 = regrid_levels(h, eps, min_side, efficiency, from_level=from_level)
+    except ValueError as e:  # nothing flagged below the first regridded level
+        return {"eps": eps, "from_level": from_level, "error": str(e)}
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    per = {}
+    for lv, _, _ in h.spec.patches:
+        per.setdefault(lv, [0, 0])[0] += 1
+    for lv, _, _ in h2.spec.patches:
+        per.setdefault(lv, [0, 0])[1] += 1
+    rep = {"eps": eps, "from_level": from_level, "levels_before": h.levels, "levels_after": h2.levels,
+           "patches_per_level_before_after": {str(k): v for k, v in sorted(per.items())},
+           "cells_after": h2.spec.cells(), "total_ms": round((t1 - t0) * 1e3, 2)}
+    del h2
+    torch.cuda.empty_cache()
+    return rep
+
+
 def state_reset(h, spec, field, precision):
     """A callable that re-uploads the initial state (generated once, kept on the host in the state's dtype)."""
     import numpy as np
@@ -372,7 +401,10 @@ def main():
     per_class = {k: round(v[0] / args.steps, 4) for k, v in timing.items() if v[1]}
     regrid_report = None
     if args.regrid_eps is not None and spec.levels() > 1:
-        regrid_report = time_regrid(h, args.regrid_eps, torch)
+        if args.regrid_from is None:
+            regrid_report = time_regrid(h, args.regrid_eps, torch)
+        else:
+            regrid_report = time_regrid_levels(h, args.regrid_eps, args.regrid_from, torch)
     reset = None  # the closure holds the hierarchy
     del h
     torch.cuda.empty_cache()
