@@ -410,14 +410,76 @@ void stage_regions(int stage, int axis, const int lo[3], const int hi[3], int rl
   }
 }
 
+// Buckets of a level's index space (periodic), each listing the patches whose boxes meet it;
+// neighbour searches visit only the buckets around a patch instead of every patch of its level.
+struct LevelBuckets {
+  int n[3] = {1, 1, 1};   // level cells per axis
+  int nb[3] = {1, 1, 1};  // buckets per axis
+  static constexpr int B = 16;
+  std::vector<std::vector<int>> ids;
+  std::vector<int> mark;  // per patch: last query that listed it
+  int query = 0;
+};
+
+void build_buckets(const amrx_hier* h, int level, LevelBuckets& L) {
+  for (int a = 0; a < 3; ++a) {
+    L.n[a] = nl_of(h, level, a);
+    L.nb[a] = (L.n[a] + LevelBuckets::B - 1) / LevelBuckets::B;
+  }
+  L.ids.assign((size_t)L.nb[0] * L.nb[1] * L.nb[2], {});
+  L.mark.assign(h->P.size(), -1);
+  for (int q : h->lev[level]) {
+    const HPatch& Q = h->P[q];
+    for (int bz = Q.lo[2] / LevelBuckets::B; bz <= (Q.hi[2] - 1) / LevelBuckets::B; ++bz)
+      for (int by = Q.lo[1] / LevelBuckets::B; by <= (Q.hi[1] - 1) / LevelBuckets::B; ++by)
+        for (int bx = Q.lo[0] / LevelBuckets::B; bx <= (Q.hi[0] - 1) / LevelBuckets::B; ++bx)
+          L.ids[((size_t)bz * L.nb[1] + by) * L.nb[0] + bx].push_back(q);
+  }
+}
+
+// Patches of p's level (ascending ids) whose box, or a periodic image of it, meets p's box grown
+// by `reach` cells on every side; p itself included.
+std::vector<int> near_patches(const amrx_hier* h, LevelBuckets& L, int pid, int reach) {
+  const HPatch& p = h->P[pid];
+  std::vector<int> bl[3];
+  for (int a = 0; a < 3; ++a) {
+    const int lo = p.lo[a] - reach, hi = p.hi[a] + reach;  // cells [lo, hi)
+    std::vector<char> seen(L.nb[a], 0);
+    if (hi - lo >= L.n[a]) {
+      for (int b = 0; b < L.nb[a]; ++b) bl[a].push_back(b);
+      continue;
+    }
+    for (int x = lo; x < hi; ++x) {
+      const int w = ((x % L.n[a]) + L.n[a]) % L.n[a];
+      const int b = w / LevelBuckets::B;
+      if (!seen[b]) {
+        seen[b] = 1;
+        bl[a].push_back(b);
+      }
+    }
+  }
+  ++L.query;
+  std::vector<int> out;
+  for (int bz : bl[2])
+    for (int by : bl[1])
+      for (int bx : bl[0])
+        for (int q : L.ids[((size_t)bz * L.nb[1] + by) * L.nb[0] + bx])
+          if (L.mark[q] != L.query) {
+            L.mark[q] = L.query;
+            out.push_back(q);
+          }
+  std::sort(out.begin(), out.end());
+  return out;
+}
+
 // Same-level sources of every padded cell and face of patch p (lowest id wins, p itself first).
-void build_sources(amrx_hier* h, int pid) {
+void build_sources(amrx_hier* h, int pid, const std::vector<int>& near) {
   HPatch& p = h->P[pid];
   auto& S = h->src[pid];
   for (int k = 0; k < 4; ++k) S[k].assign(p.vol, -1);
   std::vector<int> cands;
   cands.push_back(pid);
-  for (int q : h->lev[p.level])
+  for (int q : near)
     if (q != pid) cands.push_back(q);
   int plo[3], phi[3];
   for (int a = 0; a < 3; ++a) {
@@ -653,9 +715,9 @@ void build_parent(amrx_hier* h, int mid, std::vector<int>& covmap) {
   }
 }
 
-void build_syncs(amrx_hier* h, int pid) {
+void build_syncs(amrx_hier* h, int pid, const std::vector<int>& near) {
   const HPatch& p = h->P[pid];
-  for (int q : h->lev[p.level]) {
+  for (int q : near) {
     const HPatch& Q = h->P[q];
     for (int sz = -1; sz <= 1; ++sz)
       for (int sy = -1; sy <= 1; ++sy)
@@ -945,7 +1007,14 @@ int finalize_impl(amrx_hier* h) {
   h->fcorr_p.assign(np, {});
   h->ecorr_p.assign(np, {});
   h->sync_p.assign(np, {});
-  for (int id = 0; id < np; ++id) build_sources(h, id);
+  // neighbours within reach of every patch's padded region (faces included)
+  std::vector<std::vector<int>> near(np);
+  for (int l = 0; l < h->nlev; ++l) {
+    LevelBuckets L;
+    build_buckets(h, l, L);
+    for (int id : h->lev[l]) near[id] = near_patches(h, L, id, G + 1);
+  }
+  for (int id = 0; id < np; ++id) build_sources(h, id, near[id]);
   for (int id = 0; id < np; ++id) {
     if (h->P[id].level == 0) continue;
     if (h->time_ghosts) {
@@ -1055,7 +1124,7 @@ int finalize_impl(amrx_hier* h) {
     h->sync_b[l].first = (int)h->syncs.size();
     for (int id : h->lev[l]) {
       h->sync_p[id].first = (int)h->syncs.size();
-      build_syncs(h, id);
+      build_syncs(h, id, near[id]);
       h->sync_p[id].count = (int)h->syncs.size() - h->sync_p[id].first;
     }
     h->sync_b[l].count = (int)h->syncs.size() - h->sync_b[l].first;
