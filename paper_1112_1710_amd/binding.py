@@ -96,6 +96,10 @@ def load_library(path=LIB_PATH):
         return _lib
     if not os.path.exists(path):
         raise ImportError(f"libamrx.so not built at {path}; run __graft_entry__.build()")
+    # torch carries its own HIP runtime; loading torch first makes the library's HIP dependency
+    # resolve to that copy.  Loaded the other way round, the process maps two runtimes and the
+    # library's one finds no device.
+    import torch  # noqa: F401
     lib = C.CDLL(path)
     for name, (args, res) in EXPORTS.items():
         fn = getattr(lib, name)
