@@ -505,3 +505,16 @@ def test_init_from_levels_checks_its_sources():
     with pytest.raises(AmrxError) as ei:
         dst.init_from_bytes(old, 2, below=cur32)
     assert ei.value.code == -1
+
+
+def test_library_binds_to_the_hip_runtime_torch_loads():
+    """Loading the library maps exactly one HIP runtime into the process (torch's): a second copy,
+    mapped when the library is loaded before torch, finds no device."""
+    import subprocess
+    import sys
+    _lib()
+    code = ("from paper_1112_1710_amd import binding; binding.load_library(); "
+            "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
+    out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
+    assert out.returncode == 0, out.stderr
+    assert out.stdout.strip() == "1"
