@@ -513,7 +513,7 @@ def test_library_binds_to_the_hip_runtime_torch_loads():
     import subprocess
     import sys
     _lib()
-    code = ("from paper_1112_1710_amd import binding; binding.load_library(); "
+    code = ("from paper_1112_1710_amd import binding; binding.load_library(); import torch; "
             "print(len({l.split()[-1] for l in open('/proc/self/maps') if 'libamdhip64' in l}))")
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
