@@ -105,7 +105,7 @@ def test_fused_matches_staged_bit_for_bit(prec, tile):
     assert b.diag()["phys_flag"] == 0
 
 
-@pytest.mark.parametrize("name", ["root_tiled", "single32", "small_three_level"])
+@pytest.mark.parametrize("name", ["root_tiled", "single32", "small_three_level", "minimal_patches"])
 def test_fused_plain_and_graph_schedules(name):
     spec = H.single_patch(32) if name == "single32" else getattr(H, name)()
     _say("fused plain/graph", name)

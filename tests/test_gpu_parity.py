@@ -65,7 +65,8 @@ def test_uniform_32_cube_ten_steps_fp64():
         assert np.all(err <= 1e-12), (step, dict(zip(FIELDS, err)))
 
 
-@pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "root_tiled", "block_two_level"])
+@pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "root_tiled", "block_two_level",
+                                  "minimal_patches"])
 @pytest.mark.parametrize("precision", [FP64, FP32])
 def test_hierarchy_root_step(name, precision):
     spec = getattr(H, name)()
@@ -165,7 +166,7 @@ def _box_mask(shape, lo, hi, axis=None):
     return m
 
 
-@pytest.mark.parametrize("name", ["small_three_level", "root_tiled", "block_two_level"])
+@pytest.mark.parametrize("name", ["small_three_level", "root_tiled", "block_two_level", "minimal_patches"])
 def test_ghost_copy_bit_exact(name):
     """Same-level ghost copies equal the oracle's source maps bit for bit: 2 layers on level 0 and
     before substep 1; before substep 0 of a refined level the region its stencil reads (the update

@@ -70,7 +70,7 @@ def test_root_must_be_tiled():
         binding.Hierarchy(spec, device=None)
 
 
-@pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "root_tiled"])
+@pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "root_tiled", "minimal_patches"])
 def test_ghost_sources_match_oracle_bit_exact(name):
     _lib()
     spec = getattr(H, name)()
@@ -82,7 +82,7 @@ def test_ghost_sources_match_oracle_bit_exact(name):
             assert np.array_equal(h.debug_sources(pid, 1 + d), o.face_src[pid][d])
 
 
-@pytest.mark.parametrize("name", ["small_two_level", "small_three_level"])
+@pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "minimal_patches"])
 def test_prolongation_cells_match_oracle(name):
     _lib()
     spec = getattr(H, name)()

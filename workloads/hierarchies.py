@@ -197,6 +197,19 @@ def small_three_level(root=16):
     return spec
 
 
+def minimal_patches(root=8):
+    """Edge cases of patch size: an 8^3 root (ghost layers half its width), refined patches of the
+    minimum width R = 2 (a 2^3 cube and a 2 x 8 x 2 slab), a corner-touching and a face-sharing
+    sibling, and a 2^3 grandchild."""
+    spec = HierarchySpec(root_n=(root,) * 3, name=f"minimal patches {root}^3")
+    spec.patches.append((0, (0, 0, 0), (root,) * 3))
+    spec.patches.append((1, (2, 2, 2), (4, 4, 4)))
+    spec.patches.append((1, (4, 4, 4), (12, 12, 12)))
+    spec.patches.append((1, (12, 4, 4), (14, 12, 6)))
+    spec.patches.append((2, (10, 10, 10), (12, 12, 12)))
+    return spec
+
+
 def small_three_level_td(root=16):
     """Tiny three-level hierarchy whose level-2 patches keep their prolongation stencils inside
     data that is valid at the parent's new time (the parent's interior, or parent ghost cells a
