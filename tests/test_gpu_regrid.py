@@ -9,14 +9,14 @@ torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
 from oracle import amr, regrid as oregrid  # noqa: E402
-from paper_1112_1710_amd import BATCHED, FP32, FP64, Hierarchy  # noqa: E402
+from paper_1112_1710_amd import BATCHED, FP32, FP32_MIXED, FP64, Hierarchy  # noqa: E402
 from paper_1112_1710_amd.regrid import new_spec, regrid, regrid_levels  # noqa: E402
 from workloads import hierarchies as H  # noqa: E402
 from workloads.fields import G, SmoothField  # noqa: E402
 
 from ._common import FIELDS, rel_l1, upload_oracle_state  # noqa: E402
 
-TOL = {FP64: 1e-12, FP32: 1e-5}
+TOL = {FP64: 1e-12, FP32: 1e-5, FP32_MIXED: 1e-5}
 
 
 def _say(*a):
@@ -191,7 +191,7 @@ def test_regrid_full_size_two_level_fp32():
     assert np.all(err <= TOL[FP32]), dict(zip(FIELDS, err))
 
 
-@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("precision", [FP64, FP32, FP32_MIXED])
 @pytest.mark.parametrize("eps,levels", [(0.2, 3), (0.25, 2)])
 def test_regrid_levels_matches_oracle(precision, eps, levels):
     """Regrid levels 1 and 2 of a three-level hierarchy coarse to fine (level 2 over the flags of the new
