@@ -390,7 +390,7 @@ def test_autotune_search_and_cache(tmp_path, monkeypatch):
 
 
 @pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "small_three_level_td", "root_tiled",
-                                  "block_two_level", "two_level"])
+                                  "block_two_level", "two_level", "minimal_patches"])
 def test_time_ghost_nesting_rule_matches_oracle(name):
     """Coarse-time-derivative ghosts: the library accepts exactly the hierarchies the oracle accepts, and
     refined patches then update their interiors only, at both substeps."""
