@@ -41,6 +41,7 @@ WORDS_PER_UNIT = {
     "update": 26 + 8,    # U (5), fluxes (15), faces (3), edge EMFs (3) in; 8 out
     "copy": 2,           # one element in, one out
     "primhalf": 1,       # fused prim/bhalf/pred: the library reports its algorithmic words directly
+    "edgeupd": 1,        # fused edge/update: likewise
 }
 
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a
@@ -399,6 +400,12 @@ def main():
         else:
             roof = hbm
     per_class = {k: round(v[0] / args.steps, 4) for k, v in timing.items() if v[1]}
+    # the whole step against HBM: algorithmic bytes of every priced class that ran, over the step time (a lower
+    # bound: restriction, corrections, sync, prolongation and CFL are not priced)
+    priced = sorted(k for k in work if k in WORDS_PER_UNIT and work[k][1] > 0)
+    step_bytes = sum(work[k][0] * WORDS_PER_UNIT[k] * word for k in priced)
+    step_hbm = {"bytes_per_step": int(step_bytes), "achieved": round(step_bytes / sec / 1e9, 1), "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": round(step_bytes / sec / 1e9 / HBM_PEAK_GBS, 4), "classes": priced}
     regrid_report = None
     if args.regrid_eps is not None and spec.levels() > 1:
         if args.regrid_from is None:
@@ -437,6 +444,7 @@ def main():
                    "edge_update_stages": "staged" if args.staged or last is None else last,
                    "parallelism": "single GPU"},
         "roofline": roof,
+        "step_hbm": step_hbm,
         "kernel_ms_per_step": per_class,
     }
     if regrid_report is not None:
