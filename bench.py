@@ -284,6 +284,21 @@ def time_regrid_levels(h, eps, from_level, torch, min_side=4, efficiency=0.7):
     return rep
 
 
+def extended_overhead(h, spec):
+    """Cells advanced per root step (every patch's update region at each of its substeps, extended ghost
+    layers included) over the zone-updates counted (interior cells only)."""
+    done = 0
+    for pid, (lv, lo, hi) in enumerate(spec.patches):
+        subs = (0,) if lv == 0 else (0, 1)
+        for s in subs:
+            blo, bhi = h.update_box(pid, s)
+            vol = 1
+            for a in range(3):
+                vol *= bhi[a] - blo[a]
+            done += vol * (2 ** lv // len(subs))
+    return done / spec.zone_updates_per_root_step()
+
+
 def state_reset(h, spec, field, precision):
     """A callable that re-uploads the initial state (generated once, kept on the host in the state's dtype)."""
     import numpy as np
@@ -412,6 +427,7 @@ def main():
             regrid_report = time_regrid(h, args.regrid_eps, torch)
         else:
             regrid_report = time_regrid_levels(h, args.regrid_eps, args.regrid_from, torch)
+    overhead = extended_overhead(h, spec)
     reset = None  # the closure holds the hierarchy
     del h
     torch.cuda.empty_cache()
@@ -442,6 +458,7 @@ def main():
                    "steps_from": "t=0 state before every step" if steps_from_t0 else "consecutive steps",
                    "first_stages": "staged" if args.staged or tiles is None else tiles,
                    "edge_update_stages": "staged" if args.staged or last is None else last,
+                   "extended_ghost_overhead": round(overhead, 4),
                    "parallelism": "single GPU"},
         "roofline": roof,
         "step_hbm": step_hbm,
