@@ -52,3 +52,42 @@ def max_abs_interior(h, o):
             mk = o._closure_mask(p, d)
             worst = max(worst, float(np.max(np.abs(faces[d][mk] - p.faces[d][mk]))))
     return worst
+
+
+def max_rel(h, o):
+    """Per-field element-wise error: max |q_gpu - q_ref| over all patch interiors (cells) and
+    interior closures (faces), divided by max |q_ref| of that field; a momentum or field
+    component is measured against the largest magnitude of its vector's components, so a
+    component that is exactly zero in the reference (e.g. m_z of a plane-parallel state) is
+    still judged on the vector's scale.  Unlike rel_l1 this sees a localized error, such as one
+    at a coarse/fine corner, whatever the patch sizes."""
+    err = np.zeros(8)
+    ref = np.zeros(8)
+    for pid, p in enumerate(o.patches):
+        cells, faces = h.download(pid)
+        m = o._interior_mask(p)
+        for q in range(5):
+            err[q] = max(err[q], float(np.max(np.abs(cells[q][m] - p.cells[q][m]))))
+            ref[q] = max(ref[q], float(np.max(np.abs(p.cells[q][m]))))
+        for d in range(3):
+            mk = o._closure_mask(p, d)
+            err[5 + d] = max(err[5 + d], float(np.max(np.abs(faces[d][mk] - p.faces[d][mk]))))
+            ref[5 + d] = max(ref[5 + d], float(np.max(np.abs(p.faces[d][mk]))))
+    den = ref.copy()
+    for group in ((1, 2, 3), (5, 6, 7)):
+        top = max(ref[q] for q in group)
+        for q in group:
+            den[q] = top
+    return err / np.maximum(den, 1e-300)
+
+
+def assert_parity(h, o, tol, what=""):
+    """Both bars of a per-step comparison: relative L1 per field and the element-wise bound, each
+    <= tol (1e-12 FP64, 1e-5 FP32)."""
+    l1 = rel_l1(h, o)
+    mx = max_rel(h, o)
+    print("parity", what, "rel-L1 max %.2e, element-wise max %.2e" % (float(np.max(l1)), float(np.max(mx))),
+          flush=True)
+    assert np.all(l1 <= tol), ("rel-L1", what, dict(zip(FIELDS, l1)))
+    assert np.all(mx <= tol), ("element-wise", what, dict(zip(FIELDS, mx)))
+    return l1, mx

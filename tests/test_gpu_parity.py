@@ -18,7 +18,7 @@ from paper_1112_1710_amd import BATCHED, FP32, FP32_MIXED, FP64, GRAPH, PLAIN, A
 from workloads import hierarchies as H  # noqa: E402
 from workloads.fields import G, SmoothField, Uniform, low_beta  # noqa: E402
 
-from ._common import FIELDS, max_abs_interior, oracle_from, rel_l1, upload_oracle_state  # noqa: E402
+from ._common import FIELDS, assert_parity, max_abs_interior, oracle_from, rel_l1, upload_oracle_state  # noqa: E402
 
 TOL = {FP64: 1e-12, FP32: 1e-5, FP32_MIXED: 1e-5}
 
@@ -47,8 +47,7 @@ def test_single_patch_step(precision, mode):
     assert abs(dt_h - dt_o) <= (1e-13 if precision == FP64 else 1e-6) * dt_o
     o.root_step(dt_o)
     h.step(mode, dt_o)
-    err = rel_l1(h, o)
-    assert np.all(err <= TOL[precision]), dict(zip(FIELDS, err))
+    assert_parity(h, o, TOL[precision], "single patch")
 
 
 def test_uniform_32_cube_ten_steps_fp64():
@@ -61,8 +60,7 @@ def test_uniform_32_cube_ten_steps_fp64():
         upload_oracle_state(h, o)
         o.root_step(dt)
         h.step(PLAIN, dt)
-        err = rel_l1(h, o)
-        assert np.all(err <= 1e-12), (step, dict(zip(FIELDS, err)))
+        assert_parity(h, o, 1e-12, "32^3 step %d" % step)
 
 
 @pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "root_tiled", "block_two_level",
@@ -75,8 +73,7 @@ def test_hierarchy_root_step(name, precision):
     dt = o.cfl_dt()
     o.root_step(dt)
     h.step(BATCHED, dt)
-    err = rel_l1(h, o)
-    assert np.all(err <= TOL[precision]), dict(zip(FIELDS, err))
+    assert_parity(h, o, TOL[precision], name)
     d = h.diag()
     assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0
     assert d["phys_flag"] == 0.0
@@ -462,8 +459,7 @@ def test_time_ghost_root_step(name, precision):
     dt = o.cfl_dt()
     o.root_step(dt)
     h.step(BATCHED, dt)
-    err = rel_l1(h, o)
-    assert np.all(err <= TOL[precision]), dict(zip(FIELDS, err))
+    assert_parity(h, o, TOL[precision], name + " time ghosts")
     d = h.diag()
     assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
 

@@ -245,6 +245,54 @@ def test_ghost_sources_hold_the_periodic_image():
             assert np.all(gq >= q.lo) and np.all(gq < q.hi)
 
 
+def _image_axis(g, lo, hi, n, closure):
+    """Per 1-D global index g: does some periodic image g + k n lie in [lo, hi) ([lo, hi] for a
+    face's own axis)?  Tried for every shift k that can matter (|k| <= 2)."""
+    ok = np.zeros(g.shape, dtype=bool)
+    for k in range(-2, 3):
+        x = g + k * n
+        ok |= (x >= lo) & ((x <= hi) if closure else (x < hi))
+    return ok
+
+
+@pytest.mark.parametrize("name", ["small_two_level", "small_three_level", "root_tiled", "minimal_patches"])
+def test_ghost_sources_brute_force_over_periodic_images(name):
+    """Every padded cell and face of every patch, enumerated in global coordinates over all
+    periodic shifts (independent of the map builder): the source is the patch itself if an
+    image lies in its interior (closure, for faces), else the lowest-id same-level patch with
+    such an image, else none; the stored entry must name that patch and an entry of it holding
+    a periodic image of the same point.  Faces reach one entry further than cells on their own
+    axis, so the last face plane of the padded box is included."""
+    h = amr.build(getattr(H, name)())
+    for p in h.patches:
+        nl = h.nl(p.level)
+        Z, Y, X = p.shape
+        org = p.origin()
+        coord = [np.arange((X, Y, Z)[a]) + org[a] for a in range(3)]
+        same = [p] + [q for q in h.level_patches(p.level) if q is not p]
+        for kind in range(4):                       # 0 = cells, 1 + d = faces normal to d
+            d = kind - 1
+            src = h.cell_src[p.id] if kind == 0 else h.face_src[p.id][d]
+            valid = [coord[a] < p.hi[a] + G + (1 if a == d else 0) for a in range(3)]
+            want = np.full(p.shape, -1, dtype=np.int64)
+            for q in same:
+                hit = [_image_axis(coord[a], q.lo[a], q.hi[a], nl[a], a == d) & valid[a] for a in range(3)]
+                m = hit[2][:, None, None] & hit[1][None, :, None] & hit[0][None, None, :]
+                want[m & (want < 0)] = q.id
+            got_q = np.where(src >= 0, src >> 32, -1)
+            assert np.array_equal(got_q, want), (name, p.id, kind)
+            for (z, y, x) in np.argwhere(src >= 0):
+                q = h.patches[int(src[z, y, x] >> 32)]
+                lin = int(src[z, y, x] & (2 ** 32 - 1))
+                qz, rem = divmod(lin, q.shape[1] * q.shape[2])
+                qy, qx = divmod(rem, q.shape[2])
+                gq = np.array([qx, qy, qz]) + q.origin()
+                g = np.array([x, y, z]) + org
+                assert np.all((g - gq) % nl == 0)
+                for a in range(3):
+                    assert q.lo[a] <= gq[a] and (gq[a] <= q.hi[a] if a == d else gq[a] < q.hi[a])
+
+
 def test_ghost_sources_follow_neighbour_inheritance():
     """Sec. 3.1: a child's same-level neighbours are children of its parent or of the parent's neighbours."""
     h = amr.build(H.small_three_level())

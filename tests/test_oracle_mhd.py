@@ -295,3 +295,78 @@ def test_brio_wu_self_convergence():
         errs.append(np.mean(np.abs(u[0] - r[0])))
     orders = [math.log2(errs[i] / errs[i + 1]) for i in range(len(errs) - 1)]
     assert min(orders) > 0.6, (errs, orders)
+
+
+def _degenerate_family(eps, shear):
+    """States at HLLD's degenerate limit as eps -> 0: normal field dominant over sound
+    (Bn^2 / rho > gamma p / rho), transverse field eps on both sides, equal rho, u_n and
+    total pressure (so the contact speed equals u_n and both star-state denominators
+    rho (S - u)(S - S_M) - Bn^2 shrink like eps^2).  ``shear`` jumps the transverse velocity."""
+    wl = np.array([1.0, 0.2, 0.1, -0.05, 0.1, 1.0, eps, 0.5 * eps])[:, None]
+    wr = wl.copy()
+    if shear:
+        wr[2], wr[3] = -0.3, 0.25
+    return wl, wr
+
+
+@pytest.mark.parametrize("shear", [False, True])
+def test_hlld_degenerate_branch_is_the_limit_of_the_general_formulas(monkeypatch, shear):
+    """Miyoshi & Kusano's star-state formulas for v*_t and B*_t become 0/0 when the
+    Alfven and fast waves coincide (B_t -> 0 with Bn^2 >= gamma p).  With S_M = u their
+    limits are v*_t = v_t and B*_t = B_t, so the degenerate branch must agree with the
+    general formulas on both sides of its threshold and for both signs of B_t (no jump),
+    and consistency F(U, U) = F(U) must hold there."""
+    eps = np.concatenate([np.geomspace(3e-3, 1e-6, 40), -np.geomspace(3e-3, 1e-6, 40)])
+    f_branch, f_general = [], []
+    for e in eps:
+        wl, wr = _degenerate_family(e, shear)
+        f_branch.append(mhd.hlld(wl, wr, wl[5], 0, GAM)[:, 0])
+        if not shear:
+            ref = mhd.flux(wl, 0, GAM)[:, 0]
+            assert np.max(np.abs(f_branch[-1] - ref) / (1.0 + np.abs(ref))) < 1e-13
+    monkeypatch.setattr(mhd, "DEGEN_REL", 0.0)     # general formulas everywhere (den != 0 here)
+    for e in eps:
+        wl, wr = _degenerate_family(e, shear)
+        f_general.append(mhd.hlld(wl, wr, wl[5], 0, GAM)[:, 0])
+    f_branch, f_general = np.array(f_branch), np.array(f_general)
+    # the smallest |eps| lie well inside the threshold: |den| / (rho (S - u)^2) ~ 1.2 eps^2 < 1e-8
+    assert np.max(np.abs(f_branch - f_general)) < 1e-11
+    # and the flux is a smooth function of eps across the threshold (|eps| ~ 1e-4)
+    for sgn in (slice(0, 40), slice(40, 80)):
+        fb = f_branch[sgn]
+        steps = np.max(np.abs(np.diff(fb, axis=0)), axis=1)
+        de = np.abs(np.diff(eps[sgn]))
+        assert np.all(steps <= 10.0 * de + 1e-13), np.max(steps / de)
+
+
+def test_hlld_degenerate_branch_taken():
+    """Below the threshold the star states must come from the degenerate branch: a branch that
+    returned different transverse values would change the flux by O(1)."""
+    wl, wr = _degenerate_family(1e-6, True)
+    f = mhd.hlld(wl, wr, wl[5], 0, GAM)
+    # the flux sits between the two physical fluxes' transverse momenta in magnitude (finite, bounded)
+    assert np.all(np.isfinite(f))
+    fl, fr = mhd.flux(wl, 0, GAM), mhd.flux(wr, 0, GAM)
+    assert np.all(np.abs(f) <= np.maximum(np.abs(fl), np.abs(fr)) + 2.0)
+
+
+def test_fast_speed_is_the_flux_jacobian_spectral_radius():
+    """For random states and directions n the largest and smallest eigenvalues of the projected
+    flux Jacobian sum_d n_d dF_d/dU are v.n +- c_f(n), with c_f taken with Bn = B.n."""
+    rng = np.random.default_rng(7)
+    for _ in range(40):
+        rho = rng.uniform(0.3, 3.0)
+        v = rng.uniform(-1.0, 1.0, 3)
+        p = rng.uniform(0.05, 3.0)
+        b = rng.uniform(-2.0, 2.0, 3)
+        nh = rng.normal(size=3)
+        nh /= np.linalg.norm(nh)
+        w = np.concatenate([[rho], v, [p], b])[:, None]
+        u = mhd.cons_from_prim(w, GAM)[:, 0]
+        lam = np.linalg.eigvals(_jacobian(u, nh)).real
+        vn = float(v @ nh)
+        bn = float(b @ nh)
+        cf = float(mhd.fast_speed(rho, p, float(b @ b), bn * bn, GAM))
+        scale = abs(vn) + cf
+        assert abs(lam.max() - (vn + cf)) < 1e-6 * scale, (lam, vn, cf)
+        assert abs(lam.min() - (vn - cf)) < 1e-6 * scale, (lam, vn, cf)
