@@ -39,7 +39,13 @@ Readings where the paper is silent (the solver is not described at all):
     transverse slopes unless the coarse face already holds same-level fine
     data; the 12 faces inside a coarse cell start from the mean of the two
     aligned outer faces and receive the least-norm correction that zeroes
-    the divergence of all 8 fine cells);
+    the divergence of all 8 fine cells); positivity fallback: when one of
+    the 8 fine cells of a coarse cell would get rho <= 0 or p <= 0 (its own
+    conserved values, with the cell-centred field of its prolongated faces;
+    limiting rho, m and E separately does not bound the kinetic energy by
+    the total energy across a strong shock), all 8 take the coarse cell's
+    conserved values instead (first-order, still conservative; the faces
+    keep their divergence-free values);
   * restriction: volume mean of cells, area mean of faces on the closure of
     each child box;
   * flux correction: at coarse faces with exactly one covered side the coarse
@@ -422,6 +428,22 @@ class Hierarchy:
     def _minmod(a, b):
         return np.where(a * b > 0.0, np.sign(a) * np.minimum(np.abs(a), np.abs(b)), 0.0)
 
+    @staticmethod
+    def positivity_fallback(p, fx, fy, fz, u0, gamma):
+        """After the limited-linear prolongation of one coarse cell into the fine cells
+        [fx, fx+2) x [fy, fy+2) x [fz, fz+2) of p (and of its faces), give all 8 fine cells the
+        coarse conserved values u0 if any of them has rho <= 0, p <= 0 or a non-finite value.
+        Returns True when it did."""
+        sl = (slice(fz, fz + 2), slice(fy, fy + 2), slice(fx, fx + 2))
+        u = p.cells[(slice(None),) + sl]
+        bc = mhd.cell_centred_b([f[fz:fz + 3, fy:fy + 3, fx:fx + 3] for f in p.faces])[:, :2, :2, :2]
+        with np.errstate(all='ignore'):
+            w = mhd.prim_from_cons(u, bc, gamma)
+        if np.all(np.isfinite(w)) and np.all(w[0] > 0.0) and np.all(w[4] > 0.0):
+            return False
+        p.cells[(slice(None),) + sl] = u0[:, None, None, None]
+        return True
+
     _interior_map = None
 
     @classmethod
@@ -569,6 +591,7 @@ class Hierarchy:
                         fidx[a2] += t2
                         # interior faces of an uncovered coarse cell never lie on a same-level closure
                         p.faces[d][fidx[2], fidx[1], fidx[0]] = inner[k]
+                    self.positivity_fallback(p, fx, fy, fz, u0, self.gamma)
 
     # ------------------------------------------------------------------ advance
     def region(self, p, substep):

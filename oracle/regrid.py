@@ -317,6 +317,7 @@ def _prolong_interior(h, p, own_c, own_f):
                     fidx[a1] += t1
                     fidx[a2] += t2
                     p.faces[d][fidx[2], fidx[1], fidx[0]] = inner[k]
+                amr.Hierarchy.positivity_fallback(p, fx, fy, fz, u0, h.gamma)
 
 
 def regrid_levels(old, eps, dtype=np.float64, min_side=4, efficiency=0.7, from_level=1):

@@ -132,7 +132,9 @@ def test_stale_ghosts_never_reach_the_interior():
 
 
 class _Linear:
-    """Linear cells and the divergence-free linear field B = (1 + x + 2y, 0.5 - y + 3z, 2 - x + 0.25 y)."""
+    """Linear cells and the divergence-free linear field B = (1 + x + 2y, 0.5 - y + 3z, 2 - x + 0.25 y);
+    the total energy 30 + x + y + z exceeds the kinetic plus magnetic energy everywhere on the test
+    boxes, so every prolongated child is physical and the positivity fallback stays inactive."""
 
     def patch(self, level, root_n, lo, hi):
         h, c, l = _coords(level, root_n, lo, hi)
@@ -140,7 +142,7 @@ class _Linear:
         c = [(np.arange(lo[a] - G, hi[a] + G + 1) + 0.5) * h[a] for a in range(3)]
         l = [np.arange(lo[a] - G, hi[a] + G + 1) * h[a] for a in range(3)]
         zz, yy, xx = np.meshgrid(c[2], c[1], c[0], indexing='ij')
-        cells = np.stack([1 + 0.5 * xx - 0.25 * yy + 0.125 * zz, 0.1 * xx, -0.2 * yy, 0.3 * zz, 3 + xx + yy + zz])
+        cells = np.stack([1 + 0.5 * xx - 0.25 * yy + 0.125 * zz, 0.1 * xx, -0.2 * yy, 0.3 * zz, 30 + xx + yy + zz])
         zl, yl, xl = np.meshgrid(l[2], l[1], l[0], indexing='ij')
         bx = 1 + xl + 2 * yy
         by = 0.5 - yl + 3 * zz
@@ -201,6 +203,57 @@ def test_prolongation_is_conservative_and_divergence_free():
                 fm = p.faces[0][fz:fz + 2, fy:fy + 2, fx].mean()
                 worst = max(worst, abs(fm - m.faces[0][ci[2], ci[1], ci[0]]))
     assert worst < 1e-14
+
+
+def _shock_like_parent(o, rows):
+    """Uniform state (rho 1, v 0, p 1, B (1, 0, 0)); along x on the given (y, z) rows of coarse cells
+    0, 1, 2 the momentum rises 0, a, 2a with p = 0.01 in all three (each coarse cell physical)."""
+    m = o.patches[0]
+    gam = o.gamma
+    for (y, z, a) in rows:
+        for i, mx in enumerate((0.0, a, 2.0 * a)):
+            X, Y, Z = G + i, G + y, G + z
+            m.cells[1, Z, Y, X] = mx
+            m.cells[4, Z, Y, X] = 0.5 * mx * mx + 0.5 + 0.01 / (gam - 1.0)
+    m.old_cells, m.old_faces = m.cells.copy(), [f.copy() for f in m.faces]
+
+
+def test_prolongation_positivity_fallback():
+    """A coarse cell whose limited-linear children would carry more kinetic than total energy
+    (momentum slope 3 at p = 0.01) hands its 8 children its own conserved values; a gentle
+    slope (0.1) keeps the linear children; both keep the coarse mean exactly."""
+    o = amr.build(H.small_two_level(), Uniform(1.0, (0, 0, 0), 1.0, (1, 0, 0)))
+    _shock_like_parent(o, [(4, 4, 3.0), (4, 5, 0.1)])
+    p = o.patches[1]                          # fine box (4,6,6)-(12,14,14): coarse x = 0, 1 are ghosts
+    o._prolong(p)
+    po = p.origin()
+
+    def children(cx, cy, cz):
+        f = 2 * np.array([cx, cy, cz]) - po
+        return p.cells[:, f[2]:f[2] + 2, f[1]:f[1] + 2, f[0]:f[0] + 2]
+
+    steep = children(1, 4, 4)
+    u0 = o.patches[0].cells[:, G + 4, G + 4, G + 1]
+    assert np.array_equal(steep, np.broadcast_to(u0[:, None, None, None], steep.shape))
+    gentle = children(1, 4, 5)
+    u1 = o.patches[0].cells[:, G + 5, G + 4, G + 1]
+    assert np.ptp(gentle[1]) > 0.04                       # linear momentum children: 0.1 +- 0.025
+    assert np.allclose(gentle.reshape(5, -1).mean(axis=1), u1, rtol=0, atol=1e-15)
+    # without the fallback the steep cell's children would be unphysical
+    bc = mhd.cell_centred_b(p.faces)
+    f = 2 * np.array([1, 4, 4]) - po
+    sl = (slice(f[2], f[2] + 2), slice(f[1], f[1] + 2), slice(f[0], f[0] + 2))
+    slope = 3.0
+    lin_mx = u0[1] + 0.25 * slope * np.array([-1.0, 1.0])
+    lin_e = u0[4] + 0.25 * min(u0[4] - o.patches[0].cells[4, G + 4, G + 4, G + 0],
+                              o.patches[0].cells[4, G + 4, G + 4, G + 2] - u0[4]) * np.array([-1.0, 1.0])
+    p_lin = (o.gamma - 1) * (lin_e - 0.5 * lin_mx ** 2 - 0.5 * float(np.max(bc[0][sl] ** 2)))
+    assert p_lin.min() < 0.0
+    # the pressure of every prolongated ghost cell is positive
+    w = mhd.prim_from_cons(p.cells, bc, o.gamma)
+    ghost = o.cell_src[p.id] < 0
+    ghost[:, :, -1] = ghost[:, -1, :] = ghost[-1, :, :] = False
+    assert np.all(w[4][ghost] > 0.0)
 
 
 def test_interior_face_map_zeroes_fine_divergence():
