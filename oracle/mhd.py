@@ -42,6 +42,7 @@ import numpy as np
 N_G = 2                      # stencil depth of one substep (cells)
 DEGEN_REL = 1e-8             # HLLD star-state degeneracy threshold (relative)
 BN_SKIP_REL = 1e-12          # HLLD: skip double-star states when Bn^2 <= this * (ptL + ptR)
+MASS_FLUX_ZERO = 1e-12       # HLLD: a mass flux at most this * max(rho) * max(|S|) is exactly zero
 
 
 class PhysicsError(RuntimeError):
@@ -139,9 +140,15 @@ def hlld(wl, wr, bn, d, gamma):
     Region selection: F_L if S_L >= 0, else F*_L if S*_L >= 0, else F**_L if
     S_M >= 0, else F**_R if S*_R >= 0, else F*_R if S_R >= 0, else F_R (ties
     go to the left-hand region).  Degenerate star states (Miyoshi & Kusano's
-    vanishing denominator) keep the transverse velocity and field unchanged;
+    vanishing denominator) keep the transverse velocity and field unchanged:
+    with S_M = u the general formulas tend to exactly these values as the
+    transverse field vanishes, so the switch introduces no jump;
     when Bn^2 is negligible against the total pressures the rotational waves
     collapse onto S_M and the double-star states are skipped.
+    A mass flux no larger than MASS_FLUX_ZERO * max(rho_L, rho_R) *
+    max(|S_L|, |S_R|) is set to exactly zero: it vanishes in exact arithmetic
+    (a stagnant face ahead of a flow front), and the edge EMFs choose their
+    upwind side by its sign, a choice that jumps at zero.
     """
     t1, t2 = (d + 1) % 3, (d + 2) % 3
     g1 = gamma - 1.0
@@ -229,7 +236,8 @@ def hlld(wl, wr, bn, d, gamma):
                  np.where(ssr >= 0.0, fssr,
                  np.where(sr >= 0.0, fsr, fr))))))
     out = np.zeros((8,) + rl.shape)
-    out[0] = f[0]
+    scale = np.maximum(rl, rr) * np.maximum(np.abs(sl), np.abs(sr))
+    out[0] = np.where(np.abs(f[0]) <= MASS_FLUX_ZERO * scale, 0.0, f[0])
     out[1 + d] = f[1]
     out[1 + t1] = f[2]
     out[1 + t2] = f[3]

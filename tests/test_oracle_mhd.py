@@ -370,3 +370,24 @@ def test_fast_speed_is_the_flux_jacobian_spectral_radius():
         scale = abs(vn) + cf
         assert abs(lam.max() - (vn + cf)) < 1e-6 * scale, (lam, vn, cf)
         assert abs(lam.min() - (vn - cf)) < 1e-6 * scale, (lam, vn, cf)
+
+
+def test_hlld_mass_flux_round_off_is_exactly_zero():
+    """States at rest whose pressures or densities differ by a few ulps (a stagnant face just ahead of
+    a flow front) have a mass flux that vanishes in exact arithmetic: it must come out exactly 0.0 in
+    either orientation, so that the sign-upwinded edge EMF takes the average; a genuine flow of
+    1e-9 of the signal speed is kept."""
+    w = np.array([1.0, 0.0, 0.0, 0.0, 1.0, 0.7, 0.7, 0.0])[:, None]
+    for k in range(1, 6):
+        wr = w.copy()
+        wr[4] = np.nextafter(1.0, 2.0) + k * 2.0 ** -52
+        wr[0] = 1.0 - k * 2.0 ** -53
+        for d in range(3):
+            f1 = mhd.hlld(w, wr, w[5 + d], d, GAM)
+            f2 = mhd.hlld(wr, w, w[5 + d], d, GAM)
+            assert f1[0, 0] == 0.0 and f2[0, 0] == 0.0
+    cf = float(mhd.fast_speed(1.0, 1.0, 0.98, 0.49, GAM))
+    slow = w.copy()
+    slow[1] = 1e-9 * cf
+    f = mhd.hlld(slow, slow, w[5], 0, GAM)
+    assert abs(f[0, 0] - 1e-9 * cf) < 1e-22
