@@ -293,7 +293,12 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
       for (int q = 0; q < 7; ++q) f[q] = f[q] + ss * (uss[q] - us[q]);
     }
   }
-  out[0] = f[0];
+  // a mass flux at round-off level of its scale max(rho) max(|S|) vanishes in exact arithmetic (a
+  // stagnant face ahead of a flow front); it is set to zero because the edge EMFs take their upwind
+  // side from its sign, which would otherwise follow the rounding (the same band in every
+  // precision: a wider one for float states moves the upwind choice at genuine small mass fluxes)
+  const R mscale = fmax(rl, rr) * fmax(fabs(sl), fabs(sr));
+  out[0] = fabs(f[0]) <= R(1e-12) * mscale ? R(0) : f[0];
   out[1 + D] = f[1];
   out[1 + T1] = f[2];
   out[1 + T2] = f[3];
@@ -1253,18 +1258,19 @@ __device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int f
   };
   const long long P0 = pr.pidx;
   const long long f0 = 2LL * pr.c[0] + 2LL * pr.c[1] * FS.s[1] + 2LL * pr.c[2] * FS.s[2];
-  // cells: conservative minmod-limited linear
+  // cells: conservative minmod-limited linear; child o = ox + 2 oy + 4 oz (written after the
+  // positivity check at the end, which needs the children's faces)
+  R cv[5][8], u0v[5];
   for (int m = 0; m < 5; ++m) {
     const long long u = m * MS.v;
     const R u0 = pv(u + P0);
     const R sx = minmod2(pv(u + P0 + MS.s[0]) - u0, u0 - pv(u + P0 - MS.s[0]));
     const R sy = minmod2(pv(u + P0 + MS.s[1]) - u0, u0 - pv(u + P0 - MS.s[1]));
     const R sz = minmod2(pv(u + P0 + MS.s[2]) - u0, u0 - pv(u + P0 - MS.s[2]));
-    for (int oz = 0; oz < 2; ++oz)
-      for (int oy = 0; oy < 2; ++oy)
-        for (int ox = 0; ox < 2; ++ox)
-          F[m * FS.v + f0 + ox + oy * FS.s[1] + oz * FS.s[2]] =
-              u0 + R(0.25) * (R(2 * ox - 1) * sx + R(2 * oy - 1) * sy + R(2 * oz - 1) * sz);
+    u0v[m] = u0;
+    for (int o = 0; o < 8; ++o)
+      cv[m][o] = u0 + R(0.25) * (R(2 * (o & 1) - 1) * sx + R(2 * ((o >> 1) & 1) - 1) * sy +
+                                 R(2 * ((o >> 2) & 1) - 1) * sz);
   }
   // faces: outer[d][s][t2][t1] with (t1, t2) the offsets along the two other axes in increasing order
   R outer[3][2][2][2];
@@ -1333,9 +1339,36 @@ __device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int f
         int o_lo = (t1 << a1) | (t2 << a2);
         int o_hi = o_lo | (1 << d);
         const R val = inner[d][t2][t1] + (phi[o_lo] - phi[o_hi]);
+        inner[d][t2][t1] = val;
         fb[f0 + FS.s[d] + t1 * FS.s[a1] + t2 * FS.s[a2]] = val;
       }
   }
+  // positivity fallback: limiting rho, m and E separately does not keep the kinetic energy below
+  // the total energy, so if any child has rho <= 0 or p <= 0 (its cell-centred field the mean of
+  // its two faces per axis; decided in double in every precision) all 8 children take the coarse
+  // cell's conserved values (first order, still conservative; the faces are kept)
+  bool ok = true;
+  const double gm1 = c.gamma - 1.0;
+  for (int o = 0; o < 8; ++o) {
+    const int oo[3] = {o & 1, (o >> 1) & 1, (o >> 2) & 1};
+    double mag = 0.0;
+    for (int d = 0; d < 3; ++d) {
+      int a1, a2;
+      other_axes(d, a1, a2);
+      const int t1 = oo[a1], t2 = oo[a2];
+      const double lowf = oo[d] == 0 ? (double)outer[d][0][t2][t1] : (double)inner[d][t2][t1];
+      const double highf = oo[d] == 0 ? (double)inner[d][t2][t1] : (double)outer[d][1][t2][t1];
+      const double bc = 0.5 * (lowf + highf);
+      mag += bc * bc;
+    }
+    const double rho = cv[0][o];
+    const double kin = 0.5 * ((double)cv[1][o] * cv[1][o] + (double)cv[2][o] * cv[2][o] + (double)cv[3][o] * cv[3][o]) / rho;
+    const double prs = gm1 * ((double)cv[4][o] - kin - 0.5 * mag);
+    ok = ok && rho > 0.0 && prs > 0.0 && isfinite(prs);
+  }
+  for (int m = 0; m < 5; ++m)
+    for (int o = 0; o < 8; ++o)
+      F[m * FS.v + f0 + (o & 1) + ((o >> 1) & 1) * FS.s[1] + ((o >> 2) & 1) * FS.s[2]] = ok ? cv[m][o] : u0v[m];
 }
 
 template <typename R>

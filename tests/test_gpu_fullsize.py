@@ -275,6 +275,31 @@ def test_deep_hierarchy_root_step_properties():
         assert abs(tot1[q] - tot0[q]) <= 1e-5 * scale, (q, tot0[q], tot1[q])
 
 
+@pytest.mark.parametrize("precision,steps", [(FP32, 20), (FP64, 3)])
+def test_deep_hierarchy_consecutive_root_steps(precision, steps):
+    """The deep 8-level blast runs consecutive root steps (graph-replayed) with no unphysical state:
+    the blast's outgoing shock crosses coarse/fine boundaries, where prolongation needs the positivity
+    fallback; composite mass and energy stay conserved to the state's round-off."""
+    from workloads.fields import Blast
+    spec, centre, _ = H.deep_blast_target()
+    _say("deep hierarchy, consecutive root steps", precision, steps)
+    h = Hierarchy(spec, precision)
+    h.set_field(Blast(centre))
+    s0, c0 = h.conservation()
+    t = 0.0
+    for k in range(steps):
+        t += h.step(GRAPH)
+        if k % 5 == 4:
+            _say("  root step", k + 1, "t", t)
+    s1, c1 = h.conservation()
+    d = h.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+    tot0, tot1 = s0 + c0, s1 + c1
+    tol = 1e-5 if precision == FP32 else 1e-12
+    for q in (0, 4):
+        assert abs(tot1[q] - tot0[q]) <= tol * abs(tot0[q]), (q, tot0[q], tot1[q])
+
+
 def test_uniform_512_sampled_windows_far_corner():
     """A 512^3 patch (521^3 padded entries: 64-bit intermediate offsets beyond 2^32 bytes), FP32: windows of
     one advance, including the far corner, recomputed by the oracle from the GPU's ghost-filled input."""
