@@ -11,6 +11,7 @@ Prints one JSON line.  Inputs are seeded synthetic states resident in HBM
 before the timed region starts.
 """
 import argparse
+import functools
 import json
 import os
 import sys
@@ -72,7 +73,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="two_level",
+    ap.add_argument("--workload", default="deep",
                     choices=["two_level", "uniform256", "uniform32", "deep", "lowbeta"])
     ap.add_argument("--report-steps", type=int, default=3,
                     help="root steps of the low-beta precision report (workload lowbeta)")
@@ -82,9 +83,16 @@ def parse():
                                                          "layered"])
     ap.add_argument("--pmc-calibration", action="store_true",
                     help="after the timed steps, copy a 512 MiB buffer once (reference dispatch for HBM counters)")
-    ap.add_argument("--plain-steps", type=int, default=4, help="steps of the FP64 per-patch-launch comparison")
+    ap.add_argument("--plain-steps", type=int, default=2, help="steps of the FP64 per-patch-launch comparison")
     ap.add_argument("--skip-plain", action="store_true")
     ap.add_argument("--skip-cpu", action="store_true")
+    ap.add_argument("--skip-precision", action="store_true",
+                    help="skip the FP32-with-targeted-FP64 timing and the per-step rel-L1 report")
+    ap.add_argument("--skip-secondary", action="store_true",
+                    help="skip the two-level secondary line of the deep workload")
+    ap.add_argument("--secondary-steps", type=int, default=10)
+    ap.add_argument("--cpu-patches", type=int, default=24,
+                    help="patches of the oracle's single-core sample (the pool runs two per worker)")
     ap.add_argument("--staged", action="store_true", help="run every advance stage as a separate kernel")
     ap.add_argument("--regrid-eps", type=float, default=None,
                     help="after the timed steps, time one regrid of the finest level with this flag threshold")
@@ -100,6 +108,7 @@ def parse():
     return ap.parse_args()
 
 
+@functools.lru_cache(maxsize=None)
 def workload(name):
     from workloads import hierarchies as H
     from workloads.fields import Blast, SmoothField
@@ -116,30 +125,33 @@ def workload(name):
     return spec, Blast(centre), "deep 8-level hierarchy (64^3 root, ~40M cells), off-centre blast"
 
 
-def _interior_fields(h, spec, gamma=5.0 / 3.0):
-    """Per patch: float64 interior arrays of rho, mx, my, mz, E, p and the three face fields (interior closures)."""
+def _patch_fields(h, spec, pid, gamma=5.0 / 3.0):
+    """Float64 interior arrays of rho, mx, my, mz, E, p and the three face fields (interior closures) of one patch."""
     import numpy as np
     G = 4
-    out = []
-    for pid, (_, lo, hi) in enumerate(spec.patches):
-        cells, faces = h.download(pid)
-        n = [hi[a] - lo[a] for a in range(3)]
-        sl = (slice(G, G + n[2]), slice(G, G + n[1]), slice(G, G + n[0]))
-        c = [cells[m][sl].astype(np.float64) for m in range(5)]
-        bc = []
-        fs = []
-        for d in range(3):
-            f = faces[d].astype(np.float64)
-            up = [slice(G, G + n[2]), slice(G, G + n[1]), slice(G, G + n[0])]
-            up[2 - d] = slice(G + 1, G + n[d] + 1)
-            bc.append(0.5 * (f[sl] + f[tuple(up)]))
-            cl = [slice(G, G + n[2]), slice(G, G + n[1]), slice(G, G + n[0])]
-            cl[2 - d] = slice(G, G + n[d] + 1)
-            fs.append(f[tuple(cl)])
-        pr = (gamma - 1.0) * (c[4] - 0.5 * (c[1] ** 2 + c[2] ** 2 + c[3] ** 2) / c[0]
-                              - 0.5 * (bc[0] ** 2 + bc[1] ** 2 + bc[2] ** 2))
-        out.append(c + [pr] + fs)
-    return out
+    _, lo, hi = spec.patches[pid]
+    cells, faces = h.download(pid)
+    n = [hi[a] - lo[a] for a in range(3)]
+    sl = (slice(G, G + n[2]), slice(G, G + n[1]), slice(G, G + n[0]))
+    c = [cells[m][sl].astype(np.float64) for m in range(5)]
+    bc = []
+    fs = []
+    for d in range(3):
+        f = faces[d].astype(np.float64)
+        up = [slice(G, G + n[2]), slice(G, G + n[1]), slice(G, G + n[0])]
+        up[2 - d] = slice(G + 1, G + n[d] + 1)
+        bc.append(0.5 * (f[sl] + f[tuple(up)]))
+        cl = [slice(G, G + n[2]), slice(G, G + n[1]), slice(G, G + n[0])]
+        cl[2 - d] = slice(G, G + n[d] + 1)
+        fs.append(f[tuple(cl)])
+    pr = (gamma - 1.0) * (c[4] - 0.5 * (c[1] ** 2 + c[2] ** 2 + c[3] ** 2) / c[0]
+                          - 0.5 * (bc[0] ** 2 + bc[1] ** 2 + bc[2] ** 2))
+    return c + [pr] + fs
+
+
+def _interior_fields(h, spec, gamma=5.0 / 3.0):
+    """Per patch: the arrays of _patch_fields."""
+    return [_patch_fields(h, spec, pid, gamma) for pid in range(len(spec.patches))]
 
 
 def lowbeta_report(spec, field, steps, torch):
@@ -198,30 +210,17 @@ def lowbeta_report(spec, field, steps, torch):
                                    for k, v in drift.items()}}
 
 
-def timed_steps(h, mode, steps, warmup, torch, reset=None):
-    """Mean wall time of one root step.  With `reset`, the initial state is restored before every step,
-    outside the timed region, and each step is bracketed by device synchronisations on its own."""
+def timed_steps(h, mode, steps, warmup, torch):
+    """Mean wall time of one root step over `steps` consecutive steps after `warmup` untimed ones."""
     for _ in range(warmup):
-        if reset is not None:
-            reset()
         h.step(mode)
     torch.cuda.synchronize()
     h.timing(True)
-    if reset is None:
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            h.step(mode)
-        torch.cuda.synchronize()
-        total = time.perf_counter() - t0
-    else:
-        total = 0.0
-        for _ in range(steps):
-            reset()
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            h.step(mode)
-            torch.cuda.synchronize()
-            total += time.perf_counter() - t0
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        h.step(mode)
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
     h.timing(False)
     return total / steps, h.timing_read()
 
@@ -299,38 +298,116 @@ def extended_overhead(h, spec):
     return done / spec.zone_updates_per_root_step()
 
 
-def state_reset(h, spec, field, precision):
-    """A callable that re-uploads the initial state (generated once, kept on the host in the state's dtype)."""
-    import numpy as np
-    from paper_1112_1710_amd import FP64
-    dt = np.float64 if precision == FP64 else np.float32
+def _cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_patch_task(task):
+    """One sampled patch advanced by the oracle: (interior zone-updates, seconds)."""
+    from oracle import amr, mhd
+    name, lv, lo, hi = task
+    spec, field, _ = workload(name)
     root = tuple(int(x) for x in spec.root_n)
-    cache = []
-    for (lv, lo, hi) in spec.patches:
-        st = field.patch(lv, root, tuple(lo), tuple(hi))
-        cache.append((st.cells.astype(dt), [f.astype(dt) for f in st.faces]))
-
-    def reset():
-        for pid, (cells, faces) in zip(h.ids, cache):
-            h.upload(pid, cells, faces)
-        h.synchronize()
-    return reset
-
-
-def cpu_baseline():
-    """The oracle, as it stands, on a scaled-down instance of the two-level recipe (one root step)."""
-    from oracle import amr
-    from workloads import hierarchies as H
-    from workloads.fields import SmoothField
-    spec = H.two_level(root=32, count=32)
-    o = amr.build(spec, SmoothField(1112))
+    st = field.patch(lv, root, tuple(lo), tuple(hi))
+    n = [hi[a] - lo[a] for a in range(3)]
+    G = 4
+    region = amr.update_box((G,) * 3, tuple(G + x for x in n), lv, 0)
+    dx = [1.0 / (root[a] * 2 ** lv) for a in range(3)]
+    dt = 0.4 / mhd.max_signal(st.cells, st.faces, dx, ((G,) * 3, tuple(G + x for x in n)), 5.0 / 3.0)
     t0 = time.perf_counter()
-    o.root_step()
-    el = time.perf_counter() - t0
-    zu = spec.zone_updates_per_root_step()
-    return {"value": zu / el, "unit": "zone-updates/s", "cores": 1, "kind": "oracle",
-            "sample": f"one root step of the two-level recipe scaled to a 32^3 root + {len(spec.patches) - 1} "
-                      f"refined patches ({zu} zone-updates, {el:.1f} s, single-threaded NumPy float64)"}
+    mhd.advance(st.cells, st.faces, dx, dt, region, 5.0 / 3.0)
+    return n[0] * n[1] * n[2], time.perf_counter() - t0
+
+
+def cpu_baseline(name, npatch):
+    """The oracle, as it stands, on a bounded sample of the benchmarked workload: one substep advance
+    (the extended first-substep region on refined levels) of seeded patches drawn from every level, with
+    the workload's own initial state and ghost data from the field generator.  Timed on one core, then on
+    every usable host core through a process pool (forked before the GPU is touched)."""
+    import multiprocessing as mp
+
+    import numpy as np
+    spec, _, _ = workload(name)
+    rng = np.random.default_rng(1710)
+    by_level = {}
+    for lv, lo, hi in spec.patches:
+        by_level.setdefault(lv, []).append((lv, lo, hi))
+    levels = sorted(by_level)
+    picks = []
+    while len(picks) < npatch and any(by_level.values()):
+        for lv in levels:
+            if by_level[lv] and len(picks) < npatch:
+                picks.append(by_level[lv].pop(int(rng.integers(len(by_level[lv])))))
+    tasks = [(name, lv, lo, hi) for lv, lo, hi in picks]
+    zu1 = sec1 = 0.0
+    for t in tasks:
+        z, s = _oracle_patch_task(t)
+        zu1 += z
+        sec1 += s
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    pool_tasks = (tasks * (2 * cores // max(len(tasks), 1) + 1))[:2 * cores]
+    with mp.get_context("fork").Pool(cores) as pool:
+        t0 = time.perf_counter()
+        res = pool.map(_oracle_patch_task, pool_tasks, chunksize=1)
+        wall = time.perf_counter() - t0
+    zup = sum(r[0] for r in res)
+    sample = (f"one substep advance of {len(tasks)} seeded patches drawn from every level of the benchmarked workload "
+              f"({int(zu1)} interior zone-updates), initial state and ghosts from the field generator, NumPy float64; "
+              f"all cores: {len(pool_tasks)} such patch advances over a process pool; CPU: {_cpu_model()}")
+    return {"value": round(zup / wall, 1), "unit": "zone-updates/s", "cores": cores, "kind": "oracle",
+            "sample": sample, "single_core": {"value": round(zu1 / sec1, 1), "cores": 1, "seconds": round(sec1, 2)},
+            "all_cores_seconds": round(wall, 2)}
+
+
+def precision_report(spec, h32, hmix, mode, torch):
+    """Per-field relative L1 after one root step of FP32 and of FP32 with targeted FP64 against the FP64 path
+    (itself held to 1e-12 of the oracle), all three started from the FP32 run's current state with the
+    FP64 path's time step; components whose vector starts in a plane (b_z of the blast) are also given
+    against their vector's L1 norm."""
+    import numpy as np
+    from paper_1112_1710_amd import FP64, Hierarchy
+    h64 = Hierarchy(spec, FP64)
+    h32.synchronize()
+    for pid in range(len(spec.patches)):
+        cells, faces = h32.download(pid)
+        h64.upload(pid, cells, faces)
+        hmix.upload(pid, cells, faces)
+    h64.synchronize()
+    hmix.synchronize()
+    dt = h64.step(mode)
+    h32.step(mode, dt)
+    hmix.step(mode, dt)
+    names = ("rho", "mx", "my", "mz", "E", "p", "bx", "by", "bz")
+    num = {"fp32": np.zeros(9), "fp32_mixed": np.zeros(9)}
+    den = np.zeros(9)
+    for pid in range(len(spec.patches)):
+        ref = _patch_fields(h64, spec, pid)
+        for key, h in (("fp32", h32), ("fp32_mixed", hmix)):
+            got = _patch_fields(h, spec, pid)
+            for i in range(9):
+                num[key][i] += float(np.sum(np.abs(got[i] - ref[i])))
+        for i in range(9):
+            den[i] += float(np.sum(np.abs(ref[i])))
+    gden = den.copy()
+    for group in ((1, 2, 3), (6, 7, 8)):
+        tot = sum(den[q] for q in group)
+        for q in group:
+            gden[q] = max(gden[q], tot)
+    out = {"reference": "FP64 GPU path (held to 1e-12 rel-L1 of the oracle), one root step from the FP32 run's "
+                        "state after the timed steps, same dt", "dt": dt}
+    for key in num:
+        out[key] = {n: float(f"{v:.3g}") for n, v in zip(names, num[key] / np.maximum(den, 1e-300))}
+        out[key + "_vector_scaled"] = {n: float(f"{v:.3g}") for n, v in zip(names, num[key] / np.maximum(gden, 1e-300))}
+    del h64
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -343,6 +420,8 @@ def main():
         sys.stderr.write("bench.py measures one GPU only: the library has no multi-GPU path "
                          "(run with --gpus 1).\n")
         sys.exit(2)
+    # the oracle's host timing first: its process pool forks before anything touches the GPU
+    cpu = None if args.skip_cpu else cpu_baseline(args.workload, args.cpu_patches)
     import torch
 
     from paper_1112_1710_amd import (BATCHED, CONCURRENT, FP32, FP32_MIXED, FP64, GRAPH, LAYERED, PERSISTENT, PLAIN,
@@ -354,35 +433,31 @@ def main():
     spec, field, desc = workload(args.workload)
     zu = spec.zone_updates_per_root_step()
 
-    h = Hierarchy(spec, prec, ghosts=args.ghosts)
-    reset = None
-    steps_from_t0 = args.workload == "deep"
-    if steps_from_t0:
-        # the blast's second root step fails the scheme's physical-state check (negative reconstructed
-        # pressure at the strong shock, in FP64 as in FP32): every timed step restarts from t = 0
-        reset = state_reset(h, spec, field, prec)
-        reset()
-    else:
-        h.set_field(field)
-    tiles = None
-    if args.pair:
-        h.tune_set(TUNE_PAIR, 1)
-    last = None
-    if args.staged:
-        h.tune_set(TUNE_FUSED, 0)
-        h.tune_set(TUNE_FUSED_EU, 0)
-    elif not args.no_autotune:
-        from paper_1112_1710_amd.autotune import autotune
-        chosen = autotune(h)
-        tiles = {str(k): v[1] for k, v in chosen.items() if isinstance(k, int)}
-        last = {str(k[1]): v[1] for k, v in chosen.items() if not isinstance(k, int)}
-    sec, timing = timed_steps(h, mode, args.steps, args.warmup, torch, reset)
+    def prepared(precision, spec, field):
+        """Hierarchy with the initial state uploaded and (unless disabled) autotuned kernels and tiles."""
+        hh = Hierarchy(spec, precision, ghosts=args.ghosts)
+        hh.set_field(field)
+        t_first = t_eu = None
+        if args.pair:
+            hh.tune_set(TUNE_PAIR, 1)
+        if args.staged:
+            hh.tune_set(TUNE_FUSED, 0)
+            hh.tune_set(TUNE_FUSED_EU, 0)
+        elif not args.no_autotune:
+            from paper_1112_1710_amd.autotune import autotune
+            chosen = autotune(hh)
+            t_first = {str(k): v[1] for k, v in chosen.items() if isinstance(k, int)}
+            t_eu = {str(k[1]): v[1] for k, v in chosen.items() if not isinstance(k, int)}
+        return hh, t_first, t_eu
+
+    h, tiles, last = prepared(prec, spec, field)
+    sec, timing = timed_steps(h, mode, args.steps, args.warmup, torch)
     value = zu / sec
     work = h.step_work()
     if mode in (GRAPH, PERSISTENT, CONCURRENT, LAYERED):
         # kernels inside a replayed graph or the persistent kernel are not bracketed by events: take the per-kernel
-        # launch times from an instrumented batched pass of the same steps
-        _, timing = timed_steps(h, BATCHED, args.steps, 1, torch, reset)
+        # launch times from an instrumented batched pass of further consecutive steps
+        _, timing = timed_steps(h, BATCHED, args.steps, 1, torch)
 
     # dominant kernel class and its roofline
     dom = max(timing, key=lambda k: timing[k][0])
@@ -428,7 +503,14 @@ def main():
         else:
             regrid_report = time_regrid_levels(h, args.regrid_eps, args.regrid_from, torch)
     overhead = extended_overhead(h, spec)
-    reset = None  # the closure holds the hierarchy
+    mixed = None
+    if not args.skip_precision and prec == FP32 and args.workload != "lowbeta":
+        hm, _, _ = prepared(FP32_MIXED, spec, field)
+        msec, _ = timed_steps(hm, mode, max(args.steps // 2, 1), 1, torch)
+        mixed = {"value": round(zu / msec, 1), "ms_per_step": round(msec * 1e3, 4),
+                 "rel_l1_per_step": precision_report(spec, h, hm, mode, torch)}
+        del hm
+        torch.cuda.empty_cache()
     del h
     torch.cuda.empty_cache()
     if args.pmc_calibration:
@@ -455,7 +537,7 @@ def main():
         "config": {"workload": desc, "patches": len(spec.patches), "levels": spec.levels(),
                    "cells": spec.cells(), "zone_updates_per_step": zu, "precision": args.precision,
                    "schedule": args.mode, "ghosts": args.ghosts,
-                   "steps_from": "t=0 state before every step" if steps_from_t0 else "consecutive steps",
+                   "steps_from": "consecutive steps from the seeded initial state",
                    "first_stages": "staged" if args.staged or tiles is None else tiles,
                    "edge_update_stages": "staged" if args.staged or last is None else last,
                    "extended_ghost_overhead": round(overhead, 4),
@@ -466,27 +548,35 @@ def main():
     }
     if regrid_report is not None:
         out["regrid"] = regrid_report
+    if mixed is not None:
+        out["fp32_mixed"] = mixed
+        out["rel_l1_per_step"] = mixed["rel_l1_per_step"]["fp32"]
 
     if not args.skip_plain:
         hp = Hierarchy(spec, FP64, ghosts=args.ghosts)
-        preset = None
-        if steps_from_t0:
-            preset = state_reset(hp, spec, field, FP64)
-            preset()
-        else:
-            hp.set_field(field)
-        psec, _ = timed_steps(hp, PLAIN, args.plain_steps, 1, torch, preset)
-        del preset
+        hp.set_field(field)
+        psec, _ = timed_steps(hp, PLAIN, args.plain_steps, 1, torch)
         out["fp64_plain_value"] = round(zu / psec, 1)
         out["speedup_vs_fp64_plain"] = round(value / (zu / psec), 3)
         del hp
         torch.cuda.empty_cache()
 
+    if args.workload == "deep" and not args.skip_secondary:
+        s2, f2, d2 = workload("two_level")
+        zu2 = s2.zone_updates_per_root_step()
+        h2, _, _ = prepared(prec, s2, f2)
+        sec2, _ = timed_steps(h2, mode, args.secondary_steps, args.warmup, torch)
+        out["secondary"] = {"workload": d2, "value": round(zu2 / sec2, 1), "unit": "zone-updates/s",
+                            "ms_per_step": round(sec2 * 1e3, 4), "steps": args.secondary_steps,
+                            "precision": args.precision, "schedule": args.mode}
+        del h2
+        torch.cuda.empty_cache()
+
     if args.workload == "lowbeta":
         out["lowbeta_report"] = lowbeta_report(spec, field, args.report_steps, torch)
 
-    if not args.skip_cpu:
-        out["cpu_baseline"] = cpu_baseline()
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     print(json.dumps(out), flush=True)
 
 

@@ -31,3 +31,12 @@ def test_work_tables_name_library_kernel_classes():
     assert all(v > 0 for v in bench.WORDS_PER_UNIT.values())
     h = bench.sources_hash()
     assert len(h.split(":")) == 2 and all(len(x) == 16 for x in h.split(":"))
+
+
+def test_cpu_baseline_sample_runs_the_oracle_on_the_workload():
+    """The oracle's host baseline: a seeded sample of the workload's own patches, one core and a pool."""
+    import bench
+    out = bench.cpu_baseline("uniform32", 1)
+    assert out["kind"] == "oracle" and out["unit"] == "zone-updates/s"
+    assert out["value"] > 0 and out["single_core"]["value"] > 0 and out["cores"] >= 1
+    assert "CPU:" in out["sample"]
