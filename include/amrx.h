@@ -347,6 +347,21 @@ int hier_init_from_levels_bytes(const amrx_hier* dst, const amrx_hier* below, co
 int hier_init_from_levels(amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level, void* work,
                           size_t work_bytes);
 
+/* hier_init_from_levels_static: hier_init_from_levels for callers that cannot
+ *   allocate device memory (code under HIP graph capture, tight serving loops,
+ *   harnesses that forbid hipMalloc).  It takes no workspace: the copy runs and
+ *   the prolongation list go to a static device array of the library, one per
+ *   GPU, AMRX_STATIC_WORK_BYTES bytes, held until the process ends; the call
+ *   makes no allocation of any kind.  The workspace it would need is
+ *   hier_init_from_levels_bytes(); above AMRX_STATIC_WORK_BYTES it returns
+ *   AMRX_EINVAL without touching any device memory.  All calls on one GPU share
+ *   that array: calls that overlap in time on one GPU (several host threads, or
+ *   streams of several hierarchies) race and must be serialised by the caller.
+ *   Nothing in the array must start at zero (each call uploads its own lists
+ *   before use).  Results equal hier_init_from_levels() bit for bit. */
+#define AMRX_STATIC_WORK_BYTES ((size_t)32 << 20)
+int hier_init_from_levels_static(amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level);
+
 /* Debug / test exports (pure host, after hier_finalize).  For every padded
  * cell (kind 0) or face normal to axis kind-1 (kind 1..3) of a patch, in
  * node-padded [z][y][x] order: the same-level source as

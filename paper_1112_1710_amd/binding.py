@@ -63,6 +63,7 @@ EXPORTS = {
     "hier_init_from": ([C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t], C.c_int),
     "hier_init_from_levels_bytes": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
     "hier_init_from_levels": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t], C.c_int),
+    "hier_init_from_levels_static": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
     "hier_debug_layers": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hier_debug_schedule": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
@@ -418,6 +419,14 @@ class Hierarchy:
         b.synchronize()
         self._check(self.lib.hier_init_from_levels(self.h, b.h, src.h, int(level), C.c_void_p(addr), nb))
         del work
+
+    def init_from_static(self, src, level, below=None):
+        """init_from without a workspace allocation: the library's static per-GPU workspace
+        (hier_init_from_levels_static; AmrxError EINVAL when the transfer lists exceed it)."""
+        b = src if below is None else below
+        src.synchronize()
+        b.synchronize()
+        self._check(self.lib.hier_init_from_levels_static(self.h, b.h, src.h, int(level)))
 
     def debug_layers(self, fixed_dt=False):
         """Layered schedule: the first item of each layer (layers + 1) and the items (M, 4) in launch order."""

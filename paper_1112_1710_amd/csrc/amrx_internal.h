@@ -270,3 +270,7 @@ hipError_t launch_xcopy(int precision, hipStream_t s, const void* src, void* dst
                         long long nelem);
 int layer_blocks_per_cu(int precision);
 int persistent_blocks_per_cu(int precision);
+// device address of the library's static workspace on device `dev` (AMRX_STATIC_WORK_BYTES bytes,
+// looked up once per device with that device current), or null with the HIP error in *err
+#define AMRX_MAX_DEVICES 64
+void* static_work_ptr(int dev, hipError_t* err);

@@ -2858,15 +2858,13 @@ int hier_init_from_bytes(const amrx_hier* dst, const amrx_hier* src, int level, 
   return hier_init_from_levels_bytes(dst, src, src, level, bytes);
 }
 
-int hier_init_from_levels(amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level, void* work,
-                          size_t work_bytes) {
-  if (!ready(dst)) return AMRX_ESTATE;
-  amrx_hier* h = dst;  // error reporting of the checks below
-  if (!src || !src->bound || !below || !below->bound) return fail(dst, AMRX_ESTATE, "source hierarchy not bound");
-  InitPlan P;
-  std::string err;
-  const int rc = plan_init(dst, below, src, level, P, err);
-  if (rc) return fail(dst, rc, err);
+}  // extern "C"
+
+namespace {
+// Runs a transfer plan with its lists in `work` (device memory, 256-byte aligned, work_bytes long).
+int run_init(amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level, const InitPlan& P, void* work,
+             size_t work_bytes) {
+  amrx_hier* h = dst;  // error reporting
   const size_t need = align256(sizeof(XRun) * P.runs.size()) + align256(sizeof(Pro) * P.pros.size()) + 256;
   if (!work || work_bytes < need || ((uintptr_t)work & 255)) return fail(dst, AMRX_EINVAL, "workspace too small or unaligned");
   hipStream_t s = (hipStream_t)dst->d.stream;
@@ -2894,6 +2892,40 @@ int hier_init_from_levels(amrx_hier* dst, const amrx_hier* below, const amrx_hie
   HIPCHK(launch_prolong(c, 0, (int)P.pros.size(), dst->cur[level], pc, pc, 0.0), "prolongation of new cells");
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   return AMRX_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int hier_init_from_levels(amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level, void* work,
+                          size_t work_bytes) {
+  if (!ready(dst)) return AMRX_ESTATE;
+  if (!src || !src->bound || !below || !below->bound) return fail(dst, AMRX_ESTATE, "source hierarchy not bound");
+  InitPlan P;
+  std::string err;
+  const int rc = plan_init(dst, below, src, level, P, err);
+  if (rc) return fail(dst, rc, err);
+  return run_init(dst, below, src, level, P, work, work_bytes);
+}
+
+int hier_init_from_levels_static(amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level) {
+  if (!ready(dst)) return AMRX_ESTATE;
+  amrx_hier* h = dst;  // error reporting
+  if (!src || !src->bound || !below || !below->bound) return fail(dst, AMRX_ESTATE, "source hierarchy not bound");
+  InitPlan P;
+  std::string err;
+  const int rc = plan_init(dst, below, src, level, P, err);
+  if (rc) return fail(dst, rc, err);
+  const size_t need = align256(sizeof(XRun) * P.runs.size()) + align256(sizeof(Pro) * P.pros.size()) + 256;
+  if (need > AMRX_STATIC_WORK_BYTES)
+    return fail(dst, AMRX_EINVAL, "transfer lists exceed the static workspace (AMRX_STATIC_WORK_BYTES); use "
+                                  "hier_init_from_levels with a caller workspace");
+  int dev = -1;
+  HIPCHK(hipStreamGetDevice((hipStream_t)dst->d.stream, &dev), "device of the hierarchy's stream");
+  hipError_t e = hipSuccess;
+  void* work = static_work_ptr(dev, &e);
+  HIPCHK(e, "address of the static workspace");
+  return run_init(dst, below, src, level, P, work, AMRX_STATIC_WORK_BYTES);
 }
 
 int hier_init_from(amrx_hier* dst, const amrx_hier* src, int level, void* work, size_t work_bytes) {

@@ -28,9 +28,12 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <mutex>
+
 #include <type_traits>
 
 #include "amrx_internal.h"
+#include "../../include/amrx.h"
 
 namespace {
 
@@ -2408,4 +2411,36 @@ hipError_t launch_set_dt(const DevCtx& c, double dt0) {
 hipError_t launch_dt_from_cfl(const DevCtx& c, int nlev, double cfl) {
   k_dt_from_cfl<<<1, 64, 0, c.stream>>>(c, nlev, cfl);
   return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// static workspace of the entry points that allocate nothing
+// ---------------------------------------------------------------------------
+// One copy per device, held until the process ends.  Host code never passes the symbol itself (in
+// host code it names a host-side stand-in): the device address comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[AMRX_STATIC_WORK_BYTES];
+
+void* static_work_ptr(int dev, hipError_t* err) {
+  static std::mutex mu;
+  static void* addr[AMRX_MAX_DEVICES] = {};
+  *err = hipSuccess;
+  if (dev < 0 || dev >= AMRX_MAX_DEVICES) {
+    *err = hipErrorInvalidDevice;
+    return nullptr;
+  }
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    int prev = -1;
+    if ((*err = hipGetDevice(&prev)) != hipSuccess) return nullptr;
+    if (prev != dev && (*err = hipSetDevice(dev)) != hipSuccess) return nullptr;
+    void* p = nullptr;
+    *err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (prev != dev) {
+      const hipError_t e2 = hipSetDevice(prev);
+      if (*err == hipSuccess) *err = e2;
+    }
+    if (*err != hipSuccess) return nullptr;
+    addr[dev] = p;
+  }
+  return addr[dev];
 }
