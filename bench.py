@@ -99,6 +99,9 @@ def parse():
     ap.add_argument("--regrid-from", type=int, default=None,
                     help="with --regrid-eps: regrid every level from this one up, coarse to fine, instead of the "
                          "finest level alone")
+    ap.add_argument("--regrid-every", type=int, default=None,
+                    help="with --regrid-eps: a separate timed run of --steps root steps that regrids after every "
+                         "K root steps inside the loop (levels from --regrid-from, default the finest)")
     ap.add_argument("--ghosts", default="extended", choices=["extended", "time"],
                     help="later-substep ghost data of refined patches: extended ghost regions (default) or the "
                          "coarse time derivative")
@@ -281,6 +284,36 @@ def time_regrid_levels(h, eps, from_level, torch, min_side=4, efficiency=0.7):
     del h2
     torch.cuda.empty_cache()
     return rep
+
+
+def timed_evolve(h, mode, steps, every, eps, from_level, torch):
+    """Wall time of `steps` root steps with regridding after every `every` of them (inside the timed
+    loop), the zone-updates actually advanced (each step on the hierarchy it ran on) and the time of
+    the regrids alone."""
+    from paper_1112_1710_amd.regrid import regrid_levels
+    torch.cuda.synchronize()
+    zu = 0
+    regrid_s = 0.0
+    nreg = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        h.step(mode)
+        zu += h.spec.zone_updates_per_root_step()
+        if (k + 1) % every == 0:
+            t1 = time.perf_counter()
+            lv = h.levels - 1 if from_level is None else from_level
+            try:
+                h = regrid_levels(h, eps, from_level=lv)
+                nreg += 1
+            except ValueError:
+                pass
+            torch.cuda.synchronize()
+            regrid_s += time.perf_counter() - t1
+    torch.cuda.synchronize()
+    total = time.perf_counter() - t0
+    return {"steps": steps, "every": every, "eps": eps, "from_level": from_level, "regrids": nreg,
+            "value": round(zu / total, 1), "unit": "zone-updates/s", "seconds": round(total, 3),
+            "regrid_seconds": round(regrid_s, 3), "patches_after": len(h.spec.patches)}
 
 
 def extended_overhead(h, spec):
@@ -497,7 +530,9 @@ def main():
     step_hbm = {"bytes_per_step": int(step_bytes), "achieved": round(step_bytes / sec / 1e9, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(step_bytes / sec / 1e9 / HBM_PEAK_GBS, 4), "classes": priced}
     regrid_report = None
-    if args.regrid_eps is not None and spec.levels() > 1:
+    if args.regrid_eps is not None and spec.levels() > 1 and args.regrid_every:
+        regrid_report = timed_evolve(h, mode, args.steps, args.regrid_every, args.regrid_eps, args.regrid_from, torch)
+    elif args.regrid_eps is not None and spec.levels() > 1:
         if args.regrid_from is None:
             regrid_report = time_regrid(h, args.regrid_eps, torch)
         else:

@@ -348,3 +348,28 @@ def regrid_levels(old, eps, dtype=np.float64, min_side=4, efficiency=0.7, from_l
         init_from(new, old, level)
         cur = new
     return cur
+
+
+def evolve(h, steps, eps, every=1, from_level=None, dtype=np.float64, min_side=4, efficiency=0.7):
+    """Root steps with regridding as part of the time stepping (Sec. 2.1, 2.2: grids are created
+    anew from the flags of their parents and take the data of the preceding grids of their level
+    where those overlap them, the rest by prolongation).  After every `every` root steps, when all
+    levels have reached the same time, the levels from `from_level` (default: the finest) up are
+    regridded coarse to fine; a regrid that finds no flag keeps the hierarchy.  Returns the final
+    hierarchy and, per root step, (dt0, boxes of the regridded levels or None)."""
+    if from_level is not None and not 1 <= from_level < h.nlevels:
+        raise ValueError("from_level must name a refined level")
+    log = []
+    for k in range(steps):
+        dt = h.root_step()
+        boxes = None
+        if (k + 1) % every == 0:
+            lv = h.nlevels - 1 if from_level is None else from_level
+            try:
+                h = regrid_levels(h, eps, dtype, min_side, efficiency, from_level=lv)
+                boxes = sorted((p.level, tuple(int(v) for v in p.lo), tuple(int(v) for v in p.hi))
+                               for p in h.patches if p.level >= lv)
+            except ValueError:
+                pass
+        log.append((dt, boxes))
+    return h, log

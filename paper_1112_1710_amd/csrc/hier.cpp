@@ -8,6 +8,7 @@
 // device except through the launchers of kernels.hip.
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <array>
 #include <cstdio>
@@ -16,6 +17,8 @@
 #include <map>
 #include <string>
 #include <vector>
+#include <thread>
+#include <unordered_map>
 
 #include "amrx_internal.h"
 #include "../../include/amrx.h"
@@ -410,15 +413,32 @@ void stage_regions(int stage, int axis, const int lo[3], const int hi[3], int rl
   }
 }
 
+// Host work over independent items (patches) on up to 16 threads; fn(i) for i in [0, n).
+template <typename F>
+void parallel_for(int n, F fn) {
+  const int nt = std::max(1, std::min({16, n, (int)std::thread::hardware_concurrency()}));
+  if (nt <= 1) {
+    for (int i = 0; i < n; ++i) fn(i);
+    return;
+  }
+  std::vector<std::thread> pool;
+  std::atomic<int> next{0};
+  for (int t = 0; t < nt; ++t)
+    pool.emplace_back([&]() {
+      for (int i = next.fetch_add(1); i < n; i = next.fetch_add(1)) fn(i);
+    });
+  for (auto& th : pool) th.join();
+}
+
 // Buckets of a level's index space (periodic), each listing the patches whose boxes meet it;
 // neighbour searches visit only the buckets around a patch instead of every patch of its level.
+// Only occupied buckets are stored (a fine level's index space holds up to 2^27 of them).
 struct LevelBuckets {
   int n[3] = {1, 1, 1};   // level cells per axis
   int nb[3] = {1, 1, 1};  // buckets per axis
   static constexpr int B = 16;
-  std::vector<std::vector<int>> ids;
-  std::vector<int> mark;  // per patch: last query that listed it
-  int query = 0;
+  std::unordered_map<long long, std::vector<int>> ids;
+  long long key(int bx, int by, int bz) const { return ((long long)bz * nb[1] + by) * nb[0] + bx; }
 };
 
 void build_buckets(const amrx_hier* h, int level, LevelBuckets& L) {
@@ -426,25 +446,23 @@ void build_buckets(const amrx_hier* h, int level, LevelBuckets& L) {
     L.n[a] = nl_of(h, level, a);
     L.nb[a] = (L.n[a] + LevelBuckets::B - 1) / LevelBuckets::B;
   }
-  L.ids.assign((size_t)L.nb[0] * L.nb[1] * L.nb[2], {});
-  L.mark.assign(h->P.size(), -1);
+  L.ids.clear();
   for (int q : h->lev[level]) {
     const HPatch& Q = h->P[q];
     for (int bz = Q.lo[2] / LevelBuckets::B; bz <= (Q.hi[2] - 1) / LevelBuckets::B; ++bz)
       for (int by = Q.lo[1] / LevelBuckets::B; by <= (Q.hi[1] - 1) / LevelBuckets::B; ++by)
         for (int bx = Q.lo[0] / LevelBuckets::B; bx <= (Q.hi[0] - 1) / LevelBuckets::B; ++bx)
-          L.ids[((size_t)bz * L.nb[1] + by) * L.nb[0] + bx].push_back(q);
+          L.ids[L.key(bx, by, bz)].push_back(q);
   }
 }
 
 // Patches of p's level (ascending ids) whose box, or a periodic image of it, meets p's box grown
-// by `reach` cells on every side; p itself included.
-std::vector<int> near_patches(const amrx_hier* h, LevelBuckets& L, int pid, int reach) {
+// by `reach` cells on every side; p itself included.  Safe to call from several threads.
+std::vector<int> near_patches(const amrx_hier* h, const LevelBuckets& L, int pid, int reach) {
   const HPatch& p = h->P[pid];
   std::vector<int> bl[3];
   for (int a = 0; a < 3; ++a) {
     const int lo = p.lo[a] - reach, hi = p.hi[a] + reach;  // cells [lo, hi)
-    std::vector<char> seen(L.nb[a], 0);
     if (hi - lo >= L.n[a]) {
       for (int b = 0; b < L.nb[a]; ++b) bl[a].push_back(b);
       continue;
@@ -452,23 +470,18 @@ std::vector<int> near_patches(const amrx_hier* h, LevelBuckets& L, int pid, int 
     for (int x = lo; x < hi; ++x) {
       const int w = ((x % L.n[a]) + L.n[a]) % L.n[a];
       const int b = w / LevelBuckets::B;
-      if (!seen[b]) {
-        seen[b] = 1;
-        bl[a].push_back(b);
-      }
+      if (bl[a].empty() || std::find(bl[a].begin(), bl[a].end(), b) == bl[a].end()) bl[a].push_back(b);
     }
   }
-  ++L.query;
   std::vector<int> out;
   for (int bz : bl[2])
     for (int by : bl[1])
-      for (int bx : bl[0])
-        for (int q : L.ids[((size_t)bz * L.nb[1] + by) * L.nb[0] + bx])
-          if (L.mark[q] != L.query) {
-            L.mark[q] = L.query;
-            out.push_back(q);
-          }
+      for (int bx : bl[0]) {
+        const auto it = L.ids.find(L.key(bx, by, bz));
+        if (it != L.ids.end()) out.insert(out.end(), it->second.begin(), it->second.end());
+      }
   std::sort(out.begin(), out.end());
+  out.erase(std::unique(out.begin(), out.end()), out.end());
   return out;
 }
 
@@ -538,7 +551,7 @@ bool is_own(const HPatch& p, int kind, int i, int j, int k) {
 // Copy runs (consecutive along x) of the ghost entries of p within `depth` layers of its
 // interior; with `by_side`, sides that do not extend the substep-0 update region (their
 // ghosts feed only the stencil of the interior) take n_g layers instead.
-void build_runs(amrx_hier* h, int pid, int depth, bool by_side, int& nelem, double& comps) {
+void build_runs(const amrx_hier* h, int pid, int depth, bool by_side, int& nelem, double& comps, std::vector<Run>& runs) {
   const HPatch& p = h->P[pid];
   const auto& S = h->src[pid];
   for (int kind = 0; kind < 4; ++kind) {
@@ -585,7 +598,7 @@ void build_runs(amrx_hier* h, int pid, int depth, bool by_side, int& nelem, doub
           r.kind = kind;
           r.off = nelem;
           r.pad = 0;
-          h->runs.push_back(r);
+          runs.push_back(r);
           nelem += len;
           comps += (double)len * (kind == 0 ? 5 : 1);
           i += len;
@@ -606,39 +619,74 @@ void copy_list_blocks(amrx_hier* h, CopyList& L) {
   }
 }
 
-// The single-patch list of one patch from a batched list: the batched list is built patch by
-// patch, so that patch's runs are the contiguous range [r0, r1) of it; their element offsets
-// are rebased to start at zero.
-CopyList copy_list_of_patch(amrx_hier* h, int r0, int r1) {
-  CopyList L;
-  L.first_run = (int)h->runs.size();
-  int nelem = 0;
-  double comps = 0;
-  for (int r = r0; r < r1; ++r) {
-    Run x = h->runs[r];
-    x.off = nelem;
-    nelem += x.len;
-    comps += (double)x.len * (x.kind == 0 ? 5 : 1);
-    h->runs.push_back(x);
-  }
-  L.nrun = r1 - r0;
-  L.nelem = nelem;
-  L.comps = comps;
-  copy_list_blocks(h, L);
-  return L;
+
+// Copy runs of one level and ghost class, built per patch (in parallel) and written into the
+// run array later, once every list is known (the array is then sized once).
+struct PendingCopy {
+  int level = 0, cls = 0;
+  std::vector<int> pids;
+  std::vector<std::vector<Run>> part;
+  std::vector<int> cnt;
+  std::vector<double> cmp;
+};
+
+PendingCopy plan_copy_list(const amrx_hier* h, int level, int cls, const std::vector<int>& pids, int depth, bool by_side) {
+  PendingCopy P;
+  P.level = level;
+  P.cls = cls;
+  P.pids = pids;
+  const int n = (int)pids.size();
+  P.part.resize(n);
+  P.cnt.assign(n, 0);
+  P.cmp.assign(n, 0.0);
+  parallel_for(n, [&](int i) { build_runs(h, pids[i], depth, by_side, P.cnt[i], P.cmp[i], P.part[i]); });
+  return P;
 }
 
-CopyList make_copy_list(amrx_hier* h, const std::vector<int>& pids, int depth, bool by_side) {
-  CopyList L;
-  L.first_run = (int)h->runs.size();
-  int nelem = 0;
-  double comps = 0;
-  for (int pid : pids) build_runs(h, pid, depth, by_side, nelem, comps);
-  L.nrun = (int)h->runs.size() - L.first_run;
-  L.nelem = nelem;
-  L.comps = comps;
-  copy_list_blocks(h, L);
-  return L;
+// Writes every pending list into the run array: per list the batched copy (patches in order,
+// element offsets rebased onto the list), then each patch's own copy (offsets from zero).
+void emit_copy_lists(amrx_hier* h, const std::vector<PendingCopy>& pend) {
+  long long total = 0;
+  for (const PendingCopy& P : pend)
+    for (const auto& v : P.part) total += 2 * (long long)v.size();
+  const long long base0 = (long long)h->runs.size();
+  h->runs.resize(base0 + total);
+  long long base = base0;
+  for (const PendingCopy& P : pend) {
+    const int n = (int)P.pids.size();
+    std::vector<long long> rpre(n + 1, 0), epre(n + 1, 0);
+    for (int i = 0; i < n; ++i) {
+      rpre[i + 1] = rpre[i] + (long long)P.part[i].size();
+      epre[i + 1] = epre[i] + P.cnt[i];
+    }
+    const long long nr = rpre[n];
+    parallel_for(n, [&](int i) {
+      Run* b = h->runs.data() + base + rpre[i];
+      Run* o = h->runs.data() + base + nr + rpre[i];
+      for (size_t k = 0; k < P.part[i].size(); ++k) {
+        b[k] = P.part[i][k];
+        b[k].off += (int)epre[i];
+        o[k] = P.part[i][k];
+      }
+    });
+    CopyList& L = h->copy_b[P.level][P.cls];
+    L = CopyList{};
+    L.first_run = (int)base;
+    L.nrun = (int)nr;
+    L.nelem = (int)epre[n];
+    for (int i = 0; i < n; ++i) L.comps += P.cmp[i];
+    copy_list_blocks(h, L);
+    for (int i = 0; i < n; ++i) {
+      CopyList& C = h->copy_p[P.pids[i]][P.cls];
+      C = CopyList{};
+      C.first_run = (int)(base + nr + rpre[i]);
+      C.nrun = (int)P.part[i].size();
+      C.nelem = P.cnt[i];
+      C.comps = P.cmp[i];
+      copy_list_blocks(h, C);
+    }
+    base += 2 * nr;
+  }
 }
 
 void build_pros(amrx_hier* h, int pid) {
@@ -1012,9 +1060,10 @@ int finalize_impl(amrx_hier* h) {
   for (int l = 0; l < h->nlev; ++l) {
     LevelBuckets L;
     build_buckets(h, l, L);
-    for (int id : h->lev[l]) near[id] = near_patches(h, L, id, G + 1);
+    const std::vector<int>& ids = h->lev[l];
+    parallel_for((int)ids.size(), [&](int i) { near[ids[i]] = near_patches(h, L, ids[i], G + 1); });
   }
-  for (int id = 0; id < np; ++id) build_sources(h, id, near[id]);
+  parallel_for(np, [&](int id) { build_sources(h, id, near[id]); });
   for (int id = 0; id < np; ++id) {
     if (h->P[id].level == 0) continue;
     if (h->time_ghosts) {
@@ -1095,21 +1144,14 @@ int finalize_impl(amrx_hier* h) {
     if (h->pdev[id].cov >= 0) std::copy(covmaps[id].begin(), covmaps[id].end(), h->cov.begin() + h->pdev[id].cov);
 
   // per level lists
+  std::vector<PendingCopy> pending;
   for (int l = 0; l < h->nlev; ++l) {
     // ghost copy runs: before substep 0 of a refined level the region its stencil reads
     // (4 layers on sides it extends, 2 elsewhere), else 2 layers
     for (int cls = 0; cls < 2; ++cls) {
       if (l == 0 && cls == 0) continue;
       const int depth = cls == 0 ? G : NG;
-      h->copy_b[l][cls] = make_copy_list(h, h->lev[l], depth, cls == 0);
-      const CopyList B = h->copy_b[l][cls];
-      int r = B.first_run;
-      for (int id : h->lev[l]) {
-        const int r0 = r;
-        while (r < B.first_run + B.nrun && h->runs[r].dst_patch == id) ++r;
-        h->copy_p[id][cls] = copy_list_of_patch(h, r0, r);
-      }
-      if (r != B.first_run + B.nrun) return fail(h, AMRX_EINVAL, "copy runs out of patch order");
+      pending.push_back(plan_copy_list(h, l, cls, h->lev[l], depth, cls == 0));
     }
     // prolongation
     h->pro_b[l].first = (int)h->pros.size();
@@ -1278,6 +1320,8 @@ int finalize_impl(amrx_hier* h) {
     B.count = (int)h->tasks.size() - B.first;
     B.nblk = nb;
   }
+  emit_copy_lists(h, pending);
+  pending.clear();
   // block tables of every task list
   h->tbl.assign(h->tasks.size() + 1, 0);
   h->b2t.clear();

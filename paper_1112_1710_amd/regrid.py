@@ -87,3 +87,28 @@ def regrid_levels(h, eps, min_side=4, efficiency=0.7, from_level=1, **kwargs):
         nxt.init_from(h, level, below=cur)
         cur = nxt
     return cur
+
+
+def evolve(h, steps, eps, every=1, from_level=None, mode=None, min_side=4, efficiency=0.7, **kwargs):
+    """Root steps with regridding in the time stepping loop: after every `every` root steps (all
+    levels then at one time) the levels from `from_level` (default: the finest) up are regridded
+    coarse to fine (regrid_levels) and the run continues on the new hierarchy; a regrid that finds
+    no flag keeps the hierarchy.  Returns the final hierarchy and, per root step, (dt0, boxes of the
+    regridded levels or None)."""
+    from .binding import GRAPH
+    mode = GRAPH if mode is None else mode
+    if from_level is not None and not 1 <= from_level < h.levels:
+        raise ValueError("from_level must name a refined level")
+    log = []
+    for k in range(steps):
+        dt = h.step(mode)
+        boxes = None
+        if (k + 1) % every == 0:
+            lv = h.levels - 1 if from_level is None else from_level
+            try:
+                h = regrid_levels(h, eps, min_side, efficiency, from_level=lv, **kwargs)
+                boxes = sorted((p[0], tuple(p[1]), tuple(p[2])) for p in h.spec.patches if p[0] >= lv)
+            except ValueError:
+                pass
+        log.append((dt, boxes))
+    return h, log

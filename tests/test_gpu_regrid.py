@@ -232,3 +232,25 @@ def test_regrid_levels_matches_oracle(precision, eps, levels):
     assert np.all(err <= TOL[precision]), dict(zip(FIELDS, err))
     d = h2.diag()
     assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+
+
+def test_evolve_with_regrids_in_the_loop_matches_oracle():
+    """Regridding in the time stepping loop (FP64): three root steps of the three-level hierarchy, levels 1
+    and 2 regridded after every step on both sides; the same boxes as the oracle at every regrid, the
+    same dt0 and the state within the FP64 bar after every step."""
+    from paper_1112_1710_amd.regrid import evolve
+    from ._common import assert_parity
+    spec = H.small_three_level()
+    _say("evolve with regrids")
+    o = _bumped_oracle(spec, FP64)
+    # the same bump on the three-level hierarchy as the oracle pin uses
+    h = Hierarchy(spec, FP64)
+    upload_oracle_state(h, o)
+    for k in range(3):
+        o, olog = oregrid.evolve(o, 1, 0.05, every=1, from_level=1)
+        h, hlog = evolve(h, 1, 0.05, every=1, from_level=1, mode=BATCHED)
+        assert abs(hlog[0][0] - olog[0][0]) <= 1e-13 * olog[0][0]
+        assert olog[0][1] is not None and hlog[0][1] == olog[0][1], k
+        assert_parity(h, o, 1e-12, "evolve step %d" % k)
+    d = h.diag()
+    assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0

@@ -310,3 +310,24 @@ def test_regrid_levels_ends_at_a_level_without_flags():
     flat = amr.build(H.small_three_level(), Uniform(1.0, (0.1, 0.0, 0.0), 1.0, (0.3, 0.2, 0.1)))
     with pytest.raises(ValueError):
         regrid.regrid_levels(flat, 0.01)
+
+
+def test_evolve_regrids_in_the_time_stepping_loop_and_conserves():
+    """Three root steps of the three-level hierarchy with levels 1 and 2 regridded after every root step
+    (Sec. 2.1: new grids each step, filled from the preceding ones and the new parents): every regrid
+    finds flags, the composite sums of mass, momentum and energy are conserved to round-off through
+    the steps and the regrids (restricted coarse data under the old fine grids, copied overlaps and
+    conservative prolongation), and div B stays zero on every level."""
+    o = _bumped_three_level()
+    c0 = o.conservation()
+    scale = sum(abs(x) for x in c0[:5])
+    h, log = regrid.evolve(o, 3, 0.05, every=1, from_level=1)
+    assert all(boxes is not None for _, boxes in log)
+    assert h is not o and h.nlevels == 3
+    c1 = h.conservation()
+    assert np.all(np.abs(c1[:5] - c0[:5]) <= 1e-13 * scale), (c1[:5] - c0[:5])
+    assert h.max_divergence() < 1e-10
+    # the regridded levels nest and are disjoint (the hierarchy was accepted by freeze())
+    for p in h.patches:
+        if p.level > 0:
+            assert p.parent is not None and p.parent.level == p.level - 1
