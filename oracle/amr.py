@@ -76,7 +76,7 @@ import math
 
 import numpy as np
 
-from . import mhd
+from . import hydro, mhd
 
 R = 2
 G = 4
@@ -149,9 +149,13 @@ class Patch:
 
 
 class Hierarchy:
-    def __init__(self, root_n, gamma=5.0 / 3.0, cfl=0.4, ghosts="extended"):
+    def __init__(self, root_n, gamma=5.0 / 3.0, cfl=0.4, ghosts="extended", physics="mhd", cs=1.0):
         if ghosts not in ("extended", "time"):
             raise ValueError("ghosts must be 'extended' or 'time'")
+        if physics not in ("mhd", "isothermal"):
+            raise ValueError("physics must be 'mhd' or 'isothermal'")
+        self.physics = physics
+        self.cs = float(cs)
         self.ghosts = ghosts
         self.root_n = np.asarray(root_n, dtype=np.int64)
         self.gamma = gamma
@@ -429,13 +433,18 @@ class Hierarchy:
         return np.where(a * b > 0.0, np.sign(a) * np.minimum(np.abs(a), np.abs(b)), 0.0)
 
     @staticmethod
-    def positivity_fallback(p, fx, fy, fz, u0, gamma):
+    def positivity_fallback(p, fx, fy, fz, u0, gamma, isothermal=False):
         """After the limited-linear prolongation of one coarse cell into the fine cells
         [fx, fx+2) x [fy, fy+2) x [fz, fz+2) of p (and of its faces), give all 8 fine cells the
-        coarse conserved values u0 if any of them has rho <= 0, p <= 0 or a non-finite value.
-        Returns True when it did."""
+        coarse conserved values u0 if any of them has rho <= 0, p <= 0 or a non-finite value
+        (isothermal gas: p = c_s^2 rho, so rho <= 0 or a non-finite value).  Returns True when it did."""
         sl = (slice(fz, fz + 2), slice(fy, fy + 2), slice(fx, fx + 2))
         u = p.cells[(slice(None),) + sl]
+        if isothermal:
+            if np.all(np.isfinite(u[:4])) and np.all(u[0] > 0.0):
+                return False
+            p.cells[(slice(None),) + sl] = u0[:, None, None, None]
+            return True
         bc = mhd.cell_centred_b([f[fz:fz + 3, fy:fy + 3, fx:fx + 3] for f in p.faces])[:, :2, :2, :2]
         with np.errstate(all='ignore'):
             w = mhd.prim_from_cons(u, bc, gamma)
@@ -591,7 +600,7 @@ class Hierarchy:
                         fidx[a2] += t2
                         # interior faces of an uncovered coarse cell never lie on a same-level closure
                         p.faces[d][fidx[2], fidx[1], fidx[0]] = inner[k]
-                    self.positivity_fallback(p, fx, fy, fz, u0, self.gamma)
+                    self.positivity_fallback(p, fx, fy, fz, u0, self.gamma, self.physics == "isothermal")
 
     # ------------------------------------------------------------------ advance
     def region(self, p, substep):
@@ -603,7 +612,10 @@ class Hierarchy:
         dx = self.dxv(level)
         for p in self.level_patches(level):
             reg = self.region(p, substep)
-            res = mhd.advance(p.cells, p.faces, dx, dt, reg, self.gamma)
+            if self.physics == "isothermal":
+                res = hydro.advance(p.cells, p.faces, dx, dt, reg, self.cs)
+            else:
+                res = mhd.advance(p.cells, p.faces, dx, dt, reg, self.gamma)
             p.old_cells, p.old_faces = p.cells, p.faces
             p.cells, p.faces = res.cells, res.faces
             if self.poison:
@@ -783,7 +795,11 @@ class Hierarchy:
         for lv in range(self.nlevels):
             smax = 0.0
             for p in self.level_patches(lv):
-                smax = max(smax, mhd.max_signal(p.cells, p.faces, self.dxv(lv), p.interior_box(), self.gamma))
+                if self.physics == "isothermal":
+                    sig = hydro.max_signal(p.cells, self.dxv(lv), p.interior_box(), self.cs)
+                else:
+                    sig = mhd.max_signal(p.cells, p.faces, self.dxv(lv), p.interior_box(), self.gamma)
+                smax = max(smax, sig)
             if smax > 0.0:
                 best = min(best, R ** lv * self.cfl / smax)
         return best
@@ -833,9 +849,9 @@ class Hierarchy:
         return out
 
 
-def build(spec, field=None, gamma=5.0 / 3.0, cfl=0.4, ghosts="extended"):
+def build(spec, field=None, gamma=5.0 / 3.0, cfl=0.4, ghosts="extended", physics="mhd", cs=1.0):
     """Hierarchy from a workloads HierarchySpec (and optional initial field)."""
-    h = Hierarchy(spec.root_n, gamma=gamma, cfl=cfl, ghosts=ghosts)
+    h = Hierarchy(spec.root_n, gamma=gamma, cfl=cfl, ghosts=ghosts, physics=physics, cs=cs)
     for lv, lo, hi in spec.patches:
         h.add(lv, lo, hi)
     h.freeze()

@@ -317,7 +317,7 @@ def _prolong_interior(h, p, own_c, own_f):
                     fidx[a1] += t1
                     fidx[a2] += t2
                     p.faces[d][fidx[2], fidx[1], fidx[0]] = inner[k]
-                amr.Hierarchy.positivity_fallback(p, fx, fy, fz, u0, h.gamma)
+                amr.Hierarchy.positivity_fallback(p, fx, fy, fz, u0, h.gamma, h.physics == "isothermal")
 
 
 def regrid_levels(old, eps, dtype=np.float64, min_side=4, efficiency=0.7, from_level=1):
@@ -335,7 +335,8 @@ def regrid_levels(old, eps, dtype=np.float64, min_side=4, efficiency=0.7, from_l
             if level == from_level:
                 raise ValueError("no cell below the first regridded level is flagged")
             break
-        new = amr.Hierarchy(old.root_n, gamma=old.gamma, cfl=old.cfl, ghosts=old.ghosts)
+        new = amr.Hierarchy(old.root_n, gamma=old.gamma, cfl=old.cfl, ghosts=old.ghosts, physics=old.physics,
+                            cs=old.cs)
         keep = [p for p in cur.patches if p.level < level]
         for p in keep:
             new.add(p.level, tuple(int(v) for v in p.lo), tuple(int(v) for v in p.hi))

@@ -372,3 +372,17 @@ class LinearWave:
         bz[:, :-1, :-1] = (ay[:, :-1, 1:] - ay[:, :-1, :-1]) / h[0] - (ax[:, 1:, :-1] - ax[:, :-1, :-1]) / h[1]
         faces = [bx + self.u0[5], by + self.u0[6], bz + self.u0[7]]
         return _clean(PatchState(cells, faces))
+
+
+class Isothermal:
+    """The density and momentum of another field's state for the isothermal hydro workload: the
+    energy slot and the face fields are zero (no solver arithmetic, only a copy of the arrays)."""
+
+    def __init__(self, base):
+        self.base = base
+
+    def patch(self, level, root_n, lo, hi):
+        st = self.base.patch(level, root_n, lo, hi)
+        cells = st.cells.copy()
+        cells[4] = 0.0
+        return PatchState(cells, [np.zeros_like(f) for f in st.faces])
