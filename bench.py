@@ -74,7 +74,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="deep",
-                    choices=["two_level", "uniform256", "uniform32", "deep", "lowbeta"])
+                    choices=["two_level", "uniform256", "uniform32", "deep", "lowbeta", "iso_two_level"])
     ap.add_argument("--report-steps", type=int, default=3,
                     help="root steps of the low-beta precision report (workload lowbeta)")
     ap.add_argument("--precision", default=None, choices=["fp32", "fp32_mixed", "fp64"],
@@ -111,6 +111,10 @@ def parse():
     return ap.parse_args()
 
 
+# physics of each workload other than ideal MHD: (physics, isothermal sound speed)
+WORKLOAD_PHYSICS = {"iso_two_level": ("isothermal", 1.0)}
+
+
 @functools.lru_cache(maxsize=None)
 def workload(name):
     from workloads import hierarchies as H
@@ -121,6 +125,10 @@ def workload(name):
         return H.single_patch(256), SmoothField(1710), "single periodic 256^3 patch, smooth field"
     if name == "uniform32":
         return H.single_patch(32), SmoothField(1112), "single periodic 32^3 patch, smooth field"
+    if name == "iso_two_level":
+        from workloads.fields import Isothermal
+        return (H.two_level(), Isothermal(SmoothField(1112)),
+                "two-level 128^3 root + 512 refined patches, isothermal hydro (c_s = 1), smooth field")
     if name == "lowbeta":
         from workloads.fields import low_beta
         return H.two_level(), low_beta(5), "two-level 128^3 root + 512 refined patches, low beta (1e-3), 1% density noise"
@@ -344,18 +352,25 @@ def _cpu_model():
 
 def _oracle_patch_task(task):
     """One sampled patch advanced by the oracle: (interior zone-updates, seconds)."""
-    from oracle import amr, mhd
+    from oracle import amr, hydro, mhd
     name, lv, lo, hi = task
     spec, field, _ = workload(name)
+    physics, cs = WORKLOAD_PHYSICS.get(name, ("mhd", 1.0))
     root = tuple(int(x) for x in spec.root_n)
     st = field.patch(lv, root, tuple(lo), tuple(hi))
     n = [hi[a] - lo[a] for a in range(3)]
     G = 4
     region = amr.update_box((G,) * 3, tuple(G + x for x in n), lv, 0)
     dx = [1.0 / (root[a] * 2 ** lv) for a in range(3)]
-    dt = 0.4 / mhd.max_signal(st.cells, st.faces, dx, ((G,) * 3, tuple(G + x for x in n)), 5.0 / 3.0)
-    t0 = time.perf_counter()
-    mhd.advance(st.cells, st.faces, dx, dt, region, 5.0 / 3.0)
+    box = ((G,) * 3, tuple(G + x for x in n))
+    if physics == "isothermal":
+        dt = 0.4 / hydro.max_signal(st.cells, dx, box, cs)
+        t0 = time.perf_counter()
+        hydro.advance(st.cells, st.faces, dx, dt, region, cs)
+    else:
+        dt = 0.4 / mhd.max_signal(st.cells, st.faces, dx, box, 5.0 / 3.0)
+        t0 = time.perf_counter()
+        mhd.advance(st.cells, st.faces, dx, dt, region, 5.0 / 3.0)
     return n[0] * n[1] * n[2], time.perf_counter() - t0
 
 
@@ -399,14 +414,14 @@ def cpu_baseline(name, npatch):
             "all_cores_seconds": round(wall, 2)}
 
 
-def precision_report(spec, h32, hmix, mode, torch):
+def precision_report(spec, h32, hmix, mode, torch, physics="mhd", cs=1.0):
     """Per-field relative L1 after one root step of FP32 and of FP32 with targeted FP64 against the FP64 path
     (itself held to 1e-12 of the oracle), all three started from the FP32 run's current state with the
     FP64 path's time step; components whose vector starts in a plane (b_z of the blast) are also given
     against their vector's L1 norm."""
     import numpy as np
     from paper_1112_1710_amd import FP64, Hierarchy
-    h64 = Hierarchy(spec, FP64)
+    h64 = Hierarchy(spec, FP64, physics=physics, cs=cs)
     h32.synchronize()
     for pid in range(len(spec.patches)):
         cells, faces = h32.download(pid)
@@ -466,9 +481,11 @@ def main():
     spec, field, desc = workload(args.workload)
     zu = spec.zone_updates_per_root_step()
 
-    def prepared(precision, spec, field):
+    physics, cs = WORKLOAD_PHYSICS.get(args.workload, ("mhd", 1.0))
+
+    def prepared(precision, spec, field, physics=physics, cs=cs):
         """Hierarchy with the initial state uploaded and (unless disabled) autotuned kernels and tiles."""
-        hh = Hierarchy(spec, precision, ghosts=args.ghosts)
+        hh = Hierarchy(spec, precision, ghosts=args.ghosts, physics=physics, cs=cs)
         hh.set_field(field)
         t_first = t_eu = None
         if args.pair:
@@ -543,7 +560,7 @@ def main():
         hm, _, _ = prepared(FP32_MIXED, spec, field)
         msec, _ = timed_steps(hm, mode, max(args.steps // 2, 1), 1, torch)
         mixed = {"value": round(zu / msec, 1), "ms_per_step": round(msec * 1e3, 4),
-                 "rel_l1_per_step": precision_report(spec, h, hm, mode, torch)}
+                 "rel_l1_per_step": precision_report(spec, h, hm, mode, torch, physics, cs)}
         del hm
         torch.cuda.empty_cache()
     del h
@@ -571,7 +588,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": desc, "patches": len(spec.patches), "levels": spec.levels(),
                    "cells": spec.cells(), "zone_updates_per_step": zu, "precision": args.precision,
-                   "schedule": args.mode, "ghosts": args.ghosts,
+                   "schedule": args.mode, "ghosts": args.ghosts, "physics": physics,
                    "steps_from": "consecutive steps from the seeded initial state",
                    "first_stages": "staged" if args.staged or tiles is None else tiles,
                    "edge_update_stages": "staged" if args.staged or last is None else last,
@@ -588,7 +605,7 @@ def main():
         out["rel_l1_per_step"] = mixed["rel_l1_per_step"]["fp32"]
 
     if not args.skip_plain:
-        hp = Hierarchy(spec, FP64, ghosts=args.ghosts)
+        hp = Hierarchy(spec, FP64, ghosts=args.ghosts, physics=physics, cs=cs)
         hp.set_field(field)
         psec, _ = timed_steps(hp, PLAIN, args.plain_steps, 1, torch)
         out["fp64_plain_value"] = round(zu / psec, 1)
@@ -599,7 +616,7 @@ def main():
     if args.workload == "deep" and not args.skip_secondary:
         s2, f2, d2 = workload("two_level")
         zu2 = s2.zone_updates_per_root_step()
-        h2, _, _ = prepared(prec, s2, f2)
+        h2, _, _ = prepared(prec, s2, f2, "mhd", 1.0)
         sec2, _ = timed_steps(h2, mode, args.secondary_steps, args.warmup, torch)
         out["secondary"] = {"workload": d2, "value": round(zu2 / sec2, 1), "unit": "zone-updates/s",
                             "ms_per_step": round(sec2 * 1e3, 4), "steps": args.secondary_steps,

@@ -111,6 +111,16 @@ int hier_create(const amrx_desc* desc, amrx_hier** out);
 /* Destroy host metadata.  Bound device memory stays with its owner. */
 int hier_destroy(amrx_hier* h);
 
+/* hier_set_isothermal: switch the hierarchy to the isothermal hydro workload
+ *   (the density-and-momentum state the paper counts in its memory estimate,
+ *   Sec. 3): p = cs^2 rho, the MUSCL-Hancock step with an isothermal HLLC flux
+ *   (mass and normal momentum HLL between min(u) - cs and max(u) + cs, the
+ *   transverse momenta upwinded by the contact speed), no energy equation.
+ *   The state layout is unchanged: the caller keeps E and the face fields at
+ *   zero (they stay zero).  Call before hier_bind (AMRX_ESTATE after);
+ *   AMRX_EINVAL unless cs > 0. */
+int hier_set_isothermal(amrx_hier* h, double cs);
+
 /* Text of the last error on h (never NULL). */
 const char* hier_last_error(const amrx_hier* h);
 

@@ -37,6 +37,7 @@ EXPORTS = {
     "hier_create": ([C.POINTER(Desc), C.POINTER(C.c_void_p)], C.c_int),
     "hier_destroy": ([C.c_void_p], C.c_int),
     "hier_last_error": ([C.c_void_p], C.c_char_p),
+    "hier_set_isothermal": ([C.c_void_p, C.c_double], C.c_int),
     "patch_add": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hier_finalize": ([C.c_void_p, C.POINTER(C.c_size_t), C.POINTER(C.c_size_t)], C.c_int),
     "patch_layout": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_size_t), C.POINTER(C.c_int)], C.c_int),
@@ -123,11 +124,12 @@ class Hierarchy:
     (each grid treated as isolated) instead of only over sides lacking same-level cover.
     ``ghosts="time"`` selects coarse-time-derivative ghosts (interior-only updates; later-substep
     ghosts prolongated from the parent moved along its time derivative) instead of extended
-    ghost regions.
+    ghost regions.  ``physics="isothermal"`` selects the isothermal hydro workload with sound
+    speed ``cs`` (hier_set_isothermal; its states keep E and the face fields at zero).
     """
 
     def __init__(self, spec, precision=FP64, gamma=5.0 / 3.0, cfl=0.4, device="cuda:0", stream=None,
-                 extend_all=False, ghosts="extended"):
+                 extend_all=False, ghosts="extended", physics="mhd", cs=1.0):
         self.lib = load_library()
         self.precision = precision
         self.spec = spec
@@ -157,6 +159,11 @@ class Hierarchy:
             pid = C.c_int()
             self._check(self.lib.patch_add(self.h, int(lv), _i3(lo), _i3(hi), C.byref(pid)))
             self.ids.append(pid.value)
+        if physics not in ("mhd", "isothermal"):
+            raise ValueError("physics must be 'mhd' or 'isothermal'")
+        self.physics, self.cs = physics, float(cs)
+        if physics == "isothermal":
+            self._check(self.lib.hier_set_isothermal(self.h, float(cs)))
         if extend_all:
             self._check(self.lib.hier_tune_set(self.h, 0, TUNE_EXTEND_ALL, 1))
         if ghosts not in ("extended", "time"):

@@ -171,6 +171,8 @@ struct DevCtx {
   double* partials;       // per-block conservation partials
   int precision;
   double gamma;
+  int iso;                // isothermal hydro workload: p = cs2 * rho, HLLC fluxes, no energy, zero field
+  double cs2;             // isothermal sound speed squared
   hipStream_t stream;
 };
 

@@ -162,6 +162,8 @@ struct amrx_hier {
   bool persistent_enabled = false;
 
   // concurrent schedule: branch streams and the events of one capture
+  bool iso = false;     // isothermal hydro workload (hier_set_isothermal)
+  double cs2 = 0.0;
   std::vector<hipStream_t> cstreams;
   std::vector<hipEvent_t> cevents;
   bool concurrent_enabled = false;
@@ -1423,6 +1425,8 @@ DevCtx make_ctx(amrx_hier* h) {
   c.partials = (double*)(s + h->off_partials);
   c.precision = h->d.precision;
   c.gamma = h->d.gamma;
+  c.iso = h->iso ? 1 : 0;
+  c.cs2 = h->cs2;
   c.stream = (hipStream_t)h->d.stream;
   return c;
 }
@@ -2083,6 +2087,15 @@ int hier_destroy(amrx_hier* h) {
 }
 
 const char* hier_last_error(const amrx_hier* h) { return h ? h->err.c_str() : "null hierarchy"; }
+
+int hier_set_isothermal(amrx_hier* h, double cs) {
+  if (!h) return AMRX_EINVAL;
+  if (h->bound) return fail(h, AMRX_ESTATE, "hier_set_isothermal after hier_bind");
+  if (!(cs > 0.0) || !std::isfinite(cs)) return fail(h, AMRX_EINVAL, "isothermal sound speed must be positive");
+  h->iso = true;
+  h->cs2 = cs * cs;
+  return AMRX_OK;
+}
 
 int patch_add(amrx_hier* h, int level, const int lo[3], const int hi[3], int* patch_id) {
   if (!h || !lo || !hi) return AMRX_EINVAL;
@@ -2797,6 +2810,10 @@ struct InitPlan {
 // from dst's level - 1 elsewhere.
 int plan_init(const amrx_hier* dst, const amrx_hier* below, const amrx_hier* src, int level, InitPlan& P,
               std::string& err) {
+  if (dst->iso != src->iso || dst->iso != below->iso || dst->cs2 != src->cs2 || dst->cs2 != below->cs2) {
+    err = "regrid transfer: the hierarchies must advance the same physics";
+    return AMRX_EINVAL;
+  }
   if (dst->d.precision != src->d.precision || dst->d.precision != below->d.precision || level < 1 ||
       level >= dst->nlev || dst->nlev != level + 1) {
     err = "regrid transfer: equal precisions and the new level as the destination's finest one required";

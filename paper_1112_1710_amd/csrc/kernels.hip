@@ -182,6 +182,19 @@ __device__ __forceinline__ void to_prim(const R* u, R gm1, R* w) {
 // Transverse star-state velocity and field of one side (Miyoshi & Kusano 2005, their
 // eqs. 44-47): with dn = rho sd (s - sm) - bn^2 and num = rho sd^2 - bn^2 (sd = s - u),
 // v* = v - bn by (sm - u) / dn and by* = by num / dn; a degenerate dn keeps v and B.
+// primitives of the isothermal workload: p = cs2 rho, the field components as stored (zero)
+template <typename R>
+__device__ __forceinline__ void to_prim_iso(const R* u, R cs2, R* w) {
+  w[0] = u[0];
+  w[1] = qdiv(u[1], u[0]);
+  w[2] = qdiv(u[2], u[0]);
+  w[3] = qdiv(u[3], u[0]);
+  w[4] = cs2 * u[0];
+  w[5] = u[5];
+  w[6] = u[6];
+  w[7] = u[7];
+}
+
 template <bool FD, typename R>
 __device__ __forceinline__ void star_transverse(R r, R sd, R s, R sm, R u, R v, R z, R by, R bz, R bn, R& vs, R& zs,
                                                 R& bys, R& bzs) {
@@ -309,6 +322,47 @@ __device__ __forceinline__ void hlld(const R* wl, const R* wr, R bn, R gamma, R*
   out[5 + D] = R(0);
   out[5 + T1] = f[5];
   out[5 + T2] = f[6];
+}
+
+// Isothermal HLLC flux normal to D (the isothermal workload): mass and normal momentum are the
+// HLL fluxes between S_L = min(u) - c_s and S_R = max(u) + c_s, the transverse momenta carry the
+// transverse velocity of the side the contact speed S_M = F_rho / rho_hll comes from (left for
+// S_M >= 0); energy and field fluxes are zero.
+template <int D, typename R>
+__device__ __forceinline__ void hllc_iso(const R* wl, const R* wr, R cs, R* out) {
+  constexpr int T1 = (D + 1) % 3, T2 = (D + 2) % 3;
+  const R cs2 = cs * cs;
+  const R rl = wl[0], ul = wl[1 + D], rr = wr[0], ur = wr[1 + D];
+  const R sl = fmin(ul, ur) - cs;
+  const R sr = fmax(ul, ur) + cs;
+  const R fl0 = rl * ul, fr0 = rr * ur;
+  R f0, fn, ft1, ft2;
+  if (sl >= R(0)) {
+    f0 = fl0;
+    fn = rl * ul * ul + cs2 * rl;
+    ft1 = rl * wl[1 + T1] * ul;
+    ft2 = rl * wl[1 + T2] * ul;
+  } else if (sr <= R(0)) {
+    f0 = fr0;
+    fn = rr * ur * ur + cs2 * rr;
+    ft1 = rr * wr[1 + T1] * ur;
+    ft2 = rr * wr[1 + T2] * ur;
+  } else {
+    const R fln = rl * ul * ul + cs2 * rl, frn = rr * ur * ur + cs2 * rr;
+    const R inv = rcp(sr - sl);
+    f0 = (sr * fl0 - sl * fr0 + sl * sr * (rr - rl)) * inv;
+    fn = (sr * fln - sl * frn + sl * sr * (rr * ur - rl * ul)) * inv;
+    const R rho_hll = (sr * rr - sl * rl - (fr0 - fl0)) * inv;
+    const bool left = qdiv(f0, rho_hll) >= R(0);
+    ft1 = f0 * (left ? wl[1 + T1] : wr[1 + T1]);
+    ft2 = f0 * (left ? wl[1 + T2] : wr[1 + T2]);
+  }
+  out[0] = f0;
+  out[1 + D] = fn;
+  out[1 + T1] = ft1;
+  out[1 + T2] = ft2;
+  out[4] = R(0);
+  out[5] = out[6] = out[7] = R(0);
 }
 
 __device__ __forceinline__ void atomic_max_pos(unsigned long long* slot, double v) {
@@ -460,7 +514,7 @@ __device__ __forceinline__ void d_prim(const DevCtx& c, int vb, int nb, int firs
   const R by = R(0.5) * (U[6 * v + q] + U[6 * v + q + S.s[1]]);
   const R bz = R(0.5) * (U[7 * v + q] + U[7 * v + q + S.s[2]]);
   const R vx = qdiv(mx, rho), vy = qdiv(my, rho), vz = qdiv(mz, rho);
-  const R pr = pressure<R, MIX>(rho, mx, my, mz, e, bx, by, bz, gm1);
+  const R pr = c.iso ? R(c.cs2) * rho : pressure<R, MIX>(rho, mx, my, mz, e, bx, by, bz, gm1);
   if (!(rho > R(0)) || !(pr > R(0)) || !isfinite(e)) flag_phys(c.slots);
   const R wv[8] = {rho, vx, vy, vz, pr, bx, by, bz};
   st8(X + SCR_W * v + 8 * q, wv);
@@ -713,7 +767,7 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_fused_a(DevCtx c, int first, int
     const R by = R(0.5) * (U[6 * v + q] + U[6 * v + q + S.s[1]]);
     const R bz = R(0.5) * (U[7 * v + q] + U[7 * v + q + S.s[2]]);
     const R vx = qdiv(mx, rho), vy = qdiv(my, rho), vz = qdiv(mz, rho);
-    const R pr = pressure<R, MIX>(rho, mx, my, mz, en, bx, by, bz, gm1);
+    const R pr = c.iso ? R(c.cs2) * rho : pressure<R, MIX>(rho, mx, my, mz, en, bx, by, bz, gm1);
     const R wv[8] = {rho, vx, vy, vz, pr, bx, by, bz};
 #pragma unroll
     for (int m = 0; m < 8; ++m) sW[m * HV + t] = wv[m];
@@ -826,12 +880,14 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
   ld8(DU + 8 * (q - sd), d);
 #pragma unroll
   for (int m = 0; m < 8; ++m) u[m] += d[m];
-  to_prim<R, MIX>(u, gm1, wl);
+  if (c.iso) to_prim_iso(u, R(c.cs2), wl);
+  else to_prim<R, MIX>(u, gm1, wl);
   to_cons(wr, gm1, u);
   ld8(DU + 8 * q, d);
 #pragma unroll
   for (int m = 0; m < 8; ++m) u[m] += d[m];
-  to_prim<R, MIX>(u, gm1, wr);
+  if (c.iso) to_prim_iso(u, R(c.cs2), wr);
+  else to_prim<R, MIX>(u, gm1, wr);
   if (!(wl[0] > R(0)) || !(wl[4] > R(0)) || !(wr[0] > R(0)) || !(wr[4] > R(0))) flag_phys(c.slots);
   const R bn = X[(SCR_BH + D) * v + q];
   R f[8];
@@ -846,7 +902,9 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
     const R b2r = bn2 + wr[5 + (D + 1) % 3] * wr[5 + (D + 1) % 3] + wr[5 + (D + 2) % 3] * wr[5 + (D + 2) % 3];
     low_beta = R(20) * fmin(wl[4], wr[4]) < fmax(b2l, b2r);
   }
-  if (low_beta) {
+  if (c.iso) {
+    hllc_iso<D, R>(wl, wr, R(sqrt(c.cs2)), f);
+  } else if (low_beta) {
     double wld[8], wrd[8], fd[8];
 #pragma unroll
     for (int m = 0; m < 8; ++m) {
@@ -1366,7 +1424,8 @@ __device__ __forceinline__ void d_prolong(const DevCtx& c, int vb, int nb, int f
     }
     const double rho = cv[0][o];
     const double kin = 0.5 * ((double)cv[1][o] * cv[1][o] + (double)cv[2][o] * cv[2][o] + (double)cv[3][o] * cv[3][o]) / rho;
-    const double prs = gm1 * ((double)cv[4][o] - kin - 0.5 * mag);
+    // isothermal gas: p = cs2 rho, so the density and finite momenta decide
+    const double prs = c.iso ? (isfinite(kin) ? c.cs2 * rho : -1.0) : gm1 * ((double)cv[4][o] - kin - 0.5 * mag);
     ok = ok && rho > 0.0 && prs > 0.0 && isfinite(prs);
   }
   for (int m = 0; m < 5; ++m)
@@ -1645,13 +1704,20 @@ __device__ __forceinline__ void d_cfl(const DevCtx& c, int b0, int stride, int f
     const R bx = R(0.5) * (U[5 * v + q] + U[5 * v + q + 1]);
     const R by = R(0.5) * (U[6 * v + q] + U[6 * v + q + S.s[1]]);
     const R bz = R(0.5) * (U[7 * v + q] + U[7 * v + q + S.s[2]]);
-    const R pr = pressure<R, MIX>(rho, U[v + q], U[2 * v + q], U[3 * v + q], U[4 * v + q], bx, by, bz, gamma - R(1));
+    const R pr = c.iso ? R(c.cs2) * rho
+                       : pressure<R, MIX>(rho, U[v + q], U[2 * v + q], U[3 * v + q], U[4 * v + q], bx, by, bz, gamma - R(1));
     const R b2 = bx * bx + by * by + bz * bz;
     const R vx = qdiv(U[v + q], rho), vy = qdiv(U[2 * v + q], rho), vz = qdiv(U[3 * v + q], rho);
     const R inv = R(1.0 / p.dx);
-    const R tot = (fabs(vx) + fast_speed(rho, pr, b2, bx * bx, gamma)) * inv +
-                  (fabs(vy) + fast_speed(rho, pr, b2, by * by, gamma)) * inv +
-                  (fabs(vz) + fast_speed(rho, pr, b2, bz * bz, gamma)) * inv;
+    R tot;
+    if (c.iso) {
+      const R cs = R(sqrt(c.cs2));
+      tot = (fabs(vx) + cs) * inv + (fabs(vy) + cs) * inv + (fabs(vz) + cs) * inv;
+    } else {
+      tot = (fabs(vx) + fast_speed(rho, pr, b2, bx * bx, gamma)) * inv +
+            (fabs(vy) + fast_speed(rho, pr, b2, by * by, gamma)) * inv +
+            (fabs(vz) + fast_speed(rho, pr, b2, bz * bz, gamma)) * inv;
+    }
     double sv = (double)tot;
     if (!(rho > R(0)) || !(pr > R(0)) || !isfinite(sv)) flag_phys(c.slots);
     if (!isfinite(sv)) sv = 1.0e308;

@@ -60,6 +60,8 @@ def new_spec(h, eps, min_side=4, efficiency=0.7):
 def regrid(h, eps, min_side=4, efficiency=0.7, **kwargs):
     """A new hierarchy whose finest level covers the flagged cells of the level below, filled from h."""
     spec = new_spec(h, eps, min_side, efficiency)
+    kwargs.setdefault("physics", h.physics)
+    kwargs.setdefault("cs", h.cs)
     h2 = Hierarchy(spec, h.precision, device=h.device, **kwargs)
     h2.init_from(h, h.levels - 1)
     return h2
@@ -73,6 +75,8 @@ def regrid_levels(h, eps, min_side=4, efficiency=0.7, from_level=1, **kwargs):
     top = h.levels - 1
     if not 1 <= from_level <= top:
         raise ValueError("from_level must name a refined level")
+    kwargs.setdefault("physics", h.physics)
+    kwargs.setdefault("cs", h.cs)
     cur = h
     for level in range(from_level, top + 1):
         boxes = cur.regrid_boxes(level - 1, eps, min_side, efficiency)

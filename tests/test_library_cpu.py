@@ -518,3 +518,12 @@ def test_library_binds_to_the_hip_runtime_torch_loads():
     out = subprocess.run([sys.executable, "-c", code], cwd=ROOT, capture_output=True, text=True, timeout=300)
     assert out.returncode == 0, out.stderr
     assert out.stdout.strip() == "1"
+
+
+def test_isothermal_switch_rejects_bad_sound_speed():
+    _lib()
+    with pytest.raises(binding.AmrxError) as ei:
+        binding.Hierarchy(H.small_two_level(), device=None, physics="isothermal", cs=0.0)
+    assert ei.value.code == -1
+    h = binding.Hierarchy(H.small_two_level(), device=None, physics="isothermal", cs=0.7)
+    assert h.physics == "isothermal" and h.cs == 0.7
