@@ -853,7 +853,7 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_fused_a(DevCtx c, int first, int
 // ---------------------------------------------------------------------------
 // stage 4: HLLD fluxes through the faces normal to D, boundary registers
 // ---------------------------------------------------------------------------
-template <int D, typename R, bool MIX>
+template <int D, typename R, bool MIX, bool ISO>
 __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, R* X, int i, int j, int k, int level,
                           int substep, double dt) {
   using Q = typename RegOf<R, MIX>::T;
@@ -880,13 +880,13 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
   ld8(DU + 8 * (q - sd), d);
 #pragma unroll
   for (int m = 0; m < 8; ++m) u[m] += d[m];
-  if (c.iso) to_prim_iso(u, R(c.cs2), wl);
+  if constexpr (ISO) to_prim_iso(u, R(c.cs2), wl);
   else to_prim<R, MIX>(u, gm1, wl);
   to_cons(wr, gm1, u);
   ld8(DU + 8 * q, d);
 #pragma unroll
   for (int m = 0; m < 8; ++m) u[m] += d[m];
-  if (c.iso) to_prim_iso(u, R(c.cs2), wr);
+  if constexpr (ISO) to_prim_iso(u, R(c.cs2), wr);
   else to_prim<R, MIX>(u, gm1, wr);
   if (!(wl[0] > R(0)) || !(wl[4] > R(0)) || !(wr[0] > R(0)) || !(wr[4] > R(0))) flag_phys(c.slots);
   const R bn = X[(SCR_BH + D) * v + q];
@@ -902,7 +902,7 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
     const R b2r = bn2 + wr[5 + (D + 1) % 3] * wr[5 + (D + 1) % 3] + wr[5 + (D + 2) % 3] * wr[5 + (D + 2) % 3];
     low_beta = R(20) * fmin(wl[4], wr[4]) < fmax(b2l, b2r);
   }
-  if (c.iso) {
+  if constexpr (ISO) {
     hllc_iso<D, R>(wl, wr, R(sqrt(c.cs2)), f);
   } else if (low_beta) {
     double wld[8], wrd[8], fd[8];
@@ -959,7 +959,9 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
   }
 }
 
-template <typename R, bool MIX>
+// ISO: the isothermal workload's faces (a separate instantiation, so the MHD kernel carries no
+// branch of it)
+template <typename R, bool MIX, bool ISO = false>
 __device__ __forceinline__ void d_flux(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level, int substep) {
   (void)nb;
   const double dt = level_dt(c, level);
@@ -970,14 +972,27 @@ __device__ __forceinline__ void d_flux(const DevCtx& c, int vb, int nb, int firs
   const Strides S = strides(p);
   R* X = (R*)c.rscr + p.scr;
   (void)cur;
-  if (T.axis == 0) flux_face<0, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
-  else if (T.axis == 1) flux_face<1, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
-  else flux_face<2, R, MIX>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  if (T.axis == 0) flux_face<0, R, MIX, ISO>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else if (T.axis == 1) flux_face<1, R, MIX, ISO>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else flux_face<2, R, MIX, ISO>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+}
+
+// the flux stage of either physics from a device-side scheduler (one code path per workload)
+template <typename R, bool MIX>
+__device__ __forceinline__ void d_flux_any(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level,
+                                           int substep) {
+  if (c.iso) d_flux<R, MIX, true>(c, vb, nb, first, n, cur, level, substep);
+  else d_flux<R, MIX, false>(c, vb, nb, first, n, cur, level, substep);
 }
 
 template <typename R, bool MIX>
 __global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n, int cur, int level, int substep) {
-  d_flux<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
+  d_flux<R, MIX, false>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
+}
+
+template <typename R, bool MIX>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flux_iso(DevCtx c, int first, int n, int cur, int level, int substep) {
+  d_flux<R, MIX, true>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
 }
 
 // ---------------------------------------------------------------------------
@@ -1953,7 +1968,7 @@ __device__ __forceinline__ void run_node(const DevCtx& c, const Node& nd, int b,
     case OP_PRIM: d_prim<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur); break;
     case OP_BHALF: d_bhalf<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level); break;
     case OP_PRED: d_pred<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level); break;
-    case OP_FLUX: d_flux<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep); break;
+    case OP_FLUX: d_flux_any<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep); break;
     case OP_EDGE: d_edge<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep); break;
     case OP_UPDATE: d_update<R, MIX>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.level); break;
     case OP_RESTRICT: d_restrict<R>(c, b, nd.nblk, nd.first, nd.n, nd.cur, nd.aux); break;
@@ -2090,7 +2105,7 @@ __device__ __forceinline__ void run_op(const DevCtx& c, const Node& nd, int vb) 
   else if constexpr (OP == OP_PRIM) d_prim<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur);
   else if constexpr (OP == OP_BHALF) d_bhalf<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level);
   else if constexpr (OP == OP_PRED) d_pred<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level);
-  else if constexpr (OP == OP_FLUX) d_flux<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep);
+  else if constexpr (OP == OP_FLUX) d_flux_any<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep);
   else if constexpr (OP == OP_EDGE) d_edge<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level, nd.substep);
   else if constexpr (OP == OP_UPDATE) d_update<R, MIX>(c, vb, nd.nblk, nd.first, nd.n, nd.cur, nd.level);
 }
@@ -2217,7 +2232,10 @@ hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, i
     case STAGE_PRIM: DISPATCH(k_prim, g, c, task_first, ntask, cur); break;
     case STAGE_BHALF: DISPATCH(k_bhalf, g, c, task_first, ntask, cur, level); break;
     case STAGE_PRED: DISPATCH(k_pred, g, c, task_first, ntask, cur, level); break;
-    case STAGE_FLUX: DISPATCH(k_flux, g, c, task_first, ntask, cur, level, substep); break;
+    case STAGE_FLUX:
+      if (c.iso) DISPATCH(k_flux_iso, g, c, task_first, ntask, cur, level, substep);
+      else DISPATCH(k_flux, g, c, task_first, ntask, cur, level, substep);
+      break;
     case STAGE_EDGE: DISPATCH(k_edge, g, c, task_first, ntask, cur, level, substep); break;
     case STAGE_UPDATE: DISPATCH(k_update, g, c, task_first, ntask, cur, level); break;
     default: return hipErrorInvalidValue;
