@@ -162,6 +162,99 @@ def test_persistent_schedule_claims_complete(name, fixed_dt):
     assert np.array_equal(done, nblk)
 
 
+def _simulate_resident_claims(nodes, preds, items, queues, grid, resident, seed=2, max_idle_rounds=200):
+    """Discrete-time model of the persistent kernel's loop: `grid` workgroups of which at most `resident`
+    run at once (a workgroup not yet resident starts only when a resident one exits); a resident
+    workgroup claims the first ready item of the finest queue that has one, runs it for a random number
+    of ticks and adds its block count to its node's completion counter, polls while items are pending
+    but none is ready, and exits when no queue holds an item.  Returns (completed counts, number of
+    ticks in which every resident workgroup polled while nothing ran, i.e. a stall)."""
+    import random
+    rng = random.Random(seed)
+    nn = len(nodes)
+    nblk = nodes[:, 8]
+    done = np.zeros(nn, dtype=np.int64)
+    heads = np.zeros(len(queues), dtype=np.int64)
+    started, exited = 0, 0
+    active = {}          # workgroup -> (item, remaining ticks) or None while polling
+    stall_ticks = 0
+
+    def ready(v):
+        pf, npr = nodes[v, 10], nodes[v, 11]
+        return all(done[p] >= nblk[p] for p in preds[pf:pf + npr])
+
+    def claim():
+        pending = False
+        for q in range(len(queues) - 1, -1, -1):
+            f, L = queues[q]
+            if heads[q] < L:
+                pending = True
+                if ready(items[f + heads[q], 0]):
+                    heads[q] += 1
+                    return f + heads[q] - 1, True
+        return None, pending
+
+    while exited < grid:
+        while len(active) < resident and started < grid:
+            active[started] = None
+            started += 1
+        running = False
+        for wg in list(active):
+            st = active[wg]
+            if st is not None:
+                it, left = st
+                if left > 1:
+                    active[wg] = (it, left - 1)
+                    running = True
+                    continue
+                done[items[it, 0]] += items[it, 2] - items[it, 1]
+                active[wg] = None
+            got, pending = claim()
+            if got is not None:
+                active[wg] = (got, rng.randint(1, 4))
+                running = True
+            elif not pending:
+                del active[wg]
+                exited += 1
+        if not running and active:
+            stall_ticks += 1
+            if stall_ticks > max_idle_rounds:
+                break
+        else:
+            stall_ticks = 0
+    return done, stall_ticks
+
+
+@pytest.mark.parametrize("name", ["small_three_level", "two_level"])
+@pytest.mark.parametrize("resident", [8, 96])
+def test_persistent_schedule_residency_model(name, resident):
+    """The persistent kernel's claim loop with a grid larger than the co-resident workgroups (the launch
+    uses 4 workgroups per CU, 1024 on the MI355X): every node completes exactly its block count and no
+    tick passes with all resident workgroups polling and nothing running; the same model reports a
+    stall when one item is missing from the tables (a node whose completion count stays short)."""
+    _lib()
+    spec = getattr(H, name)()
+    h = binding.Hierarchy(spec, device=None)
+    nodes, preds, items, queues = h.debug_schedule(False, 1024)
+    for v in range(len(nodes)):                       # items of every node cover its blocks exactly once
+        cover = np.zeros(nodes[v, 8], dtype=np.int64)
+        for it in items[items[:, 0] == v]:
+            cover[it[1]:it[2]] += 1
+        assert np.all(cover == 1), v
+    done, stall = _simulate_resident_claims(nodes, preds, items, queues, grid=1024, resident=resident)
+    assert stall == 0 and np.array_equal(done, nodes[:, 8])
+    # control: drop one item of a node that has successors; its completion count stays short
+    succ = set(int(p) for p in preds)
+    victim = next(i for i in range(len(items)) if int(items[i, 0]) in succ)
+    q = next(k for k, (f, L) in enumerate(queues) if f <= victim < f + L)
+    items2 = np.delete(items, victim, axis=0)
+    queues2 = queues.copy()
+    queues2[q, 1] -= 1
+    queues2[q + 1:, 0] -= 1
+    done2, stall2 = _simulate_resident_claims(nodes, preds, items2, queues2, grid=1024, resident=resident)
+    assert stall2 > 0 and not np.array_equal(done2, nodes[:, 8])
+
+
 @pytest.mark.parametrize("name", ["small_three_level", "root_tiled", "two_level"])
 @pytest.mark.parametrize("fixed_dt", [False, True])
 def test_layered_schedule_plan(name, fixed_dt):
