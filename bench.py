@@ -30,6 +30,11 @@ VALU_PEAK_TFLOPS = 78.6
 # processed entry (add, multiply, divide, square root, min/max each count one; a fused multiply-add two).
 # flux: MUSCL reconstruction of both face states (about 260) + HLLD on its double-star path (about 310).
 ALU_BOUND = {"flux": 570}
+# The fused first stages (class primhalf), priced per cell of the regions they cover: primitives and cell EMFs
+# (about 40 per cell of the update region grown by 2), the half-step face field (3 faces x 21 = 63) and the
+# Hancock increments with the reference EMF (3 axes x (limited slopes of 8 components, two face states, two
+# physical fluxes, the increment) + the half-step reference EMF: about 694), both per cell of the region grown by 1.
+PRIMHALF_FLOPS = {"grown2": 40, "grown1": 63 + 694}
 
 # Algorithmic words moved per processed entry of each kernel class (reads + writes of
 # distinct values, neighbour re-reads not counted).
@@ -49,13 +54,14 @@ WORDS_PER_UNIT = {
 # 512 MiB copy's readings), keyed by (workload, precision, kernel class); valid only for the kernel sources whose
 # hash is stored beside it, null otherwise.
 MEASURED_TRAFFIC = {
-    ("two_level", "fp32", "flux"): {"bytes_per_launch": 645.0e6, "sources": "36c943071a633992:ac4a7d69d709b97f"},
+    ("deep", "fp32", "primhalf"): {"bytes_per_launch": 2.737e9, "sources": "ea1b8d8e1fea16ca:3f418b2c5abe106a"},
 }
 
 # Fraction of the dominant kernel's vector-ALU issue slots used (SQ_INSTS_VALU against 256 CUs x one
 # wave-instruction per cycle x 2.4 GHz over its mean duration), from rocprofv3 counters, same validity rule.
 MEASURED_VALU_ISSUE = {
-    ("two_level", "fp32", "flux"): {"frac": 0.66, "sources": "36c943071a633992:ac4a7d69d709b97f"},
+    ("deep", "fp32", "primhalf"): {"frac": 0.68, "sources": "ea1b8d8e1fea16ca:3f418b2c5abe106a"},
+    ("deep", "fp32", "flux"): {"frac": 0.78, "sources": "ea1b8d8e1fea16ca:3f418b2c5abe106a"},
 }
 
 
@@ -324,6 +330,29 @@ def timed_evolve(h, mode, steps, every, eps, from_level, torch):
             "regrid_seconds": round(regrid_s, 3), "patches_after": len(h.spec.patches)}
 
 
+def primhalf_flops_per_step(h, spec, fused_levels):
+    """Algorithmic flops of the fused first stages per root step: the update box of every patch of a fused
+    level at each substep, grown by 2 (primitives) and by 1 (half-step faces, Hancock increments)."""
+    G = 4
+    tot = 0.0
+    for pid, (lv, lo, hi) in enumerate(spec.patches):
+        if lv not in fused_levels:
+            continue
+        subs = (0,) if lv == 0 else (0, 1)
+        reps = 1 if lv == 0 else 2 ** (lv - 1)
+        for s in subs:
+            if lv == 0:
+                blo, bhi = (G, G, G), tuple(G + hi[a] - lo[a] for a in range(3))
+            else:
+                blo, bhi = h.update_box(pid, s)
+            v1 = v2 = 1
+            for a in range(3):
+                v1 *= bhi[a] - blo[a] + 2
+                v2 *= bhi[a] - blo[a] + 4
+            tot += reps * (PRIMHALF_FLOPS["grown2"] * v2 + PRIMHALF_FLOPS["grown1"] * v1)
+    return tot
+
+
 def extended_overhead(h, spec):
     """Cells advanced per root step (every patch's update region at each of its substeps, extended ghost
     layers included) over the zone-updates counted (interior cells only)."""
@@ -527,8 +556,12 @@ def main():
                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(bytes_per_launch),
                "traffic_bytes_per_launch": None if traffic is None else int(meas["bytes_per_launch"])}
-        if dom in ALU_BOUND:
-            flops_per_launch = units_per_step * ALU_BOUND[dom] / max(launches_per_step, 1)
+        fused_levels = {int(k) for k, v in (tiles or {}).items() if v != "staged"}
+        if dom in ALU_BOUND or (dom == "primhalf" and fused_levels):
+            if dom == "primhalf":
+                flops_per_launch = primhalf_flops_per_step(h, spec, fused_levels) / max(launches_per_step, 1)
+            else:
+                flops_per_launch = units_per_step * ALU_BOUND[dom] / max(launches_per_step, 1)
             tf = flops_per_launch / (avg_ms * 1e-3) / 1e12
             issue = MEASURED_VALU_ISSUE.get((args.workload, args.precision, dom)) if args.ghosts == "extended" else None
             issue = issue["frac"] if issue is not None and issue["sources"] == sources_hash() else None
