@@ -9,6 +9,7 @@ are pure integer/geometry code and hold none of the solver's arithmetic.
 """
 from __future__ import annotations
 
+import heapq
 import math
 from dataclasses import dataclass, field
 
@@ -61,32 +62,49 @@ def kd_ball_patches(rng, n_fine, centre, radius, count, lo_lim, hi_lim, smin=8, 
     """
     lo = [max(lo_lim, int(math.floor((centre[a] - radius) / 2)) * 2) for a in range(3)]
     hi = [min(hi_lim, int(math.ceil((centre[a] + radius) / 2)) * 2) for a in range(3)]
-    leaves = [(tuple(lo), tuple(hi))]
+    r2 = radius * radius
 
     def meets(b):
-        return _box_dist2(b[0], b[1], centre) < radius * radius
+        return _box_dist2(b[0], b[1], centre) < r2
+
+    def ext(b):
+        return [b[1][a] - b[0][a] for a in range(3)]
 
     def vol(b):
-        return int(np.prod(np.asarray(b[1]) - np.asarray(b[0])))
+        e = ext(b)
+        return e[0] * e[1] * e[2]
 
-    while True:
-        hits = [b for b in leaves if meets(b)]
-        big = [b for b in hits if max(np.asarray(b[1]) - np.asarray(b[0])) > smax]
-        if len(hits) >= count and not big:
-            break
-        cand = [b for b in hits if max(np.asarray(b[1]) - np.asarray(b[0])) >= 2 * smin]
-        if not cand:
+    # the leaves, the number of ball-meeting leaves and of those wider than smax, and a heap
+    # of the ball-meeting leaves that can still be cut, largest volume first
+    leaves = set()
+    counts = [0, 0]
+    heap = []
+
+    def add(b):
+        leaves.add(b)
+        if meets(b):
+            w = max(ext(b))
+            counts[0] += 1
+            counts[1] += w > smax
+            if w >= 2 * smin:
+                heapq.heappush(heap, (-vol(b), b))
+
+    add((tuple(lo), tuple(hi)))
+    while counts[0] < count or counts[1]:
+        if not heap:
             raise ValueError("cannot reach the requested patch count")
-        cand.sort(key=lambda b: (-vol(b), b))
-        b = cand[0]
-        ext = np.asarray(b[1]) - np.asarray(b[0])
-        ax = int(np.argmax(ext))
-        ncut = (ext[ax] - 2 * smin) // 2 + 1
+        _, b = heapq.heappop(heap)
+        e = ext(b)
+        leaves.remove(b)
+        counts[0] -= 1
+        counts[1] -= max(e) > smax
+        ax = e.index(max(e))  # first longest axis
+        ncut = (e[ax] - 2 * smin) // 2 + 1
         cut = b[0][ax] + smin + 2 * int(rng.integers(0, ncut))
         l1 = list(b[1]); l1[ax] = cut
         h2 = list(b[0]); h2[ax] = cut
-        leaves.remove(b)
-        leaves += [(b[0], tuple(l1)), (tuple(h2), b[1])]
+        add((b[0], tuple(l1)))
+        add((tuple(h2), b[1]))
     hits = sorted([b for b in leaves if meets(b)])
     if len(hits) > count:
         # drop the leaves farthest from the centre (deterministic)
