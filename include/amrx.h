@@ -393,6 +393,15 @@ int hier_debug_layers(amrx_hier* h, int fixed_dt, int* sizes, int* first, int* i
 int hier_debug_schedule(amrx_hier* h, int fixed_dt, int nworkgroups, int* sizes, int* nodes, int* preds, int* items,
                         int* queues);
 
+/* The concurrent schedule's capture plan (AMRX_CONCURRENT, which is switched
+ * off) for the current buffer parities and tuning: sizes = (nodes, preds, ops,
+ * side streams, events); nodes and preds as hier_debug_schedule reports them
+ * (fused tiles included where the tuning enables them); ops (4 ints each:
+ * kind, stream, event, node) in issue order, kind 0 = record event on stream,
+ * 1 = stream waits for event, 2 = launch node on stream, 3 = clear the device
+ * slots; stream -1 is the capturing stream.  Pure host call. */
+int hier_debug_concurrent(amrx_hier* h, int fixed_dt, int* sizes, int* nodes, int* preds, int* ops);
+
 /* The update region [lo, hi) (padded cell indices) of a patch at `substep`. */
 int hier_debug_update_box(const amrx_hier* h, int patch_id, int substep, int lo[3], int hi[3]);
 

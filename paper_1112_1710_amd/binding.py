@@ -65,6 +65,8 @@ EXPORTS = {
     "hier_init_from_levels_bytes": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.POINTER(C.c_size_t)], C.c_int),
     "hier_init_from_levels": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int, C.c_void_p, C.c_size_t], C.c_int),
     "hier_init_from_levels_static": ([C.c_void_p, C.c_void_p, C.c_void_p, C.c_int], C.c_int),
+    "hier_debug_concurrent": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int),
+                               C.POINTER(C.c_int)], C.c_int),
     "hier_debug_layers": ([C.c_void_p, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
     "hier_debug_schedule": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int),
                              C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
@@ -434,6 +436,20 @@ class Hierarchy:
         src.synchronize()
         b.synchronize()
         self._check(self.lib.hier_init_from_levels_static(self.h, b.h, src.h, int(level)))
+
+    def debug_concurrent(self, fixed_dt=False):
+        """Concurrent schedule capture plan: nodes (N, 12), preds, ops (K, 4: kind, stream, event,
+        node), side streams, events."""
+        sizes = (C.c_int * 5)()
+        self._check(self.lib.hier_debug_concurrent(self.h, int(fixed_dt), sizes, None, None, None))
+        nn, npr, nop = sizes[0], sizes[1], sizes[2]
+        nodes = (C.c_int * max(1, 12 * nn))()
+        preds = (C.c_int * max(1, npr))()
+        ops = (C.c_int * max(1, 4 * nop))()
+        self._check(self.lib.hier_debug_concurrent(self.h, int(fixed_dt), sizes, nodes, preds, ops))
+        a = np.ctypeslib.as_array
+        return (a(nodes)[:12 * nn].reshape(nn, 12).copy(), a(preds)[:npr].copy(),
+                a(ops)[:4 * nop].reshape(nop, 4).copy(), sizes[3], sizes[4])
 
     def debug_layers(self, fixed_dt=False):
         """Layered schedule: the first item of each layer (layers + 1) and the items (M, 4) in launch order."""

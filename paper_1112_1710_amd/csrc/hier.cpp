@@ -1799,6 +1799,50 @@ hipError_t launch_node(amrx_hier* h, const Node& nd, hipStream_t s) {
 // stream per level (levels beyond the stream count share streams round-robin); an edge
 // between launches on different streams becomes an event wait, so each launch waits
 // only for the launches whose data it reads or overwrites.
+//
+// The capture is planned on the host as a list of stream operations in issue order, and
+// concurrent_step only replays the list.  Streams: -1 is the capturing stream, 0..ns-1 the
+// side streams.  Events: v < nn is recorded after node v, nn is the fork (recorded on the
+// capturing stream, waited for by every side stream before its first launch), nn + 1 + i
+// the join of side stream i (waited for by the capturing stream at the end).
+enum { CAP_RECORD = 0, CAP_WAIT = 1, CAP_LAUNCH = 2, CAP_CLEAR = 3 };
+struct CapOp {
+  int kind, stream, event, node;
+};
+struct CapPlan {
+  int nstreams = 0, nevents = 0;
+  std::vector<CapOp> ops;
+};
+
+CapPlan plan_concurrent(const SchedImage& img, int nlev, bool fixed_dt) {
+  CapPlan P;
+  const int nn = (int)img.nodes.size();
+  const int ns = std::max(1, std::min(nlev, NCSTREAM));
+  P.nstreams = ns;
+  P.nevents = nn + ns + 1;
+  auto stream_of = [&](int v) { return img.nodes[v].level % ns; };
+  // with dt from the CFL condition the slots are cleared inside the graph; with a preset dt the
+  // host clears them and sets dt before each replay
+  if (!fixed_dt) P.ops.push_back({CAP_CLEAR, -1, -1, -1});
+  P.ops.push_back({CAP_RECORD, -1, nn, -1});
+  for (int i = 0; i < ns; ++i) P.ops.push_back({CAP_WAIT, i, nn, -1});
+  for (int v = 0; v < nn; ++v) {
+    const Node& nd = img.nodes[v];
+    const int sv = stream_of(v);
+    for (int k = nd.pred_first; k < nd.pred_first + nd.npred; ++k) {
+      const int p = img.preds[k];
+      if (stream_of(p) != sv) P.ops.push_back({CAP_WAIT, sv, p, -1});
+    }
+    P.ops.push_back({CAP_LAUNCH, sv, -1, v});
+    P.ops.push_back({CAP_RECORD, sv, v, -1});
+  }
+  for (int i = 0; i < ns; ++i) {
+    P.ops.push_back({CAP_RECORD, i, nn + 1 + i, -1});
+    P.ops.push_back({CAP_WAIT, -1, nn + 1 + i, -1});
+  }
+  return P;
+}
+
 int concurrent_step(amrx_hier* h, double* dt0) {
   hipStream_t s = (hipStream_t)h->d.stream;
   if (!s) return fail(h, AMRX_EINVAL, "the concurrent schedule needs a non-default stream");
@@ -1807,42 +1851,31 @@ int concurrent_step(amrx_hier* h, double* dt0) {
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
     const SchedImage img = build_sched(h, fixed, 1, true);
-    const int nn = (int)img.nodes.size();
-    const int ns = std::max(1, std::min(h->nlev, NCSTREAM));
-    for (int i = (int)h->cstreams.size(); i < ns; ++i) {
+    const CapPlan P = plan_concurrent(img, h->nlev, fixed);
+    for (int i = (int)h->cstreams.size(); i < P.nstreams; ++i) {
       hipStream_t t = nullptr;
       HIPCHK(hipStreamCreateWithFlags(&t, hipStreamNonBlocking), "stream create");
       h->cstreams.push_back(t);
     }
-    while ((int)h->cevents.size() < nn + ns + 1) {
+    while ((int)h->cevents.size() < P.nevents) {
       hipEvent_t e = nullptr;
       HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming), "event create");
       h->cevents.push_back(e);
     }
-    auto stream_of = [&](const Node& nd) { return nd.level % ns; };
+    auto stream = [&](int i) { return i < 0 ? s : h->cstreams[i]; };
     const bool timing = h->timing;
     h->timing = false;
     HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
     hipError_t e = hipSuccess;
-    if (!fixed) e = launch_clear_slots(h->ctx);
-    // fork: every branch stream starts after the work already captured on s
-    hipEvent_t fork = h->cevents[nn];
-    if (e == hipSuccess) e = hipEventRecord(fork, s);
-    for (int i = 0; i < ns && e == hipSuccess; ++i) e = hipStreamWaitEvent(h->cstreams[i], fork, 0);
-    for (int v = 0; v < nn && e == hipSuccess; ++v) {
-      const Node& nd = img.nodes[v];
-      const int sv = stream_of(nd);
-      for (int k = nd.pred_first; k < nd.pred_first + nd.npred && e == hipSuccess; ++k) {
-        const int p = img.preds[k];
-        if (stream_of(img.nodes[p]) != sv) e = hipStreamWaitEvent(h->cstreams[sv], h->cevents[p], 0);
+    for (size_t k = 0; k < P.ops.size() && e == hipSuccess; ++k) {
+      const CapOp& op = P.ops[k];
+      switch (op.kind) {
+        case CAP_CLEAR: e = launch_clear_slots(h->ctx); break;  // h->ctx launches on s
+        case CAP_RECORD: e = hipEventRecord(h->cevents[op.event], stream(op.stream)); break;
+        case CAP_WAIT: e = hipStreamWaitEvent(stream(op.stream), h->cevents[op.event], 0); break;
+        case CAP_LAUNCH: e = launch_node(h, img.nodes[op.node], stream(op.stream)); break;
+        default: e = hipErrorInvalidValue;
       }
-      if (e == hipSuccess) e = launch_node(h, nd, h->cstreams[sv]);
-      if (e == hipSuccess) e = hipEventRecord(h->cevents[v], h->cstreams[sv]);
-    }
-    // join every branch back into s
-    for (int i = 0; i < ns && e == hipSuccess; ++i) {
-      e = hipEventRecord(h->cevents[nn + 1 + i], h->cstreams[i]);
-      if (e == hipSuccess) e = hipStreamWaitEvent(s, h->cevents[nn + 1 + i], 0);
     }
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(s, &g);
@@ -3019,6 +3052,23 @@ int hier_debug_schedule(amrx_hier* h, int fixed_dt, int nworkgroups, int* sizes,
   if (preds) std::memcpy(preds, img.preds.data(), sizeof(int) * img.preds.size());
   if (items) std::memcpy(items, img.items.data(), sizeof(Item) * img.items.size());
   if (queues) std::memcpy(queues, img.queues.data(), sizeof(Queue) * img.queues.size());
+  return AMRX_OK;
+}
+
+int hier_debug_concurrent(amrx_hier* h, int fixed_dt, int* sizes, int* nodes, int* preds, int* ops) {
+  if (!h || !sizes) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  if (h->time_ghosts) return AMRX_EINVAL;
+  const SchedImage img = build_sched(h, fixed_dt != 0, 1, true);
+  const CapPlan P = plan_concurrent(img, h->nlev, fixed_dt != 0);
+  sizes[0] = (int)img.nodes.size();
+  sizes[1] = (int)img.preds.size();
+  sizes[2] = (int)P.ops.size();
+  sizes[3] = P.nstreams;
+  sizes[4] = P.nevents;
+  if (nodes) std::memcpy(nodes, img.nodes.data(), sizeof(Node) * img.nodes.size());
+  if (preds) std::memcpy(preds, img.preds.data(), sizeof(int) * img.preds.size());
+  if (ops) std::memcpy(ops, P.ops.data(), sizeof(CapOp) * P.ops.size());
   return AMRX_OK;
 }
 

@@ -5,6 +5,7 @@ C++) must equal the oracle's brute-force maps bit for bit (Sec. 2: data
 shared with same-level neighbours; Sec. 2.2: prolongation from the parent).
 """
 import ctypes
+import functools
 import os
 import re
 
@@ -23,6 +24,13 @@ def _lib():
         return binding.load_library()
     except ImportError as e:  # not built
         pytest.skip(str(e))
+
+
+@functools.lru_cache(maxsize=None)
+def _schedule_hier(name):
+    """Host-only hierarchy shared by the schedule-table tests (their calls are pure host reads;
+    the tests that tune set every switch they depend on)."""
+    return binding.Hierarchy(getattr(H, name)(), device=None)
 
 
 def test_exports_every_declared_symbol():
@@ -123,7 +131,7 @@ def test_persistent_schedule_claims_complete(name, fixed_dt):
     import random
     _lib()
     spec = getattr(H, name)()
-    h = binding.Hierarchy(spec, device=None)
+    h = _schedule_hier(name)
     nodes, preds, items, queues = h.debug_schedule(fixed_dt, 1024)
     nn = len(nodes)
     nblk = nodes[:, 8]
@@ -234,7 +242,7 @@ def test_persistent_schedule_residency_model(name, resident):
     stall when one item is missing from the tables (a node whose completion count stays short)."""
     _lib()
     spec = getattr(H, name)()
-    h = binding.Hierarchy(spec, device=None)
+    h = _schedule_hier(name)
     nodes, preds, items, queues = h.debug_schedule(False, 1024)
     for v in range(len(nodes)):                       # items of every node cover its blocks exactly once
         cover = np.zeros(nodes[v, 8], dtype=np.int64)
@@ -263,7 +271,7 @@ def test_layered_schedule_plan(name, fixed_dt):
     and orders a layer's items finest level first, program order within a level."""
     _lib()
     spec = getattr(H, name)()
-    h = binding.Hierarchy(spec, device=None)
+    h = _schedule_hier(name)
     nodes, preds, _, _ = h.debug_schedule(fixed_dt, 1)
     first, items = h.debug_layers(fixed_dt)
     nn = len(nodes)
@@ -292,6 +300,88 @@ def test_layered_schedule_plan(name, fixed_dt):
     assert len(first) - 1 <= nn
     if spec.levels() > 1:
         assert len(first) - 1 < nn  # launches of different levels share layers
+
+
+def _simulate_capture(ops, nn, nstreams, nevents):
+    """Stream-capture semantics over a capture plan: a stream joins the capture by waiting for an
+    event recorded in it, a launch depends on everything its stream has seen so far, a record
+    snapshots that set.  Returns each launch's direct dependencies, the ancestor bitmasks, the
+    capturing stream's final set and each side stream's final set (bit nn = the slot clear)."""
+    CLEAR = nn
+    frontier = {-1: 0}
+    events = {}
+    deps = {}
+    for kind, st, ev, v in ops:
+        assert -1 <= st < nstreams
+        if kind == 0:  # record
+            assert st in frontier, "record on a stream outside the capture"
+            assert 0 <= ev < nevents and ev not in events, ev
+            events[ev] = frontier[st]
+        elif kind == 1:  # wait
+            assert ev in events, "wait for an event not recorded in this capture"
+            frontier[st] = frontier.get(st, 0) | events[ev]
+        elif kind == 2:  # launch
+            assert st in frontier, "launch on a stream outside the capture"
+            assert 0 <= v < nn and v not in deps, v
+            deps[v] = frontier[st]
+            frontier[st] = 1 << v
+        else:  # slot clear
+            assert kind == 3 and st == -1 and CLEAR not in deps
+            deps[CLEAR] = frontier[st]
+            frontier[st] = 1 << CLEAR
+    anc = {}
+    for v in sorted(deps, key=lambda x: -1 if x == CLEAR else x):
+        m = deps[v]
+        a = m
+        for u in range(nn + 1):
+            if m >> u & 1:
+                a |= anc[u]
+        anc[v] = a
+    return deps, anc, frontier
+
+
+@pytest.mark.parametrize("name", ["small_three_level", "root_tiled", "two_level"])
+@pytest.mark.parametrize("fixed_dt", [False, True])
+@pytest.mark.parametrize("fused", [(0, 0), (1, 0), (1, 1)])
+def test_concurrent_capture_plan(name, fixed_dt, fused):
+    """The concurrent schedule's capture plan (switched off after its first capture crashed on the
+    GPU): every operation names a stream, event and node inside the pools the library creates for
+    it, every side stream enters the capture through the fork before its first launch and is joined
+    back before the capture ends, every event is recorded before it is waited for, every node is
+    launched exactly once after all its predecessors (and after the slot clear when dt comes from
+    the CFL condition), and launches of different levels are left free to overlap."""
+    _lib()
+    spec = getattr(H, name)()
+    h = _schedule_hier(name)
+    h.tune_set(binding.TUNE_FUSED, fused[0])
+    h.tune_set(binding.TUNE_FUSED_EU, fused[1])
+    nodes, preds, ops, nstreams, nevents = h.debug_concurrent(fixed_dt)
+    nn = len(nodes)
+    assert nstreams == max(1, min(spec.levels(), 4)) and nevents == nn + nstreams + 1
+    sched_nodes, sched_preds, _, _ = h.debug_schedule(fixed_dt, 1)
+    if fused == (0, 0):  # without fused tiles the plan runs the persistent schedule's graph
+        assert np.array_equal(nodes, sched_nodes) and np.array_equal(preds, sched_preds)
+    fused_ops = {14, 15}  # fused first stages, fused edge EMF + update
+    assert bool(np.isin(nodes[:, 0], list(fused_ops)).any()) == (fused != (0, 0))
+    deps, anc, frontier = _simulate_capture([tuple(int(x) for x in o) for o in ops], nn, nstreams, nevents)
+    assert sorted(v for v in deps if v < nn) == list(range(nn))
+    assert (nn in deps) == (not fixed_dt)
+    for v in range(nn):
+        pf, npr = nodes[v, 10], nodes[v, 11]
+        for p in preds[pf:pf + npr]:
+            assert p < v and anc[v] >> int(p) & 1, (p, v)
+        if not fixed_dt:
+            assert anc[v] >> nn & 1, v
+    final = frontier[-1]
+    for u in range(nn + 1):
+        if final >> u & 1:
+            final |= anc[u]
+    for st in range(nstreams):
+        assert st in frontier and frontier[st] & ~final == 0, st
+    if spec.levels() > 1:
+        free = any(not (anc[v] >> u & 1) and not (anc[u] >> v & 1)
+                   for v in range(nn) for u in range(v) if nodes[u, 1] != nodes[v, 1])
+        assert free
 
 
 def test_padded_volume_limit():
