@@ -227,15 +227,24 @@ def lowbeta_report(spec, field, steps, torch):
                                    for k, v in drift.items()}}
 
 
+def run_steps(h, mode, n):
+    """`n` consecutive root steps: one hier_steps call (no host synchronisation between the steps)
+    where the schedule supports it, else one synchronising hier_step per step."""
+    from paper_1112_1710_amd import BATCHED, GRAPH, PLAIN
+    if mode in (PLAIN, BATCHED, GRAPH):
+        h.steps(n, mode)
+    else:
+        for _ in range(n):
+            h.step(mode)
+
+
 def timed_steps(h, mode, steps, warmup, torch):
     """Mean wall time of one root step over `steps` consecutive steps after `warmup` untimed ones."""
-    for _ in range(warmup):
-        h.step(mode)
+    run_steps(h, mode, warmup)
     torch.cuda.synchronize()
     h.timing(True)
     t0 = time.perf_counter()
-    for _ in range(steps):
-        h.step(mode)
+    run_steps(h, mode, steps)
     torch.cuda.synchronize()
     total = time.perf_counter() - t0
     h.timing(False)

@@ -191,6 +191,18 @@ int cfl_dt(amrx_hier* h, double* dt0);
  * cfl_dt() chooses it and it is returned.  Synchronising. */
 int hier_step(amrx_hier* h, int mode, double* dt0);
 
+/* `nsteps` root steps (Sec. 2.2 recursion AMR(0), one after another) enqueued
+ * back to back with no host synchronisation between them; mode AMRX_PLAIN,
+ * AMRX_BATCHED or AMRX_GRAPH.  Every step takes dt0 if dt0 > 0, otherwise
+ * its own dt from the CFL condition, computed on the device.  Synchronises
+ * once, at the end.  *t_advanced = the sum of the steps' dt, accumulated on
+ * the device in float64 in step order; *dt_last = the last step's dt (0 for
+ * nsteps = 0); either pointer may be NULL.  EPHYS if any of the steps flagged
+ * an unphysical state (the flag is latched over the whole run).  States and
+ * dts equal those of nsteps hier_step() calls with the same mode and dt0,
+ * bit for bit.  EINVAL for another mode, nsteps < 0 or dt0 < 0 or NaN. */
+int hier_steps(amrx_hier* h, int mode, int nsteps, double dt0, double* t_advanced, double* dt_last);
+
 /* Sums over leaf cells (not covered by a finer patch) of (rho, m_x, m_y,
  * m_z, E, B_x, B_y, B_z) * cell volume, in float64 with compensated
  * summation: sum[i] + comp[i] is the result.  Synchronising. */

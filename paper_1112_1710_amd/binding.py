@@ -49,6 +49,8 @@ EXPORTS = {
     "sync_level": ([C.c_void_p, C.c_int], C.c_int),
     "cfl_dt": ([C.c_void_p, C.POINTER(C.c_double)], C.c_int),
     "hier_step": ([C.c_void_p, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "hier_steps": ([C.c_void_p, C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)],
+                   C.c_int),
     "hier_conservation": ([C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_double)], C.c_int),
     "hier_diag": ([C.c_void_p, C.POINTER(C.c_double), C.c_int], C.c_int),
     "hier_timing_enable": ([C.c_void_p, C.c_int], C.c_int),
@@ -284,6 +286,13 @@ class Hierarchy:
         v = C.c_double(float(dt))
         self._check(self.lib.hier_step(self.h, mode, C.byref(v)))
         return v.value
+
+    def steps(self, n, mode=BATCHED, dt=0.0):
+        """`n` root steps with one synchronisation at the end (hier_steps): (time advanced, last dt)."""
+        t = C.c_double()
+        last = C.c_double()
+        self._check(self.lib.hier_steps(self.h, mode, int(n), float(dt), C.byref(t), C.byref(last)))
+        return t.value, last.value
 
     def conservation(self):
         s = (C.c_double * 8)()

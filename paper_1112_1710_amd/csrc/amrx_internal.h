@@ -183,6 +183,8 @@ enum { STAGE_PRIM = 0, STAGE_BHALF, STAGE_PRED, STAGE_FLUX, STAGE_EDGE, STAGE_UP
 // SLOT_SCHED is set when a persistent workgroup gave up waiting for work.
 enum { SLOT_PHYS = 0, SLOT_SYNC_F = 1, SLOT_SYNC_B = 2, SLOT_DT = 3, SLOT_SCHED = 4, SLOT_SMAX = 8 /* + level */,
        NSLOT = 8 + AMRX_MAXLEV };
+// accumulators of a run of root steps (hier_steps), after the slots: k_clear_slots leaves them alone
+enum { ACC_PHYS = NSLOT, ACC_TIME = NSLOT + 1, ACC_STEPS = NSLOT + 2, NSLOT_ALL = NSLOT + 3 };
 
 // ---------------------------------------------------------------------------
 // persistent schedule of one root step: nodes (one batched launch's worth of
@@ -244,6 +246,8 @@ hipError_t launch_cfl(const DevCtx& c, int task_first, int ntask, int blk_first,
 hipError_t launch_conservation(const DevCtx& c, int task_first, int ntask, int blk_first, int nblk,
                                const int* cur_of_level);
 hipError_t launch_clear_slots(const DevCtx& c);
+hipError_t launch_clear_acc(const DevCtx& c);
+hipError_t launch_step_acc(const DevCtx& c);
 // every level's CFL reduction in one launch; level l takes blocks [grid0[l], grid0[l + 1])
 struct CflLevels {
   int nlev;

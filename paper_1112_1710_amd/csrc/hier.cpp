@@ -1375,7 +1375,7 @@ int finalize_impl(amrx_hier* h) {
   h->off_sync = o; o = align256(o + sizeof(SyncPair) * h->syncs.size());
   h->off_cov = o; o = align256(o + sizeof(int) * h->cov.size());
   h->meta_bytes = o;
-  h->off_slots = o; o = align256(o + sizeof(unsigned long long) * NSLOT);
+  h->off_slots = o; o = align256(o + sizeof(unsigned long long) * NSLOT_ALL);
   {
     // conservation: 16 doubles per block; CFL: one double per block of every level's reduction
     size_t cfl_blocks = 0;
@@ -1652,7 +1652,7 @@ int amr_recursive(amrx_hier* h, int level, double dt, bool plain, bool first_don
 int amr_recursive(amrx_hier* h, int level, double dt, bool plain) { return amr_recursive(h, level, dt, plain, false); }
 
 int read_slots(amrx_hier* h, unsigned long long* out) {
-  HIPCHK(hipMemcpyAsync(out, h->scratch + h->off_slots, sizeof(unsigned long long) * NSLOT, hipMemcpyDeviceToHost,
+  HIPCHK(hipMemcpyAsync(out, h->scratch + h->off_slots, sizeof(unsigned long long) * NSLOT_ALL, hipMemcpyDeviceToHost,
                         (hipStream_t)h->d.stream),
          "slot readback");
   HIPCHK(hipStreamSynchronize((hipStream_t)h->d.stream), "stream synchronize");
@@ -1685,7 +1685,7 @@ int enqueue_cfl(amrx_hier* h) {
 
 // Read dt0 and the unphysical-state flag after the stream drained.
 int finish_step(amrx_hier* h, double* dt0) {
-  unsigned long long sl[NSLOT];
+  unsigned long long sl[NSLOT_ALL];
   int rc = read_slots(h, sl);
   if (rc) return rc;
   if (dt0) *dt0 = bits_to_double(sl[SLOT_DT]);
@@ -1719,10 +1719,11 @@ unsigned parity_key(const amrx_hier* h) {
 }
 
 // Graph schedule: the batched root step captured once per (buffer parities, dt source) and replayed.
-int graph_step(amrx_hier* h, double* dt0) {
+// Enqueues one step (dt0 > 0 fixes it) without waiting for it.
+int graph_enqueue(amrx_hier* h, double dt0) {
   hipStream_t s = (hipStream_t)h->d.stream;
   if (!s) return fail(h, AMRX_EINVAL, "the graph schedule needs a non-default stream");
-  const bool fixed = *dt0 > 0.0;
+  const bool fixed = dt0 > 0.0;
   const unsigned key = parity_key(h) * 2u + (fixed ? 1u : 0u);
   auto it = h->graphs.find(key);
   if (it == h->graphs.end()) {
@@ -1756,10 +1757,16 @@ int graph_step(amrx_hier* h, double* dt0) {
   }
   if (fixed) {
     HIPCHK(launch_clear_slots(h->ctx), "clear slots");
-    HIPCHK(launch_set_dt(h->ctx, *dt0), "set dt");
+    HIPCHK(launch_set_dt(h->ctx, dt0), "set dt");
   }
   HIPCHK(hipGraphLaunch(it->second.exec, s), "graph launch");
   std::memcpy(h->cur, it->second.cur_after, sizeof h->cur);
+  return AMRX_OK;
+}
+
+int graph_step(amrx_hier* h, double* dt0) {
+  const int rc = graph_enqueue(h, *dt0);
+  if (rc) return rc;
   return finish_step(h, dt0);
 }
 
@@ -2006,7 +2013,7 @@ int layered_step(amrx_hier* h, double* dt0) {
            "layer launch");
   }
   std::memcpy(h->cur, v.cur_after, sizeof h->cur);
-  unsigned long long sl[NSLOT];
+  unsigned long long sl[NSLOT_ALL];
   const int rc = read_slots(h, sl);
   if (rc) return rc;
   *dt0 = bits_to_double(sl[SLOT_DT]);
@@ -2070,7 +2077,7 @@ int persistent_step(amrx_hier* h, double* dt0) {
   if (fixed) HIPCHK(launch_set_dt(h->ctx, *dt0), "set dt");
   HIPCHK(launch_persistent(h->ctx, sc, v.nnodes, h->nworkgroups, h->nlev, h->d.cfl), "persistent launch");
   std::memcpy(h->cur, v.cur_after, sizeof h->cur);
-  unsigned long long sl[NSLOT];
+  unsigned long long sl[NSLOT_ALL];
   const int rc = read_slots(h, sl);
   if (rc) return rc;
   *dt0 = bits_to_double(sl[SLOT_DT]);
@@ -2310,6 +2317,26 @@ int hier_step(amrx_hier* h, int mode, double* dt0) {
   return finish_step(h, dt0);
 }
 
+int hier_steps(amrx_hier* h, int mode, int nsteps, double dt0, double* t_advanced, double* dt_last) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (nsteps < 0 || !(dt0 >= 0.0) || (mode != AMRX_PLAIN && mode != AMRX_BATCHED && mode != AMRX_GRAPH))
+    return AMRX_EINVAL;
+  HIPCHK(launch_clear_acc(h->ctx), "clear step accumulators");
+  for (int n = 0; n < nsteps; ++n) {
+    const int rc = mode == AMRX_GRAPH ? graph_enqueue(h, dt0) : enqueue_step(h, mode == AMRX_PLAIN, dt0);
+    if (rc) return rc;
+    HIPCHK(launch_step_acc(h->ctx), "step accumulators");
+  }
+  unsigned long long sl[NSLOT_ALL];
+  const int rc = read_slots(h, sl);
+  if (rc) return rc;
+  if (t_advanced) *t_advanced = bits_to_double(sl[ACC_TIME]);
+  if (dt_last) *dt_last = nsteps > 0 ? bits_to_double(sl[SLOT_DT]) : 0.0;
+  if (sl[ACC_STEPS] != (unsigned long long)nsteps) return fail(h, AMRX_EHIP, "step accumulator count mismatch");
+  if (sl[ACC_PHYS]) return fail(h, AMRX_EPHYS, "unphysical state (rho<=0, p<=0 or non-finite) in one of the steps");
+  return AMRX_OK;
+}
+
 int hier_conservation(amrx_hier* h, double sum[8], double comp[8]) {
   if (!ready(h)) return AMRX_ESTATE;
   if (!sum || !comp) return AMRX_EINVAL;
@@ -2330,7 +2357,7 @@ int hier_conservation(amrx_hier* h, double sum[8], double comp[8]) {
 int hier_diag(amrx_hier* h, double* out, int n) {
   if (!ready(h)) return AMRX_ESTATE;
   if (!out || n < 0 || n > 3) return AMRX_EINVAL;
-  unsigned long long sl[NSLOT];
+  unsigned long long sl[NSLOT_ALL];
   const int rc = read_slots(h, sl);
   if (rc) return rc;
   const double v[3] = {bits_to_double(sl[SLOT_SYNC_F]), bits_to_double(sl[SLOT_SYNC_B]), sl[SLOT_PHYS] ? 1.0 : 0.0};

@@ -1887,6 +1887,22 @@ __global__ void k_clear_slots(DevCtx c) {
   if (t < NSLOT) c.slots[t] = 0ULL;
 }
 
+__global__ void k_clear_acc(DevCtx c) {
+  const int t = threadIdx.x;
+  if (t < NSLOT_ALL - NSLOT) c.slots[NSLOT + t] = 0ULL;
+}
+
+// after a root step: latch its unphysical-state flag, add its dt to the time advanced, count it
+__global__ void k_step_acc(DevCtx c) {
+  if (threadIdx.x == 0) {
+    unsigned long long* s = c.slots;
+    s[ACC_PHYS] |= s[SLOT_PHYS];
+    const double t = __longlong_as_double((long long)s[ACC_TIME]) + __longlong_as_double((long long)s[SLOT_DT]);
+    s[ACC_TIME] = (unsigned long long)__double_as_longlong(t);
+    s[ACC_STEPS] += 1ULL;
+  }
+}
+
 __global__ void k_set_dt(DevCtx c, double dt0) {
   if (threadIdx.x == 0) c.slots[SLOT_DT] = (unsigned long long)__double_as_longlong(dt0);
 }
@@ -2395,6 +2411,16 @@ hipError_t launch_conservation(const DevCtx& c, int task_first, int ntask, int b
 
 hipError_t launch_clear_slots(const DevCtx& c) {
   k_clear_slots<<<1, 64, 0, c.stream>>>(c);
+  return hipGetLastError();
+}
+
+hipError_t launch_clear_acc(const DevCtx& c) {
+  k_clear_acc<<<1, 64, 0, c.stream>>>(c);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_acc(const DevCtx& c) {
+  k_step_acc<<<1, 64, 0, c.stream>>>(c);
   return hipGetLastError();
 }
 

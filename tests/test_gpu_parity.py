@@ -608,3 +608,63 @@ def test_time_ghost_schedules_and_fused_kernels_bit_identical():
         assert abs(tot1[q] - tot0[q]) <= 1e-13 * abs(tot0[q]), q
     d = ref.diag()
     assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("mode", [PLAIN, BATCHED, GRAPH])
+@pytest.mark.parametrize("fixed", [False, True])
+def test_steps_without_host_synchronisation_equal_single_steps(precision, mode, fixed):
+    """hier_steps: four root steps enqueued with one synchronisation at the end give the states,
+    the dts and the time advanced of four synchronising hier_step calls, bit for bit."""
+    spec = H.small_three_level()
+    _say("hier_steps against hier_step", precision, mode, "fixed dt" if fixed else "CFL dt")
+    field = SmoothField(1112)
+    a = Hierarchy(spec, precision)
+    b = Hierarchy(spec, precision)
+    a.set_field(field)
+    b.set_field(field)
+    dt0 = 0.5 * a.cfl_dt() if fixed else 0.0
+    dts = [a.step(mode, dt0) for _ in range(4)]
+    t, last = b.steps(4, mode, dt0)
+    total = 0.0
+    for d in dts:
+        total += d
+    assert t == total and last == dts[-1]
+    assert len(set(dts)) == 1 if fixed else len(set(dts)) > 1
+    _assert_same_interiors(spec, a, b)
+    assert b.steps(0, mode, dt0) == (0.0, 0.0)
+
+
+def test_steps_latch_an_unphysical_state_over_the_run():
+    """One coarse cell under a refined patch, far from the patch's edges, with negative pressure:
+    the first root step flags it, restriction then replaces the cell by the mean of its children,
+    and the second step is clean.  Single steps report EPHYS for the first step only; a two-step
+    run still reports it at its end, and its states equal those of the single steps."""
+    spec = H.HierarchySpec(root_n=(16, 16, 16),
+                           patches=[(0, (0, 0, 0), (16, 16, 16)), (1, (4, 4, 4), (28, 28, 28))])
+    field = SmoothField(1112)
+    _say("hier_steps, unphysical coarse cell under a refined patch")
+    clean = Hierarchy(spec, FP64)
+    clean.set_field(field)
+    dt0 = 0.5 * clean.cfl_dt()
+
+    def corrupted():
+        h = Hierarchy(spec, FP64)
+        h.set_field(field)
+        cells, faces = h.download(0)
+        cells[4][G + 8, G + 8, G + 8] = 0.01  # E below the magnetic energy: p < 0
+        h.upload(0, cells, faces)
+        h.synchronize()
+        return h
+
+    single = corrupted()
+    with pytest.raises(AmrxError) as err:
+        single.step(BATCHED, dt0)
+    assert err.value.code == -7
+    assert single.step(BATCHED, dt0) == dt0  # the second step alone is clean
+    run = corrupted()
+    with pytest.raises(AmrxError) as err:
+        run.steps(2, BATCHED, dt0)
+    assert err.value.code == -7
+    _assert_same_interiors(spec, single, run)
+    assert run.steps(1, BATCHED, dt0) == (dt0, dt0)  # the latch starts afresh with every run

@@ -64,6 +64,7 @@ def test_error_codes_on_bad_input():
     assert lib.patch_add(hh, 1, i3((10, 10, 10)), i3((14, 14, 14)), ctypes.byref(pid)) == -3  # overlap
     assert lib.patch_add(hh, 3, i3((4, 4, 4)), i3((8, 8, 8)), ctypes.byref(pid)) == -1      # level > max
     assert lib.hier_bind(hh, None, 0, None, 0) == -1
+    assert lib.hier_steps(h.h, binding.BATCHED, 1, 0.0, None, None) == -6  # not bound
     lib.hier_destroy(hh)
     d.ratio = 3
     assert lib.hier_create(ctypes.byref(d), ctypes.byref(hh)) == -1
