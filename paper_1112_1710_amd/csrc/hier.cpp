@@ -15,10 +15,12 @@
 #include <climits>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <string>
 #include <vector>
 #include <thread>
 #include <unordered_map>
+#include <utility>
 
 #include "amrx_internal.h"
 #include "../../include/amrx.h"
@@ -82,6 +84,28 @@ struct HPatch {
 
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
+// Allocator whose value-less construct() leaves trivially constructible elements uninitialised,
+// so that resizing a large list does not zero it on one thread before the threads that fill it
+// touch it.
+template <typename T>
+struct NoInit : std::allocator<T> {
+  template <typename U>
+  struct rebind {
+    using other = NoInit<U>;
+  };
+  NoInit() = default;
+  template <typename U>
+  NoInit(const NoInit<U>&) noexcept {}
+  template <typename U>
+  void construct(U* p) noexcept {
+    ::new ((void*)p) U;
+  }
+  template <typename U, typename... A>
+  void construct(U* p, A&&... a) {
+    ::new ((void*)p) U(std::forward<A>(a)...);
+  }
+};
+
 }  // namespace
 
 struct amrx_hier {
@@ -97,10 +121,11 @@ struct amrx_hier {
   std::vector<PatchDev> pdev;
   std::vector<Task> tasks;
   std::vector<int> blk;
-  std::vector<Run> runs;
-  std::vector<Pro> pros;
-  std::vector<Corr> fcorrs, ecorrs;
-  std::vector<SyncPair> syncs;
+  // (lists filled by append_parts or emit_copy_lists: every element is written after a resize)
+  std::vector<Run, NoInit<Run>> runs;
+  std::vector<Pro, NoInit<Pro>> pros;
+  std::vector<Corr, NoInit<Corr>> fcorrs, ecorrs;
+  std::vector<SyncPair, NoInit<SyncPair>> syncs;
   std::vector<int> cov;
   // debug copies of the source maps: per patch, 4 arrays (cells, faces x/y/z) of vol entries
   std::vector<std::array<std::vector<long long>, 4>> src;
@@ -432,6 +457,18 @@ void parallel_for(int n, F fn) {
   for (auto& th : pool) th.join();
 }
 
+// Appends parts[0], parts[1], ... to dst in order: one resize, then every part copied by a
+// worker thread (which also first-touches that range).  at[i] = where part i starts in dst.
+template <typename T, typename A>
+std::vector<size_t> append_parts(std::vector<T, A>& dst, const std::vector<std::vector<T>>& parts) {
+  const size_t n = parts.size();
+  std::vector<size_t> at(n + 1, dst.size());
+  for (size_t i = 0; i < n; ++i) at[i + 1] = at[i] + parts[i].size();
+  dst.resize(at[n]);
+  parallel_for((int)n, [&](int i) { std::copy(parts[i].begin(), parts[i].end(), dst.begin() + at[i]); });
+  return at;
+}
+
 // Buckets of a level's index space (periodic), each listing the patches whose boxes meet it;
 // neighbour searches visit only the buckets around a patch instead of every patch of its level.
 // Only occupied buckets are stored (a fine level's index space holds up to 2^27 of them).
@@ -691,7 +728,7 @@ void emit_copy_lists(amrx_hier* h, const std::vector<PendingCopy>& pend) {
   }
 }
 
-void build_pros(amrx_hier* h, int pid) {
+void build_pros(const amrx_hier* h, int pid, std::vector<Pro>& out) {
   const HPatch& p = h->P[pid];
   const HPatch& m = h->P[p.parent];
   const auto& S = h->src[pid];
@@ -717,12 +754,12 @@ void build_pros(amrx_hier* h, int pid) {
             if (S[1 + d][lin_of(p, f[0], f[1], f[2])] >= 0) flags |= 1 << (2 * d + s);
           }
         pr.flags = flags;
-        h->pros.push_back(pr);
+        out.push_back(pr);
       }
 }
 
 // Coverage map and correction lists of a parent patch.
-void build_parent(amrx_hier* h, int mid, std::vector<int>& covmap) {
+void build_parent(const amrx_hier* h, int mid, std::vector<int>& covmap, std::vector<Corr>& fc, std::vector<Corr>& ec) {
   const HPatch& m = h->P[mid];
   covmap.assign(m.vol, -1);
   for (int c : m.children) {
@@ -742,7 +779,7 @@ void build_parent(amrx_hier* h, int mid, std::vector<int>& covmap) {
         if (covered(q)) continue;
         bool nb = false;
         for (int d = 0; d < 3; ++d) nb = nb || covered(q + s[d]) || covered(q - s[d]);
-        if (nb) h->fcorrs.push_back(Corr{mid, 0, (int)q});
+        if (nb) fc.push_back(Corr{mid, 0, (int)q});
       }
   // uncovered faces with a coverage-boundary edge on their perimeter
   auto edge_boundary = [&](int e, long long q) {
@@ -760,12 +797,12 @@ void build_parent(amrx_hier* h, int mid, std::vector<int>& covmap) {
           if (covered(q) || covered(q - s[d])) continue;
           const bool b = edge_boundary(C, q) || edge_boundary(C, q + s[A]) || edge_boundary(A, q) ||
                          edge_boundary(A, q + s[C]);
-          if (b) h->ecorrs.push_back(Corr{mid, d, (int)q});
+          if (b) ec.push_back(Corr{mid, d, (int)q});
         }
   }
 }
 
-void build_syncs(amrx_hier* h, int pid, const std::vector<int>& near) {
+void build_syncs(const amrx_hier* h, int pid, const std::vector<int>& near, std::vector<SyncPair>& out) {
   const HPatch& p = h->P[pid];
   for (int q : near) {
     const HPatch& Q = h->P[q];
@@ -808,7 +845,7 @@ void build_syncs(amrx_hier* h, int pid, const std::vector<int>& near) {
                   int ca[3] = {pa[0], pa[1], pa[2]};
                   if (side == 1) ca[d] -= 1;
                   sp.a_cell = (int)lin_of(p, ca[0], ca[1], ca[2]);
-                  h->syncs.push_back(sp);
+                  out.push_back(sp);
                 }
             }
           }
@@ -966,7 +1003,19 @@ struct SchedImage {
   int cur_after[AMRX_MAXLEV];
 };
 
-SchedImage build_sched(amrx_hier* h, bool fixed_dt, int nworkgroups, bool allow_fused = false) {
+// Largest persistent grid the schedule slots of the scratch arena are sized for (the device
+// schedules clamp their grids to it).
+constexpr int SCHED_MAX_WG = 2048;
+
+// Blocks per work item of a node of nb blocks for a persistent grid of `nworkgroups`: at least two
+// items per workgroup where the node allows, at most 16 blocks each.  Non-increasing in
+// nworkgroups, so the item count for SCHED_MAX_WG bounds every grid up to it.
+int item_chunk(int nb, int nworkgroups) { return std::max(1, std::min(16, nb / std::max(1, 2 * nworkgroups))); }
+
+// reduce = false keeps every predecessor (a superset of the reduced lists) and with_items = false
+// leaves the queues empty: enough for sizing.
+SchedImage build_sched(amrx_hier* h, bool fixed_dt, int nworkgroups, bool allow_fused = false, bool reduce = true,
+                       bool with_items = true) {
   SchedBuild B;
   int cur[AMRX_MAXLEV];
   std::memcpy(cur, h->cur, sizeof cur);
@@ -982,11 +1031,20 @@ SchedImage build_sched(amrx_hier* h, bool fixed_dt, int nworkgroups, bool allow_
   }
   sched_level(h, B, 0, cur, fixed_dt, allow_fused);
   const int nn = (int)B.nodes.size();
-  // transitive reduction of the predecessor lists (nodes are in topological order)
-  const int words = (nn + 63) / 64;
-  std::vector<std::vector<uint64_t>> anc(nn, std::vector<uint64_t>(words, 0));
   SchedImage img;
-  for (int v = 0; v < nn; ++v) {
+  if (!reduce) {
+    for (int v = 0; v < nn; ++v) {
+      Node nd = B.nodes[v];
+      nd.pred_first = (int)img.preds.size();
+      img.preds.insert(img.preds.end(), B.preds[v].begin(), B.preds[v].end());
+      nd.npred = (int)B.preds[v].size();
+      img.nodes.push_back(nd);
+    }
+  }
+  // transitive reduction of the predecessor lists (nodes are in topological order)
+  const int words = reduce ? (nn + 63) / 64 : 0;
+  std::vector<std::vector<uint64_t>> anc(reduce ? nn : 0, std::vector<uint64_t>(words, 0));
+  for (int v = 0; v < nn && reduce; ++v) {
     for (int p : B.preds[v]) {
       for (int w = 0; w < words; ++w) anc[v][w] |= anc[p][w];
       anc[v][p >> 6] |= 1ULL << (p & 63);
@@ -1011,10 +1069,10 @@ SchedImage build_sched(amrx_hier* h, bool fixed_dt, int nworkgroups, bool allow_
   for (int q = 0; q < nq; ++q) {
     Queue Q;
     Q.first = (int)img.items.size();
-    for (int v = 0; v < nn; ++v) {
+    for (int v = 0; v < nn && with_items; ++v) {
       if (B.queue[v] != q) continue;
       const int nb = img.nodes[v].nblk;
-      const int chunk = std::max(1, std::min(16, nb / std::max(1, 2 * nworkgroups)));
+      const int chunk = item_chunk(nb, nworkgroups);
       for (int b = 0; b < nb; b += chunk) img.items.push_back(Item{v, b, std::min(nb, b + chunk), 0});
     }
     Q.len = (int)img.items.size() - Q.first;
@@ -1119,12 +1177,23 @@ int finalize_impl(amrx_hier* h) {
       d.dx = 1.0 / (double)nl_of(h, p.level, 0);
       if (!p.children.empty()) {
         d.cov = covoff;
-        build_parent(h, id, covmaps[id]);
         covoff += p.vol;
       } else {
         d.cov = -1;
       }
     }
+  // coverage maps and correction lists of every parent, built in parallel and appended in level order
+  {
+    std::vector<int> order;
+    for (int l = 0; l < h->nlev; ++l) order.insert(order.end(), h->lev[l].begin(), h->lev[l].end());
+    std::vector<std::vector<Corr>> fc(np), ec(np);
+    parallel_for(np, [&](int i) {
+      const int id = order[i];
+      if (!h->P[id].children.empty()) build_parent(h, id, covmaps[id], fc[i], ec[i]);
+    });
+    append_parts(h->fcorrs, fc);
+    append_parts(h->ecorrs, ec);
+  }
   // the correction lists were appended in level order above; record per-parent ranges
   {
     std::vector<Range> f(np), e(np);
@@ -1155,23 +1224,23 @@ int finalize_impl(amrx_hier* h) {
       const int depth = cls == 0 ? G : NG;
       pending.push_back(plan_copy_list(h, l, cls, h->lev[l], depth, cls == 0));
     }
-    // prolongation
-    h->pro_b[l].first = (int)h->pros.size();
-    if (l > 0)
-      for (int id : h->lev[l]) {
-        h->pro_p[id].first = (int)h->pros.size();
-        build_pros(h, id);
-        h->pro_p[id].count = (int)h->pros.size() - h->pro_p[id].first;
-      }
-    h->pro_b[l].count = (int)h->pros.size() - h->pro_b[l].first;
-    // sync pairs
-    h->sync_b[l].first = (int)h->syncs.size();
-    for (int id : h->lev[l]) {
-      h->sync_p[id].first = (int)h->syncs.size();
-      build_syncs(h, id, near[id]);
-      h->sync_p[id].count = (int)h->syncs.size() - h->sync_p[id].first;
+    // prolongation cells and sync pairs of the level's patches, built in parallel and appended in order
+    const std::vector<int>& ids = h->lev[l];
+    const int nl = (int)ids.size();
+    std::vector<std::vector<Pro>> pros(nl);
+    std::vector<std::vector<SyncPair>> syncs(nl);
+    parallel_for(nl, [&](int i) {
+      if (l > 0) build_pros(h, ids[i], pros[i]);
+      build_syncs(h, ids[i], near[ids[i]], syncs[i]);
+    });
+    const std::vector<size_t> pat = append_parts(h->pros, pros);
+    const std::vector<size_t> sat = append_parts(h->syncs, syncs);
+    for (int i = 0; i < nl; ++i) {
+      h->pro_p[ids[i]] = Range{(int)pat[i], (int)(pat[i + 1] - pat[i])};
+      h->sync_p[ids[i]] = Range{(int)sat[i], (int)(sat[i + 1] - sat[i])};
     }
-    h->sync_b[l].count = (int)h->syncs.size() - h->sync_b[l].first;
+    h->pro_b[l] = Range{(int)pat[0], (int)(pat[nl] - pat[0])};
+    h->sync_b[l] = Range{(int)sat[0], (int)(sat[nl] - sat[0])};
     // correction ranges of the level's parents are contiguous (built in level order)
     Range fb, eb;
     bool fset = false, eset = false;
@@ -1385,10 +1454,13 @@ int finalize_impl(amrx_hier* h) {
     o = align256(o + sizeof(double) * n);
   }
   {
-    // 4 schedule variants; items depend on the persistent grid, bounded by one item per block
-    SchedImage dry = build_sched(h, false, 1);
+    // 4 schedule variants; items depend on the persistent grid, bounded by their count for the largest one
+    SchedImage dry = build_sched(h, false, 1, false, false, false);
     size_t items_max = 0;
-    for (const Node& nd : dry.nodes) items_max += (size_t)nd.nblk;
+    for (const Node& nd : dry.nodes) {
+      const int chunk = item_chunk(nd.nblk, SCHED_MAX_WG);
+      items_max += (size_t)((nd.nblk + chunk - 1) / chunk);
+    }
     h->sched_slot_bytes = align256(sizeof(Node) * dry.nodes.size()) + align256(sizeof(int) * dry.preds.size()) +
                           align256(sizeof(Item) * items_max) + align256(sizeof(Queue) * dry.queues.size()) +
                           align256(sizeof(int) * dry.queues.size()) + align256(sizeof(int) * dry.nodes.size()) + 4096;
@@ -2226,10 +2298,11 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
     return fail(h, AMRX_EINVAL, "arenas must be 256-byte aligned");
   h->state = (char*)state;
   h->scratch = (char*)scratch;
-  // metadata image
-  std::vector<char> img(h->meta_bytes, 0);
+  // index lists, each copied straight from its host array (the gaps between them are never read)
+  hipStream_t s = (hipStream_t)h->d.stream;
+  hipError_t e = hipSuccess;
   auto put = [&](size_t off, const void* src, size_t n) {
-    if (n) std::memcpy(img.data() + off, src, n);
+    if (n && e == hipSuccess) e = hipMemcpyAsync(h->scratch + off, src, n, hipMemcpyHostToDevice, s);
   };
   put(h->off_pdev, h->pdev.data(), sizeof(PatchDev) * h->pdev.size());
   put(h->off_tasks, h->tasks.data(), sizeof(Task) * h->tasks.size());
@@ -2243,8 +2316,7 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
   put(h->off_ecorr, h->ecorrs.data(), sizeof(Corr) * h->ecorrs.size());
   put(h->off_sync, h->syncs.data(), sizeof(SyncPair) * h->syncs.size());
   put(h->off_cov, h->cov.data(), sizeof(int) * h->cov.size());
-  hipStream_t s = (hipStream_t)h->d.stream;
-  HIPCHK(hipMemcpyAsync(h->scratch, img.data(), img.size(), hipMemcpyHostToDevice, s), "upload index lists");
+  HIPCHK(e, "upload index lists");
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   h->ctx = make_ctx(h);
   HIPCHK(launch_clear_slots(h->ctx), "clear slots");
@@ -2253,8 +2325,8 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
     HIPCHK(hipGetDevice(&dev), "get device");
     HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev), "CU count");
     // at most 4 workgroups (16 waves) per CU: enough to hide latency, few enough idle pollers
-    h->nworkgroups = std::max(1, ncu) * std::min(4, persistent_blocks_per_cu(h->d.precision));
-    h->layer_wg = std::max(1, ncu) * layer_blocks_per_cu(h->d.precision);
+    h->nworkgroups = std::min(SCHED_MAX_WG, std::max(1, ncu) * std::min(4, persistent_blocks_per_cu(h->d.precision)));
+    h->layer_wg = std::min(SCHED_MAX_WG, std::max(1, ncu) * layer_blocks_per_cu(h->d.precision));
     h->layer_op_wg = std::max(1, ncu) * 8;  // one-operation layers: up to 8 workgroups (32 waves) per CU
   }
   for (int l = 0; l < AMRX_MAXLEV; ++l) h->cur[l] = 0;
