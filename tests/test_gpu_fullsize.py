@@ -41,7 +41,8 @@ def _fused_config(h):
 @pytest.mark.parametrize("config", ["staged", "fused"])
 @pytest.mark.parametrize("precision", [FP32, FP64])
 def test_two_level_sampled_patches(precision, config):
-    """Ghost fill + prolongation and the extended substep-0 advance of sampled level-1 patches."""
+    """Ghost fill + prolongation and the extended substep-0 advance of sampled level-1 patches, then
+    their substep-1 ghost fill and advance."""
     spec = H.two_level()
     _say("two-level full size, sampled patches", precision, config)
     field = SmoothField(1112)
@@ -113,6 +114,28 @@ def test_two_level_sampled_patches(precision, config):
         for d in range(3):
             fsel = mhd._face_sel(reg, d)
             assert _rel_l1(got_f[d][fsel], ref.faces[d][fsel]) <= tol, (pid, d)
+    # substep 1: the same-level fill of its two ghost layers, then the advance of the interiors,
+    # recomputed by the oracle from the GPU's filled input
+    h.ghost_fill(1, 1)
+    h.synchronize()
+    pre1 = {pid: h.download(pid) for pid in samples}
+    h.advance(1, dt / 2, 1)
+    h.synchronize()
+    for pid in samples:
+        p = o.patches[pid]
+        cells, faces = pre1[pid]
+        reg = h.update_box(pid, 1)
+        assert reg == amr.update_box(p.interior_box()[0], p.interior_box()[1], 1, 1)
+        ref = mhd.advance(cells, faces, [o.dx(1)] * 3, dt / 2, reg, o.gamma)
+        got_c, got_f = h.download(pid)
+        sel = mhd._sel(reg)
+        for m in range(5):
+            assert _rel_l1(got_c[m][sel], ref.cells[m][sel]) <= tol, ("substep 1", pid, m)
+            scale = float(np.max(np.abs(ref.cells[m][sel]))) or 1.0
+            assert float(np.max(np.abs(got_c[m][sel] - ref.cells[m][sel]))) <= 50 * tol * scale, ("substep 1", pid, m)
+        for d in range(3):
+            fsel = mhd._face_sel(reg, d)
+            assert _rel_l1(got_f[d][fsel], ref.faces[d][fsel]) <= tol, ("substep 1", pid, d)
 
 
 def test_two_level_full_root_steps_properties():
