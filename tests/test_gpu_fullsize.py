@@ -236,17 +236,22 @@ def _deep_samples(spec, centre):
     return [pick3[0][1], pick3[1][1], best_f]
 
 
-def test_deep_hierarchy_sampled_patches():
-    """Deep 8-level blast hierarchy (64^3 root, ~40M cells), autotuned, FP32: the first-substep chain of a
-    root step (ghost fill + advance of every level in turn) and the oracle's advance of sampled patches
-    from the GPU's own ghost-filled input."""
+@pytest.mark.parametrize("steps_before", [0, 2])
+def test_deep_hierarchy_sampled_patches(steps_before):
+    """Deep 8-level blast hierarchy (64^3 root, ~40M cells), autotuned, FP32, from the initial state and
+    after two graph-replayed root steps (the blast's shock then crosses patch and level boundaries):
+    the first-substep chain of a root step (ghost fill + advance of every level in turn), then the
+    finest level's substep-1 fill and advance; the oracle advances the sampled patches from the GPU's
+    own ghost-filled input."""
     from paper_1112_1710_amd.autotune import autotune
     from workloads.fields import Blast
     spec, centre, _ = H.deep_blast_target()
-    _say("deep hierarchy, sampled patches", len(spec.patches), "patches")
+    _say("deep hierarchy, sampled patches", len(spec.patches), "patches,", steps_before, "root steps before")
     h = Hierarchy(spec, FP32)
     h.set_field(Blast(centre))
     autotune(h, reps=2, use_cache=False)
+    if steps_before:
+        h.steps(steps_before, GRAPH)
     samples = _deep_samples(spec, centre)
     by_level = {}
     for pid in samples:
@@ -277,6 +282,26 @@ def test_deep_hierarchy_sampled_patches():
         for d in range(3):
             fsel = mhd._face_sel(reg, d)
             assert _rel_l1(got_f[d][fsel], ref.faces[d][fsel]) <= 1e-5, (pid, lv, d)
+    # the finest level's second substep
+    top = spec.levels() - 1
+    fine = by_level.get(top, [])
+    assert fine
+    h.ghost_fill(top, 1)
+    h.synchronize()
+    pre1 = {pid: h.download(pid) for pid in fine}
+    h.advance(top, dt0 / 2 ** top, 1)
+    h.synchronize()
+    for pid in fine:
+        cells, faces = pre1[pid]
+        reg = h.update_box(pid, 1)
+        ref = mhd.advance(cells, faces, [o.dx(top)] * 3, dt0 / 2 ** top, reg, 5.0 / 3.0)
+        got_c, got_f = h.download(pid)
+        sel = mhd._sel(reg)
+        for m in range(5):
+            assert _rel_l1(got_c[m][sel], ref.cells[m][sel]) <= 1e-5, ("substep 1", pid, m)
+        for d in range(3):
+            fsel = mhd._face_sel(reg, d)
+            assert _rel_l1(got_f[d][fsel], ref.faces[d][fsel]) <= 1e-5, ("substep 1", pid, d)
 
 
 def test_deep_hierarchy_root_step_properties():
