@@ -2741,26 +2741,31 @@ struct Flags3 {
   bool at(int x, int y, int z) const { return f[((size_t)z * n[1] + y) * n[0] + x] != 0; }
 };
 
-// signature along axis a: flags in each plane normal to a, inside the box
-std::vector<long long> box_signature(const Flags3& F, const CBox& b, int a) {
-  std::vector<long long> s(b.hi[a] - b.lo[a], 0);
+// signatures of a box along the three axes (flags in each plane normal to the axis, inside the
+// box), in one pass over it
+void box_signatures(const Flags3& F, const CBox& b, std::vector<long long> s[3]) {
+  for (int a = 0; a < 3; ++a) s[a].assign(b.hi[a] - b.lo[a], 0);
   for (int z = b.lo[2]; z < b.hi[2]; ++z)
-    for (int y = b.lo[1]; y < b.hi[1]; ++y)
+    for (int y = b.lo[1]; y < b.hi[1]; ++y) {
+      const unsigned char* row = F.f + ((size_t)z * F.n[1] + y) * F.n[0];
+      long long nrow = 0;
       for (int x = b.lo[0]; x < b.hi[0]; ++x)
-        if (F.at(x, y, z)) {
-          const int c[3] = {x, y, z};
-          ++s[c[a] - b.lo[a]];
+        if (row[x]) {
+          ++s[0][x - b.lo[0]];
+          ++nrow;
         }
-  return s;
+      s[1][y - b.lo[1]] += nrow;
+      s[2][z - b.lo[2]] += nrow;
+    }
 }
 
-bool shrink_to_flags(const Flags3& F, CBox& b) {
+// The box shrunk to its flagged cells, from its signatures (false if it holds none).
+bool shrink_to_flags(const std::vector<long long> s[3], CBox& b) {
   CBox out;
   for (int a = 0; a < 3; ++a) {
-    const std::vector<long long> s = box_signature(F, b, a);
     int first = -1, last = -1;
-    for (int i = 0; i < (int)s.size(); ++i)
-      if (s[i] > 0) {
+    for (int i = 0; i < (int)s[a].size(); ++i)
+      if (s[a][i] > 0) {
         if (first < 0) first = i;
         last = i;
       }
@@ -2772,8 +2777,8 @@ bool shrink_to_flags(const Flags3& F, CBox& b) {
   return true;
 }
 
-// (axis, absolute cut) or axis -1
-void choose_cut(const Flags3& F, const CBox& b, int min_side, int& axis, int& cut) {
+// (axis, absolute cut) or axis -1, from the box's signatures
+void choose_cut(const std::vector<long long> s[3], const CBox& b, int min_side, int& axis, int& cut) {
   int n[3];
   for (int a = 0; a < 3; ++a) n[a] = b.hi[a] - b.lo[a];
   axis = -1;
@@ -2781,9 +2786,8 @@ void choose_cut(const Flags3& F, const CBox& b, int min_side, int& axis, int& cu
   long long best_d = 0;
   for (int a = 0; a < 3; ++a) {
     if (n[a] < 2 * min_side) continue;
-    const std::vector<long long> s = box_signature(F, b, a);
     for (int i = min_side; i <= n[a] - min_side; ++i) {
-      if (i >= n[a] || s[i] != 0) continue;
+      if (i >= n[a] || s[a][i] != 0) continue;
       const long long d = std::llabs(2LL * i - n[a]);
       if (axis < 0 || d < best_d) {
         axis = a;
@@ -2797,9 +2801,8 @@ void choose_cut(const Flags3& F, const CBox& b, int min_side, int& axis, int& cu
   long long best_str = 0;
   for (int a = 0; a < 3; ++a) {
     if (n[a] < 2 * min_side) continue;
-    const std::vector<long long> s = box_signature(F, b, a);
     std::vector<long long> lap(n[a], 0);
-    for (int i = 1; i + 1 < n[a]; ++i) lap[i] = s[i + 1] - 2 * s[i] + s[i - 1];
+    for (int i = 1; i + 1 < n[a]; ++i) lap[i] = s[a][i + 1] - 2 * s[a][i] + s[a][i - 1];
     for (int i = 1; i + 2 < n[a]; ++i) {
       const int c = i + 1;
       if (c < min_side || n[a] - c < min_side) continue;
@@ -2829,21 +2832,25 @@ std::vector<CBox> cluster_flags(const Flags3& F, int min_side, double efficiency
     all.hi[a] = F.n[a];
   }
   stack.push_back(all);
+  std::vector<long long> s[3];
   while (!stack.empty()) {
     CBox b = stack.back();
     stack.pop_back();
-    if (!shrink_to_flags(F, b)) continue;
+    box_signatures(F, b, s);
+    const CBox before = b;
+    if (!shrink_to_flags(s, b)) continue;
+    bool same = true;
+    for (int a = 0; a < 3; ++a) same = same && b.lo[a] == before.lo[a] && b.hi[a] == before.hi[a];
+    if (!same) box_signatures(F, b, s);
     long long vol = 1, nf = 0;
     for (int a = 0; a < 3; ++a) vol *= b.hi[a] - b.lo[a];
-    for (int z = b.lo[2]; z < b.hi[2]; ++z)
-      for (int y = b.lo[1]; y < b.hi[1]; ++y)
-        for (int x = b.lo[0]; x < b.hi[0]; ++x) nf += F.at(x, y, z) ? 1 : 0;
+    for (long long v : s[0]) nf += v;
     if ((double)nf >= efficiency * (double)vol) {
       out.push_back(b);
       continue;
     }
     int axis, cut;
-    choose_cut(F, b, min_side, axis, cut);
+    choose_cut(s, b, min_side, axis, cut);
     if (axis < 0) {
       out.push_back(b);
       continue;
