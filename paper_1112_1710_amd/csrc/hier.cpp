@@ -403,21 +403,15 @@ int add_task_tiles(amrx_hier* h, int patch, const int lo[3], const int hi[3], in
 
 // Block table of one task list: the task of each of its blocks, so a kernel finds its task with
 // one lookup instead of a search over the block prefix.  Lists without blocks get none.
-bool add_block_table(amrx_hier* h, const TaskList& L) {
-  if (L.count <= 0 || L.nblk <= 0) return true;
-  const size_t at = h->b2t.size();
-  h->tbl[L.first] = (int)at;
+// Block table of one task list into b2t[at, at + nblk): one entry per block, each the last task
+// whose first block is <= b.  False if the list's block offsets are inconsistent.
+bool fill_block_table(amrx_hier* h, const TaskList& L, size_t at) {
   for (int t = L.first; t < L.first + L.count; ++t) {
-    const int b1 = t + 1 < L.first + L.count ? h->blk[t + 1] : L.nblk;
-    for (int b = h->blk[t]; b < b1; ++b) h->b2t.push_back(t);
+    const int b0 = h->blk[t], b1 = t + 1 < L.first + L.count ? h->blk[t + 1] : L.nblk;
+    if (b0 < 0 || b1 > L.nblk || b0 > b1) return false;
+    for (int b = b0; b < b1; ++b) h->b2t[at + b] = t;
   }
-  // one entry per block, each the last task whose first block is <= b
-  if (h->blk[L.first] != 0 || h->b2t.size() - at != (size_t)L.nblk) return false;
-  for (int b = 0; b < L.nblk; ++b) {
-    const int t = h->b2t[at + b];
-    if (h->blk[t] > b || (t + 1 < L.first + L.count && h->blk[t + 1] <= b)) return false;
-  }
-  return true;
+  return h->blk[L.first] == 0;
 }
 
 // Regions of the advance stages for update region [lo, hi).
@@ -1393,31 +1387,46 @@ int finalize_impl(amrx_hier* h) {
   }
   emit_copy_lists(h, pending);
   pending.clear();
-  // block tables of every task list
+  // block tables of every task list: laid out in list order, filled in parallel
   h->tbl.assign(h->tasks.size() + 1, 0);
-  h->b2t.clear();
   {
-    bool ok = true;
+    std::vector<const TaskList*> lists;
     for (int l = 0; l < h->nlev; ++l) {
       for (int s = 0; s < 2; ++s) {
-        for (int stg = 0; stg < NSTAGE; ++stg) ok = add_block_table(h, h->stage_b[l][s][stg]) && ok;
-        for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fa_b[l][s][t]) && ok;
-        for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fb_b[l][s][t]) && ok;
+        for (int stg = 0; stg < NSTAGE; ++stg) lists.push_back(&h->stage_b[l][s][stg]);
+        for (int t = 0; t < NTILE; ++t) lists.push_back(&h->fa_b[l][s][t]);
+        for (int t = 0; t < NTILE; ++t) lists.push_back(&h->fb_b[l][s][t]);
       }
-      ok = add_block_table(h, h->restr_b[l]) && ok;
-      ok = add_block_table(h, h->cfl_b[l]) && ok;
+      lists.push_back(&h->restr_b[l]);
+      lists.push_back(&h->cfl_b[l]);
     }
     for (size_t id = 0; id < h->P.size(); ++id) {
       for (int s = 0; s < 2; ++s) {
-        for (int stg = 0; stg < NSTAGE; ++stg) ok = add_block_table(h, h->stage_p[id][s][stg]) && ok;
-        for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fa_p[id][s][t]) && ok;
-        for (int t = 0; t < NTILE; ++t) ok = add_block_table(h, h->fb_p[id][s][t]) && ok;
+        for (int stg = 0; stg < NSTAGE; ++stg) lists.push_back(&h->stage_p[id][s][stg]);
+        for (int t = 0; t < NTILE; ++t) lists.push_back(&h->fa_p[id][s][t]);
+        for (int t = 0; t < NTILE; ++t) lists.push_back(&h->fb_p[id][s][t]);
       }
-      ok = add_block_table(h, h->restr_p[id]) && ok;
+      lists.push_back(&h->restr_p[id]);
     }
-    ok = add_block_table(h, h->cons_all) && ok;
+    lists.push_back(&h->cons_all);
+    const int nlist = (int)lists.size();
+    std::vector<size_t> at(nlist + 1, 0);
+    for (int i = 0; i < nlist; ++i) {
+      const TaskList& L = *lists[i];
+      const bool used = L.count > 0 && L.nblk > 0;
+      at[i + 1] = at[i] + (used ? (size_t)L.nblk : 0);
+      if (used) h->tbl[L.first] = (int)at[i];
+    }
+    if (at[nlist] >= (size_t)INT_MAX) return fail(h, AMRX_ENOMEM, "block tables exceed 2^31 entries");
+    h->b2t.assign(at[nlist], -1);
+    std::vector<char> good(nlist, 1);
+    parallel_for(nlist, [&](int i) {
+      const TaskList& L = *lists[i];
+      if (L.count > 0 && L.nblk > 0) good[i] = fill_block_table(h, L, at[i]) ? 1 : 0;
+    });
+    bool ok = std::all_of(good.begin(), good.end(), [](char g) { return g != 0; });
+    ok = ok && std::none_of(h->b2t.begin(), h->b2t.end(), [](int t) { return t < 0; });
     if (!ok) return fail(h, AMRX_EINVAL, "internal error: inconsistent block table");
-    if (h->b2t.size() >= (size_t)INT_MAX) return fail(h, AMRX_ENOMEM, "block tables exceed 2^31 entries");
   }
 
   // host-side bounds checks of everything the kernels index
