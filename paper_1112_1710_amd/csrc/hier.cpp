@@ -149,7 +149,7 @@ struct amrx_hier {
   // ghost-copy lists per depth class (0: 4 ghost layers, 1: 2 ghost layers)
   CopyList copy_b[AMRX_MAXLEV][2];
   std::vector<std::array<CopyList, 2>> copy_p;
-  std::vector<int> run_blk;
+  std::vector<int, NoInit<int>> run_blk;  // every element is written by emit_copy_lists
   Range pro_b[AMRX_MAXLEV];
   std::vector<Range> pro_p;
   TaskList restr_b[AMRX_MAXLEV];
@@ -640,15 +640,14 @@ void build_runs(const amrx_hier* h, int pid, int depth, bool by_side, int& nelem
   }
 }
 
-// Blocks of a copy list: the run holding the first element of every block.
-void copy_list_blocks(amrx_hier* h, CopyList& L) {
-  L.first_blk = (int)h->run_blk.size();
-  L.nblk = (L.nelem + AMRX_BLOCK - 1) / AMRX_BLOCK;
+// Blocks of a copy list: the run holding the first element of every block, written to
+// run_blk[L.first_blk, L.first_blk + L.nblk).
+void fill_copy_blocks(amrx_hier* h, const CopyList& L) {
   int r = 0;
   for (int b = 0; b < L.nblk; ++b) {
     const int e0 = b * AMRX_BLOCK;
     while (r + 1 < L.nrun && h->runs[L.first_run + r + 1].off <= e0) ++r;
-    h->run_blk.push_back(r);
+    h->run_blk[L.first_blk + b] = r;
   }
 }
 
@@ -685,6 +684,7 @@ void emit_copy_lists(amrx_hier* h, const std::vector<PendingCopy>& pend) {
   const long long base0 = (long long)h->runs.size();
   h->runs.resize(base0 + total);
   long long base = base0;
+  std::vector<CopyList*> lists;
   for (const PendingCopy& P : pend) {
     const int n = (int)P.pids.size();
     std::vector<long long> rpre(n + 1, 0), epre(n + 1, 0);
@@ -708,7 +708,7 @@ void emit_copy_lists(amrx_hier* h, const std::vector<PendingCopy>& pend) {
     L.nrun = (int)nr;
     L.nelem = (int)epre[n];
     for (int i = 0; i < n; ++i) L.comps += P.cmp[i];
-    copy_list_blocks(h, L);
+    lists.push_back(&L);
     for (int i = 0; i < n; ++i) {
       CopyList& C = h->copy_p[P.pids[i]][P.cls];
       C = CopyList{};
@@ -716,10 +716,19 @@ void emit_copy_lists(amrx_hier* h, const std::vector<PendingCopy>& pend) {
       C.nrun = (int)P.part[i].size();
       C.nelem = P.cnt[i];
       C.comps = P.cmp[i];
-      copy_list_blocks(h, C);
+      lists.push_back(&C);
     }
     base += 2 * nr;
   }
+  // block tables of the lists, laid out in list order and filled in parallel
+  size_t nb = h->run_blk.size();
+  for (CopyList* L : lists) {
+    L->first_blk = (int)nb;
+    L->nblk = (L->nelem + AMRX_BLOCK - 1) / AMRX_BLOCK;
+    nb += (size_t)L->nblk;
+  }
+  h->run_blk.resize(nb);
+  parallel_for((int)lists.size(), [&](int i) { fill_copy_blocks(h, *lists[i]); });
 }
 
 void build_pros(const amrx_hier* h, int pid, std::vector<Pro>& out) {
