@@ -762,7 +762,10 @@ void build_pros(const amrx_hier* h, int pid, std::vector<Pro>& out) {
 }
 
 // Coverage map and correction lists of a parent patch.
-void build_parent(const amrx_hier* h, int mid, std::vector<int>& covmap, std::vector<Corr>& fc, std::vector<Corr>& ec) {
+// split: the planes of the two scans run in parallel (for a large parent built on its own), their
+// entries appended in plane order, so the lists are the same either way.
+void build_parent(const amrx_hier* h, int mid, std::vector<int>& covmap, std::vector<Corr>& fc, std::vector<Corr>& ec,
+                  bool split = false) {
   const HPatch& m = h->P[mid];
   covmap.assign(m.vol, -1);
   for (int c : m.children) {
@@ -775,15 +778,16 @@ void build_parent(const amrx_hier* h, int mid, std::vector<int>& covmap, std::ve
   const long long s[3] = {1, m.dim[0], (long long)m.dim[0] * m.dim[1]};
   auto covered = [&](long long q) { return covmap[q] >= 0; };
   // uncovered interior cells with a covered face neighbour
-  for (int k = G; k < G + m.n[2]; ++k)
+  auto cell_plane = [&](int k, std::vector<Corr>& out) {
     for (int j = G; j < G + m.n[1]; ++j)
       for (int i = G; i < G + m.n[0]; ++i) {
         const long long q = lin_of(m, i, j, k);
         if (covered(q)) continue;
         bool nb = false;
         for (int d = 0; d < 3; ++d) nb = nb || covered(q + s[d]) || covered(q - s[d]);
-        if (nb) fc.push_back(Corr{mid, 0, (int)q});
+        if (nb) out.push_back(Corr{mid, 0, (int)q});
       }
+  };
   // uncovered faces with a coverage-boundary edge on their perimeter
   auto edge_boundary = [&](int e, long long q) {
     const int A = (e + 1) % 3, C = (e + 2) % 3;
@@ -791,18 +795,36 @@ void build_parent(const amrx_hier* h, int mid, std::vector<int>& covmap, std::ve
     const bool any = c0 || c1 || c2 || c3, all = c0 && c1 && c2 && c3;
     return any && !all;
   };
-  for (int d = 0; d < 3; ++d) {
+  auto face_plane = [&](int d, int k, std::vector<Corr>& out) {
     const int A = (d + 1) % 3, C = (d + 2) % 3;
-    for (int k = G; k < G + m.n[2] + (d == 2); ++k)
-      for (int j = G; j < G + m.n[1] + (d == 1); ++j)
-        for (int i = G; i < G + m.n[0] + (d == 0); ++i) {
-          const long long q = lin_of(m, i, j, k);
-          if (covered(q) || covered(q - s[d])) continue;
-          const bool b = edge_boundary(C, q) || edge_boundary(C, q + s[A]) || edge_boundary(A, q) ||
-                         edge_boundary(A, q + s[C]);
-          if (b) ec.push_back(Corr{mid, d, (int)q});
-        }
+    for (int j = G; j < G + m.n[1] + (d == 1); ++j)
+      for (int i = G; i < G + m.n[0] + (d == 0); ++i) {
+        const long long q = lin_of(m, i, j, k);
+        if (covered(q) || covered(q - s[d])) continue;
+        const bool b = edge_boundary(C, q) || edge_boundary(C, q + s[A]) || edge_boundary(A, q) ||
+                       edge_boundary(A, q + s[C]);
+        if (b) out.push_back(Corr{mid, d, (int)q});
+      }
+  };
+  if (!split) {
+    for (int k = G; k < G + m.n[2]; ++k) cell_plane(k, fc);
+    for (int d = 0; d < 3; ++d)
+      for (int k = G; k < G + m.n[2] + (d == 2); ++k) face_plane(d, k, ec);
+    return;
   }
+  const int nk = m.n[2] + 1;  // planes per scan (the cell scan uses the first n[2])
+  std::vector<std::vector<Corr>> part(4 * (size_t)nk);
+  parallel_for(4 * nk, [&](int t) {
+    const int scan = t / nk, k = G + t % nk;
+    if (scan == 0) {
+      if (k < G + m.n[2]) cell_plane(k, part[t]);
+    } else {
+      const int d = scan - 1;
+      if (k < G + m.n[2] + (d == 2)) face_plane(d, k, part[t]);
+    }
+  });
+  for (int t = 0; t < nk; ++t) fc.insert(fc.end(), part[t].begin(), part[t].end());
+  for (int t = nk; t < 4 * nk; ++t) ec.insert(ec.end(), part[t].begin(), part[t].end());
 }
 
 void build_syncs(const amrx_hier* h, int pid, const std::vector<int>& near, std::vector<SyncPair>& out) {
@@ -1190,9 +1212,15 @@ int finalize_impl(amrx_hier* h) {
     std::vector<int> order;
     for (int l = 0; l < h->nlev; ++l) order.insert(order.end(), h->lev[l].begin(), h->lev[l].end());
     std::vector<std::vector<Corr>> fc(np), ec(np);
+    // large parents one at a time with their planes in parallel, the others one per thread
+    auto large = [&](int id) { return h->P[id].vol > (1LL << 20); };
+    for (int i = 0; i < np; ++i) {
+      const int id = order[i];
+      if (!h->P[id].children.empty() && large(id)) build_parent(h, id, covmaps[id], fc[i], ec[i], true);
+    }
     parallel_for(np, [&](int i) {
       const int id = order[i];
-      if (!h->P[id].children.empty()) build_parent(h, id, covmaps[id], fc[i], ec[i]);
+      if (!h->P[id].children.empty() && !large(id)) build_parent(h, id, covmaps[id], fc[i], ec[i]);
     });
     append_parts(h->fcorrs, fc);
     append_parts(h->ecorrs, ec);
