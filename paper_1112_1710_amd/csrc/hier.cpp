@@ -519,19 +519,21 @@ std::vector<int> near_patches(const amrx_hier* h, const LevelBuckets& L, int pid
 }
 
 // Same-level sources of every padded cell and face of patch p (lowest id wins, p itself first).
-void build_sources(amrx_hier* h, int pid, const std::vector<int>& near) {
+// Same-level sources of the entries of a patch in the planes z0 <= z < z1 (level index space): the
+// patch itself first, then its neighbours, each over its 27 periodic images in a fixed order; the
+// first candidate holding an entry is its source.  The planes of a large patch are split between
+// threads; every entry still sees the candidates in the same order.
+void build_sources_planes(amrx_hier* h, int pid, const std::vector<int>& cands, int z0, int z1) {
   HPatch& p = h->P[pid];
   auto& S = h->src[pid];
-  for (int k = 0; k < 4; ++k) S[k].assign(p.vol, -1);
-  std::vector<int> cands;
-  cands.push_back(pid);
-  for (int q : near)
-    if (q != pid) cands.push_back(q);
   int plo[3], phi[3];
   for (int a = 0; a < 3; ++a) {
     plo[a] = p.lo[a] - G;
     phi[a] = p.hi[a] + G;
   }
+  const long long plane = (long long)p.dim[0] * p.dim[1];
+  for (int k = 0; k < 4; ++k)
+    std::fill(S[k].begin() + (z0 - plo[2]) * plane, S[k].begin() + (z1 - plo[2]) * plane, -1LL);
   for (int q : cands) {
     const HPatch& Q = h->P[q];
     for (int sz = -1; sz <= 1; ++sz)
@@ -557,7 +559,9 @@ void build_sources(amrx_hier* h, int pid, const std::vector<int>& near) {
               hi[a] = std::min(top_p, top_q);
               if (hi[a] <= lo[a]) empty = true;
             }
-            if (empty) continue;
+            lo[2] = std::max(lo[2], z0);
+            hi[2] = std::min(hi[2], z1);
+            if (empty || hi[2] <= lo[2]) continue;
             std::vector<long long>& arr = S[kind];
             for (int z = lo[2]; z < hi[2]; ++z)
               for (int y = lo[1]; y < hi[1]; ++y)
@@ -570,6 +574,25 @@ void build_sources(amrx_hier* h, int pid, const std::vector<int>& near) {
           }
         }
   }
+}
+
+// split: the patch's planes in parallel (for a large patch built on its own).
+void build_sources(amrx_hier* h, int pid, const std::vector<int>& near, bool split = false) {
+  HPatch& p = h->P[pid];
+  auto& S = h->src[pid];
+  for (int k = 0; k < 4; ++k) S[k].resize(p.vol);
+  std::vector<int> cands;
+  cands.push_back(pid);
+  for (int q : near)
+    if (q != pid) cands.push_back(q);
+  const int z0 = p.lo[2] - G, nz = p.dim[2];
+  if (!split) {
+    build_sources_planes(h, pid, cands, z0, z0 + nz);
+    return;
+  }
+  const int per = 4;  // planes per task
+  parallel_for((nz + per - 1) / per,
+               [&](int t) { build_sources_planes(h, pid, cands, z0 + t * per, std::min(z0 + nz, z0 + (t + 1) * per)); });
 }
 
 bool is_own(const HPatch& p, int kind, int i, int j, int k) {
@@ -1148,7 +1171,12 @@ int finalize_impl(amrx_hier* h) {
     const std::vector<int>& ids = h->lev[l];
     parallel_for((int)ids.size(), [&](int i) { near[ids[i]] = near_patches(h, L, ids[i], G + 1); });
   }
-  parallel_for(np, [&](int id) { build_sources(h, id, near[id]); });
+  // large patches one at a time with their planes in parallel, the others one per thread
+  for (int id = 0; id < np; ++id)
+    if (h->P[id].vol > (1LL << 20)) build_sources(h, id, near[id], true);
+  parallel_for(np, [&](int id) {
+    if (h->P[id].vol <= (1LL << 20)) build_sources(h, id, near[id]);
+  });
   for (int id = 0; id < np; ++id) {
     if (h->P[id].level == 0) continue;
     if (h->time_ghosts) {
