@@ -79,13 +79,13 @@ def test_hierarchy_root_step(name, precision):
     assert d["phys_flag"] == 0.0
 
 
-@pytest.mark.parametrize("precision", [FP64, FP32])
+@pytest.mark.parametrize("precision", [FP64, FP32, FP32_MIXED])
 def test_deep_blast_three_root_steps(precision):
     """A scaled-down deep blast (16^3 root, 4 levels around the same seeded off-centre blast): per-step
     parity over three consecutive root steps, each started from the oracle's state (rounded to
     float32 in FP32 mode), with the strong-shock data crossing the coarse/fine boundaries.
 
-    FP32: b_z starts at zero (the field lies in the x-y plane), so it is measured against the
+    FP32 (and FP32 with targeted FP64): b_z starts at zero (the field lies in the x-y plane), so it is measured against the
     field's magnitude.  Ahead of the outgoing front the fluid is at rest and its mass fluxes vanish
     in exact arithmetic; float32 rounding leaves values of 1e-8..1e-7 of their scale there, whose
     sign picks the upwind side of the edge EMFs next to the front (the oracle and the FP64 path
