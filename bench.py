@@ -539,7 +539,8 @@ def main():
             from paper_1112_1710_amd.autotune import autotune
             chosen = autotune(hh)
             t_first = {str(k): v[1] for k, v in chosen.items() if isinstance(k, int)}
-            t_eu = {str(k[1]): v[1] for k, v in chosen.items() if not isinstance(k, int)}
+            t_eu = {str(k[1]): v[1] for k, v in chosen.items() if not isinstance(k, int) and k[0] == "eu"}
+            hh.flux_forms = {str(k[1]): v[1] for k, v in chosen.items() if not isinstance(k, int) and k[0] == "flux"}
         return hh, t_first, t_eu
 
     h, tiles, last = prepared(prec, spec, field)
@@ -607,6 +608,7 @@ def main():
         hm, _, _ = prepared(FP32_MIXED, spec, field)
         msec, _ = timed_steps(hm, mode, max(args.steps // 2, 1), 1, torch)
         mixed = {"value": round(zu / msec, 1), "ms_per_step": round(msec * 1e3, 4),
+                 "flux_stage": getattr(hm, "flux_forms", None),
                  "rel_l1_per_step": precision_report(spec, h, hm, mode, torch, physics, cs)}
         del hm
         torch.cuda.empty_cache()
@@ -645,6 +647,8 @@ def main():
         "step_hbm": step_hbm,
         "kernel_ms_per_step": per_class,
     }
+    if getattr(h, "flux_forms", None):
+        out["config"]["flux_stage"] = h.flux_forms
     if regrid_report is not None:
         out["regrid"] = regrid_report
     if mixed is not None:

@@ -285,11 +285,18 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
  *     (closure, for faces) nor a same-level-sourced ghost entry within n_g
  *     layers.  Only before hier_finalize (ESTATE after); level ignored; the
  *     persistent and concurrent schedules refuse it (EINVAL).
+ *   AMRX_TUNE_FLUX_SPLIT (FP32_MIXED only; other precisions ignore it): 1
+ *     (default) the flux stage runs as two launches over the same faces, a
+ *     float one that leaves the low-beta faces (a NaN mass flux, one flag per
+ *     block) and one that solves those faces' Riemann problems in double, so
+ *     the float kernel keeps the plain FP32 kernel's register footprint; 0 one
+ *     launch with the double solver inline, better where most faces are
+ *     low-beta.  Bit-identical results.
  * level = -1 sets every level.  Pure host calls (captured graph-schedule steps
  * are discarded on a change).  EINVAL for a bad parameter, level or index, or
  * a tile whose LDS footprint exceeds the limit for the hierarchy's precision. */
 enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1, AMRX_TUNE_EXTEND_ALL = 2, AMRX_TUNE_PAIR = 3,
-       AMRX_TUNE_FUSED_EU = 4, AMRX_TUNE_TILE_EU = 5, AMRX_TUNE_GHOSTS = 6 };
+       AMRX_TUNE_FUSED_EU = 4, AMRX_TUNE_TILE_EU = 5, AMRX_TUNE_GHOSTS = 6, AMRX_TUNE_FLUX_SPLIT = 7 };
 int hier_tune_set(amrx_hier* h, int level, int param, int value);
 int hier_tune_get(const amrx_hier* h, int level, int param, int* value);
 
@@ -314,6 +321,15 @@ int hier_tune_time(amrx_hier* h, int level, int substep, int tile, int reps, dou
  * between root steps: call it only between steps (hier_step), never inside a
  * sequence of per-level calls.  Synchronising.  Needs hier_bind. */
 int hier_tune_time_eu(amrx_hier* h, int level, int tile, int reps, double* ms);
+
+/* Time the flux stage of substep 0 of `level` in FP32_MIXED's two-launch
+ * (split = 1) or one-launch (split = 0) form (other precisions: their one
+ * form), after one untimed pass of the staged first stages so the low-beta
+ * faces are those of the current state; *ms = mean device time per
+ * repetition.  Writes intermediates and the level's flux registers, which hold
+ * nothing needed between root steps: call it only between steps.
+ * Synchronising.  Needs hier_bind. */
+int hier_tune_time_flux(amrx_hier* h, int level, int split, int reps, double* ms);
 
 /* Regridding of the finest level (Sec. 2.2: a level's grids decide which cells
  * to refine and lay down child grids over them; new grids take the data of the

@@ -21,7 +21,7 @@ set, else ``~/.cache/amrx/tune.json``.
 import json
 import os
 
-from .binding import TUNE_FUSED, TUNE_FUSED_EU, TUNE_TILE, TUNE_TILE_EU, tile_table
+from .binding import FP32_MIXED, TUNE_FLUX_SPLIT, TUNE_FUSED, TUNE_FUSED_EU, TUNE_TILE, TUNE_TILE_EU, tile_table
 
 G = 4
 
@@ -94,12 +94,15 @@ def _shape(table, choice):
     return "staged" if choice == STAGED else "x".join(str(x) for x in table[choice][:3])
 
 
-def autotune(h, reps=5, use_cache=True, path=None, groups=("a", "eu")):
+def autotune(h, reps=5, use_cache=True, path=None, groups=("a", "eu", "flux")):
     """Select staged or fused (and the tile) for every level of the bound hierarchy `h` and each group.
 
     Returns {level: (choice, shape, ms, source)} for the first three stages, and, when "eu" is in `groups`,
     the same for the edge/update stages under the key ("eu", level): choice -1 = staged, else the tile index;
-    shape "staged" or "TXxTYxTZ"; ms the measured time; source "search" or "cache".
+    shape "staged" or "TXxTYxTZ"; ms the measured time; source "search" or "cache".  In FP32_MIXED, "flux"
+    also times the flux stage's two-launch and one-launch forms per level under ("flux", level), choice 1 or
+    0; that choice depends on how many faces of the current state are low-beta, not on the level's shape,
+    so it is never cached.
     """
     path = path or cache_path()
     cache = _load(path) if use_cache else {}
@@ -110,7 +113,18 @@ def autotune(h, reps=5, use_cache=True, path=None, groups=("a", "eu")):
     levels = 1 + max(p[0] for p in h.spec.patches)
     out = {}
     changed = False
+    if "flux" in groups and h.precision == FP32_MIXED:
+        for level in range(levels):
+            times = {}
+            for split in (1, 0):
+                h.tune_time_flux(level, split, 1)  # warm-up
+                times[split] = h.tune_time_flux(level, split, reps)
+            best = min(times, key=times.get)
+            h.tune_set(TUNE_FLUX_SPLIT, best, level)
+            out[("flux", level)] = (best, "two launches" if best else "one launch", times[best], "search")
     for group in groups:
+        if group == "flux":
+            continue
         for level in range(levels):
             tag = "" if group == "a" else "|eu"
             key = f"{arch}|p{h.precision}|l{min(level, 1)}|{size_class(h.spec, level)}{tag}"

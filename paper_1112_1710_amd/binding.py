@@ -15,7 +15,7 @@ G = 4
 
 KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
                   "fluxcorr", "emfcorr", "sync", "cfl", "cons", "primhalf", "edgeupd")
-TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL, TUNE_PAIR, TUNE_FUSED_EU, TUNE_TILE_EU, TUNE_GHOSTS = 0, 1, 2, 3, 4, 5, 6
+TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL, TUNE_PAIR, TUNE_FUSED_EU, TUNE_TILE_EU, TUNE_GHOSTS, TUNE_FLUX_SPLIT = range(8)
 
 _ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
 
@@ -79,6 +79,7 @@ EXPORTS = {
     "hier_tile_table": ([C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int], C.c_int),
     "hier_tune_time": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
     "hier_tune_time_eu": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "hier_tune_time_flux": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
     "hier_debug_update_box": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
 }
 
@@ -342,6 +343,13 @@ class Hierarchy:
         """Mean ms of the edge EMF and update stages of substep 0 (tile -1: staged); between steps only."""
         ms = C.c_double()
         self._check(self.lib.hier_tune_time_eu(self.h, level, tile, reps, C.byref(ms)))
+        return ms.value
+
+    def tune_time_flux(self, level, split, reps=5):
+        """Mean ms of the flux stage of substep 0 in FP32_MIXED's two-launch (split 1) or one-launch (0)
+        form; between steps only."""
+        ms = C.c_double()
+        self._check(self.lib.hier_tune_time_flux(self.h, level, int(split), reps, C.byref(ms)))
         return ms.value
 
     # ------------------------------------------------------------------ bookkeeping exports

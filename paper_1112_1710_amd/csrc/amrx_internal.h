@@ -169,6 +169,7 @@ struct DevCtx {
   int* cov;               // coverage maps
   unsigned long long* slots;  // reduction / diagnostic slots
   double* partials;       // per-block conservation partials
+  int* lbflag;            // FP32_MIXED flux: per block of a launch, 1 if a face was left to the low-beta pass
   int precision;
   double gamma;
   int iso;                // isothermal hydro workload: p = cs2 * rho, HLLC fluxes, no energy, zero field
@@ -222,6 +223,10 @@ struct Sched {
 
 hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, int blk_first, int nblk,
                         int cur, int level, int substep);
+// The flux stage; FP32_MIXED: split = float pass + low-beta pass, otherwise one pass with the
+// double Riemann solver inline (other precisions ignore it).
+hipError_t launch_flux(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, int substep,
+                       bool split);
 hipError_t launch_set_dt(const DevCtx& c, double dt0);
 hipError_t launch_dt_from_cfl(const DevCtx& c, int nlev, double cfl);
 hipError_t launch_copy(const DevCtx& c, int run_first, int nrun, int blk_first, int nblk, int nelem, int cur);

@@ -141,6 +141,7 @@ struct amrx_hier {
   TaskList fb_b[AMRX_MAXLEV][2][NTILE];
   std::vector<std::array<std::array<TaskList, NTILE>, 2>> fb_p;
   bool fused_b[AMRX_MAXLEV] = {false};  // per level: fused (true) or staged edge EMF and update stages
+  bool flux_split[AMRX_MAXLEV];         // FP32_MIXED, per level: float + low-beta pass (true) or one pass
   int tile_b[AMRX_MAXLEV] = {0};
   bool extend_all = false;            // extend every side of refined patches (set before finalize)
   bool time_ghosts = false;           // coarse-time-derivative ghosts instead of extended ghost regions
@@ -179,7 +180,8 @@ struct amrx_hier {
 
   // persistent schedule variants (device copies in the scratch arena)
   SchedVariant sv[4];
-  size_t off_sched = 0, sched_slot_bytes = 0;
+  size_t off_sched = 0, sched_slot_bytes = 0, off_lbflag = 0;
+  int lbflag_n = 0;
   unsigned long long sched_clock = 0;
   int nworkgroups = 0;
   int layer_wg = 0;     // persistent grid of a mixed layer launch (the generic kernel's residency)
@@ -1528,6 +1530,17 @@ int finalize_impl(amrx_hier* h) {
     o = align256(o + sizeof(double) * n);
   }
   {
+    // FP32_MIXED flux: one flag per block of the largest flux launch (batched or per patch)
+    int nb = 1;
+    for (int l = 0; l < h->nlev; ++l)
+      for (int sub = 0; sub < 2; ++sub) nb = std::max(nb, h->stage_b[l][sub][STAGE_FLUX].nblk);
+    for (size_t id = 0; id < h->P.size(); ++id)
+      for (int sub = 0; sub < 2; ++sub) nb = std::max(nb, h->stage_p[id][sub][STAGE_FLUX].nblk);
+    h->lbflag_n = nb;
+    h->off_lbflag = o;
+    o = align256(o + sizeof(int) * (size_t)nb);
+  }
+  {
     // 4 schedule variants; items depend on the persistent grid, bounded by their count for the largest one
     SchedImage dry = build_sched(h, false, 1, false, false, false);
     size_t items_max = 0;
@@ -1569,6 +1582,7 @@ DevCtx make_ctx(amrx_hier* h) {
   c.cov = (int*)(s + h->off_cov);
   c.slots = (unsigned long long*)(s + h->off_slots);
   c.partials = (double*)(s + h->off_partials);
+  c.lbflag = (int*)(s + h->off_lbflag);
   c.precision = h->d.precision;
   c.gamma = h->d.gamma;
   c.iso = h->iso ? 1 : 0;
@@ -1653,11 +1667,15 @@ int do_advance(amrx_hier* h, int level, double dt, int substep, bool plain) {
     if (plain) {
       for (int id : h->lev[level]) {
         const TaskList& T = h->stage_p[id][substep][stg];
-        HIPCHK(TIMED(AMRX_K_PRIM + stg, launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep)), "advance stage");
+        HIPCHK(TIMED(AMRX_K_PRIM + stg, stg == STAGE_FLUX ? launch_flux(c, T.first, T.count, T.nblk, cur, level, substep, h->flux_split[level])
+                                                         : launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep)),
+               "advance stage");
       }
     } else {
       const TaskList& T = h->stage_b[level][substep][stg];
-      HIPCHK(TIMED(AMRX_K_PRIM + stg, launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep)), "advance stage");
+      HIPCHK(TIMED(AMRX_K_PRIM + stg, stg == STAGE_FLUX ? launch_flux(c, T.first, T.count, T.nblk, cur, level, substep, h->flux_split[level])
+                                                       : launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep)),
+             "advance stage");
     }
   }
   if (h->fused_b[level]) {
@@ -2263,6 +2281,7 @@ int hier_create(const amrx_desc* desc, amrx_hier** out) {
   h->lev.assign(AMRX_MAXLEV, {});
   h->real_size = desc->precision == AMRX_FP64 ? 8 : 4;
   h->reg_size = desc->precision == AMRX_FP32 ? 4 : 8;
+  for (int l = 0; l < AMRX_MAXLEV; ++l) h->flux_split[l] = true;
   *out = h;
   return AMRX_OK;
 }
@@ -2394,6 +2413,7 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   h->ctx = make_ctx(h);
   HIPCHK(launch_clear_slots(h->ctx), "clear slots");
+  HIPCHK(launch_clear_ints(h->ctx, h->ctx.lbflag, h->lbflag_n), "clear flux block flags");
   {
     int dev = 0, ncu = 0;
     HIPCHK(hipGetDevice(&dev), "get device");
@@ -2554,6 +2574,12 @@ int hier_tune_set(amrx_hier* h, int level, int param, int value) {
       changed = changed || h->tile_b[l] != value;
       h->tile_b[l] = value;
     }
+  } else if (param == AMRX_TUNE_FLUX_SPLIT) {
+    if (value != 0 && value != 1) return fail(h, AMRX_EINVAL, "AMRX_TUNE_FLUX_SPLIT takes 0 or 1");
+    for (int l = l0; l < l1; ++l) {
+      changed = changed || h->flux_split[l] != (value == 1);
+      h->flux_split[l] = value == 1;
+    }
   } else {
     return fail(h, AMRX_EINVAL, "unknown tuning parameter");
   }
@@ -2590,6 +2616,8 @@ int hier_tune_get(const amrx_hier* h, int level, int param, int* value) {
     *value = h->fused_b[level] ? 1 : 0;
   } else if (param == AMRX_TUNE_TILE_EU) {
     *value = h->tile_b[level];
+  } else if (param == AMRX_TUNE_FLUX_SPLIT) {
+    *value = h->flux_split[level] ? 1 : 0;
   } else {
     return AMRX_EINVAL;
   }
@@ -2686,6 +2714,36 @@ int hier_tune_time_eu(amrx_hier* h, int level, int tile, int reps, double* ms) {
   (void)hipEventDestroy(a);
   (void)hipEventDestroy(b);
   HIPCHK(e, "tile timing");
+  *ms = (double)t_ms / reps;
+  return AMRX_OK;
+}
+
+int hier_tune_time_flux(amrx_hier* h, int level, int split, int reps, double* ms) {
+  if (!ready(h)) return AMRX_ESTATE;
+  if (!ms || reps < 1 || level < 0 || level >= h->nlev || (split != 0 && split != 1))
+    return fail(h, AMRX_EINVAL, "bad level, variant, repetition count or output");
+  const TaskList& T = h->stage_b[level][0][STAGE_FLUX];
+  hipStream_t s = (hipStream_t)h->d.stream;
+  for (int stg = STAGE_PRIM; stg <= STAGE_PRED; ++stg) {
+    const TaskList& L = h->stage_b[level][0][stg];
+    HIPCHK(launch_stage(h->ctx, stg, L.first, L.count, 0, L.nblk, h->cur[level], level, 0), "first stages");
+  }
+  hipEvent_t a = nullptr, b = nullptr;
+  HIPCHK(hipEventCreate(&a), "event create");
+  if (!hip_ok(h, hipEventCreate(&b), "event create")) {
+    (void)hipEventDestroy(a);
+    return AMRX_EHIP;
+  }
+  hipError_t e = hipEventRecord(a, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r)
+    e = launch_flux(h->ctx, T.first, T.count, T.nblk, h->cur[level], level, 0, split == 1);
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float t_ms = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&t_ms, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  HIPCHK(e, "flux timing");
   *ms = (double)t_ms / reps;
   return AMRX_OK;
 }

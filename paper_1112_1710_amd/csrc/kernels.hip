@@ -105,19 +105,21 @@ __device__ __forceinline__ R upwind(R flux, R minus_val, R plus_val) {
   return flux > R(0) ? minus_val : (flux < R(0) ? plus_val : mean);
 }
 
-// gas pressure from conserved variables; MIX evaluates it in double
+// gas pressure from conserved variables.  MIX evaluates it again in double where the subtraction
+// cancels: the float result keeps about log2(e / (e - kin - mag)) fewer bits than e, so where the
+// kinetic and magnetic energies exceed 15/16 of e (low beta, fast flow) more than 4 bits would go.
 template <typename R, bool MIX>
 __device__ __forceinline__ R pressure(R rho, R mx, R my, R mz, R e, R bx, R by, R bz, R gm1) {
-  if (MIX) {
-    double r = rho;
-    double kin = 0.5 * ((double)mx * mx + (double)my * my + (double)mz * mz) / r;
-    double mag = 0.5 * ((double)bx * bx + (double)by * by + (double)bz * bz);
-    return (R)((double)gm1 * ((double)e - kin - mag));
-  } else {
-    R kin = qdiv(R(0.5) * (mx * mx + my * my + mz * mz), rho);
-    R mag = R(0.5) * (bx * bx + by * by + bz * bz);
-    return gm1 * (e - kin - mag);
+  const R kin = qdiv(R(0.5) * (mx * mx + my * my + mz * mz), rho);
+  const R mag = R(0.5) * (bx * bx + by * by + bz * bz);
+  const R eint = e - kin - mag;
+  if (MIX && !(R(16) * eint > e)) {
+    const double r = rho;
+    const double kd = 0.5 * ((double)mx * mx + (double)my * my + (double)mz * mz) / r;
+    const double md = 0.5 * ((double)bx * bx + (double)by * by + (double)bz * bz);
+    return (R)((double)gm1 * ((double)e - kd - md));
   }
+  return gm1 * eint;
 }
 
 template <typename R, bool FD = false>
@@ -853,8 +855,12 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_fused_a(DevCtx c, int first, int
 // ---------------------------------------------------------------------------
 // stage 4: HLLD fluxes through the faces normal to D, boundary registers
 // ---------------------------------------------------------------------------
-template <int D, typename R, bool MIX, bool ISO>
-__device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, R* X, int i, int j, int k, int level,
+// PASS (FP32_MIXED only): 0 = every face in one pass, the Riemann solver in double at low-beta
+// faces; 1 = float faces only, a low-beta face gets a NaN mass flux and nothing else; 2 = the faces
+// pass 1 left, in double.  Split in two launches, the float kernel keeps the register footprint of
+// the plain FP32 one; the arithmetic of every face is the same in both forms.
+template <int D, typename R, bool MIX, bool ISO, int PASS = 0>
+__device__ bool flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, R* X, int i, int j, int k, int level,
                           int substep, double dt) {
   using Q = typename RegOf<R, MIX>::T;
   constexpr int A = (D + 1) % 3, C = (D + 2) % 3;
@@ -904,18 +910,27 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
   }
   if constexpr (ISO) {
     hllc_iso<D, R>(wl, wr, R(sqrt(c.cs2)), f);
-  } else if (low_beta) {
-    double wld[8], wrd[8], fd[8];
-#pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      wld[m] = wl[m];
-      wrd[m] = wr[m];
+  } else if constexpr (PASS == 1) {
+    if (low_beta) {
+      X[(SCR_F0 + D) * v + q] = R(__builtin_nan(""));
+      return true;
     }
-    hlld<D, double, true>(wld, wrd, (double)bn, c.gamma, fd);
-#pragma unroll
-    for (int m = 0; m < 8; ++m) f[m] = (R)fd[m];
-  } else {
     hlld<D, R>(wl, wr, bn, gamma, f);
+  } else {
+    if (PASS == 2 && !low_beta) return false;  // a non-finite flux of pass 1, not a face left to this pass
+    if (low_beta) {
+      double wld[8], wrd[8], fd[8];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        wld[m] = wl[m];
+        wrd[m] = wr[m];
+      }
+      hlld<D, double, true>(wld, wrd, (double)bn, c.gamma, fd);
+#pragma unroll
+      for (int m = 0; m < 8; ++m) f[m] = (R)fd[m];
+    } else {
+      hlld<D, R>(wl, wr, bn, gamma, f);
+    }
   }
   const R rec[4] = {f[1], f[2], f[3], f[4]};
   st4(X + (SCR_F4 + 4 * D) * v + 4 * q, rec);
@@ -957,13 +972,21 @@ __device__ void flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
       for (int m = 0; m < 5; ++m) regs[cp.creg + face_reg_index(nc, D, side, m, t1, t2)] = (Q)f[m] * (Q)dt;
     }
   }
+  return false;
 }
 
 // ISO: the isothermal workload's faces (a separate instantiation, so the MHD kernel carries no
-// branch of it)
-template <typename R, bool MIX, bool ISO = false>
+// branch of it); PASS as in flux_face (pass 2 first checks the face's mark)
+template <typename R, bool MIX, bool ISO = false, int PASS = 0>
 __device__ __forceinline__ void d_flux(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level, int substep) {
   (void)nb;
+  if constexpr (PASS == 2) {
+    // only blocks whose pass 1 left a face; the flag is cleared for the next pass 1
+    const int flagged = c.lbflag[vb];
+    __syncthreads();
+    if (flagged == 0) return;
+    if (threadIdx.x == 0) c.lbflag[vb] = 0;
+  }
   const double dt = level_dt(c, level);
   Where w;
   if (!locate(c, first, n, vb, w)) return;
@@ -972,9 +995,17 @@ __device__ __forceinline__ void d_flux(const DevCtx& c, int vb, int nb, int firs
   const Strides S = strides(p);
   R* X = (R*)c.rscr + p.scr;
   (void)cur;
-  if (T.axis == 0) flux_face<0, R, MIX, ISO>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
-  else if (T.axis == 1) flux_face<1, R, MIX, ISO>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
-  else flux_face<2, R, MIX, ISO>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  if constexpr (PASS == 2) {
+    const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+    if (!isnan(X[(SCR_F0 + T.axis) * S.v + q])) return;
+  }
+  bool left;
+  if (T.axis == 0) left = flux_face<0, R, MIX, ISO, PASS>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else if (T.axis == 1) left = flux_face<1, R, MIX, ISO, PASS>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else left = flux_face<2, R, MIX, ISO, PASS>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  if constexpr (PASS == 1) {
+    if (left) c.lbflag[vb] = 1;
+  }
 }
 
 // the flux stage of either physics from a device-side scheduler (one code path per workload)
@@ -985,9 +1016,23 @@ __device__ __forceinline__ void d_flux_any(const DevCtx& c, int vb, int nb, int 
   else d_flux<R, MIX, false>(c, vb, nb, first, n, cur, level, substep);
 }
 
+// FP32_MIXED runs this kernel as pass 1 and k_flux_low_beta as pass 2 over the same grid
 template <typename R, bool MIX>
 __global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n, int cur, int level, int substep) {
-  d_flux<R, MIX, false>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
+  d_flux<R, MIX, false, MIX ? 1 : 0>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
+}
+
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flux_low_beta(DevCtx c, int first, int n, int cur, int level,
+                                                              int substep) {
+  d_flux<R, true, false, 2>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
+}
+
+// FP32_MIXED in one pass (the double Riemann solver inline at low-beta faces)
+template <typename R>
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flux_mixed_one_pass(DevCtx c, int first, int n, int cur, int level,
+                                                                    int substep) {
+  d_flux<R, true, false, 0>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
 }
 
 template <typename R, bool MIX>
@@ -2249,12 +2294,34 @@ hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, i
     case STAGE_BHALF: DISPATCH(k_bhalf, g, c, task_first, ntask, cur, level); break;
     case STAGE_PRED: DISPATCH(k_pred, g, c, task_first, ntask, cur, level); break;
     case STAGE_FLUX:
-      if (c.iso) DISPATCH(k_flux_iso, g, c, task_first, ntask, cur, level, substep);
-      else DISPATCH(k_flux, g, c, task_first, ntask, cur, level, substep);
+      if (c.iso) {
+        DISPATCH(k_flux_iso, g, c, task_first, ntask, cur, level, substep);
+      } else {
+        return launch_flux(c, task_first, ntask, nblk, cur, level, substep, true);
+      }
       break;
     case STAGE_EDGE: DISPATCH(k_edge, g, c, task_first, ntask, cur, level, substep); break;
     case STAGE_UPDATE: DISPATCH(k_update, g, c, task_first, ntask, cur, level); break;
     default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_flux(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, int substep,
+                       bool split) {
+  if (ntask == 0 || nblk == 0) return hipSuccess;
+  const dim3 g(nblk);
+  if (c.iso) {
+    DISPATCH(k_flux_iso, g, c, task_first, ntask, cur, level, substep);
+  } else if (c.precision == 2 && !split) {
+    k_flux_mixed_one_pass<float><<<g, AMRX_BLOCK, 0, c.stream>>>(c, task_first, ntask, cur, level, substep);
+  } else {
+    DISPATCH(k_flux, g, c, task_first, ntask, cur, level, substep);
+    if (c.precision == 2) {
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      k_flux_low_beta<float><<<g, AMRX_BLOCK, 0, c.stream>>>(c, task_first, ntask, cur, level, substep);
+    }
   }
   return hipGetLastError();
 }

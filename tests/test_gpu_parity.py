@@ -670,3 +670,27 @@ def test_steps_latch_an_unphysical_state_over_the_run():
     assert err.value.code == -7
     _assert_same_interiors(spec, single, run)
     assert run.steps(1, BATCHED, dt0) == (dt0, dt0)  # the latch starts afresh with every run
+
+
+@pytest.mark.parametrize("beta", [None, 0.1, 1e-3])
+def test_mixed_flux_two_launch_and_one_launch_forms_are_bit_identical(beta):
+    """FP32_MIXED: the flux stage as a float launch plus a launch for the low-beta faces it leaves
+    (the default) and as one launch with the double Riemann solver inline give the same states and
+    dts bit for bit, with no face (smooth field at beta 2), part of the faces (beta 0.1 with field
+    and pressure fluctuations about the threshold) and every face (beta 1e-3) low-beta, over plain,
+    batched and graph-replayed root steps."""
+    from paper_1112_1710_amd import binding
+    spec = H.small_three_level()
+    field = SmoothField(1112) if beta is None else low_beta(5, beta=beta)
+    _say("mixed flux forms, beta", beta)
+    a = Hierarchy(spec, FP32_MIXED)
+    b = Hierarchy(spec, FP32_MIXED)
+    b.tune_set(binding.TUNE_FLUX_SPLIT, 0)
+    assert a.tune_get(binding.TUNE_FLUX_SPLIT, level=1) == 1
+    a.set_field(field)
+    b.set_field(field)
+    for mode in (PLAIN, BATCHED, GRAPH, GRAPH):
+        assert a.step(mode) == b.step(mode)
+    _assert_same_interiors(spec, a, b)
+    d = a.diag()
+    assert d["phys_flag"] == 0.0 and d["sync_flux_max"] == 0.0

@@ -454,7 +454,14 @@ def test_tile_table_and_tuning_switches(prec):
     with pytest.raises(binding.AmrxError):
         h.tune_set(binding.TUNE_FUSED, 2)
     with pytest.raises(binding.AmrxError):
-        h.tune_set(7, 0)
+        h.tune_set(8, 0)
+    # FP32_MIXED flux stage: two launches by default, one launch selectable per level
+    assert all(h.tune_get(binding.TUNE_FLUX_SPLIT, level=lv) == 1 for lv in range(3))
+    h.tune_set(binding.TUNE_FLUX_SPLIT, 0, level=2)
+    assert [h.tune_get(binding.TUNE_FLUX_SPLIT, level=lv) for lv in range(3)] == [1, 1, 0]
+    with pytest.raises(binding.AmrxError):
+        h.tune_set(binding.TUNE_FLUX_SPLIT, 2)
+    h.tune_set(binding.TUNE_FLUX_SPLIT, 1)
     with pytest.raises(binding.AmrxError):
         h.tune_set(binding.TUNE_TILE, 0, level=16)
     # fused edge EMF + update stages: every tile allowed (LDS 3 (tx+1)(ty+1)(tz+1) reals)
