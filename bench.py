@@ -612,6 +612,7 @@ def main():
                  "rel_l1_per_step": precision_report(spec, h, hm, mode, torch, physics, cs)}
         del hm
         torch.cuda.empty_cache()
+    flux_forms = getattr(h, "flux_forms", None)
     del h
     torch.cuda.empty_cache()
     if args.pmc_calibration:
@@ -647,8 +648,8 @@ def main():
         "step_hbm": step_hbm,
         "kernel_ms_per_step": per_class,
     }
-    if getattr(h, "flux_forms", None):
-        out["config"]["flux_stage"] = h.flux_forms
+    if flux_forms:
+        out["config"]["flux_stage"] = flux_forms
     if regrid_report is not None:
         out["regrid"] = regrid_report
     if mixed is not None:
