@@ -58,14 +58,14 @@ WORDS_PER_UNIT = {
 # 512 MiB copy's readings), keyed by (workload, precision, kernel class); valid only for the kernel sources whose
 # hash is stored beside it, null otherwise.
 MEASURED_TRAFFIC = {
-    ("deep", "fp32", "primhalf"): {"bytes_per_launch": 2.748e9, "sources": "a2fb636c71d05d19:9479ed42ed520f09"},
+    ("deep", "fp32", "primhalf"): {"bytes_per_launch": 2.828e9, "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
 }
 
 # Fraction of the dominant kernel's vector-ALU issue slots used (SQ_INSTS_VALU against 256 CUs x one
 # wave-instruction per cycle x 2.4 GHz over its mean duration), from rocprofv3 counters, same validity rule.
 MEASURED_VALU_ISSUE = {
-    ("deep", "fp32", "primhalf"): {"frac": 0.68, "sources": "a2fb636c71d05d19:9479ed42ed520f09"},
-    ("deep", "fp32", "flux"): {"frac": 0.78, "sources": "a2fb636c71d05d19:9479ed42ed520f09"},
+    ("deep", "fp32", "primhalf"): {"frac": 0.68, "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
+    ("deep", "fp32", "flux"): {"frac": 0.78, "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
 }
 
 
