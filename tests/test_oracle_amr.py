@@ -10,6 +10,7 @@ prolongation, exactness of prolongation on linear fields, and
 bit-identical results when stale ghost data are poisoned with NaN.
 """
 import math
+import os
 
 import numpy as np
 import pytest
@@ -19,19 +20,39 @@ from workloads import hierarchies as H
 from workloads.fields import G, SmoothField, Uniform, _coords, _clean, PatchState
 
 
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def _golden(name):
+    """Key = value lines of a fixture under tests/golden (values as integer lists; '#' lines are comments)."""
+    out = {}
+    with open(os.path.join(GOLDEN, name)) as fh:
+        for line in fh:
+            line = line.split("#", 1)[0].strip()
+            if line:
+                key, val = (t.strip() for t in line.split("=", 1))
+                out[key] = [int(x) for x in val.split()]
+    return out
+
+
 def _boxcells(box):
     lo, hi = box
     return int(np.prod(np.asarray(hi) - np.asarray(lo)))
 
 
 def test_extended_ghost_counts_of_the_paper_example():
-    """4x4 grid, R=2, n_ghost=4: 12x12 + 4x4 = 160 updates; four 2x2 pieces: 4 x (10x10 + 2x2) = 416; 38 %."""
-    whole = sum(_boxcells(amr.update_box((0, 0), (4, 4), 1, s, ratio=2, n_g=4)) for s in range(2))
-    piece = sum(_boxcells(amr.update_box((0, 0), (2, 2), 1, s, ratio=2, n_g=4)) for s in range(2))
-    assert whole == 160
-    assert piece == 104
-    assert 4 * piece == 416
-    assert round(100 * whole / (4 * piece)) == 38
+    """The paper's 2-D example: 4x4 grid, R=2, n_ghost=4: 12x12 + 4x4 = 160 updates; four 2x2 pieces:
+    4 x (10x10 + 2x2) = 416; 38 %.  The printed values come from tests/golden."""
+    g = _golden("sec4_extended_ghost_example.txt")
+    n, r, ng, k = g["grid"], g["ratio"][0], g["n_ghost"][0], g["pieces"][0]
+    side = int(round(math.sqrt(k)))
+    sub = tuple(x // side for x in n)
+    whole = sum(_boxcells(amr.update_box((0, 0), tuple(n), 1, s, ratio=r, n_g=ng)) for s in range(r))
+    piece = sum(_boxcells(amr.update_box((0, 0), sub, 1, s, ratio=r, n_g=ng)) for s in range(r))
+    assert whole == g["updates_whole"][0]
+    assert piece == g["updates_per_piece"][0]
+    assert k * piece == g["updates_split_total"][0]
+    assert round(100 * whole / (k * piece)) == g["efficiency_percent"][0]
 
 
 def test_update_region_shrinks_by_stencil_depth():
@@ -64,11 +85,14 @@ def test_nesting_rules():
 
 
 def test_visit_order_and_substep_counts():
-    h = amr.build(H.small_three_level(), SmoothField(7))
+    g = _golden("sec4_serial_visit_order.txt")
+    spec = H.small_three_level()
+    assert spec.levels() == g["levels"][0]
+    h = amr.build(spec, SmoothField(7))
     h.root_step()
-    assert h.log == [0, 1, 2, 2, 1, 2, 2]
-    for lv in range(3):
-        assert h.log.count(lv) == 2 ** lv
+    assert h.log == g["order"]
+    for lv in range(g["levels"][0]):
+        assert h.log.count(lv) == g["ratio"][0] ** lv
 
 
 @pytest.fixture(scope="module")
