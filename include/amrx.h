@@ -433,6 +433,14 @@ int hier_debug_concurrent(amrx_hier* h, int fixed_dt, int* sizes, int* nodes, in
 /* The update region [lo, hi) (padded cell indices) of a patch at `substep`. */
 int hier_debug_update_box(const amrx_hier* h, int patch_id, int substep, int lo[3], int hi[3]);
 
+/* The batched task list of one advance stage (0 primitives, 1 half-step
+ * field, 2 predictor, 3 flux, 4 edge EMFs, 5 update) of a level substep:
+ * *count tasks; if out is non-NULL, up to cap records of 9 ints each (patch,
+ * axis, lo[3], hi[3] in padded entry indices, first block of the task within
+ * the launch).  The flux and edge stages hold one task per axis and slab of
+ * z planes, the axes of a slab adjacent and in order.  Pure host call. */
+int hier_debug_tasks(const amrx_hier* h, int level, int substep, int stage, int* count, int* out, int cap);
+
 /* Number of parent cells prolongated into a patch at substep 0, and (if out
  * is non-NULL, cap entries) their level-(l-1) (x, y, z) indices. */
 int hier_debug_prolong_cells(const amrx_hier* h, int patch_id, int* count, int* out, int cap);

@@ -80,6 +80,8 @@ EXPORTS = {
     "hier_tune_time": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
     "hier_tune_time_eu": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
     "hier_tune_time_flux": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_double)], C.c_int),
+    "hier_debug_tasks": ([C.c_void_p, C.c_int, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int), C.c_int],
+                         C.c_int),
     "hier_debug_update_box": ([C.c_void_p, C.c_int, C.c_int, C.POINTER(C.c_int), C.POINTER(C.c_int)], C.c_int),
 }
 
@@ -358,6 +360,14 @@ class Hierarchy:
         lo, hi = (C.c_int * 3)(), (C.c_int * 3)()
         self._check(self.lib.hier_debug_update_box(self.h, pid, substep, lo, hi))
         return tuple(lo), tuple(hi)
+
+    def debug_tasks(self, level, substep, stage):
+        """Batched task list of an advance stage: (n, 9) int array of (patch, axis, lo[3], hi[3], first block)."""
+        cnt = C.c_int(0)
+        self._check(self.lib.hier_debug_tasks(self.h, level, substep, stage, C.byref(cnt), None, 0))
+        out = (C.c_int * (9 * max(cnt.value, 1)))()
+        self._check(self.lib.hier_debug_tasks(self.h, level, substep, stage, C.byref(cnt), out, cnt.value))
+        return np.frombuffer(out, dtype=np.int32, count=9 * cnt.value).reshape(cnt.value, 9).copy()
 
     def debug_sources(self, pid, kind):
         offs, shape = self.layout(pid, 0)

@@ -436,6 +436,34 @@ void stage_regions(int stage, int axis, const int lo[3], const int hi[3], int rl
   }
 }
 
+// Tasks of a per-axis stage (flux, edge) of one patch: the three axes' regions cut into slabs of
+// whole z planes (as many planes as fit in kAxisSlabEntries entries, at least one), ordered slab
+// by slab with the three axes of a slab adjacent, so that the workgroups of all three axes over
+// the same cells run close together in time and find the cells' intermediates in L2.  A patch
+// whose planes are small keeps one slab, the three whole-axis tasks.  Returns the blocks added.
+constexpr long long kAxisSlabEntries = 32768;
+
+int add_axis_tasks(amrx_hier* h, int patch, int stage, const int lo[3], const int hi[3], int blk_start) {
+  int rlo[3][3], rhi[3][3];
+  for (int ax = 0; ax < 3; ++ax) stage_regions(stage, ax, lo, hi, rlo[ax], rhi[ax]);
+  int nb = 0;
+  int z0 = rlo[0][2], z1 = rhi[0][2];
+  long long plane = 1;
+  for (int ax = 0; ax < 3; ++ax) {
+    z0 = std::min(z0, rlo[ax][2]);
+    z1 = std::max(z1, rhi[ax][2]);
+    plane = std::max(plane, (long long)std::max(0, rhi[ax][0] - rlo[ax][0]) * std::max(0, rhi[ax][1] - rlo[ax][1]));
+  }
+  const int dz = (int)std::max(1LL, kAxisSlabEntries / plane);
+  for (int z = z0; z < z1; z += dz)
+    for (int ax = 0; ax < 3; ++ax) {
+      int a[3] = {rlo[ax][0], rlo[ax][1], std::max(rlo[ax][2], z)};
+      int b[3] = {rhi[ax][0], rhi[ax][1], std::min(rhi[ax][2], z + dz)};
+      if (a[2] < b[2] && a[0] < b[0] && a[1] < b[1]) nb += add_task(h, patch, ax, a, b, blk_start + nb);
+    }
+  return nb;
+}
+
 // Host work over independent items (patches) on up to 16 threads; fn(i) for i in [0, n).
 template <typename F>
 void parallel_for(int n, F fn) {
@@ -1329,11 +1357,13 @@ int finalize_impl(amrx_hier* h) {
         for (int id : h->lev[l]) {
           int lo[3], hi[3];
           update_box(h->P[id], s, lo, hi);
-          for (int ax = 0; ax < naxes; ++ax) {
-            int rlo[3], rhi[3];
-            stage_regions(stg, ax, lo, hi, rlo, rhi);
-            nb += add_task(h, id, ax, rlo, rhi, nb);
+          if (naxes == 3) {
+            nb += add_axis_tasks(h, id, stg, lo, hi, nb);
+            continue;
           }
+          int rlo[3], rhi[3];
+          stage_regions(stg, 0, lo, hi, rlo, rhi);
+          nb += add_task(h, id, 0, rlo, rhi, nb);
         }
         B.count = (int)h->tasks.size() - B.first;
         B.nblk = nb;
@@ -1343,10 +1373,12 @@ int finalize_impl(amrx_hier* h) {
           int lo[3], hi[3];
           update_box(h->P[id], s, lo, hi);
           int nbp = 0;
-          for (int ax = 0; ax < naxes; ++ax) {
+          if (naxes == 3) {
+            nbp = add_axis_tasks(h, id, stg, lo, hi, 0);
+          } else {
             int rlo[3], rhi[3];
-            stage_regions(stg, ax, lo, hi, rlo, rhi);
-            nbp += add_task(h, id, ax, rlo, rhi, nbp);
+            stage_regions(stg, 0, lo, hi, rlo, rhi);
+            nbp = add_task(h, id, 0, rlo, rhi, 0);
           }
           T.count = (int)h->tasks.size() - T.first;
           T.nblk = nbp;
@@ -2629,6 +2661,29 @@ int hier_debug_update_box(const amrx_hier* h, int patch_id, int substep, int lo[
   if (!h->frozen) return AMRX_ESTATE;
   if (patch_id < 0 || patch_id >= (int)h->P.size() || substep < 0 || substep >= R) return AMRX_EINVAL;
   update_box(h->P[patch_id], substep, lo, hi);
+  return AMRX_OK;
+}
+
+int hier_debug_tasks(const amrx_hier* h, int level, int substep, int stage, int* count, int* out, int cap) {
+  if (!h || !count || cap < 0) return AMRX_EINVAL;
+  if (!h->frozen) return AMRX_ESTATE;
+  if (level < 0 || level >= h->nlev || substep < 0 || substep >= (level == 0 ? 1 : R) || stage < 0 ||
+      stage >= NSTAGE)
+    return AMRX_EINVAL;
+  const TaskList& L = h->stage_b[level][substep][stage];
+  *count = L.count;
+  if (out)
+    for (int t = 0; t < L.count && t < cap; ++t) {
+      const Task& T = h->tasks[L.first + t];
+      int* o = out + 9 * t;
+      o[0] = T.patch;
+      o[1] = T.axis;
+      for (int a = 0; a < 3; ++a) {
+        o[2 + a] = T.lo[a];
+        o[5 + a] = T.hi[a];
+      }
+      o[8] = h->blk[L.first + t];
+    }
   return AMRX_OK;
 }
 

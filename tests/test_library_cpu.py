@@ -731,3 +731,58 @@ def test_isothermal_switch_rejects_bad_sound_speed():
     assert ei.value.code == -1
     h = binding.Hierarchy(H.small_two_level(), device=None, physics="isothermal", cs=0.7)
     assert h.physics == "isothermal" and h.cs == 0.7
+
+
+def _stage_region(stage, axis, lo, hi):
+    """Entries a stage visits for an update box [lo, hi): flux faces normal to `axis` and the face
+    layers around them, edge EMFs along `axis`."""
+    rlo, rhi = list(lo), list(hi)
+    for a in range(3):
+        if stage == 3:
+            rlo[a], rhi[a] = (lo[a], hi[a] + 1) if a == axis else (lo[a] - 1, hi[a] + 1)
+        else:
+            rlo[a], rhi[a] = (lo[a], hi[a]) if a == axis else (lo[a], hi[a] + 1)
+    return rlo, rhi
+
+
+_TASK_SPECS = {"uniform256": lambda: H.single_patch((256, 256, 256)), "two_level": H.two_level,
+               "small_three_level": H.small_three_level}
+
+
+@pytest.mark.parametrize("name", sorted(_TASK_SPECS))
+def test_flux_and_edge_tasks_are_axis_interleaved_slabs(name):
+    """The flux and edge stages' task lists: per patch, each axis's region covered exactly once by
+    slabs of whole z planes (at most 32768 entries a slab unless a single plane is larger), the
+    axes of a slab adjacent, and the first blocks of the tasks consecutive in whole blocks."""
+    spec = _TASK_SPECS[name]()
+    h = binding.Hierarchy(spec, device=None)
+    for level in range(spec.levels()):
+        for substep in range(1 if level == 0 else 2):
+            for stage in (3, 4):
+                t = h.debug_tasks(level, substep, stage)
+                assert len(t)
+                blk = 0
+                for row in t:
+                    assert row[8] == blk
+                    blk += -(-int(np.prod(row[5:8] - row[2:5])) // 256)
+                by_patch = {}
+                for row in t:
+                    by_patch.setdefault(int(row[0]), []).append(row)
+                for pid, rows in by_patch.items():
+                    lo, hi = h.update_box(pid, substep)
+                    for axis in range(3):
+                        rlo, rhi = _stage_region(stage, axis, lo, hi)
+                        mine = [r for r in rows if r[1] == axis]
+                        assert all(list(r[2:4]) == rlo[:2] and list(r[5:7]) == rhi[:2] for r in mine)
+                        z = sorted((int(r[4]), int(r[7])) for r in mine)
+                        assert z[0][0] == rlo[2] and z[-1][1] == rhi[2]
+                        assert all(a[1] == b[0] for a, b in zip(z, z[1:]))       # contiguous, disjoint
+                        plane = (rhi[0] - rlo[0]) * (rhi[1] - rlo[1])
+                        assert all(b - a == 1 or (b - a) * plane <= 32768 for a, b in z)
+                    # slab by slab, the axes of a slab adjacent and in order: (slab, axis) increases
+                    zmin = min(int(r[4]) for r in rows)
+                    dz = max(int(r[7]) - int(r[4]) for r in rows)
+                    keys = [((int(r[4]) - zmin) // dz, int(r[1])) for r in rows]
+                    assert all(a < b for a, b in zip(keys, keys[1:])), keys
+                    if name == "uniform256" and level == 0:
+                        assert len(rows) > 3                                       # large planes: one per slab
