@@ -56,16 +56,20 @@ WORDS_PER_UNIT = {
 
 # HBM bytes per launch of the dominant kernel measured with rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a
 # 512 MiB copy's readings), keyed by (workload, precision, kernel class); valid only for the kernel sources whose
-# hash is stored beside it, null otherwise.
+# hash is stored beside it and, for the fused first stages, for the same set of fused levels (which sets the
+# launches the average runs over), null otherwise.
 MEASURED_TRAFFIC = {
-    ("deep", "fp32", "primhalf"): {"bytes_per_launch": 2.828e9, "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
+    ("deep", "fp32", "primhalf"): [
+        {"bytes_per_launch": 2.749e9, "fused_levels": [3, 4, 5, 6, 7], "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
+        {"bytes_per_launch": 2.828e9, "fused_levels": [4, 5, 6, 7], "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
+    ],
 }
 
 # Fraction of the dominant kernel's vector-ALU issue slots used (SQ_INSTS_VALU against 256 CUs x one
 # wave-instruction per cycle x 2.4 GHz over its mean duration), from rocprofv3 counters, same validity rule.
 MEASURED_VALU_ISSUE = {
-    ("deep", "fp32", "primhalf"): {"frac": 0.68, "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
-    ("deep", "fp32", "flux"): {"frac": 0.78, "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
+    ("deep", "fp32", "primhalf"): {"frac": 0.67, "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
+    ("deep", "fp32", "flux"): {"frac": 0.79, "sources": "928bf9c4e441990e:898ba12b2794eaf3"},
 }
 
 
@@ -562,15 +566,17 @@ def main():
         bytes_per_launch = units_per_step * WORDS_PER_UNIT[dom] * word / max(launches_per_step, 1)
         avg_ms = ms_total / nlaunch
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
-        meas = MEASURED_TRAFFIC.get((args.workload, args.precision, dom)) if args.ghosts == "extended" else None
+        fused_levels = {int(k) for k, v in (tiles or {}).items() if v != "staged"}
+        readings = MEASURED_TRAFFIC.get((args.workload, args.precision, dom), []) if args.ghosts == "extended" else []
+        meas = next((m for m in readings if m["sources"] == sources_hash()
+                     and m.get("fused_levels", sorted(fused_levels)) == sorted(fused_levels)), None)
         traffic = None
-        if meas is not None and meas["sources"] == sources_hash():
+        if meas is not None:
             traffic = round(meas["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)
         hbm = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
                "avg_launch_ms": round(avg_ms, 4), "bytes_per_launch": int(bytes_per_launch),
                "traffic_bytes_per_launch": None if traffic is None else int(meas["bytes_per_launch"])}
-        fused_levels = {int(k) for k, v in (tiles or {}).items() if v != "staged"}
         # the flop prices are the MHD scheme's; the isothermal workload's kernels are reported against HBM
         if physics == "mhd" and (dom in ALU_BOUND or (dom == "primhalf" and fused_levels)):
             if dom == "primhalf":
