@@ -169,7 +169,7 @@ struct DevCtx {
   int* cov;               // coverage maps
   unsigned long long* slots;  // reduction / diagnostic slots
   double* partials;       // per-block conservation partials
-  int* lbflag;            // FP32_MIXED flux: per block of a launch, 1 if a face was left to the low-beta pass
+  int* lbflag;            // FP32_MIXED flux: count + list of the waves whose faces were left to the low-beta pass
   int precision;
   double gamma;
   int iso;                // isothermal hydro workload: p = cs2 * rho, HLLC fluxes, no energy, zero field

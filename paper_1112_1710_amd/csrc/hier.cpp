@@ -1562,15 +1562,15 @@ int finalize_impl(amrx_hier* h) {
     o = align256(o + sizeof(double) * n);
   }
   {
-    // FP32_MIXED flux: one flag per block of the largest flux launch (batched or per patch)
+    // FP32_MIXED flux: a count and one item per wave of the largest flux launch (batched or per patch)
     int nb = 1;
     for (int l = 0; l < h->nlev; ++l)
       for (int sub = 0; sub < 2; ++sub) nb = std::max(nb, h->stage_b[l][sub][STAGE_FLUX].nblk);
     for (size_t id = 0; id < h->P.size(); ++id)
       for (int sub = 0; sub < 2; ++sub) nb = std::max(nb, h->stage_p[id][sub][STAGE_FLUX].nblk);
-    h->lbflag_n = nb;
+    h->lbflag_n = 1 + nb * (AMRX_BLOCK / 64);
     h->off_lbflag = o;
-    o = align256(o + sizeof(int) * (size_t)nb);
+    o = align256(o + sizeof(int) * (size_t)h->lbflag_n);
   }
   {
     // 4 schedule variants; items depend on the persistent grid, bounded by their count for the largest one

@@ -414,13 +414,14 @@ __device__ __forceinline__ void split_index(unsigned n, unsigned d, double inv, 
 // in the list's block table.
 __device__ __forceinline__ int task_of_block(const DevCtx& c, int first, int b) { return c.b2t[c.tbl[first] + b]; }
 
-__device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, int b, Where& w) {
+// Entry of thread `tid` of block b of a launch over a task list (its task and padded (i, j, k)).
+__device__ __forceinline__ bool locate_tid(const DevCtx& c, int first, int n, int b, int tid, Where& w) {
   (void)n;
   const int t = task_of_block(c, first, b);
   const Task& T = c.tasks[t];
   // a region lies inside one padded patch, whose volume the host keeps below 2^31 entries
   const unsigned ex = T.hi[0] - T.lo[0], ey = T.hi[1] - T.lo[1], ez = T.hi[2] - T.lo[2];
-  const unsigned local = (unsigned)(b - c.blk[t]) * AMRX_BLOCK + threadIdx.x;
+  const unsigned local = (unsigned)(b - c.blk[t]) * AMRX_BLOCK + (unsigned)tid;
   if (local >= ex * ey * ez) return false;
   w.task = t;
   unsigned row, k;
@@ -430,6 +431,10 @@ __device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, int b,
   w.j += T.lo[1];
   w.k = T.lo[2] + (int)k;
   return true;
+}
+
+__device__ __forceinline__ bool locate(const DevCtx& c, int first, int n, int b, Where& w) {
+  return locate_tid(c, first, n, b, (int)threadIdx.x, w);
 }
 
 struct Strides {
@@ -976,17 +981,15 @@ __device__ bool flux_face(const DevCtx& c, const PatchDev& p, const Strides& S, 
 }
 
 // ISO: the isothermal workload's faces (a separate instantiation, so the MHD kernel carries no
-// branch of it); PASS as in flux_face (pass 2 first checks the face's mark)
+// branch of it); PASS 0 or 1 as in flux_face
+// PASS 1 lists every wave that left a face: lbflag[0] counts the items, lbflag[1 + i] holds item i,
+// block * (waves per block) + wave, appended by the wave's first lane that left one.
+constexpr int kWavesPerBlock = AMRX_BLOCK / 64;
+
 template <typename R, bool MIX, bool ISO = false, int PASS = 0>
 __device__ __forceinline__ void d_flux(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level, int substep) {
+  static_assert(PASS != 2, "pass 2 runs over the listed waves (d_flux_left)");
   (void)nb;
-  if constexpr (PASS == 2) {
-    // only blocks whose pass 1 left a face; the flag is cleared for the next pass 1
-    const int flagged = c.lbflag[vb];
-    __syncthreads();
-    if (flagged == 0) return;
-    if (threadIdx.x == 0) c.lbflag[vb] = 0;
-  }
   const double dt = level_dt(c, level);
   Where w;
   if (!locate(c, first, n, vb, w)) return;
@@ -995,17 +998,36 @@ __device__ __forceinline__ void d_flux(const DevCtx& c, int vb, int nb, int firs
   const Strides S = strides(p);
   R* X = (R*)c.rscr + p.scr;
   (void)cur;
-  if constexpr (PASS == 2) {
-    const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
-    if (!isnan(X[(SCR_F0 + T.axis) * S.v + q])) return;
-  }
   bool left;
   if (T.axis == 0) left = flux_face<0, R, MIX, ISO, PASS>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
   else if (T.axis == 1) left = flux_face<1, R, MIX, ISO, PASS>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
   else left = flux_face<2, R, MIX, ISO, PASS>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
   if constexpr (PASS == 1) {
-    if (left) c.lbflag[vb] = 1;
+    const unsigned long long m = __ballot(left);
+    if (m != 0ull && (int)(threadIdx.x & 63) == __builtin_ctzll(m)) {
+      const int at = atomicAdd(c.lbflag, 1);
+      c.lbflag[1 + at] = vb * kWavesPerBlock + (int)(threadIdx.x >> 6);
+    }
   }
+}
+
+// Pass 2 of FP32_MIXED: the entry of lane `tid` (0..255 within its block) of a listed pass-1 block
+// whose mass flux pass 1 left as NaN, solved with the double Riemann solver.
+template <typename R>
+__device__ __forceinline__ void d_flux_left(const DevCtx& c, int vb, int tid, int first, int n, int level,
+                                            int substep) {
+  const double dt = level_dt(c, level);
+  Where w;
+  if (!locate_tid(c, first, n, vb, tid, w)) return;
+  const Task& T = c.tasks[w.task];
+  const PatchDev& p = c.patches[T.patch];
+  const Strides S = strides(p);
+  R* X = (R*)c.rscr + p.scr;
+  const long long q = w.i + w.j * S.s[1] + w.k * S.s[2];
+  if (!isnan(X[(SCR_F0 + T.axis) * S.v + q])) return;
+  if (T.axis == 0) flux_face<0, R, true, false, 2>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else if (T.axis == 1) flux_face<1, R, true, false, 2>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
+  else flux_face<2, R, true, false, 2>(c, p, S, X, w.i, w.j, w.k, level, substep, dt);
 }
 
 // the flux stage of either physics from a device-side scheduler (one code path per workload)
@@ -1016,16 +1038,23 @@ __device__ __forceinline__ void d_flux_any(const DevCtx& c, int vb, int nb, int 
   else d_flux<R, MIX, false>(c, vb, nb, first, n, cur, level, substep);
 }
 
-// FP32_MIXED runs this kernel as pass 1 and k_flux_low_beta as pass 2 over the same grid
+// FP32_MIXED runs this kernel as pass 1 and k_flux_low_beta as pass 2 over the waves it listed
 template <typename R, bool MIX>
 __global__ __launch_bounds__(AMRX_BLOCK) void k_flux(DevCtx c, int first, int n, int cur, int level, int substep) {
   d_flux<R, MIX, false, MIX ? 1 : 0>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
 }
 
+// each wave takes listed items in turn (a grid smaller than the list strides over it)
 template <typename R>
-__global__ __launch_bounds__(AMRX_BLOCK) void k_flux_low_beta(DevCtx c, int first, int n, int cur, int level,
-                                                              int substep) {
-  d_flux<R, true, false, 2>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level, substep);
+__global__ __launch_bounds__(AMRX_BLOCK) void k_flux_low_beta(DevCtx c, int first, int n, int level, int substep) {
+  const int count = c.lbflag[0];
+  const int lane = (int)(threadIdx.x & 63);
+#pragma unroll 1
+  for (int it = (int)blockIdx.x * kWavesPerBlock + (int)(threadIdx.x >> 6); it < count;
+       it += (int)gridDim.x * kWavesPerBlock) {
+    const int item = __builtin_amdgcn_readfirstlane(c.lbflag[1 + it]);  // one item per wave
+    d_flux_left<R>(c, item / kWavesPerBlock, (item % kWavesPerBlock) * 64 + lane, first, n, level, substep);
+  }
 }
 
 // FP32_MIXED in one pass (the double Riemann solver inline at low-beta faces)
@@ -2316,11 +2345,16 @@ hipError_t launch_flux(const DevCtx& c, int task_first, int ntask, int nblk, int
   } else if (c.precision == 2 && !split) {
     k_flux_mixed_one_pass<float><<<g, AMRX_BLOCK, 0, c.stream>>>(c, task_first, ntask, cur, level, substep);
   } else {
+    if (c.precision == 2) {
+      const hipError_t e = launch_clear_ints(c, c.lbflag, 1);  // the list of waves pass 1 appends to
+      if (e != hipSuccess) return e;
+    }
     DISPATCH(k_flux, g, c, task_first, ntask, cur, level, substep);
     if (c.precision == 2) {
       const hipError_t e = hipGetLastError();
       if (e != hipSuccess) return e;
-      k_flux_low_beta<float><<<g, AMRX_BLOCK, 0, c.stream>>>(c, task_first, ntask, cur, level, substep);
+      k_flux_low_beta<float><<<dim3(std::min(nblk, 1024)), AMRX_BLOCK, 0, c.stream>>>(c, task_first, ntask, level,
+                                                                                     substep);
     }
   }
   return hipGetLastError();
