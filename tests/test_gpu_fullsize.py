@@ -383,3 +383,37 @@ def test_uniform_512_sampled_windows_far_corner():
         for d in range(3):
             fsel = mhd._face_sel(region, d)
             assert _rel_l1(got_f[d][fsel], ref.faces[d][fsel]) <= 1e-5, (c, d)
+
+
+def test_two_level_low_beta_flux_forms_bit_identical():
+    """FP32 with targeted FP64 on the full two-level hierarchy at beta 1e-3, where every face is
+    low-beta: the float flux pass lists four waves per block, far more than the low-beta kernel's grid
+    of at most 1024 workgroups covers in one sweep, so its walk over the list strides many times.  The
+    two-launch form and the one-launch form give the same states and dts bit for bit, batched and
+    graph-replayed, and the whole-hierarchy checks stay clean."""
+    from paper_1112_1710_amd import FP32_MIXED, binding
+    from workloads.fields import low_beta
+    spec = H.two_level()
+    field = low_beta(5)
+    _say("two-level low beta, flux forms")
+    a = Hierarchy(spec, FP32_MIXED)
+    b = Hierarchy(spec, FP32_MIXED)
+    b.tune_set(binding.TUNE_FLUX_SPLIT, 0)
+    assert a.tune_get(binding.TUNE_FLUX_SPLIT, level=0) == 1
+    n_root = a.debug_tasks(0, 0, 3)
+    assert int(n_root[-1, 8]) + 1 > 1024           # more than one sweep of the list walk
+    a.set_field(field)
+    b.set_field(field)
+    for mode in (BATCHED, GRAPH, GRAPH):
+        assert a.step(mode) == b.step(mode)
+    o = amr.build(spec)
+    for pid, p in enumerate(o.patches):
+        ca, fa = a.download(pid)
+        cb, fb = b.download(pid)
+        m = o._interior_mask(p)
+        assert np.array_equal(ca[:, m], cb[:, m]), pid
+        for d in range(3):
+            mk = o._closure_mask(p, d)
+            assert np.array_equal(fa[d][mk], fb[d][mk]), (pid, d)
+    da = a.diag()
+    assert da["phys_flag"] == 0.0 and da["sync_flux_max"] == 0.0
