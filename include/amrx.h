@@ -287,16 +287,20 @@ int hier_step_work(const amrx_hier* h, int n, double* units, int* launches);
  *     persistent and concurrent schedules refuse it (EINVAL).
  *   AMRX_TUNE_FLUX_SPLIT (FP32_MIXED only; other precisions ignore it): 1
  *     (default) the flux stage runs as two launches over the same faces, a
- *     float one that leaves the low-beta faces (a NaN mass flux, one flag per
- *     block) and one that solves those faces' Riemann problems in double, so
- *     the float kernel keeps the plain FP32 kernel's register footprint; 0 one
- *     launch with the double solver inline, better where most faces are
- *     low-beta.  Bit-identical results.
+ *     float one that leaves the low-beta faces (a NaN mass flux, and the
+ *     wave holding one appended to a device list) and one that solves those
+ *     faces' Riemann problems in double, so the float kernel keeps the plain
+ *     FP32 kernel's register footprint; 0 one launch with the double solver
+ *     inline, better where most faces are low-beta.  Bit-identical results.
+ *   AMRX_TUNE_UPDATE_NT: 1 = the staged update kernel writes the next state
+ *     with non-temporal stores (a cache hint; faster on some levels, slower
+ *     on others), 0 (default) ordinary stores.  Bit-identical results.
  * level = -1 sets every level.  Pure host calls (captured graph-schedule steps
  * are discarded on a change).  EINVAL for a bad parameter, level or index, or
  * a tile whose LDS footprint exceeds the limit for the hierarchy's precision. */
 enum { AMRX_TUNE_FUSED = 0, AMRX_TUNE_TILE = 1, AMRX_TUNE_EXTEND_ALL = 2, AMRX_TUNE_PAIR = 3,
-       AMRX_TUNE_FUSED_EU = 4, AMRX_TUNE_TILE_EU = 5, AMRX_TUNE_GHOSTS = 6, AMRX_TUNE_FLUX_SPLIT = 7 };
+       AMRX_TUNE_FUSED_EU = 4, AMRX_TUNE_TILE_EU = 5, AMRX_TUNE_GHOSTS = 6, AMRX_TUNE_FLUX_SPLIT = 7,
+       AMRX_TUNE_UPDATE_NT = 8 };
 int hier_tune_set(amrx_hier* h, int level, int param, int value);
 int hier_tune_get(const amrx_hier* h, int level, int param, int* value);
 
@@ -315,8 +319,8 @@ int hier_tune_time(amrx_hier* h, int level, int substep, int tile, int reps, dou
 
 /* Time the edge EMF and update stages of substep 0 of `level`: the fused
  * kernel with tile `tile` (every table entry is allowed: its LDS footprint is
- * 3 (tx+1)(ty+1)(tz+1) reals), or the two staged kernels for tile = -1;
- * `reps` repetitions, *ms = mean device time per repetition.  Writes the
+ * 3 (tx+1)(ty+1)(tz+1) reals), or the two staged kernels for tile = -1
+ * (-2: with the non-temporal update of AMRX_TUNE_UPDATE_NT); `reps` repetitions, *ms = mean device time per repetition.  Writes the
  * level's next-state buffer and its EMF registers, which hold nothing needed
  * between root steps: call it only between steps (hier_step), never inside a
  * sequence of per-level calls.  Synchronising.  Needs hier_bind. */

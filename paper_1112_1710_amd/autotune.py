@@ -4,7 +4,9 @@ EMFs, update).
 
 For every level of a bound hierarchy and each group the candidates are the
 staged kernels and the fused LDS-tiled kernel with each tile shape of the
-library's table that fits the LDS limit at the hierarchy's precision.  Each is
+library's table that fits the LDS limit at the hierarchy's precision (for the
+last group also the staged kernels with the update's next-state stores marked
+non-temporal, which helps on some levels and hurts on others).  Each is
 timed on the level's own patches (``hier_tune_time``: the first group, writing
 only intermediate scratch, summed over the level's substeps;
 ``hier_tune_time_eu``: the last group on substep 0, writing only the level's
@@ -21,7 +23,8 @@ set, else ``~/.cache/amrx/tune.json``.
 import json
 import os
 
-from .binding import FP32_MIXED, TUNE_FLUX_SPLIT, TUNE_FUSED, TUNE_FUSED_EU, TUNE_TILE, TUNE_TILE_EU, tile_table
+from .binding import (FP32_MIXED, TUNE_FLUX_SPLIT, TUNE_FUSED, TUNE_FUSED_EU, TUNE_TILE, TUNE_TILE_EU, TUNE_UPDATE_NT,
+                      tile_table)
 
 G = 4
 
@@ -79,11 +82,14 @@ def _store(path, data):
 
 
 STAGED = -1
+STAGED_NT = -2   # edge/update group only: the staged kernels, the update storing non-temporally
 
 
 def _apply(h, level, choice, group="a"):
     fused, tile = (TUNE_FUSED, TUNE_TILE) if group == "a" else (TUNE_FUSED_EU, TUNE_TILE_EU)
-    if choice == STAGED:
+    if group != "a":
+        h.tune_set(TUNE_UPDATE_NT, 1 if choice == STAGED_NT else 0, level)
+    if choice in (STAGED, STAGED_NT):
         h.tune_set(fused, 0, level)
     else:
         h.tune_set(fused, 1, level)
@@ -91,15 +97,20 @@ def _apply(h, level, choice, group="a"):
 
 
 def _shape(table, choice):
-    return "staged" if choice == STAGED else "x".join(str(x) for x in table[choice][:3])
+    if choice == STAGED:
+        return "staged"
+    if choice == STAGED_NT:
+        return "staged-nt"
+    return "x".join(str(x) for x in table[choice][:3])
 
 
 def autotune(h, reps=5, use_cache=True, path=None, groups=("a", "eu", "flux")):
     """Select staged or fused (and the tile) for every level of the bound hierarchy `h` and each group.
 
     Returns {level: (choice, shape, ms, source)} for the first three stages, and, when "eu" is in `groups`,
-    the same for the edge/update stages under the key ("eu", level): choice -1 = staged, else the tile index;
-    shape "staged" or "TXxTYxTZ"; ms the measured time; source "search" or "cache".  In FP32_MIXED, "flux"
+    the same for the edge/update stages under the key ("eu", level): choice -1 = staged, -2 = staged with the
+    update storing the next state non-temporally (edge/update only), else the tile index; shape "staged",
+    "staged-nt" or "TXxTYxTZ"; ms the measured time; source "search" or "cache".  In FP32_MIXED, "flux"
     also times the flux stage's two-launch and one-launch forms per level under ("flux", level), choice 1 or
     0; that choice depends on how many faces of the current state are low-beta, not on the level's shape,
     so it is never cached.
@@ -108,7 +119,7 @@ def autotune(h, reps=5, use_cache=True, path=None, groups=("a", "eu", "flux")):
     cache = _load(path) if use_cache else {}
     table = tile_table(h.precision)
     candidates = {"a": [STAGED] + [t for t, (_, _, _, lds) in enumerate(table) if lds > 0],
-                  "eu": [STAGED] + list(range(len(table)))}
+                  "eu": [STAGED, STAGED_NT] + list(range(len(table)))}
     arch = arch_name()
     levels = 1 + max(p[0] for p in h.spec.patches)
     out = {}
@@ -126,7 +137,7 @@ def autotune(h, reps=5, use_cache=True, path=None, groups=("a", "eu", "flux")):
         if group == "flux":
             continue
         for level in range(levels):
-            tag = "" if group == "a" else "|eu"
+            tag = "" if group == "a" else "|eu2"
             key = f"{arch}|p{h.precision}|l{min(level, 1)}|{size_class(h.spec, level)}{tag}"
             okey = level if group == "a" else ("eu", level)
             cands = candidates[group]

@@ -15,7 +15,8 @@ G = 4
 
 KERNEL_CLASSES = ("prim", "bhalf", "pred", "flux", "edge", "update", "copy", "prolong", "restrict",
                   "fluxcorr", "emfcorr", "sync", "cfl", "cons", "primhalf", "edgeupd")
-TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL, TUNE_PAIR, TUNE_FUSED_EU, TUNE_TILE_EU, TUNE_GHOSTS, TUNE_FLUX_SPLIT = range(8)
+(TUNE_FUSED, TUNE_TILE, TUNE_EXTEND_ALL, TUNE_PAIR, TUNE_FUSED_EU, TUNE_TILE_EU, TUNE_GHOSTS, TUNE_FLUX_SPLIT,
+ TUNE_UPDATE_NT) = range(9)
 
 _ERRORS = {-1: "EINVAL", -2: "ENEST", -3: "EOVERLAP", -4: "ENOMEM", -5: "EHIP", -6: "ESTATE", -7: "EPHYS"}
 
@@ -342,7 +343,8 @@ class Hierarchy:
         return ms.value
 
     def tune_time_eu(self, level, tile, reps=5):
-        """Mean ms of the edge EMF and update stages of substep 0 (tile -1: staged); between steps only."""
+        """Mean ms of the edge EMF and update stages of substep 0 (tile -1: staged, -2: staged with the
+        non-temporal update); between steps only."""
         ms = C.c_double()
         self._check(self.lib.hier_tune_time_eu(self.h, level, tile, reps, C.byref(ms)))
         return ms.value

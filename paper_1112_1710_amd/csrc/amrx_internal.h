@@ -223,6 +223,8 @@ struct Sched {
 
 hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, int blk_first, int nblk,
                         int cur, int level, int substep);
+// The update stage's kernel over a task list; nt: the next state written with non-temporal stores.
+hipError_t launch_update(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, bool nt);
 // The flux stage; FP32_MIXED: split = float pass + low-beta pass, otherwise one pass with the
 // double Riemann solver inline (other precisions ignore it).
 hipError_t launch_flux(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, int substep,

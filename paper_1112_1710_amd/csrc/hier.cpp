@@ -142,6 +142,7 @@ struct amrx_hier {
   std::vector<std::array<std::array<TaskList, NTILE>, 2>> fb_p;
   bool fused_b[AMRX_MAXLEV] = {false};  // per level: fused (true) or staged edge EMF and update stages
   bool flux_split[AMRX_MAXLEV];         // FP32_MIXED, per level: float + low-beta pass (true) or one pass
+  bool update_nt[AMRX_MAXLEV];          // per level: the staged update writes the next state non-temporally
   int tile_b[AMRX_MAXLEV] = {0};
   bool extend_all = false;            // extend every side of refined patches (set before finalize)
   bool time_ghosts = false;           // coarse-time-derivative ghosts instead of extended ghost regions
@@ -1695,19 +1696,21 @@ int do_advance(amrx_hier* h, int level, double dt, int substep, bool plain) {
     stg0 = STAGE_FLUX;
   }
   const int stg1 = h->fused_b[level] ? STAGE_EDGE : NSTAGE;
+  // the flux and update stages take the level's tuned variants
+  auto stage = [&](const TaskList& T, int stg) {
+    if (stg == STAGE_FLUX) return launch_flux(c, T.first, T.count, T.nblk, cur, level, substep, h->flux_split[level]);
+    if (stg == STAGE_UPDATE) return launch_update(c, T.first, T.count, T.nblk, cur, level, h->update_nt[level]);
+    return launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep);
+  };
   for (int stg = stg0; stg < stg1; ++stg) {
     if (plain) {
       for (int id : h->lev[level]) {
         const TaskList& T = h->stage_p[id][substep][stg];
-        HIPCHK(TIMED(AMRX_K_PRIM + stg, stg == STAGE_FLUX ? launch_flux(c, T.first, T.count, T.nblk, cur, level, substep, h->flux_split[level])
-                                                         : launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep)),
-               "advance stage");
+        HIPCHK(TIMED(AMRX_K_PRIM + stg, stage(T, stg)), "advance stage");
       }
     } else {
       const TaskList& T = h->stage_b[level][substep][stg];
-      HIPCHK(TIMED(AMRX_K_PRIM + stg, stg == STAGE_FLUX ? launch_flux(c, T.first, T.count, T.nblk, cur, level, substep, h->flux_split[level])
-                                                       : launch_stage(c, stg, T.first, T.count, 0, T.nblk, cur, level, substep)),
-             "advance stage");
+      HIPCHK(TIMED(AMRX_K_PRIM + stg, stage(T, stg)), "advance stage");
     }
   }
   if (h->fused_b[level]) {
@@ -2313,7 +2316,10 @@ int hier_create(const amrx_desc* desc, amrx_hier** out) {
   h->lev.assign(AMRX_MAXLEV, {});
   h->real_size = desc->precision == AMRX_FP64 ? 8 : 4;
   h->reg_size = desc->precision == AMRX_FP32 ? 4 : 8;
-  for (int l = 0; l < AMRX_MAXLEV; ++l) h->flux_split[l] = true;
+  for (int l = 0; l < AMRX_MAXLEV; ++l) {
+    h->flux_split[l] = true;
+    h->update_nt[l] = false;
+  }
   *out = h;
   return AMRX_OK;
 }
@@ -2612,6 +2618,12 @@ int hier_tune_set(amrx_hier* h, int level, int param, int value) {
       changed = changed || h->flux_split[l] != (value == 1);
       h->flux_split[l] = value == 1;
     }
+  } else if (param == AMRX_TUNE_UPDATE_NT) {
+    if (value != 0 && value != 1) return fail(h, AMRX_EINVAL, "AMRX_TUNE_UPDATE_NT takes 0 or 1");
+    for (int l = l0; l < l1; ++l) {
+      changed = changed || h->update_nt[l] != (value == 1);
+      h->update_nt[l] = value == 1;
+    }
   } else {
     return fail(h, AMRX_EINVAL, "unknown tuning parameter");
   }
@@ -2650,6 +2662,8 @@ int hier_tune_get(const amrx_hier* h, int level, int param, int* value) {
     *value = h->tile_b[level];
   } else if (param == AMRX_TUNE_FLUX_SPLIT) {
     *value = h->flux_split[level] ? 1 : 0;
+  } else if (param == AMRX_TUNE_UPDATE_NT) {
+    *value = h->update_nt[level] ? 1 : 0;
   } else {
     return AMRX_EINVAL;
   }
@@ -2741,7 +2755,7 @@ int hier_tune_time(amrx_hier* h, int level, int substep, int tile, int reps, dou
 int hier_tune_time_eu(amrx_hier* h, int level, int tile, int reps, double* ms) {
   if (!ready(h)) return AMRX_ESTATE;
   if (!ms || reps < 1 || level < 0 || level >= h->nlev) return fail(h, AMRX_EINVAL, "bad level, repetition count or output");
-  if (tile < -1 || tile >= NTILE) return fail(h, AMRX_EINVAL, "tile index out of range");
+  if (tile < -2 || tile >= NTILE) return fail(h, AMRX_EINVAL, "tile index out of range");
   const TaskList& T = h->fb_b[level][0][tile < 0 ? 0 : tile];
   const int* ts = kTiles[tile < 0 ? 0 : tile];
   hipStream_t s = (hipStream_t)h->d.stream;
@@ -2756,10 +2770,10 @@ int hier_tune_time_eu(amrx_hier* h, int level, int tile, int reps, double* ms) {
     if (tile >= 0) {
       e = launch_fused_b(h->ctx, T.first, T.count, T.nblk, h->cur[level], level, 0, ts[0], ts[1], ts[2]);
     } else {
-      for (int stg = STAGE_EDGE; stg <= STAGE_UPDATE && e == hipSuccess; ++stg) {
-        const TaskList& L = h->stage_b[level][0][stg];
-        e = launch_stage(h->ctx, stg, L.first, L.count, 0, L.nblk, h->cur[level], level, 0);
-      }
+      const TaskList& LE = h->stage_b[level][0][STAGE_EDGE];
+      const TaskList& LU = h->stage_b[level][0][STAGE_UPDATE];
+      e = launch_stage(h->ctx, STAGE_EDGE, LE.first, LE.count, 0, LE.nblk, h->cur[level], level, 0);
+      if (e == hipSuccess) e = launch_update(h->ctx, LU.first, LU.count, LU.nblk, h->cur[level], level, tile == -2);
     }
   }
   if (e == hipSuccess) e = hipEventRecord(b, s);

@@ -1172,7 +1172,14 @@ __global__ __launch_bounds__(AMRX_BLOCK) void k_edge(DevCtx c, int first, int n,
 // index eq + offsets is ee[E][...] with strides es (global arrays or an LDS tile).  Every operand is
 // loaded before the first store: both state buffers share one arena, so a load after a store could
 // not be moved ahead of it.
-template <typename R, typename I>
+// Store of the next state: NT marks it non-temporal (a cache hint only; the value is the same).
+template <bool NT, typename R>
+__device__ __forceinline__ void store_next(R* p, R v) {
+  if constexpr (NT) __builtin_nontemporal_store(v, p);
+  else *p = v;
+}
+
+template <typename R, typename I, bool NT = false>
 __device__ __forceinline__ void update_entry(const R* U, R* N, const R* X, const Strides& S, long long q, bool ix,
                                              bool iy, bool iz, R dt_dx, const R* const ee[3], const I es[3], I eq) {
   const long long v = S.v;
@@ -1214,18 +1221,18 @@ __device__ __forceinline__ void update_entry(const R* U, R* N, const R* X, const
       for (int m = 0; m < 4; ++m) div[1 + m] += f1[d][m] - f0[d][m];
     }
 #pragma unroll
-    for (int m = 0; m < 5; ++m) N[m * v + q] = u[m] - dt_dx * div[m];
+    for (int m = 0; m < 5; ++m) store_next<NT>(N + m * v + q, u[m] - dt_dx * div[m]);
   }
 #pragma unroll
   for (int D = 0; D < 3; ++D) {
     if (face[D]) {
       const R curl = (ec_hi[D] - ec_lo[D]) - (ea_hi[D] - ea_lo[D]);
-      N[(5 + D) * v + q] = bo[D] - dt_dx * curl;
+      store_next<NT>(N + (5 + D) * v + q, bo[D] - dt_dx * curl);
     }
   }
 }
 
-template <typename R, bool MIX>
+template <typename R, bool MIX, bool NT = false>
 __device__ __forceinline__ void d_update(const DevCtx& c, int vb, int nb, int first, int n, int cur, int level) {
   (void)nb;
   const double dt = level_dt(c, level);
@@ -1242,12 +1249,12 @@ __device__ __forceinline__ void d_update(const DevCtx& c, int vb, int nb, int fi
   const bool ix = w.i < T.hi[0] - 1, iy = w.j < T.hi[1] - 1, iz = w.k < T.hi[2] - 1;
   const R* EE = X + SCR_E * S.v;
   const R* const ee[3] = {EE, EE + S.v, EE + 2 * S.v};
-  update_entry<R, long long>(U, N, X, S, q, ix, iy, iz, dt_dx, ee, S.s, q);
+  update_entry<R, long long, NT>(U, N, X, S, q, ix, iy, iz, dt_dx, ee, S.s, q);
 }
 
-template <typename R, bool MIX>
+template <typename R, bool MIX, bool NT = false>
 __global__ __launch_bounds__(AMRX_BLOCK) void k_update(DevCtx c, int first, int n, int cur, int level) {
-  d_update<R, MIX>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level);
+  d_update<R, MIX, NT>(c, xcd_block(blockIdx.x, gridDim.x), gridDim.x, first, n, cur, level);
 }
 
 // ---------------------------------------------------------------------------
@@ -2333,6 +2340,16 @@ hipError_t launch_stage(const DevCtx& c, int stage, int task_first, int ntask, i
     case STAGE_UPDATE: DISPATCH(k_update, g, c, task_first, ntask, cur, level); break;
     default: return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_update(const DevCtx& c, int task_first, int ntask, int nblk, int cur, int level, bool nt) {
+  if (ntask == 0 || nblk == 0) return hipSuccess;
+  const dim3 g(nblk);
+  if (!nt) DISPATCH(k_update, g, c, task_first, ntask, cur, level);
+  else if (c.precision == 0) k_update<double, false, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, task_first, ntask, cur, level);
+  else if (c.precision == 1) k_update<float, false, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, task_first, ntask, cur, level);
+  else k_update<float, true, true><<<g, AMRX_BLOCK, 0, c.stream>>>(c, task_first, ntask, cur, level);
   return hipGetLastError();
 }
 

@@ -153,7 +153,8 @@ def test_autotune_selects_allowed_tiles_and_keeps_results(tmp_path):
             if t >= 0:
                 assert b.tune_get(binding.TUNE_TILE, level=key) == t
         else:
-            assert b.tune_get(binding.TUNE_FUSED_EU, level=key[1]) == (0 if t == -1 else 1)
+            assert b.tune_get(binding.TUNE_FUSED_EU, level=key[1]) == (0 if t < 0 else 1)
+            assert b.tune_get(binding.TUNE_UPDATE_NT, level=key[1]) == (1 if t == -2 else 0)
             if t >= 0:
                 assert b.tune_get(binding.TUNE_TILE_EU, level=key[1]) == t
     again = autotune(b, reps=2, path=cache)
@@ -266,3 +267,24 @@ def test_paired_levels_bit_identical(name, prec):
     _same_interiors(spec, a, g)
     d = g.diag()
     assert d["sync_flux_max"] == 0.0 and d["sync_face_max"] == 0.0 and d["phys_flag"] == 0.0
+
+
+@pytest.mark.parametrize("prec", [FP64, FP32, FP32_MIXED])
+def test_non_temporal_update_is_bit_identical(prec):
+    """The staged update with its next-state stores marked non-temporal (on every level, then on one level)
+    gives the same states and dts as ordinary stores, batched and graph-replayed."""
+    spec = H.small_three_level()
+    _say("non-temporal update", prec)
+    field = SmoothField(26)
+    a = Hierarchy(spec, prec)
+    b = Hierarchy(spec, prec)
+    b.tune_set(binding.TUNE_UPDATE_NT, 1)
+    a.set_field(field)
+    b.set_field(field)
+    for mode in (BATCHED, GRAPH, GRAPH):
+        assert a.step(mode) == b.step(mode)
+    b.tune_set(binding.TUNE_UPDATE_NT, 0, level=1)
+    for mode in (PLAIN, GRAPH):
+        assert a.step(mode) == b.step(mode)
+    _same_interiors(spec, a, b)
+    assert b.tune_time_eu(1, -2, 1) > 0

@@ -454,7 +454,14 @@ def test_tile_table_and_tuning_switches(prec):
     with pytest.raises(binding.AmrxError):
         h.tune_set(binding.TUNE_FUSED, 2)
     with pytest.raises(binding.AmrxError):
-        h.tune_set(8, 0)
+        h.tune_set(9, 0)
+    # non-temporal stores of the staged update: off by default, selectable per level
+    assert all(h.tune_get(binding.TUNE_UPDATE_NT, level=lv) == 0 for lv in range(3))
+    h.tune_set(binding.TUNE_UPDATE_NT, 1, level=1)
+    assert [h.tune_get(binding.TUNE_UPDATE_NT, level=lv) for lv in range(3)] == [0, 1, 0]
+    with pytest.raises(binding.AmrxError):
+        h.tune_set(binding.TUNE_UPDATE_NT, 2)
+    h.tune_set(binding.TUNE_UPDATE_NT, 0)
     # FP32_MIXED flux stage: two launches by default, one launch selectable per level
     assert all(h.tune_get(binding.TUNE_FLUX_SPLIT, level=lv) == 1 for lv in range(3))
     h.tune_set(binding.TUNE_FLUX_SPLIT, 0, level=2)
@@ -556,8 +563,9 @@ class _FakeTuned:
 
 
 def test_autotune_search_and_cache(tmp_path, monkeypatch):
-    """The autotuner keeps the fastest candidate per level (staged = -1 or a tile), caches it, and a
-    second run applies the cached choice without timing."""
+    """The autotuner keeps the fastest candidate per level (staged = -1, for edge/update also staged with
+    the non-temporal update = -2, or a tile), caches it, and a second run applies the cached choice
+    without timing."""
     _lib()
     from paper_1112_1710_amd import autotune as at
     monkeypatch.setattr(at, "arch_name", lambda device=0: "gfx950")
@@ -568,8 +576,8 @@ def test_autotune_search_and_cache(tmp_path, monkeypatch):
     times[(0, -1)] = 0.5           # level 0: staged fastest
     times[(1, allowed[2])] = 0.1   # level 1: one tile fastest
     for lv in range(2):
-        for t in [-1] + list(range(len(table))):
-            times[("eu", lv, t)] = 1.0 + 0.01 * (t + 1)
+        for t in [-2, -1] + list(range(len(table))):
+            times[("eu", lv, t)] = 1.0 + 0.01 * (t + 3)
     times[("eu", 0, len(table) - 1)] = 0.2  # edge/update: a tile on level 0, staged on level 1
     times[("eu", 1, -1)] = 0.3
     fake = _FakeTuned(spec, 1, times)
@@ -582,6 +590,14 @@ def test_autotune_search_and_cache(tmp_path, monkeypatch):
     assert out[("eu", 0)][0] == len(table) - 1 and out[("eu", 1)][1] == "staged"
     assert (binding.TUNE_FUSED_EU, 1, 0) in fake.calls and (binding.TUNE_TILE_EU, len(table) - 1, 0) in fake.calls
     assert (binding.TUNE_FUSED_EU, 0, 1) in fake.calls
+    assert (binding.TUNE_UPDATE_NT, 0, 0) in fake.calls and (binding.TUNE_UPDATE_NT, 0, 1) in fake.calls
+    # the non-temporal staged update wins where it is fastest
+    times_nt = dict(times)
+    times_nt[("eu", 1, -2)] = 0.25
+    fake_nt = _FakeTuned(spec, 1, times_nt)
+    out_nt = at.autotune(fake_nt, reps=1, use_cache=False)
+    assert out_nt[("eu", 1)][:2] == (-2, "staged-nt")
+    assert (binding.TUNE_UPDATE_NT, 1, 1) in fake_nt.calls and (binding.TUNE_FUSED_EU, 0, 1) in fake_nt.calls
 
     def no_timing(*a, **k):
         raise AssertionError("timed although cached")
