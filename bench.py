@@ -60,16 +60,16 @@ WORDS_PER_UNIT = {
 # launches the average runs over), null otherwise.
 MEASURED_TRAFFIC = {
     ("deep", "fp32", "primhalf"): [
-        {"bytes_per_launch": 2.827e9, "fused_levels": [4, 5, 6, 7], "sources": "a614ac8997705d0f:45beca525afb9b2e"},
-        {"bytes_per_launch": 2.747e9, "fused_levels": [3, 4, 5, 6, 7], "sources": "a614ac8997705d0f:45beca525afb9b2e"},
+        {"bytes_per_launch": 2.827e9, "fused_levels": [4, 5, 6, 7], "sources": "587fb17101c0194d:af5e83b69d950ea5"},
+        {"bytes_per_launch": 2.747e9, "fused_levels": [3, 4, 5, 6, 7], "sources": "587fb17101c0194d:af5e83b69d950ea5"},
     ],
 }
 
 # Fraction of the dominant kernel's vector-ALU issue slots used (SQ_INSTS_VALU against 256 CUs x one
 # wave-instruction per cycle x 2.4 GHz over its mean duration), from rocprofv3 counters, same validity rule.
 MEASURED_VALU_ISSUE = {
-    ("deep", "fp32", "primhalf"): {"frac": 0.68, "sources": "a614ac8997705d0f:45beca525afb9b2e"},
-    ("deep", "fp32", "flux"): {"frac": 0.79, "sources": "a614ac8997705d0f:45beca525afb9b2e"},
+    ("deep", "fp32", "primhalf"): {"frac": 0.67, "sources": "587fb17101c0194d:af5e83b69d950ea5"},
+    ("deep", "fp32", "flux"): {"frac": 0.79, "sources": "587fb17101c0194d:af5e83b69d950ea5"},
 }
 
 
