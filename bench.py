@@ -73,6 +73,15 @@ MEASURED_VALU_ISSUE = {
 }
 
 
+def measured_traffic(workload, precision, kernel_class, fused_levels):
+    """The stored counter reading of a kernel class that applies to a run: same workload, precision and
+    kernel sources and, where the reading names them, the same fused levels; None if there is none."""
+    for m in MEASURED_TRAFFIC.get((workload, precision, kernel_class), []):
+        if m["sources"] == sources_hash() and m.get("fused_levels", sorted(fused_levels)) == sorted(fused_levels):
+            return m
+    return None
+
+
 def sources_hash():
     import hashlib
     out = []
@@ -567,9 +576,7 @@ def main():
         avg_ms = ms_total / nlaunch
         achieved = bytes_per_launch / (avg_ms * 1e-3) / 1e9
         fused_levels = {int(k) for k, v in (tiles or {}).items() if v != "staged"}
-        readings = MEASURED_TRAFFIC.get((args.workload, args.precision, dom), []) if args.ghosts == "extended" else []
-        meas = next((m for m in readings if m["sources"] == sources_hash()
-                     and m.get("fused_levels", sorted(fused_levels)) == sorted(fused_levels)), None)
+        meas = measured_traffic(args.workload, args.precision, dom, fused_levels) if args.ghosts == "extended" else None
         traffic = None
         if meas is not None:
             traffic = round(meas["bytes_per_launch"] / (avg_ms * 1e-3) / 1e9, 1)

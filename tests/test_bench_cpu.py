@@ -40,3 +40,27 @@ def test_cpu_baseline_sample_runs_the_oracle_on_the_workload():
     assert out["kind"] == "oracle" and out["unit"] == "zone-updates/s"
     assert out["value"] > 0 and out["single_core"]["value"] > 0 and out["cores"] >= 1
     assert "CPU:" in out["sample"]
+
+
+def test_measured_traffic_applies_only_to_its_sources_and_fused_levels(monkeypatch):
+    """A stored HBM reading is reported only for the kernel sources it was taken on and for a run that
+    fused the same levels (the launches its per-launch average runs over)."""
+    import bench
+    monkeypatch.setattr(bench, "MEASURED_TRAFFIC", {("deep", "fp32", "primhalf"): [
+        {"bytes_per_launch": 1.0, "fused_levels": [4, 5], "sources": bench.sources_hash()},
+        {"bytes_per_launch": 2.0, "fused_levels": [3, 4, 5], "sources": bench.sources_hash()},
+        {"bytes_per_launch": 3.0, "fused_levels": [5], "sources": "0" * 16 + ":" + "0" * 16}]})
+    assert bench.measured_traffic("deep", "fp32", "primhalf", {4, 5})["bytes_per_launch"] == 1.0
+    assert bench.measured_traffic("deep", "fp32", "primhalf", {5, 4, 3})["bytes_per_launch"] == 2.0
+    assert bench.measured_traffic("deep", "fp32", "primhalf", {5}) is None           # other sources
+    assert bench.measured_traffic("deep", "fp32", "primhalf", {2, 3, 4, 5}) is None  # no reading
+    assert bench.measured_traffic("deep", "fp32_mixed", "primhalf", {4, 5}) is None
+    assert bench.measured_traffic("two_level", "fp32", "flux", set()) is None
+
+
+def test_stored_readings_match_the_current_kernel_sources():
+    """The committed counter readings were taken on the kernel sources in the tree."""
+    import bench
+    for recs in bench.MEASURED_TRAFFIC.values():
+        assert all(r["sources"] == bench.sources_hash() for r in recs)
+    assert all(r["sources"] == bench.sources_hash() for r in bench.MEASURED_VALU_ISSUE.values())
