@@ -2451,7 +2451,7 @@ int hier_bind(amrx_hier* h, void* state, size_t state_bytes, void* scratch, size
   HIPCHK(hipStreamSynchronize(s), "stream synchronize");
   h->ctx = make_ctx(h);
   HIPCHK(launch_clear_slots(h->ctx), "clear slots");
-  HIPCHK(launch_clear_ints(h->ctx, h->ctx.lbflag, h->lbflag_n), "clear flux block flags");
+  HIPCHK(launch_clear_ints(h->ctx, h->ctx.lbflag, h->lbflag_n), "clear the low-beta wave list");
   {
     int dev = 0, ncu = 0;
     HIPCHK(hipGetDevice(&dev), "get device");
